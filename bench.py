@@ -1,0 +1,224 @@
+"""Benchmark: P2M queries/sec on one MI355X.
+
+Workload (the headline configuration): icosphere level 8 (655,362 vertices,
+1,310,720 triangles) displaced by 4-octave value-noise fbm, float32; 10^7
+queries, half uniform in the 1.5x AABB and half near the surface.  One step
+is one pass of the whole query path over the batch with the inputs resident
+in HBM: Morton keys + stable radix sort of the queries, then the query
+kernel (KD-tree nearest vertex, interception-list scan with exact
+point-segment / point-triangle tests, resolved primitive, closest point,
+distance).  The host precompute is timed separately and never counted.
+
+Also reported on the same GPU: forward+backward on 10^6 near-surface queries
+of the same mesh (loss = sum of squared distances), the FP64 brute-force
+oracle on a bounded sample of the workload's queries (host cores), and the
+multi-threaded CPU P2M query over the same tree and table.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_query_c2.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("query_core.hpp", "p2m_device.hip"):
+        with open(os.path.join(ROOT, "paper_2308_16084_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n_queries: int):
+    """HBM bytes per query-kernel launch from committed rocprofv3 counter
+    summaries, if they were taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if int(vals.get("queries", -1)) != n_queries:
+        return None
+    return float(vals["hbm_bytes_per_launch"])
+
+
+def b_alg(nodes: float, edges: float, faces: float) -> float:
+    """Algorithmic bytes per query: query in (12) + results out (20) + 16 per
+    KD-tree node + 8 for the list offsets + per edge (id 4 + endpoints' ids 8
+    + coordinates 24) + per face (id 4 + vertex ids 12 + coordinates 36)."""
+    return 12 + 20 + 16 * nodes + 8 + 36 * edges + 52 * faces
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--queries", type=int, default=10_000_000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
+    ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward leg")
+    ap.add_argument("--cache", default=os.environ.get("P2M_CACHE_DIR", ""),
+                    help="directory to save/load the precomputed mesh (default $P2M_CACHE_DIR; empty: none)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2308_16084_amd as P
+    from synth import configs as C
+    from synth import queries as SQ
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+
+    t0 = time.time()
+    w = C.c2(n_queries=args.queries)
+    log(f"[bench] workload generated in {time.time() - t0:.1f}s: {w.V.shape[0]} V, {w.F.shape[0]} F, {len(w.Q)} queries")
+    t0 = time.time()
+    mesh, stats = P.Mesh.cached(w.V, w.F, (w.domain_lo, w.domain_hi), args.cache or None)
+    t_pre = time.time() - t0
+    log(f"[bench] host precompute {t_pre:.1f}s {json.dumps({k: stats[k] for k in stats if k.startswith('t_') or k in ('avg_list', 'max_list', 'flood_tests')})}")
+    dev_bytes = mesh.upload(0)
+    q = torch.from_numpy(w.Q).to(dev)
+    n = q.shape[0]
+    out = {"prim": torch.empty(n, dtype=torch.int32, device=dev),
+           "closest": torch.empty((n, 3), dtype=torch.float32, device=dev),
+           "dist": torch.empty(n, dtype=torch.float32, device=dev),
+           "status": torch.empty(n, dtype=torch.uint8, device=dev)}
+    torch.cuda.synchronize()
+
+    def step(profile=False):
+        mesh.query(q, out=out, profile=profile)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    qps = n / (ms_step / 1e3)
+    log(f"[bench] forward: {ms_step:.3f} ms/step ({wall / args.steps * 1e3:.3f} ms wall), {qps / 1e9:.3f} Gq/s")
+
+    # live per-kernel timing of the dominant (query) kernel over profiled steps
+    order_ms, query_ms = [], []
+    for _ in range(args.steps):
+        step(profile=True)
+        a, b = mesh.query_profile()
+        order_ms.append(a)
+        query_ms.append(b)
+    order_avg, query_avg = float(np.mean(order_ms)), float(np.mean(query_ms))
+    log(f"[bench] stage times: ordering {order_avg:.3f} ms, query kernel {query_avg:.3f} ms")
+
+    # algorithmic bytes per query from the same tree/table (host model counts)
+    rng = np.random.default_rng(123)
+    sub = w.Q[rng.choice(n, size=min(n, 200_000), replace=False)]
+    hs = mesh.query_host(sub)
+    nodes, edges, faces = hs["nodes"] / len(sub), hs["edges"] / len(sub), hs["faces"] / len(sub)
+    balg = b_alg(nodes, edges, faces)
+    achieved = balg * n / (query_avg / 1e3) / 1e9
+    traffic = measured_traffic(n)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_query", "kernel_ms": round(query_avg, 4),
+                "b_alg_bytes_per_query": round(balg, 1),
+                "per_query": {"kdtree_nodes": round(nodes, 2), "edges_tested": round(edges, 2),
+                              "faces_tested": round(faces, 2)}}
+
+    result = {"metric": "P2M queries/sec at 1.3M tris (fwd, fwd+bwd, batched); % of HBM peak",
+              "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+              "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+              "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+              "data": "synthetic (seeded displaced icosphere; generated queries)",
+              "config": {"workload": "icosphere level 8 + 4-octave fbm displacement (655,362 V, 1,310,720 F), "
+                                     "1e7 queries: 50% uniform in 1.5x AABB, 50% near-surface (sigma 1% diag)",
+                         "queries": n, "ordering": "morton30+radix", "host_precompute_s": round(t_pre, 1),
+                         "precompute_cached": "loaded_from" in stats,
+                         "avg_list": round(float(stats.get("avg_list", 0.0)), 2),
+                         "device_bytes": dev_bytes},
+              "roofline": roofline,
+              "stages_ms": {"ordering": round(order_avg, 4), "query": round(query_avg, 4)}}
+
+    if not args.no_bwd:
+        w5 = C.c5()
+        q5 = torch.from_numpy(w5.Q).to(dev)
+        Vt = torch.from_numpy(w.V).to(dev)
+        n5 = q5.shape[0]
+
+        def fb():
+            qq = q5.detach().requires_grad_(True)
+            VV = Vt.detach().requires_grad_(True)
+            d, _, _ = P.p2m_distance(qq, VV, mesh)
+            (d * d).sum().backward()
+            return qq.grad, VV.grad
+
+        for _ in range(args.warmup):
+            fb()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            fb()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_fb = e0.elapsed_time(e1) / args.steps
+        result["fwd_bwd"] = {"value": round(n5 / (ms_fb / 1e3), 1), "unit": "queries/s", "ms_per_step": round(ms_fb, 4),
+                             "workload": "same mesh, 1e6 near-surface queries, loss = sum d^2, grads wrt q [1e6,3] and V [655362,3]"}
+        log(f"[bench] fwd+bwd: {ms_fb:.3f} ms/step, {n5 / (ms_fb / 1e3) / 1e9:.3f} Gq/s")
+
+    if not args.no_cpu:
+        import oracle
+        om = oracle.OracleMesh(w.V, w.F)
+        ns = 1500
+        qs = w.Q[rng.choice(n, size=ns, replace=False)]
+        t0 = time.perf_counter()
+        om.query(qs)
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(ns / dt, 2), "unit": "queries/s", "cores": oracle.num_threads(),
+                                  "kind": "oracle",
+                                  "sample": f"{ns} queries drawn from the workload's 1e7 (seed 123), FP64 brute force over all V, E, F; {dt:.1f}s"}
+        log(f"[bench] oracle: {ns / dt:.1f} q/s on {oracle.num_threads()} threads ({dt:.1f}s)")
+        sub2 = w.Q[:1_000_000]
+        nth = len(os.sched_getaffinity(0))
+        t0 = time.perf_counter()
+        mesh.query_host(sub2, threads=nth)
+        dt = time.perf_counter() - t0
+        result["cpu_p2m"] = {"value": round(len(sub2) / dt, 1), "unit": "queries/s", "threads": nth,
+                             "kind": "multi-threaded CPU P2M query, same KD tree and table, float32",
+                             "sample": "first 1e6 queries of the workload"}
+        log(f"[bench] CPU P2M: {len(sub2) / dt:.0f} q/s")
+
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * p2m.h -- C interface of the MI355X point-to-mesh (P2M) query library.
+ *
+ * Method: Zong, Xu, Song, Chen, Xin, Wang, Tu, "P2M: A Fast Solver for
+ * Querying Distance from Point to Mesh Surface" (ACM TOG; arXiv 2308.16084).
+ * Given a triangle mesh with one copy of each vertex (Sec. 4.1), a host
+ * precompute builds a KD tree of the vertices and the interception table
+ * (Sec. 4; Appendix, Algorithm A.1).  A query then finds the nearest vertex
+ * v with the KD tree and tests v and the edges and faces in v's interception
+ * list (Algorithm A.2), returning the closest primitive (vertex, edge or
+ * face), the closest point and the distance (Sec. 1).
+ *
+ * Conventions
+ *  - No exceptions cross this interface; every call returns a p2m_status and
+ *    p2m_last_error() gives a message for the calling thread's last failure.
+ *  - "host" pointers are ordinary CPU memory; "dev" pointers are device
+ *    memory on the device the mesh was uploaded to (e.g. torch tensors).
+ *    Device buffers passed in are owned by the caller and never freed here.
+ *    Mesh and batch handles own their host structures and device arenas;
+ *    the *_destroy calls free them.
+ *  - Device calls are asynchronous and ordered on the caller's stream
+ *    (hipStream_t passed as void*; NULL = the null stream).  They do not
+ *    synchronise the host, except where stated.
+ *  - Primitive codes: prim = type << 30 | id, with type P2M_VERTEX, P2M_EDGE
+ *    or P2M_FACE.  Vertex id = input index, face id = input row, edge id =
+ *    rank of the undirected pair (min,max) among all face sides sorted
+ *    lexicographically (p2m_mesh_edges lists them).
+ *  - All coordinates are float32.  The host precompute runs in float64.
+ */
+#ifndef P2M_H
+#define P2M_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    P2M_OK = 0,
+    P2M_ERR_ARG = -1,      /* null pointer, negative count, bad option */
+    P2M_ERR_MESH = -2,     /* invalid mesh (see p2m_mesh_create) */
+    P2M_ERR_STATE = -3,    /* call out of order (e.g. query before upload) */
+    P2M_ERR_OOM = -4,      /* host or device allocation failed */
+    P2M_ERR_HIP = -5,      /* a HIP runtime call failed */
+    P2M_ERR_INTERNAL = -6, /* unexpected internal failure */
+    P2M_ERR_IO = -7        /* file could not be read or written */
+} p2m_status;
+
+enum { P2M_VERTEX = 0, P2M_EDGE = 1, P2M_FACE = 2, P2M_NONE = 3 };
+#define P2M_PRIM_TYPE(p) ((int32_t)((uint32_t)(p) >> 30))
+#define P2M_PRIM_ID(p) ((int32_t)((uint32_t)(p)&0x3FFFFFFFu))
+
+/* per-query status bits */
+enum { P2M_Q_OUT_OF_DOMAIN = 1, P2M_Q_NONFINITE = 2 };
+
+typedef struct p2m_mesh p2m_mesh;
+typedef struct p2m_batch p2m_batch;
+
+/* Interception-table construction modes. */
+enum {
+    P2M_TABLE_FLOODING = 0,  /* convexity filter + flooding (Sec. 4.4-4.5) */
+    P2M_TABLE_ALL_PAIRS = 1, /* convexity filter on every vertex-primitive pair (tiny meshes) */
+    P2M_TABLE_EVERYTHING = 2 /* every primitive in every list (tiny meshes; test aid) */
+};
+
+typedef struct {
+    /* Query domain D: the box queries are expected in.  Voronoi cells are
+     * clipped to D (the paper bounds them with 8 far virtual points, Sec.
+     * 4.3 Remark); answers for queries outside D are valid distances to the
+     * mesh but need not be the closest and are flagged P2M_Q_OUT_OF_DOMAIN. */
+    double domain_lo[3], domain_hi[3];
+    int use_default_domain; /* nonzero: D = mesh AABB scaled 10x about its centre */
+    int num_threads;        /* host threads for the precompute; 0 = all */
+    double margin_rel;      /* conservative margin, times diag(D); 0 = 1e-9 */
+    int table_mode;         /* P2M_TABLE_* */
+} p2m_build_opts;
+
+typedef struct {
+    double t_validate, t_kdt, t_delaunay, t_cells, t_flood, t_pack; /* seconds */
+    int64_t nv, ne, nf;
+    int64_t delaunay_edges, tets, exact_predicates;
+    int64_t flood_tests, flood_hits, quick_rejects, skipped_clips;
+    int64_t nnz_edges, nnz_faces, max_list;
+    double avg_list; /* (nnz_edges + nnz_faces) / nv */
+} p2m_build_stats;
+
+typedef struct {
+    int sort_queries;   /* <0 default (on), 0 off, 1 Morton-order the batch */
+    int block_size;     /* 0 default; else 64..1024, a multiple of 64 */
+    int profile;        /* nonzero: record HIP events around the ordering and
+                           query kernels (read with p2m_query_profile) */
+    int reserved[5];    /* must be 0 */
+} p2m_query_opts;
+
+/* ------------------------------------------------------------ host side */
+
+/* Copy a mesh: V host float [nv*3], F host int32 [nf*3].  Rejects (P2M_ERR_MESH)
+ * a vertex index out of range, a face that repeats a vertex or has zero area,
+ * non-finite coordinates, two vertices with equal coordinates (the problem
+ * statement assumes one copy per vertex, Sec. 4.1), nv or nf < 1, or more
+ * than 2^30-1 vertices, edges or faces. */
+p2m_status p2m_mesh_create(const float* V, int64_t nv, const int32_t* F, int64_t nf, p2m_mesh** out);
+void p2m_mesh_destroy(p2m_mesh* m);
+
+/* Vertex, edge and face counts (any pointer may be NULL). */
+p2m_status p2m_mesh_counts(const p2m_mesh* m, int64_t* nv, int64_t* ne, int64_t* nf);
+
+/* Canonical edges: *ne receives the count; pairs (host int32 [ne*2]) may be NULL. */
+p2m_status p2m_mesh_edges(const p2m_mesh* m, int64_t* ne, int32_t* pairs);
+
+/* Host precompute (Algorithm A.1 without R-trees): KD tree, Voronoi cells
+ * clipped to D, convexity-filtered flooding inspection, CSR table.  Blocks.
+ * opts may be NULL (default domain, all threads). */
+p2m_status p2m_precompute(p2m_mesh* m, const p2m_build_opts* opts, p2m_build_stats* stats);
+
+/* Inspect the precomputed structures.
+ * Table: off host uint32 [2*nv+1], ent host int32 [nnz]; vertex v's edges are
+ * ent[off[2v]..off[2v+1]) and its faces ent[off[2v+1]..off[2v+2]).  Pass
+ * NULL arrays to read *nnz only.
+ * Neighbours: Voronoi neighbours of each vertex, CSR (nb_off int64 [nv+1]).
+ * KD tree: node coordinates xyz float [nv*3] and vertex ids vid int32 [nv] in
+ * implicit left-balanced order (children of node i: 2i+1, 2i+2). */
+p2m_status p2m_mesh_table(const p2m_mesh* m, int64_t* nnz, uint32_t* off, int32_t* ent);
+p2m_status p2m_mesh_neighbors(const p2m_mesh* m, int64_t* nnz, int64_t* nb_off, int32_t* nb);
+p2m_status p2m_mesh_kdtree(const p2m_mesh* m, float* xyz, int32_t* vid);
+
+/* Save / load the mesh with its precomputed structures (versioned binary). */
+p2m_status p2m_save(const p2m_mesh* m, const char* path);
+p2m_status p2m_load(const char* path, p2m_mesh** out);
+
+/* Plain multi-threaded CPU P2M query over the same KD tree and table with
+ * the same float32 arithmetic as the device kernel (host arrays).  A
+ * reported baseline, never used by the device path.  counters (may be NULL)
+ * receive sums over queries: [0] KD-tree nodes visited, [1] edges tested,
+ * [2] faces tested. */
+p2m_status p2m_query_host(const p2m_mesh* m, const float* q, int64_t n, int32_t* prim, float* closest,
+                          float* dist, uint8_t* status, int num_threads, int64_t counters[3]);
+
+const char* p2m_last_error(void);
+
+/* ---------------------------------------------------------- device side */
+
+/* Copy the mesh structures to device `device` (ordered on stream; returns
+ * after the copies are enqueued, host staging is kept until destroy).
+ * Requires p2m_precompute (or p2m_load).  *bytes (may be NULL) receives the
+ * device arena size. */
+p2m_status p2m_upload(p2m_mesh* m, int device, void* stream, int64_t* bytes);
+
+/* P2M query of n points q_dev float [n*3] (Algorithm A.2 with exact clamped
+ * point-segment / point-triangle tests).  Outputs (device): prim int32 [n],
+ * closest float [n*3], dist float [n]; status uint8 [n] (may be NULL).  For
+ * the backward pass, bary float [n*3] and pvid int32 [n*3] (both NULL or
+ * both set) receive the closest point's barycentric weights over the
+ * primitive's vertices (unused slots: weight 0, id -1).  Non-finite queries
+ * give P2M_NONE, NaN distance and P2M_Q_NONFINITE.  n = 0 is a no-op.
+ * Scratch device memory for ordering is owned by the mesh and reused;
+ * concurrent calls on the same mesh from different streams race. */
+p2m_status p2m_query(p2m_mesh* m, const float* q_dev, int64_t n, int32_t* prim_dev, float* closest_dev,
+                     float* dist_dev, uint8_t* status_dev, float* bary_dev, int32_t* pvid_dev,
+                     const p2m_query_opts* opts, void* stream);
+
+/* Stage times of the last p2m_query on this mesh that set opts->profile:
+ * ordering (Morton keys + sort) and query kernel, in milliseconds, from HIP
+ * events recorded on the call's stream.  Waits for those events. */
+p2m_status p2m_query_profile(p2m_mesh* m, float* order_ms, float* query_ms);
+
+/* KD-tree nearest vertex only (the first step of Algorithm A.2): vid int32
+ * [n] and squared distance d2 float [n] (may be NULL). */
+p2m_status p2m_nearest_vertex(p2m_mesh* m, const float* q_dev, int64_t n, int32_t* vid_dev, float* d2_dev,
+                              void* stream);
+
+/* Query ordering: 30-bit Morton keys of q in D (10 bits per axis, cells
+ * floor((q-lo)*1024/(hi-lo)) taken in float32 and clamped to [0,1023]) and
+ * their stable sort.  keys_dev uint32 [n] receives the sorted keys, perm_dev
+ * int32 [n] the input index of each sorted position. */
+p2m_status p2m_order_queries(p2m_mesh* m, const float* q_dev, int64_t n, uint32_t* keys_dev, int32_t* perm_dev,
+                             void* stream);
+
+/* Backward of dist w.r.t. the query points and the vertex positions, from
+ * the forward's closest, bary and pvid (not in the paper; envelope theorem):
+ *   grad_q[i]   = g[i] (q_i - c_i) / d_i            (0 when d_i = 0)
+ *   grad_V[k]  += -g[i] w_ik (q_i - c_i) / d_i      (float atomics)
+ * grad_dist_dev float [n]; grad_q_dev float [n*3] is overwritten (may be
+ * NULL); grad_V_dev float [nv*3] is accumulated into (may be NULL). */
+p2m_status p2m_query_backward(p2m_mesh* m, const float* q_dev, int64_t n, const float* closest_dev,
+                              const float* dist_dev, const float* bary_dev, const int32_t* pvid_dev,
+                              const float* grad_dist_dev, float* grad_q_dev, float* grad_V_dev, void* stream);
+
+/* ------------------------------------------------------------- batching */
+
+/* Pack uploaded-or-not meshes (each precomputed, all for `device`) into one
+ * device arena for a single persistent launch over all of them.  The
+ * meshes must outlive the batch. */
+p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, void* stream, p2m_batch** out);
+void p2m_batch_destroy(p2m_batch* b);
+
+/* Query all meshes in one launch: q_dev float [N*3] holds the queries of
+ * mesh k at rows q_offsets_host[k] .. q_offsets_host[k+1] (host int64
+ * [count+1], q_offsets_host[0] = 0, N = q_offsets_host[count]).  Outputs as
+ * p2m_query, in the same row order.  The first call for a given offset
+ * layout captures the launch sequence into a HIP graph on `stream`; later
+ * calls with the same layout replay it. */
+p2m_status p2m_batch_query(p2m_batch* b, const float* q_dev, const int64_t* q_offsets_host, int32_t* prim_dev,
+                           float* closest_dev, float* dist_dev, void* stream);
+
+/* Time candidate launch shapes (block size, queries per lane) of the batched
+ * kernel on the given queries and keep the fastest; *best_block and
+ * *best_qpl (may be NULL) report the choice.  Synchronises the stream. */
+p2m_status p2m_batch_autotune(p2m_batch* b, const float* q_dev, const int64_t* q_offsets_host, int32_t* prim_dev,
+                              float* closest_dev, float* dist_dev, void* stream, int* best_block, int* best_qpl);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* P2M_H */

@@ -1,0 +1,71 @@
+// Device helpers shared by the query, batch and sort translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace p2m {
+
+constexpr int kXcds = 8;  // MI355X: 8 XCDs, blocks dispatched round-robin
+
+// 30-bit Morton key: 10 bits per axis, cell = clamp(floor((q-lo)*s), 0, 1023)
+// in float32 (one subtract, one multiply); x takes the top bit of each triple.
+__host__ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+__host__ __device__ __forceinline__ uint32_t quant10(float q, float lo, float s) {
+    const float t = (q - lo) * s;
+    if (!(t >= 0.f)) return 0u;
+    if (t >= 1023.f) return 1023u;
+    return (uint32_t)t;
+}
+
+__host__ __device__ __forceinline__ uint32_t morton30(float x, float y, float z, float lox, float loy, float loz,
+                                                      float sx, float sy, float sz) {
+    return (spread10(quant10(x, lox, sx)) << 2) | (spread10(quant10(y, loy, sy)) << 1) | spread10(quant10(z, loz, sz));
+}
+
+// lo rounded to float, s = float(1024 / (hi - lo)) computed in double.
+inline void morton_params(const double dlo[3], const double dhi[3], float lo[3], float s[3]) {
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = (float)dlo[k];
+        s[k] = (float)(1024.0 / (dhi[k] - dlo[k]));
+    }
+}
+
+// ---------------------------------------------------------------- sort
+
+// Stable LSD radix sort of (uint32 key, int32 value) pairs, 8-bit digits.
+struct RadixPlan {
+    int64_t n = 0;
+    int64_t tiles = 0;       // blocks of kRadixTile keys
+    int64_t counts = 0;      // 256 * tiles
+    int64_t scan_blocks = 0; // blocks of the count scan
+    int64_t bytes = 0;       // scratch bytes
+};
+
+struct RadixBuffers {
+    uint32_t* keys[2];
+    int32_t* vals[2];
+    uint32_t* counts;
+    uint32_t* sums;
+};
+
+constexpr int kRadixThreads = 256;
+constexpr int kRadixItems = 16;
+constexpr int64_t kRadixTile = kRadixThreads * kRadixItems;
+
+RadixPlan radix_plan(int64_t n);
+RadixBuffers radix_buffers(const RadixPlan& p, void* scratch);
+// Sorts keys[0]/vals[0] by the low `bits` bits; returns which buffer (0/1)
+// holds the result.  All work is enqueued on `st`.
+int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int bits, hipStream_t st);
+
+}  // namespace p2m

@@ -1,0 +1,516 @@
+// Device side of the P2M query for gfx950: arena upload, query ordering
+// (Morton keys + stable LSD radix sort), the query kernel (Algorithm A.2),
+// the nearest-vertex kernel, the backward kernel, and the host CPU baseline
+// that runs the same per-query code.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "device_common.hpp"
+#include "p2m_internal.hpp"
+#include "query_core.hpp"
+
+namespace p2m {
+
+// ------------------------------------------------------------- packing
+
+float float_down(double d) {
+    float f = (float)d;
+    if ((double)f > d) f = std::nextafter(f, -INFINITY);
+    return f;
+}
+float float_up(double d) {
+    float f = (float)d;
+    if ((double)f < d) f = std::nextafter(f, INFINITY);
+    return f;
+}
+
+static float bits_as_float(int32_t i) {
+    float f;
+    std::memcpy(&f, &i, 4);
+    return f;
+}
+
+void pack_mesh(MeshState& s) {
+    if (s.packed) return;
+    const MeshData& m = s.m;
+    // KD-tree nodes: point + vertex id, then left / right subtree boxes
+    const int64_t n = m.nv;
+    std::vector<float> box((size_t)(6 * n));  // subtree box of node i: lo.xyz, hi.xyz
+    for (int64_t i = n - 1; i >= 0; --i) {
+        float* bx = &box[(size_t)(6 * i)];
+        const float p[3] = {s.kd.x[(size_t)i], s.kd.y[(size_t)i], s.kd.z[(size_t)i]};
+        for (int k = 0; k < 3; ++k) bx[k] = bx[3 + k] = p[k];
+        for (int64_t c = 2 * i + 1; c <= 2 * i + 2 && c < n; ++c)
+            for (int k = 0; k < 3; ++k) {
+                bx[k] = std::min(bx[k], box[(size_t)(6 * c + k)]);
+                bx[3 + k] = std::max(bx[3 + k], box[(size_t)(6 * c + 3 + k)]);
+            }
+    }
+    s.pk_node.assign((size_t)(16 * n), 0.f);
+    for (int64_t i = 0; i < n; ++i) {
+        float* d = &s.pk_node[(size_t)(16 * i)];
+        d[0] = s.kd.x[(size_t)i];
+        d[1] = s.kd.y[(size_t)i];
+        d[2] = s.kd.z[(size_t)i];
+        d[3] = bits_as_float(s.kd.vid[(size_t)i]);
+        for (int side = 0; side < 2; ++side) {
+            const int64_t c = 2 * i + 1 + side;
+            float* o = d + 4 + 6 * side;
+            for (int k = 0; k < 3; ++k) {
+                o[k] = c < n ? box[(size_t)(6 * c + k)] : INFINITY;
+                o[3 + k] = c < n ? box[(size_t)(6 * c + 3 + k)] : -INFINITY;
+            }
+        }
+    }
+    s.pk_seg.resize((size_t)(8 * m.ne));
+    for (int64_t e = 0; e < m.ne; ++e)
+        for (int k = 0; k < 2; ++k) {
+            int32_t v = m.E[(size_t)(2 * e + k)];
+            float* d = &s.pk_seg[(size_t)(8 * e + 4 * k)];
+            d[0] = m.V[3 * (size_t)v];
+            d[1] = m.V[3 * (size_t)v + 1];
+            d[2] = m.V[3 * (size_t)v + 2];
+            d[3] = bits_as_float(v);
+        }
+    s.pk_tri.resize((size_t)(12 * m.nf));
+    s.pk_fedge.resize((size_t)(4 * m.nf));
+    for (int64_t f = 0; f < m.nf; ++f) {
+        for (int k = 0; k < 3; ++k) {
+            int32_t v = m.F[(size_t)(3 * f + k)];
+            float* d = &s.pk_tri[(size_t)(12 * f + 4 * k)];
+            d[0] = m.V[3 * (size_t)v];
+            d[1] = m.V[3 * (size_t)v + 1];
+            d[2] = m.V[3 * (size_t)v + 2];
+            d[3] = bits_as_float(v);
+            s.pk_fedge[(size_t)(4 * f + k)] = m.FE[(size_t)(3 * f + k)];
+        }
+        s.pk_fedge[(size_t)(4 * f + 3)] = -1;
+    }
+    s.packed = true;
+}
+
+MeshView host_view(const MeshState& s) {
+    MeshView v;
+    v.node = (const KdNode*)s.pk_node.data();
+    v.nv = (int32_t)s.m.nv;
+    v.off = s.t.off.data();
+    v.ent = s.t.ent.data();
+    v.seg = (const float4*)s.pk_seg.data();
+    v.tri = (const float4*)s.pk_tri.data();
+    v.fedge = s.pk_fedge.data();
+    for (int k = 0; k < 3; ++k) {
+        v.dlo[k] = float_down(s.dlo[k]);
+        v.dhi[k] = float_up(s.dhi[k]);
+    }
+    return v;
+}
+
+MeshView device_view(const MeshState& s) {
+    MeshView v = host_view(s);
+    v.node = (const KdNode*)s.dev.node;
+    v.off = (const uint32_t*)s.dev.off;
+    v.ent = (const int32_t*)s.dev.ent;
+    v.seg = (const float4*)s.dev.seg;
+    v.tri = (const float4*)s.dev.tri;
+    v.fedge = (const int32_t*)s.dev.fedge;
+    return v;
+}
+
+void device_release(MeshState& s) {
+    if (s.dev.device < 0) return;
+    int old = -1;
+    (void)hipGetDevice(&old);
+    (void)hipSetDevice(s.dev.device);
+    if (s.dev.base) (void)hipFree(s.dev.base);
+    if (s.dev.scratch) (void)hipFree(s.dev.scratch);
+    for (void*& e : s.dev.ev)
+        if (e) (void)hipEventDestroy((hipEvent_t)e);
+    if (old >= 0) (void)hipSetDevice(old);
+    s.dev = DeviceMesh();
+}
+
+// ------------------------------------------------------------- kernels
+
+// XCD-aware tile order: consecutive hardware blocks go round-robin to the 8
+// XCDs, each with its own L2.  Give XCD x the contiguous tile range
+// [x*chunk, (x+1)*chunk) so spatially adjacent (Morton-ordered) tiles share
+// an L2.  The grid is 8*chunk blocks; tiles >= ntiles are skipped.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t chunk) { return (b % kXcds) * chunk + b / kXcds; }
+
+__global__ void k_morton(const float* __restrict__ q, int64_t n, float lox, float loy, float loz, float sx, float sy,
+                         float sz, uint32_t* __restrict__ keys, int32_t* __restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = morton30(q[3 * i], q[3 * i + 1], q[3 * i + 2], lox, loy, loz, sx, sy, sz);
+    vals[i] = (int32_t)i;
+}
+
+template <bool kWriteExtras>
+__global__ __launch_bounds__(256) void k_query(MeshView m, const float* __restrict__ q,
+                                                const int32_t* __restrict__ perm, int64_t n, int64_t chunk,
+                                                int32_t* __restrict__ prim, float* __restrict__ closest,
+                                                float* __restrict__ dist, uint8_t* __restrict__ status,
+                                                float* __restrict__ bary, int32_t* __restrict__ pvid) {
+    const int64_t tile = xcd_tile(blockIdx.x, chunk);
+    const int64_t j = tile * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int64_t i = perm ? (int64_t)perm[j] : j;
+    const float qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
+    uint8_t st;
+    ScanCounters c;
+    const Answer a = p2m_query_point(m, qx, qy, qz, st, c);
+    prim[i] = a.prim;
+    closest[3 * i] = a.cx;
+    closest[3 * i + 1] = a.cy;
+    closest[3 * i + 2] = a.cz;
+    dist[i] = a.dist;
+    if (status) status[i] = st;
+    if (kWriteExtras) {
+        for (int k = 0; k < 3; ++k) {
+            bary[3 * i + k] = a.w[k];
+            pvid[3 * i + k] = a.pv[k];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_nearest(MeshView m, const float* __restrict__ q, int64_t n,
+                                                  int32_t* __restrict__ vid, float* __restrict__ d2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
+    if (!(isfinite(qx) && isfinite(qy) && isfinite(qz))) {
+        vid[i] = -1;
+        if (d2) d2[i] = NAN;
+        return;
+    }
+    uint64_t visits = 0;
+    const Nearest b = kdt_nearest(m.node, m.nv, qx, qy, qz, visits);
+    vid[i] = b.vid;
+    if (d2) d2[i] = b.d2;
+}
+
+__global__ __launch_bounds__(256) void k_backward(const float* __restrict__ q, int64_t n,
+                                                   const float* __restrict__ closest, const float* __restrict__ dist,
+                                                   const float* __restrict__ bary, const int32_t* __restrict__ pvid,
+                                                   const float* __restrict__ gd, float* __restrict__ gq,
+                                                   float* __restrict__ gV, int32_t nv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float d = dist[i];
+    const float g = gd[i];
+    float ux = 0.f, uy = 0.f, uz = 0.f;
+    if (d > 0.f && isfinite(d)) {
+        const float inv = 1.f / d;
+        ux = (q[3 * i] - closest[3 * i]) * inv;
+        uy = (q[3 * i + 1] - closest[3 * i + 1]) * inv;
+        uz = (q[3 * i + 2] - closest[3 * i + 2]) * inv;
+    }
+    if (gq) {
+        gq[3 * i] = g * ux;
+        gq[3 * i + 1] = g * uy;
+        gq[3 * i + 2] = g * uz;
+    }
+    if (gV && (ux != 0.f || uy != 0.f || uz != 0.f) && g != 0.f) {
+        for (int k = 0; k < 3; ++k) {
+            const int32_t v = pvid[3 * i + k];
+            const float w = bary[3 * i + k];
+            if (v < 0 || v >= nv || w == 0.f) continue;
+            const float s = -g * w;
+            unsafeAtomicAdd(&gV[3 * (int64_t)v], s * ux);
+            unsafeAtomicAdd(&gV[3 * (int64_t)v + 1], s * uy);
+            unsafeAtomicAdd(&gV[3 * (int64_t)v + 2], s * uz);
+        }
+    }
+}
+
+// ------------------------------------------------------------ launches
+
+struct DeviceGuard {
+    int old = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&old) != hipSuccess) old = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (old >= 0) (void)hipSetDevice(old);
+    }
+};
+
+static p2m_status check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(P2M_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return P2M_OK;
+}
+
+static p2m_status ensure_scratch(MeshState& s, int64_t bytes) {
+    if (s.dev.scratch_bytes >= bytes) return P2M_OK;
+    if (s.dev.scratch) {
+        (void)hipFree(s.dev.scratch);
+        s.dev.scratch = nullptr;
+        s.dev.scratch_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&s.dev.scratch, (size_t)bytes);
+    if (e != hipSuccess) {
+        s.dev.scratch = nullptr;
+        return fail(e == hipErrorOutOfMemory ? P2M_ERR_OOM : P2M_ERR_HIP,
+                    std::string("scratch allocation: ") + hipGetErrorString(e));
+    }
+    s.dev.scratch_bytes = bytes;
+    return P2M_OK;
+}
+
+// Morton keys + stable sort into scratch; returns the permutation pointer.
+static p2m_status order_into_scratch(MeshState& s, const float* q, int64_t n, hipStream_t st, uint32_t** keys_out,
+                                     int32_t** perm_out) {
+    RadixPlan plan = radix_plan(n);
+    p2m_status r = ensure_scratch(s, plan.bytes);
+    if (r != P2M_OK) return r;
+    RadixBuffers b = radix_buffers(plan, s.dev.scratch);
+    float lo[3], sc[3];
+    morton_params(s.dlo, s.dhi, lo, sc);
+    const int64_t blocks = (n + 255) / 256;
+    k_morton<<<(unsigned)blocks, 256, 0, st>>>(q, n, lo[0], lo[1], lo[2], sc[0], sc[1], sc[2], b.keys[0], b.vals[0]);
+    r = check_launch("morton keys");
+    if (r != P2M_OK) return r;
+    int cur = radix_sort_pairs(plan, b, 30, st);
+    r = check_launch("radix sort");
+    if (r != P2M_OK) return r;
+    *keys_out = b.keys[cur];
+    *perm_out = b.vals[cur];
+    return P2M_OK;
+}
+
+}  // namespace p2m
+
+using namespace p2m;
+
+extern "C" {
+
+p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
+    if (!mh) return fail(P2M_ERR_ARG, "mesh is NULL");
+    MeshState& s = mh->s;
+    if (!s.precomputed) return fail(P2M_ERR_STATE, "p2m_upload before p2m_precompute");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(P2M_ERR_HIP, "no HIP device");
+    if (device < 0 || device >= ndev) return fail(P2M_ERR_ARG, "device index out of range");
+    DeviceGuard g(device);
+    if (!g.ok) return fail(P2M_ERR_HIP, "hipSetDevice failed");
+    device_release(s);
+    pack_mesh(s);
+    const size_t a = 256;
+    auto up = [&](size_t x) { return (x + a - 1) / a * a; };
+    const size_t b_node = sizeof(float) * s.pk_node.size();
+    const size_t b_off = sizeof(uint32_t) * s.t.off.size();
+    const size_t b_ent = sizeof(int32_t) * std::max<size_t>(1, s.t.ent.size());
+    const size_t b_seg = sizeof(float) * s.pk_seg.size();
+    const size_t b_tri = sizeof(float) * s.pk_tri.size();
+    const size_t b_fe = sizeof(int32_t) * s.pk_fedge.size();
+    const size_t total = up(b_node) + up(b_off) + up(b_ent) + up(b_seg) + up(b_tri) + up(b_fe);
+    void* base = nullptr;
+    hipError_t e = hipMalloc(&base, total);
+    if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? P2M_ERR_OOM : P2M_ERR_HIP, "device arena allocation");
+    s.dev.device = device;
+    s.dev.base = base;
+    s.dev.bytes = (int64_t)total;
+    char* p = (char*)base;
+    s.dev.node = p;
+    p += up(b_node);
+    s.dev.off = p;
+    p += up(b_off);
+    s.dev.ent = p;
+    p += up(b_ent);
+    s.dev.seg = p;
+    p += up(b_seg);
+    s.dev.tri = p;
+    p += up(b_tri);
+    s.dev.fedge = p;
+    hipStream_t st = (hipStream_t)stream;
+    struct Cp {
+        void* dst;
+        const void* src;
+        size_t n;
+    } cps[] = {{s.dev.node, s.pk_node.data(), b_node}, {s.dev.off, s.t.off.data(), b_off},
+               {s.dev.ent, s.t.ent.data(), s.t.ent.size() * sizeof(int32_t)}, {s.dev.seg, s.pk_seg.data(), b_seg},
+               {s.dev.tri, s.pk_tri.data(), b_tri}, {s.dev.fedge, s.pk_fedge.data(), b_fe}};
+    for (const Cp& c : cps) {
+        if (c.n == 0) continue;
+        e = hipMemcpyAsync(c.dst, c.src, c.n, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return fail(P2M_ERR_HIP, std::string("upload copy: ") + hipGetErrorString(e));
+    }
+    if (bytes) *bytes = (int64_t)total;
+    return P2M_OK;
+}
+
+p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, float* closest, float* dist,
+                     uint8_t* status, float* bary, int32_t* pvid, const p2m_query_opts* opts, void* stream) {
+    if (!mh) return fail(P2M_ERR_ARG, "mesh is NULL");
+    MeshState& s = mh->s;
+    if (n < 0) return fail(P2M_ERR_ARG, "negative query count");
+    if (s.dev.device < 0) return fail(P2M_ERR_STATE, "p2m_query before p2m_upload");
+    if (n == 0) return P2M_OK;
+    if (!q || !prim || !closest || !dist) return fail(P2M_ERR_ARG, "NULL query or output pointer");
+    if ((bary == nullptr) != (pvid == nullptr)) return fail(P2M_ERR_ARG, "bary and pvid must both be set or both NULL");
+    if (n > (int64_t)INT32_MAX) return fail(P2M_ERR_ARG, "more than 2^31-1 queries in one call");
+    int sort = 1, block = 256, profile = 0;
+    if (opts) {
+        profile = opts->profile;
+        if (opts->sort_queries >= 0) sort = opts->sort_queries ? 1 : 0;
+        if (opts->block_size != 0) {
+            if (opts->block_size < 64 || opts->block_size > 1024 || opts->block_size % 64)
+                return fail(P2M_ERR_ARG, "block_size must be a multiple of 64 in [64, 1024]");
+            block = opts->block_size;
+        }
+    }
+    DeviceGuard g(s.dev.device);
+    if (!g.ok) return fail(P2M_ERR_HIP, "hipSetDevice failed");
+    hipStream_t st = (hipStream_t)stream;
+    if (profile) {
+        for (void*& e : s.dev.ev)
+            if (!e && hipEventCreate((hipEvent_t*)&e) != hipSuccess) return fail(P2M_ERR_HIP, "hipEventCreate");
+        (void)hipEventRecord((hipEvent_t)s.dev.ev[0], st);
+    }
+    int32_t* perm = nullptr;
+    if (sort) {
+        uint32_t* keys = nullptr;
+        p2m_status r = order_into_scratch(s, q, n, st, &keys, &perm);
+        if (r != P2M_OK) return r;
+    }
+    if (profile) (void)hipEventRecord((hipEvent_t)s.dev.ev[1], st);
+    const MeshView v = device_view(s);
+    const int64_t tiles = (n + block - 1) / block;
+    const int64_t chunk = (tiles + kXcds - 1) / kXcds;
+    const unsigned grid = (unsigned)(chunk * kXcds);
+    if (bary)
+        k_query<true><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid);
+    else
+        k_query<false><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid);
+    p2m_status r = check_launch("query kernel");
+    if (r == P2M_OK && profile) {
+        (void)hipEventRecord((hipEvent_t)s.dev.ev[2], st);
+        s.dev.ev_recorded = true;
+        s.dev.ev_sorted = sort != 0;
+    }
+    return r;
+}
+
+p2m_status p2m_query_profile(p2m_mesh* mh, float* order_ms, float* query_ms) {
+    if (!mh) return fail(P2M_ERR_ARG, "mesh is NULL");
+    MeshState& s = mh->s;
+    if (!s.dev.ev_recorded) return fail(P2M_ERR_STATE, "no profiled p2m_query on this mesh");
+    DeviceGuard g(s.dev.device);
+    float a = 0.f, b = 0.f;
+    hipError_t e = hipEventSynchronize((hipEvent_t)s.dev.ev[2]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&a, (hipEvent_t)s.dev.ev[0], (hipEvent_t)s.dev.ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&b, (hipEvent_t)s.dev.ev[1], (hipEvent_t)s.dev.ev[2]);
+    if (e != hipSuccess) return fail(P2M_ERR_HIP, std::string("profile events: ") + hipGetErrorString(e));
+    if (order_ms) *order_ms = s.dev.ev_sorted ? a : 0.f;
+    if (query_ms) *query_ms = b;
+    return P2M_OK;
+}
+
+p2m_status p2m_nearest_vertex(p2m_mesh* mh, const float* q, int64_t n, int32_t* vid, float* d2, void* stream) {
+    if (!mh) return fail(P2M_ERR_ARG, "mesh is NULL");
+    MeshState& s = mh->s;
+    if (n < 0) return fail(P2M_ERR_ARG, "negative query count");
+    if (s.dev.device < 0) return fail(P2M_ERR_STATE, "p2m_nearest_vertex before p2m_upload");
+    if (n == 0) return P2M_OK;
+    if (!q || !vid) return fail(P2M_ERR_ARG, "NULL pointer");
+    DeviceGuard g(s.dev.device);
+    const MeshView v = device_view(s);
+    k_nearest<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(v, q, n, vid, d2);
+    return check_launch("nearest-vertex kernel");
+}
+
+p2m_status p2m_order_queries(p2m_mesh* mh, const float* q, int64_t n, uint32_t* keys_out, int32_t* perm_out,
+                             void* stream) {
+    if (!mh) return fail(P2M_ERR_ARG, "mesh is NULL");
+    MeshState& s = mh->s;
+    if (n < 0) return fail(P2M_ERR_ARG, "negative query count");
+    if (s.dev.device < 0) return fail(P2M_ERR_STATE, "p2m_order_queries before p2m_upload");
+    if (n == 0) return P2M_OK;
+    if (!q || !keys_out || !perm_out) return fail(P2M_ERR_ARG, "NULL pointer");
+    if (n > (int64_t)INT32_MAX) return fail(P2M_ERR_ARG, "more than 2^31-1 queries in one call");
+    DeviceGuard g(s.dev.device);
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t* keys = nullptr;
+    int32_t* perm = nullptr;
+    p2m_status r = order_into_scratch(s, q, n, st, &keys, &perm);
+    if (r != P2M_OK) return r;
+    hipError_t e = hipMemcpyAsync(keys_out, keys, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(perm_out, perm, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return fail(P2M_ERR_HIP, std::string("order copy: ") + hipGetErrorString(e));
+    return P2M_OK;
+}
+
+p2m_status p2m_query_backward(p2m_mesh* mh, const float* q, int64_t n, const float* closest, const float* dist,
+                              const float* bary, const int32_t* pvid, const float* gd, float* gq, float* gV,
+                              void* stream) {
+    if (!mh) return fail(P2M_ERR_ARG, "mesh is NULL");
+    MeshState& s = mh->s;
+    if (n < 0) return fail(P2M_ERR_ARG, "negative query count");
+    if (s.dev.device < 0) return fail(P2M_ERR_STATE, "p2m_query_backward before p2m_upload");
+    if (n == 0) return P2M_OK;
+    if (!q || !closest || !dist || !gd) return fail(P2M_ERR_ARG, "NULL pointer");
+    if (gV && (!bary || !pvid)) return fail(P2M_ERR_ARG, "grad_V needs bary and pvid from the forward");
+    DeviceGuard g(s.dev.device);
+    k_backward<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(q, n, closest, dist, bary, pvid, gd,
+                                                                            gq, gV, (int32_t)s.m.nv);
+    return check_launch("backward kernel");
+}
+
+p2m_status p2m_query_host(const p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, float* closest, float* dist,
+                          uint8_t* status, int num_threads, int64_t counters[3]) {
+    if (!mh) return fail(P2M_ERR_ARG, "mesh is NULL");
+    MeshState& s = const_cast<MeshState&>(mh->s);
+    if (!s.precomputed) return fail(P2M_ERR_STATE, "p2m_query_host before p2m_precompute");
+    if (n < 0) return fail(P2M_ERR_ARG, "negative query count");
+    if (n > 0 && (!q || !prim || !closest || !dist)) return fail(P2M_ERR_ARG, "NULL pointer");
+    pack_mesh(s);
+    const MeshView v = host_view(s);
+    int nt = num_threads > 0 ? num_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    nt = (int)std::min<int64_t>(nt, std::max<int64_t>(1, n / 1024));
+    std::vector<ScanCounters> cnt((size_t)nt);
+    std::atomic<int64_t> cursor{0};
+    auto work = [&](int t) {
+        ScanCounters& c = cnt[(size_t)t];
+        for (;;) {
+            int64_t b = cursor.fetch_add(1024);
+            if (b >= n) break;
+            int64_t e = std::min(n, b + 1024);
+            for (int64_t i = b; i < e; ++i) {
+                uint8_t stt;
+                Answer a = p2m_query_point(v, q[3 * i], q[3 * i + 1], q[3 * i + 2], stt, c);
+                prim[i] = a.prim;
+                closest[3 * i] = a.cx;
+                closest[3 * i + 1] = a.cy;
+                closest[3 * i + 2] = a.cz;
+                dist[i] = a.dist;
+                if (status) status[i] = stt;
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto& x : th) x.join();
+    if (counters) {
+        counters[0] = counters[1] = counters[2] = 0;
+        for (auto& c : cnt) {
+            counters[0] += c.nodes;
+            counters[1] += c.edges;
+            counters[2] += c.faces;
+        }
+    }
+    return P2M_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Internal state behind the opaque p2m_mesh / p2m_batch handles, shared by
+// the host translation units (g++) and the device one (hipcc).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/p2m.h"
+#include "interception.hpp"
+#include "kdtree.hpp"
+#include "mesh.hpp"
+
+namespace p2m {
+
+// Device copy of one mesh's query structures (all in one allocation).
+// Layouts (device):
+//   node  float4[4nv]    KD-tree node: x, y, z, vertex id (int bits), then the
+//                        bounding boxes of the left and right subtrees
+//   off   uint32[2nv+1]  interception-table offsets (edges, then faces, per vertex)
+//   ent   int32[nnz]     edge / face ids
+//   seg   float4[2ne]    edge end points: a.xyz|id_a, b.xyz|id_b
+//   tri   float4[3nf]    face corners:    a.xyz|id_a, b.xyz|id_b, c.xyz|id_c
+//   fedge int32[4nf]     edge ids of the sides (a,b), (b,c), (c,a), pad
+struct DeviceMesh {
+    int device = -1;
+    void* base = nullptr;
+    int64_t bytes = 0;
+    void* node = nullptr;
+    void* off = nullptr;
+    void* ent = nullptr;
+    void* seg = nullptr;
+    void* tri = nullptr;
+    void* fedge = nullptr;
+    // ordering scratch (keys/values, double-buffered), grown on demand
+    void* scratch = nullptr;
+    int64_t scratch_bytes = 0;
+    // profiling events (hipEvent_t): start, after ordering, after query
+    void* ev[3] = {nullptr, nullptr, nullptr};
+    bool ev_recorded = false;
+    bool ev_sorted = false;
+};
+
+struct MeshState {
+    MeshData m;
+    KdTree kd;
+    Table t;
+    TableStats ts;
+    bool precomputed = false;
+    double dlo[3] = {0, 0, 0}, dhi[3] = {0, 0, 0};
+    double tau = 0.0;
+    double t_validate = 0.0, t_kdt = 0.0;
+    // Packed query structures (host staging of the device layouts above;
+    // also read directly by the host CPU query).
+    bool packed = false;
+    std::vector<float> pk_node;                  // 16 floats per KD-tree node
+    std::vector<float> pk_seg, pk_tri;           // 4 floats per entry
+    std::vector<int32_t> pk_fedge;               // 4 ints per face
+    DeviceMesh dev;
+};
+
+void set_error(const std::string& msg);
+p2m_status fail(p2m_status s, const std::string& msg);
+
+// Device-side teardown (defined in the device translation unit).
+void device_release(MeshState& s);
+
+}  // namespace p2m
+
+struct p2m_mesh {
+    p2m::MeshState s;
+};

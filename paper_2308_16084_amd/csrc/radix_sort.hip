@@ -1,0 +1,192 @@
+// Stable LSD radix sort of (uint32 key, int32 value) pairs for gfx950.
+//
+// Per 8-bit digit pass: (1) every tile of 4096 keys counts its digits in
+// LDS; (2) an exclusive scan over the digit-major count matrix gives each
+// (digit, tile) its output offset; (3) every tile re-reads its keys in
+// order, 256 at a time, ranks each key among equal digits with wave-wide
+// ballots (stable within a wave), adds the counts of earlier waves and of
+// earlier chunks of the tile, and writes the pair to its place.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+
+namespace p2m {
+
+namespace {
+
+constexpr int kT = kRadixThreads;
+constexpr int kI = kRadixItems;
+constexpr int kWaves = kT / 64;
+
+__global__ __launch_bounds__(kT) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                                   uint32_t* __restrict__ counts, int64_t tiles) {
+    __shared__ uint32_t h[256];
+    const int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+#pragma unroll
+    for (int it = 0; it < kI; ++it) {
+        const int64_t i = base + (int64_t)it * kT + t;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(int64_t)t * tiles + blockIdx.x] = h[t];
+}
+
+// Exclusive scan of 4096-element blocks in place; block totals to sums.
+__global__ __launch_bounds__(kT) void k_scan_local(uint32_t* __restrict__ a, int64_t n, uint32_t* __restrict__ sums) {
+    __shared__ uint32_t part[kT];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile + (int64_t)t * kI;
+    uint32_t v[kI];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kI; ++k) {
+        v[k] = (base + k < n) ? a[base + k] : 0u;
+        s += v[k];
+    }
+    part[t] = s;
+    __syncthreads();
+    // inclusive Hillis-Steele scan of the per-thread sums
+    for (int d = 1; d < kT; d <<= 1) {
+        uint32_t x = t >= d ? part[t - d] : 0u;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    uint32_t run = t > 0 ? part[t - 1] : 0u;
+#pragma unroll
+    for (int k = 0; k < kI; ++k) {
+        if (base + k < n) a[base + k] = run;
+        run += v[k];
+    }
+    if (t == kT - 1) sums[blockIdx.x] = part[kT - 1];
+}
+
+// Exclusive scan of `n` block sums by one block, in chunks with a carry.
+__global__ __launch_bounds__(kT) void k_scan_sums(uint32_t* __restrict__ a, int64_t n) {
+    __shared__ uint32_t part[kT];
+    __shared__ uint32_t carry;
+    const int t = threadIdx.x;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int64_t c = 0; c < n; c += kT) {
+        const int64_t i = c + t;
+        const uint32_t x0 = i < n ? a[i] : 0u;
+        part[t] = x0;
+        __syncthreads();
+        for (int d = 1; d < kT; d <<= 1) {
+            uint32_t x = t >= d ? part[t - d] : 0u;
+            __syncthreads();
+            part[t] += x;
+            __syncthreads();
+        }
+        const uint32_t excl = part[t] - x0 + carry;
+        __syncthreads();
+        if (i < n) a[i] = excl;
+        if (t == kT - 1) carry += part[kT - 1];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_scan_add(uint32_t* __restrict__ a, int64_t n, const uint32_t* __restrict__ sums) {
+    const uint32_t add = sums[blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile + (int64_t)threadIdx.x * kI;
+#pragma unroll
+    for (int k = 0; k < kI; ++k)
+        if (base + k < n) a[base + k] += add;
+}
+
+__global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
+                                                      int64_t n, int shift, const uint32_t* __restrict__ offs,
+                                                      int64_t tiles, uint32_t* __restrict__ kout,
+                                                      int32_t* __restrict__ vout) {
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wc[kWaves][256];
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int w = t >> 6;
+    base[t] = offs[(int64_t)t * tiles + blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) wc[k][t] = 0;
+    __syncthreads();
+    const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int it = 0; it < kI; ++it) {
+        const int64_t i = tile0 + (int64_t)it * kT + t;
+        const bool valid = i < n;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const int32_t val = valid ? vin[i] : 0;
+        const uint32_t d = (key >> shift) & 255u;
+        unsigned long long mask = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const unsigned long long bm = __ballot(bit);
+            mask &= bit ? bm : ~bm;
+        }
+        const uint32_t rank = (uint32_t)__popcll(mask & lt);
+        if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(mask);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base[d] + rank;
+            for (int k = 0; k < w; ++k) pos += wc[k][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) {
+            tot += wc[k][t];
+            wc[k][t] = 0;
+        }
+        base[t] += tot;
+        __syncthreads();
+    }
+}
+
+int64_t up256(int64_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+RadixPlan radix_plan(int64_t n) {
+    RadixPlan p;
+    p.n = n;
+    p.tiles = (n + kRadixTile - 1) / kRadixTile;
+    p.counts = 256 * p.tiles;
+    p.scan_blocks = (p.counts + kRadixTile - 1) / kRadixTile;
+    p.bytes = 4 * up256(4 * n) + up256(4 * p.counts) + up256(4 * std::max<int64_t>(1, p.scan_blocks));
+    return p;
+}
+
+RadixBuffers radix_buffers(const RadixPlan& p, void* scratch) {
+    RadixBuffers b;
+    char* c = (char*)scratch;
+    const int64_t s = up256(4 * p.n);
+    b.keys[0] = (uint32_t*)c;
+    b.keys[1] = (uint32_t*)(c + s);
+    b.vals[0] = (int32_t*)(c + 2 * s);
+    b.vals[1] = (int32_t*)(c + 3 * s);
+    b.counts = (uint32_t*)(c + 4 * s);
+    b.sums = (uint32_t*)(c + 4 * s + up256(4 * p.counts));
+    return b;
+}
+
+int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int bits, hipStream_t st) {
+    int cur = 0;
+    if (p.n <= 1) return cur;
+    for (int shift = 0; shift < bits; shift += 8) {
+        k_radix_hist<<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], p.n, shift, b.counts, p.tiles);
+        k_scan_local<<<(unsigned)p.scan_blocks, kT, 0, st>>>(b.counts, p.counts, b.sums);
+        k_scan_sums<<<1, kT, 0, st>>>(b.sums, p.scan_blocks);
+        k_scan_add<<<(unsigned)p.scan_blocks, kT, 0, st>>>(b.counts, p.counts, b.sums);
+        k_radix_scatter<<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], b.vals[cur], p.n, shift, b.counts, p.tiles,
+                                                          b.keys[cur ^ 1], b.vals[cur ^ 1]);
+        cur ^= 1;
+    }
+    return cur;
+}
+
+}  // namespace p2m

@@ -1,0 +1,64 @@
+"""Acceptance rule for a P2M answer against the FP64 brute-force oracle.
+
+With tol = 1e-5 x the mesh AABB diagonal (float32 storage of coordinates):
+  * |d - d*| <= tol and d >= 0;
+  * the reported primitive is the oracle's best, or belongs to the oracle's
+    near-optimal set (primitives whose distance under tolerance-relaxed
+    gates is within tol of d*): exact or rounding-level ties may go either
+    way, so only a genuinely worse primitive is a failure;
+  * | |q - c| - d | <= tol and c lies within tol of the reported (closed)
+    primitive;
+  * when the near-optimal set is a single primitive, |c - c*| <= tol.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def prim_split(prim):
+    p = np.asarray(prim).astype(np.int64) & 0xFFFFFFFF
+    return p >> 30, p & 0x3FFFFFFF
+
+
+def check_answers(om, Q, ans, prim, closest, dist, tol=None, idx=None, max_report=5):
+    """Returns a list of failure strings (empty when all rows pass).
+
+    om: oracle.OracleMesh; Q [n,3] float32 queries; ans: om.query(Q);
+    prim/closest/dist: the answers under test for the same rows.
+    """
+    if tol is None:
+        tol = 1e-5 * om.diag
+    Q = np.asarray(Q, dtype=np.float32).astype(np.float64).reshape(-1, 3)
+    typ, pid = prim_split(prim)
+    closest = np.asarray(closest, dtype=np.float64).reshape(-1, 3)
+    dist = np.asarray(dist, dtype=np.float64)
+    fails = []
+
+    def bad(i, why):
+        if len(fails) < max_report:
+            j = i if idx is None else idx[i]
+            fails.append(f"row {j}: {why} (q={Q[i].tolist()}, got {(int(typ[i]), int(pid[i]))} d={dist[i]!r}, "
+                         f"oracle {(int(ans['type'][i]), int(ans['id'][i]))} d*={ans['dist'][i]!r})")
+        else:
+            fails.append("...")
+
+    dd = np.abs(dist - ans["dist"])
+    for i in np.nonzero(~(dd <= tol))[0]:
+        bad(i, f"|d-d*|={dd[i]:.3g} > tol={tol:.3g}")
+    for i in np.nonzero(~(dist >= 0))[0]:
+        bad(i, "negative or NaN distance")
+    qc = np.linalg.norm(Q - closest, axis=1)
+    for i in np.nonzero(~(np.abs(qc - dist) <= tol))[0]:
+        bad(i, f"| |q-c| - d | = {abs(qc[i]-dist[i]):.3g}")
+    same = (typ == ans["type"]) & (pid == ans["id"])
+    for i in range(Q.shape[0]):
+        on = om.point_to_primitive(int(typ[i]), int(pid[i]), closest[i])
+        if not (on <= tol):
+            bad(i, f"closest point is {on:.3g} off the reported primitive")
+        if not same[i] or np.linalg.norm(closest[i] - ans["closest"][i]) > tol:
+            ns = om.near_set(Q[i], ans["dist"][i], tol)
+            if not same[i] and (int(typ[i]), int(pid[i])) not in ns:
+                bad(i, "primitive not in the oracle's near-optimal set")
+            if len(ns) == 1 and np.linalg.norm(closest[i] - ans["closest"][i]) > tol:
+                bad(i, "closest point differs from the unique optimum")
+    return fails

@@ -1,0 +1,191 @@
+"""GPU parity: the HIP path through the C interface against the FP64
+brute-force oracle (acceptance rule in tests/_accept.py), and the query
+ordering against its definition, bit for bit."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import morton as OM
+from synth import configs as C
+from synth import queries as SQ
+from tests._accept import check_answers
+from tests._helpers import CUBE_F, CUBE_V, TETRA_F, TETRA_V, random_tiny_mesh
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _build(V, F, domain, mode=0):
+    import paper_2308_16084_amd as P
+    m = P.Mesh(V, F)
+    m.precompute(domain=domain, table_mode=mode)
+    m.upload(0)
+    return m
+
+
+def _run(m, Q, **kw):
+    torch = _torch()
+    q = torch.from_numpy(np.ascontiguousarray(Q, dtype=np.float32)).cuda()
+    out = m.query(q, **kw)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = C.c1()
+    m = _build(w.V, w.F, (w.domain_lo, w.domain_hi))
+    om = oracle.OracleMesh(w.V, w.F)
+    return w, m, om, om.query(w.Q)
+
+
+def test_c1_all_queries(c1):
+    """Workload C1: icosphere level 4, all 10^4 queries, sorted launch."""
+    w, m, om, ans = c1
+    print("case: c1 sorted", flush=True)
+    out = _run(m, w.Q)
+    assert check_answers(om, w.Q, ans, out["prim"], out["closest"], out["dist"]) == []
+    assert np.all(out["status"] == 0)
+
+
+def test_c1_unsorted_and_block_sizes_identical(c1):
+    """Ordering and launch shape change which lane runs a query, never its answer."""
+    w, m, om, ans = c1
+    ref = _run(m, w.Q)
+    for kw in ({"sort": False}, {"block_size": 64}, {"block_size": 1024, "sort": False}):
+        print("case: c1", kw, flush=True)
+        out = _run(m, w.Q, **kw)
+        for k in ("prim", "closest", "dist"):
+            assert np.array_equal(out[k], ref[k]), (kw, k)
+
+
+def test_c1_matches_host_model(c1):
+    """Same tree, table and float32 code on host and device: same primitive,
+    distances equal to a few ulps (the device may fuse multiply-adds)."""
+    w, m, om, ans = c1
+    out = _run(m, w.Q)
+    h = m.query_host(w.Q)
+    assert np.mean(out["prim"] == h["prim"]) > 0.999
+    assert np.max(np.abs(out["dist"] - h["dist"])) <= 1e-6
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_tiny_meshes(mode):
+    rng = np.random.default_rng(40 + mode)
+    meshes = [(TETRA_V, TETRA_F), (CUBE_V, CUBE_F), random_tiny_mesh(rng, "sphere"),
+              random_tiny_mesh(rng, "heightfield")]
+    for k, (V, F) in enumerate(meshes):
+        lo, hi = SQ.aabb(V)
+        dom = SQ.scaled_box(lo, hi, 3.0)
+        print(f"case: tiny mesh {k} mode {mode}", flush=True)
+        m = _build(V, F, dom, mode)
+        Q = rng.uniform(dom[0], dom[1], size=(5000, 3)).astype(np.float32)
+        om = oracle.OracleMesh(V, F)
+        out = _run(m, Q)
+        assert check_answers(om, Q, om.query(Q), out["prim"], out["closest"], out["dist"]) == []
+
+
+def test_golden_points_on_device():
+    from tests._helpers import load_golden, primitive_vertices
+    for V, F, name in ((TETRA_V, TETRA_F, "tetra.txt"), (CUBE_V, CUBE_F, "cube.txt")):
+        rows = load_golden(name)
+        Q = np.array([r[0] for r in rows], np.float32)
+        lo, hi = SQ.aabb(V)
+        m = _build(V, F, SQ.scaled_box(lo, hi, 8.0))
+        out = _run(m, Q)
+        om = oracle.OracleMesh(V, F)
+        for i, (q, prims, d, c) in enumerate(rows):
+            t = int((np.int64(out["prim"][i]) & 0xFFFFFFFF) >> 30)
+            pid = int(out["prim"][i] & 0x3FFFFFFF)
+            assert (t, primitive_vertices(om.F, om.E, t, pid)) in prims or abs(out["dist"][i] - d) <= 1e-6
+            assert abs(out["dist"][i] - d) <= 1e-6
+
+
+@pytest.mark.parametrize("n", [1, 2, 255, 4096, 4097, 70001, 1 << 20])
+def test_order_bit_exact(c1, n):
+    """Morton keys and their stable sort equal the definition exactly."""
+    torch = _torch()
+    w, m, _, _ = c1
+    rng = np.random.default_rng(n)
+    lo, hi = w.domain_lo, w.domain_hi
+    Q = rng.uniform(lo - 0.2, hi + 0.2, size=(n, 3)).astype(np.float32)
+    if n > 100:
+        Q[10:60] = Q[3]                 # runs of equal keys
+        Q[70] = np.nan                  # non-finite -> cell 0
+    keys, perm = m.order_queries(torch.from_numpy(Q).cuda())
+    torch.cuda.synchronize()
+    rk, rp = OM.order(Q, lo, hi)
+    assert np.array_equal(keys.cpu().numpy().view(np.uint32), rk)
+    assert np.array_equal(perm.cpu().numpy(), rp)
+
+
+def test_nearest_vertex_brute_force(c1):
+    torch = _torch()
+    w, m, om, _ = c1
+    vid, d2 = m.nearest_vertex(torch.from_numpy(w.Q).cuda())
+    torch.cuda.synchronize()
+    vid = vid.cpu().numpy()
+    D = ((w.Q.astype(np.float64)[:, None, :] - om.V[None]) ** 2).sum(-1)
+    best = D.min(1)
+    got = D[np.arange(len(w.Q)), vid]
+    # exact nearest, or a tie within float64 rounding of the squared distance
+    assert np.all(got <= best * (1 + 1e-12) + 1e-300)
+
+
+def test_edge_cases(c1):
+    torch = _torch()
+    import paper_2308_16084_amd as P
+    w, m, om, _ = c1
+    out = _run(m, np.zeros((0, 3), np.float32))
+    assert out["dist"].shape == (0,)
+    Q = np.array([[0.1, 0.2, 0.3], [np.nan, 0, 0], [0, np.inf, 0], [30.0, 0, 0]], np.float32)
+    out = _run(m, Q)
+    assert out["status"].tolist() == [0, P.NONFINITE, P.NONFINITE, P.OUT_OF_DOMAIN]
+    assert np.isnan(out["dist"][1]) and np.isnan(out["dist"][2])
+    assert P.prim_type(out["prim"][1]) == P.NONE
+    a = om.query(Q[[0, 3]])
+    assert abs(out["dist"][0] - a["dist"][0]) <= 1e-5 * om.diag
+    assert out["dist"][3] >= a["dist"][1] - 1e-5 * om.diag  # an upper bound outside the domain
+    with pytest.raises(TypeError):
+        m.query(torch.zeros((4, 3), dtype=torch.float64, device="cuda"))
+    with pytest.raises(P.P2MError):
+        P.Mesh(TETRA_V, TETRA_F).upload(0)  # before precompute
+
+
+def _sampled_parity(w, m, n_sample, seed):
+    om = oracle.OracleMesh(w.V, w.F)
+    out = _run(m, w.Q)
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(len(w.Q), size=n_sample, replace=False))
+    ans = om.query(w.Q[idx])
+    fails = check_answers(om, w.Q[idx], ans, out["prim"][idx], out["closest"][idx], out["dist"][idx], idx=idx)
+    return fails, out
+
+
+@pytest.fixture(scope="module")
+def c2_full():
+    print("case: building c2 (655,362 V / 1,310,720 F)", flush=True)
+    import os
+    import paper_2308_16084_amd as P
+    w = C.c2()
+    m, _ = P.Mesh.cached(w.V, w.F, (w.domain_lo, w.domain_hi), os.environ.get("P2M_CACHE_DIR") or None)
+    m.upload(0)
+    return w, m
+
+
+def test_c2_full_size_sampled(c2_full):
+    """Workload C2 at full size (10^7 queries, one sorted launch as timed by
+    the benchmark); 1,500 sampled rows checked against the oracle; all
+    distances finite and non-negative; no row flagged out of domain."""
+    w, m = c2_full
+    print("case: c2 sampled parity", flush=True)
+    fails, out = _sampled_parity(w, m, 1500, 77)
+    assert fails == []
+    assert np.all(np.isfinite(out["dist"])) and np.all(out["dist"] >= 0)
+    assert np.all(out["status"] == 0)

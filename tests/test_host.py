@@ -1,0 +1,235 @@
+"""Host side (no GPU): mesh validation, KD tree, Voronoi neighbours, the
+interception table's properties, and the full query through the host model
+of the kernel (same tree, table and float32 code), checked against the
+FP64 brute-force oracle."""
+from __future__ import annotations
+
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2308_16084_amd as P
+from synth import configs as C
+from synth import queries as SQ
+from tests._accept import check_answers
+from tests._helpers import CUBE_F, CUBE_V, TETRA_F, TETRA_V, random_tiny_mesh
+
+
+def _mesh(V, F, domain=None, mode=P.TABLE_FLOODING, scale=1.5):
+    m = P.Mesh(V, F)
+    if domain is None:
+        lo, hi = SQ.aabb(V)
+        domain = SQ.scaled_box(lo, hi, scale)
+    st = m.precompute(domain=domain, table_mode=mode)
+    return m, st, domain
+
+
+@pytest.mark.parametrize("bad,msg", [
+    ("oob", "out of range"), ("repeat", "repeats"), ("zero_area", "zero area"), ("nan", "non-finite"),
+    ("dup", "coincide")])
+def test_mesh_validation(bad, msg):
+    V = TETRA_V.copy()
+    F = TETRA_F.copy()
+    if bad == "oob":
+        F[1, 2] = 7
+    elif bad == "repeat":
+        F[1, 2] = F[1, 0]
+    elif bad == "zero_area":
+        V = np.concatenate([V, [[0.5, 0, 0]]]).astype(np.float32)
+        F = np.concatenate([F, [[0, 1, 4]]]).astype(np.int32)
+    elif bad == "nan":
+        V[2, 1] = np.nan
+    elif bad == "dup":
+        V = np.concatenate([V, V[2:3]]).astype(np.float32)
+    with pytest.raises(P.P2MError) as e:
+        P.Mesh(V, F)
+    assert e.value.status == -2 and msg in str(e.value)
+
+
+def test_state_errors():
+    m = P.Mesh(TETRA_V, TETRA_F)
+    with pytest.raises(P.P2MError) as e:
+        m.table()
+    assert e.value.status == -3
+    with pytest.raises(P.P2MError):
+        m.query_host(np.zeros((1, 3), np.float32))
+    with pytest.raises(P.P2MError) as e:
+        m.precompute(domain=([0, 0, 0], [0, 1, 1]))
+    assert e.value.status == -1
+
+
+def test_edges_match_oracle():
+    rng = np.random.default_rng(0)
+    V, F = random_tiny_mesh(rng, "heightfield")
+    m = P.Mesh(V, F)
+    assert np.array_equal(m.edges(), oracle.OracleMesh(V, F).E)
+
+
+def test_kdtree_is_a_kd_tree():
+    rng = np.random.default_rng(1)
+    V = rng.random((1000, 3)).astype(np.float32)
+    F = np.array([[0, 1, 2]], np.int32)
+    m = P.Mesh(V, F)
+    m.precompute()
+    xyz, vid = m.kdtree()
+    assert sorted(vid.tolist()) == list(range(1000))
+    assert np.array_equal(xyz, V[vid])
+    n = len(vid)
+
+    def check(node, depth, lo, hi):
+        if node >= n:
+            return
+        d = depth % 3
+        assert np.all(xyz[node] >= lo) and np.all(xyz[node] <= hi)
+        s = xyz[node, d]
+        hl = hi.copy(); hl[d] = s
+        lr = lo.copy(); lr[d] = s
+        check(2 * node + 1, depth + 1, lo, hl)
+        check(2 * node + 2, depth + 1, lr, hi)
+
+    check(0, 0, np.full(3, -np.inf, np.float32), np.full(3, np.inf, np.float32))
+
+
+def test_voronoi_neighbours_match_qhull():
+    """Delaunay edges whose Voronoi facet meets the domain are all present:
+    every pair of nearest and second-nearest vertices of a point in D is a
+    neighbour pair; and (away from the hull) the graph equals Qhull's."""
+    from scipy.spatial import Delaunay, cKDTree
+    rng = np.random.default_rng(2)
+    V, F = random_tiny_mesh(rng, "sphere")
+    m, st, (lo, hi) = _mesh(V, F)
+    off, nb = m.neighbors()
+    mine = {(i, int(j)) for i in range(len(V)) for j in nb[off[i]:off[i + 1]]}
+    assert all((j, i) in mine for i, j in mine)
+    d = Delaunay(V.astype(np.float64))
+    qh = set()
+    for t in d.simplices:
+        for a in range(4):
+            for b in range(4):
+                if a != b:
+                    qh.add((int(t[a]), int(t[b])))
+    assert mine <= qh
+    X = rng.uniform(lo, hi, size=(20000, 3))
+    _, ii = cKDTree(V.astype(np.float64)).query(X, k=2)
+    assert all((int(a), int(b)) in mine for a, b in ii)
+
+
+def test_table_contains_incident_primitives():
+    """Theorem 2: every vertex intercepts its incident edges and faces."""
+    rng = np.random.default_rng(3)
+    V, F = random_tiny_mesh(rng, "sphere")
+    m, _, _ = _mesh(V, F)
+    off, ent = m.table()
+    E = m.edges()
+    for v in range(len(V)):
+        edges = set(ent[off[2 * v]:off[2 * v + 1]].tolist())
+        faces = set(ent[off[2 * v + 1]:off[2 * v + 2]].tolist())
+        assert {e for e in range(len(E)) if v in E[e]} <= edges
+        assert {f for f in range(len(F)) if v in F[f]} <= faces
+        assert sorted(edges) == ent[off[2 * v]:off[2 * v + 1]].tolist()
+
+
+def test_flooding_subset_of_all_pairs():
+    """Flooding only visits what the all-pairs filter would accept (Theorem 7
+    says it finds all of them; the equality is checked too)."""
+    rng = np.random.default_rng(4)
+    for kind in ("sphere", "heightfield"):
+        V, F = random_tiny_mesh(rng, kind)
+        m1, _, dom = _mesh(V, F)
+        m2, _, _ = _mesh(V, F, domain=dom, mode=P.TABLE_ALL_PAIRS)
+        o1, e1 = m1.table()
+        o2, e2 = m2.table()
+        for v in range(len(V)):
+            a = set(e1[o1[2 * v]:o1[2 * v + 1]].tolist()), set(e1[o1[2 * v + 1]:o1[2 * v + 2]].tolist())
+            b = set(e2[o2[2 * v]:o2[2 * v + 1]].tolist()), set(e2[o2[2 * v + 1]:o2[2 * v + 2]].tolist())
+            assert a[0] <= b[0] and a[1] <= b[1]
+            assert a == b
+
+
+@pytest.mark.parametrize("name,V,F", [("tetra", TETRA_V, TETRA_F), ("cube", CUBE_V, CUBE_F)])
+def test_host_query_closed_forms(name, V, F):
+    m, _, dom = _mesh(V, F, scale=4.0)
+    rng = np.random.default_rng(5)
+    Q = rng.uniform(dom[0], dom[1], size=(4000, 3)).astype(np.float32)
+    om = oracle.OracleMesh(V, F)
+    ans = om.query(Q)
+    h = m.query_host(Q)
+    assert check_answers(om, Q, ans, h["prim"], h["closest"], h["dist"]) == []
+
+
+@pytest.mark.parametrize("mode", [P.TABLE_FLOODING, P.TABLE_ALL_PAIRS, P.TABLE_EVERYTHING])
+def test_host_query_tiny_meshes(mode):
+    rng = np.random.default_rng(6 + mode)
+    for kind in ("sphere", "heightfield"):
+        V, F = random_tiny_mesh(rng, kind)
+        m, _, dom = _mesh(V, F, mode=mode)
+        Q = rng.uniform(dom[0], dom[1], size=(3000, 3)).astype(np.float32)
+        om = oracle.OracleMesh(V, F)
+        h = m.query_host(Q)
+        assert check_answers(om, Q, om.query(Q), h["prim"], h["closest"], h["dist"]) == []
+
+
+def test_host_query_c1_all_queries():
+    """Workload C1 (icosphere level 4, 10^4 queries): every query accepted."""
+    w = C.c1()
+    m, st, _ = _mesh(w.V, w.F, domain=(w.domain_lo, w.domain_hi))
+    om = oracle.OracleMesh(w.V, w.F)
+    h = m.query_host(w.Q)
+    assert check_answers(om, w.Q, om.query(w.Q), h["prim"], h["closest"], h["dist"]) == []
+    assert st["nv"] == 2562 and st["nf"] == 5120 and st["ne"] == 7680
+
+
+def test_table_completeness_dense_sampling():
+    """Completeness by dense sampling: for many random points of D, the
+    oracle's optimal primitive (or a member of its near-optimal set) is the
+    nearest vertex itself or in that vertex's list."""
+    rng = np.random.default_rng(9)
+    V, F = random_tiny_mesh(rng, "heightfield")
+    m, _, dom = _mesh(V, F)
+    off, ent = m.table()
+    om = oracle.OracleMesh(V, F)
+    Q = rng.uniform(dom[0], dom[1], size=(20000, 3)).astype(np.float32)
+    ans = om.query(Q)
+    nn = np.argmin(((Q[:, None, :].astype(np.float64) - om.V[None]) ** 2).sum(-1), axis=1)
+    tol = 1e-5 * om.diag
+    for i in range(Q.shape[0]):
+        v, t, p = int(nn[i]), int(ans["type"][i]), int(ans["id"][i])
+        ok = (t == 0 and p == v) or (t == 1 and p in ent[off[2 * v]:off[2 * v + 1]]) or \
+             (t == 2 and p in ent[off[2 * v + 1]:off[2 * v + 2]])
+        if not ok:
+            ns = om.near_set(Q[i], ans["dist"][i], tol)
+            ok = any((tt == 0 and pp == v) or (tt == 1 and pp in ent[off[2 * v]:off[2 * v + 1]]) or
+                     (tt == 2 and pp in ent[off[2 * v + 1]:off[2 * v + 2]]) for tt, pp in ns)
+        assert ok, (i, Q[i], v, t, p)
+
+
+def test_out_of_domain_and_nonfinite_flags():
+    m, _, dom = _mesh(TETRA_V, TETRA_F, scale=2.0)
+    Q = np.array([[0.2, 0.2, 0.2], [50, 0, 0], [np.nan, 0, 0]], np.float32)
+    h = m.query_host(Q)
+    assert h["status"].tolist() == [0, P.OUT_OF_DOMAIN, P.NONFINITE]
+    assert np.isnan(h["dist"][2]) and P.prim_type(h["prim"][2]) == P.NONE
+    assert abs(h["dist"][1] - 49.0) < 1e-4  # still a valid distance (to vertex (1,0,0))
+
+
+def test_save_load_roundtrip():
+    rng = np.random.default_rng(10)
+    V, F = random_tiny_mesh(rng, "sphere")
+    m, _, dom = _mesh(V, F)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "m.p2m")
+        m.save(path)
+        m2 = P.Mesh.load(path)
+        for a, b in zip(m.table(), m2.table()):
+            assert np.array_equal(a, b)
+        Q = rng.uniform(dom[0], dom[1], size=(500, 3)).astype(np.float32)
+        h1, h2 = m.query_host(Q), m2.query_host(Q)
+        assert np.array_equal(h1["prim"], h2["prim"]) and np.array_equal(h1["dist"], h2["dist"])
+        with open(path, "r+b") as fh:
+            fh.seek(40)
+            fh.write(b"\x00\x01\x02\x03")
+        with pytest.raises(P.P2MError):
+            P.Mesh.load(path)
