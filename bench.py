@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--queries", type=int, default=10_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB-in / 1 GiB-out elementwise copy kernel (counter calibration)")
     ap.add_argument("--cache", default=os.environ.get("P2M_CACHE_DIR", ""),
                     help="directory to save/load the precomputed mesh (default $P2M_CACHE_DIR; empty: none)")
     args = ap.parse_args()
@@ -101,6 +103,9 @@ def main():
     t0 = time.time()
     mesh, stats = P.Mesh.cached(w.V, w.F, (w.domain_lo, w.domain_hi), args.cache or None)
     t_pre = time.time() - t0
+    if "avg_list" not in stats:
+        off, _ = mesh.table()
+        stats["avg_list"] = float(off[-1]) / mesh.nv
     log(f"[bench] host precompute {t_pre:.1f}s {json.dumps({k: stats[k] for k in stats if k.startswith('t_') or k in ('avg_list', 'max_list', 'flood_tests')})}")
     dev_bytes = mesh.upload(0)
     q = torch.from_numpy(w.Q).to(dev)
@@ -113,6 +118,14 @@ def main():
 
     def step(profile=False):
         mesh.query(q, out=out, profile=profile)
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
 
     for _ in range(args.warmup):
         step()
@@ -139,6 +152,27 @@ def main():
         query_ms.append(b)
     order_avg, query_avg = float(np.mean(order_ms)), float(np.mean(query_ms))
     log(f"[bench] stage times: ordering {order_avg:.3f} ms, query kernel {query_avg:.3f} ms")
+
+    # cost breakdown: KD-tree nearest vertex alone vs the whole query kernel,
+    # both on the Morton-ordered batch without the ordering step
+    _, perm = mesh.order_queries(q)
+    qs = q[perm.long()].contiguous()
+    kd_ms, full_ms = [], []
+    trav = 2 if n >= (1 << 22) else 1  # the walk the sorted step uses
+    for _ in range(args.steps):
+        e0.record()
+        mesh.nearest_vertex(qs, traversal=trav)
+        e1.record()
+        torch.cuda.synchronize()
+        kd_ms.append(e0.elapsed_time(e1))
+        e0.record()
+        mesh.query(qs, out=out, sort=False, traversal=trav)
+        e1.record()
+        torch.cuda.synchronize()
+        full_ms.append(e0.elapsed_time(e1))
+    del qs, perm
+    breakdown = {"kdtree_only_ms": round(float(np.mean(kd_ms)), 4), "query_presorted_ms": round(float(np.mean(full_ms)), 4)}
+    log(f"[bench] breakdown on pre-sorted queries: KD tree {breakdown['kdtree_only_ms']:.3f} ms, whole query {breakdown['query_presorted_ms']:.3f} ms")
 
     # algorithmic bytes per query from the same tree/table (host model counts)
     rng = np.random.default_rng(123)
@@ -167,7 +201,8 @@ def main():
                          "avg_list": round(float(stats.get("avg_list", 0.0)), 2),
                          "device_bytes": dev_bytes},
               "roofline": roofline,
-              "stages_ms": {"ordering": round(order_avg, 4), "query": round(query_avg, 4)}}
+              "stages_ms": {"ordering": round(order_avg, 4), "query": round(query_avg, 4)},
+              "breakdown": breakdown}
 
     if not args.no_bwd:
         w5 = C.c5()

@@ -87,10 +87,14 @@ typedef struct {
 
 typedef struct {
     int sort_queries;   /* <0 default (on), 0 off, 1 Morton-order the batch */
-    int block_size;     /* 0 default; else 64..1024, a multiple of 64 */
+    int block_size;     /* 0 default (256); else 64, 128, 192 or 256 */
     int profile;        /* nonzero: record HIP events around the ordering and
                            query kernels (read with p2m_query_profile) */
-    int reserved[5];    /* must be 0 */
+    int traversal;      /* KD-tree walk: 0 automatic (wavefront-coherent for
+                           sorted batches of >= 2^22 queries), 1 one search per
+                           lane, 2 wavefront-coherent; every choice returns
+                           each query's exact nearest vertex */
+    int reserved[4];    /* must be 0 */
 } p2m_query_opts;
 
 /* ------------------------------------------------------------ host side */
@@ -166,9 +170,10 @@ p2m_status p2m_query(p2m_mesh* m, const float* q_dev, int64_t n, int32_t* prim_d
 p2m_status p2m_query_profile(p2m_mesh* m, float* order_ms, float* query_ms);
 
 /* KD-tree nearest vertex only (the first step of Algorithm A.2): vid int32
- * [n] and squared distance d2 float [n] (may be NULL). */
+ * [n] and squared distance d2 float [n] (may be NULL).  traversal as in
+ * p2m_query_opts.  Queries are taken in the given order (no ordering step). */
 p2m_status p2m_nearest_vertex(p2m_mesh* m, const float* q_dev, int64_t n, int32_t* vid_dev, float* d2_dev,
-                              void* stream);
+                              int traversal, void* stream);
 
 /* Query ordering: 30-bit Morton keys of q in D (10 bits per axis, cells
  * floor((q-lo)*1024/(hi-lo)) taken in float32 and clamped to [0,1023]) and

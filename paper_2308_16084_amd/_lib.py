@@ -37,7 +37,8 @@ class BuildStats(ctypes.Structure):
 
 
 class QueryOpts(ctypes.Structure):
-    _fields_ = [("sort_queries", INT), ("block_size", INT), ("profile", INT), ("reserved", INT * 5)]
+    _fields_ = [("sort_queries", INT), ("block_size", INT), ("profile", INT), ("traversal", INT),
+                ("reserved", INT * 4)]
 
 
 _SIGS = {
@@ -56,7 +57,7 @@ _SIGS = {
     "p2m_upload": (INT, [P, INT, P, P]),
     "p2m_query": (INT, [P, P, I64, P, P, P, P, P, P, P, P]),
     "p2m_query_profile": (INT, [P, P, P]),
-    "p2m_nearest_vertex": (INT, [P, P, I64, P, P, P]),
+    "p2m_nearest_vertex": (INT, [P, P, I64, P, P, INT, P]),
     "p2m_order_queries": (INT, [P, P, I64, P, P, P]),
     "p2m_query_backward": (INT, [P, P, I64, P, P, P, P, P, P, P, P]),
     "p2m_batch_create": (INT, [P, I32, INT, P, P]),

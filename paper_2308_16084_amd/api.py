@@ -195,7 +195,7 @@ class Mesh:
         return nbytes.value
 
     def query(self, q, sort: bool = True, block_size: int = 0, out: dict | None = None, status: bool = True,
-              for_backward: bool = False, profile: bool = False, stream=None) -> dict:
+              for_backward: bool = False, profile: bool = False, traversal: int = 0, stream=None) -> dict:
         """P2M query of a CUDA float32 [n,3] tensor; returns device tensors."""
         torch = _torch()
         q = _dev_tensor(q, torch.float32, (3,), "q")
@@ -214,6 +214,7 @@ class Mesh:
         o.sort_queries = 1 if sort else 0
         o.block_size = int(block_size)
         o.profile = 1 if profile else 0
+        o.traversal = int(traversal)
         check(lib().p2m_query(self._h, _ptr(q), n, _ptr(out["prim"]), _ptr(out["closest"]), _ptr(out["dist"]),
                               _ptr(out.get("status")), _ptr(out.get("bary")), _ptr(out.get("pvid")),
                               ctypes.byref(o), _stream(stream)))
@@ -225,13 +226,13 @@ class Mesh:
         check(lib().p2m_query_profile(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
-    def nearest_vertex(self, q, stream=None):
+    def nearest_vertex(self, q, traversal: int = 0, stream=None):
         torch = _torch()
         q = _dev_tensor(q, torch.float32, (3,), "q")
         n = q.shape[0]
         vid = torch.empty(n, dtype=torch.int32, device=q.device)
         d2 = torch.empty(n, dtype=torch.float32, device=q.device)
-        check(lib().p2m_nearest_vertex(self._h, _ptr(q), n, _ptr(vid), _ptr(d2), _stream(stream)))
+        check(lib().p2m_nearest_vertex(self._h, _ptr(q), n, _ptr(vid), _ptr(d2), int(traversal), _stream(stream)))
         return vid, d2
 
     def order_queries(self, q, stream=None):

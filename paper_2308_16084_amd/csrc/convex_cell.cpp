@@ -73,28 +73,34 @@ ConvexCell::ClipResult ConvexCell::clip(const HalfSpace& h) {
         pos_.clear();
         return EMPTY;
     }
-    // Boundary of the removed region: directed edges of removed triangles
-    // whose reverse edge belongs to a kept triangle.
-    bedges_.clear();
-    for (size_t t = 0; t < nt; ++t) {
-        if (!out_[t]) continue;
-        const auto& T = tris_[t];
-        for (int e = 0; e < 3; ++e) bedges_.push_back({T[(size_t)e], T[(size_t)((e + 1) % 3)]});
-    }
-    // cancel interior edges (both directions present among removed triangles)
-    std::vector<std::array<uint16_t, 2>>& sorted = bedges_;
-    auto key = [](const std::array<uint16_t, 2>& e) {
-        return ((uint32_t)std::min(e[0], e[1]) << 16) | std::max(e[0], e[1]);
-    };
-    std::sort(sorted.begin(), sorted.end(), [&](const auto& x, const auto& y) { return key(x) < key(y); });
+    // Boundary of the removed region: directed edges (a -> b) of removed
+    // triangles whose reverse (b -> a) belongs to a kept triangle.  Found by
+    // a direct search inside the smaller of the two sets: from the removed
+    // side an edge is on the boundary when its reverse is not among removed
+    // edges; from the kept side, a kept edge (b -> a) whose reverse is not
+    // among kept edges gives the boundary edge (a -> b).
+    const bool from_removed = 2 * nout <= nt;
+    removed_.clear();
+    for (size_t t = 0; t < nt; ++t)
+        if ((out_[t] != 0) == from_removed) removed_.push_back((uint32_t)t);
     std::vector<std::array<uint16_t, 2>>& boundary = boundary_;
     boundary.clear();
-    for (size_t i = 0; i < sorted.size();) {
-        size_t j = i + 1;
-        while (j < sorted.size() && key(sorted[j]) == key(sorted[i])) ++j;
-        if (j - i == 1) boundary.push_back(sorted[i]);
-        else if (j - i != 2 || sorted[i][0] != sorted[i + 1][1]) return SKIPPED;  // inconsistent topology
-        i = j;
+    for (uint32_t ti : removed_) {
+        const auto& T = tris_[ti];
+        for (int e = 0; e < 3; ++e) {
+            const uint16_t a = T[(size_t)e], b = T[(size_t)((e + 1) % 3)];
+            int twins = 0;
+            for (uint32_t tj : removed_) {
+                const auto& U = tris_[tj];
+                twins += (U[0] == b && U[1] == a) + (U[1] == b && U[2] == a) + (U[2] == b && U[0] == a);
+            }
+            if (twins == 0) {
+                if (from_removed) boundary.push_back({a, b});
+                else boundary.push_back({b, a});
+            } else if (twins != 1) {
+                return SKIPPED;  // inconsistent topology
+            }
+        }
     }
     if (boundary.size() < 3) return SKIPPED;
     // boundary must be one cycle

@@ -53,6 +53,7 @@ class ConvexCell {
     bool empty_ = false;
     // scratch
     std::vector<uint8_t> out_;
+    std::vector<uint32_t> removed_;
     std::vector<std::array<uint16_t, 2>> bedges_, boundary_;
     std::vector<std::array<uint16_t, 3>> newt_;
     std::vector<std::array<double, 3>> newp_;

@@ -33,10 +33,6 @@ inline void normalize3(double* a) {
     a[1] /= l;
     a[2] /= l;
 }
-inline double dist3(const double* a, const double* b) {
-    double d[3] = {a[0] - b[0], a[1] - b[1], a[2] - b[2]};
-    return std::sqrt(dot3(d, d));
-}
 
 int num_threads(int requested) {
 #ifdef _OPENMP
@@ -63,6 +59,16 @@ struct CellStore {
         c.load(planes[(size_t)r.thread].data() + 4 * r.poff, r.np, tris[(size_t)r.thread].data() + 3 * r.toff,
                pos[(size_t)r.thread].data() + 3 * r.toff, r.nt);
     }
+    const double* corners(int64_t v, uint32_t& n) const {
+        const Ref& r = ref[(size_t)v];
+        n = r.nt;
+        return pos[(size_t)r.thread].data() + 3 * r.toff;
+    }
+    const double* plane_data(int64_t v, uint32_t& n) const {
+        const Ref& r = ref[(size_t)v];
+        n = r.np;
+        return planes[(size_t)r.thread].data() + 4 * r.poff;
+    }
 };
 
 // Space-perp(p) as half-spaces, the vertices of p, and the distance from a
@@ -76,12 +82,16 @@ struct Primitive {
     HalfSpace perp[8];
     int nperp;
 
-    double dist(const double* x) const {
+    // squared distance to the line (edge) or plane (face)
+    double dist2(const double* x) const {
         double d[3] = {x[0] - a[0], x[1] - a[1], x[2] - a[2]};
-        if (face) return std::fabs(dot3(d, dir));
+        if (face) {
+            double h = dot3(d, dir);
+            return h * h;
+        }
         double c[3];
         cross3(d, dir, c);
-        return std::sqrt(dot3(c, c));
+        return dot3(c, c);
     }
 };
 
@@ -160,7 +170,8 @@ void make_edge(const MeshData& m, int64_t e, double tau, Primitive& p) {
 }
 
 struct ThreadCtx {
-    ConvexCell cell;
+    ConvexCell cell, base;
+    double blo_[3], bhi_[3];
     std::vector<uint32_t> stamp;
     uint32_t cur = 0;
     std::vector<int32_t> queue;
@@ -168,31 +179,61 @@ struct ThreadCtx {
     int64_t tests = 0, hits = 0, quick = 0, skipped = 0;
 };
 
-// Convexity filter (Theorems 5/6) on ConvexPoly(w,p) = Cell(w) n Space-perp(p).
-bool intercepts(const MeshData& m, const CellStore& cs, int64_t w, const Primitive& p, double tau, ThreadCtx& c) {
-    ++c.tests;
-    cs.load(w, c.cell);
-    const double* W = &m.Vd[3 * (size_t)w];
-    // The filtered quantity |x-w| - Dist(x, p) is convex, so if it is below
-    // -tau on every corner of the whole cell it is below on any sub-polytope.
-    bool all_far = true;
-    for (size_t t = 0; t < c.cell.num_corners() && all_far; ++t) {
-        const double* x = c.cell.corner(t);
-        all_far = dist3(x, W) <= p.dist(x) - tau;
+// Space-perp(p) n D (all half-spaces moved outward by tau), built once per
+// primitive; ConvexPoly(w,p) is then this polytope cut by w's cell planes.
+// base_empty: the primitive's Space-perp misses D altogether.
+void make_base(const Primitive& p, const double blo[3], const double bhi[3], ThreadCtx& c, bool& base_empty) {
+    c.base.init_box(blo, bhi);
+    base_empty = false;
+    for (int i = 0; i < p.nperp && !base_empty; ++i) {
+        ConvexCell::ClipResult r = c.base.clip(p.perp[i]);
+        if (r == ConvexCell::EMPTY) base_empty = true;
+        if (r == ConvexCell::SKIPPED) ++c.skipped;
     }
+}
+
+// Convexity filter (Theorems 5/6) on ConvexPoly(w,p) = Cell(w) n Space-perp(p).
+// A corner x keeps w out when |x-w| <= Dist(x,p) - tau; with Dist <= dmax this
+// follows from the squared test |x-w|^2 + 2 tau dmax <= Dist^2, used here.
+bool intercepts(const MeshData& m, const CellStore& cs, int64_t w, const Primitive& p, double tau, double dmax,
+                bool base_empty, ThreadCtx& c) {
+    ++c.tests;
+    const double* W = &m.Vd[3 * (size_t)w];
+    const double slack = 2.0 * tau * dmax;
+    const double* blo_ = c.blo_;
+    const double* bhi_ = c.bhi_;
+    auto far_enough = [&](const double* x) {
+        double d[3] = {x[0] - W[0], x[1] - W[1], x[2] - W[2]};
+        return dot3(d, d) + slack <= p.dist2(x);
+    };
+    // |x-w| - Dist(x, p) is convex, so if every corner of the whole cell keeps
+    // w out, every corner of any sub-polytope does too.
+    uint32_t nc = 0;
+    const double* X = cs.corners(w, nc);
+    bool all_far = true;
+    for (uint32_t t = 0; t < nc && all_far; ++t) all_far = far_enough(X + 3 * t);
     if (all_far) {
         ++c.quick;
         return false;
     }
-    for (int i = 0; i < p.nperp; ++i) {
-        ConvexCell::ClipResult r = c.cell.clip(p.perp[i]);
+    if (base_empty) return false;
+    c.cell = c.base;
+    uint32_t np = 0;
+    const double* H = cs.plane_data(w, np);
+    for (uint32_t i = 0; i < np; ++i) {
+        HalfSpace h{{H[4 * i], H[4 * i + 1], H[4 * i + 2]}, H[4 * i + 3]};
+        // the cell's domain-box faces are already faces of the base polytope
+        const int axes = (h.n[0] != 0.0) + (h.n[1] != 0.0) + (h.n[2] != 0.0);
+        if (axes == 1 && (std::fabs(h.n[0]) == 1.0 || std::fabs(h.n[1]) == 1.0 || std::fabs(h.n[2]) == 1.0)) {
+            const int k = h.n[0] != 0.0 ? 0 : (h.n[1] != 0.0 ? 1 : 2);
+            if ((h.n[k] > 0 && h.off == bhi_[k]) || (h.n[k] < 0 && h.off == -blo_[k])) continue;
+        }
+        ConvexCell::ClipResult r = c.cell.clip(h);
         if (r == ConvexCell::EMPTY) return false;
         if (r == ConvexCell::SKIPPED) ++c.skipped;
     }
-    for (size_t t = 0; t < c.cell.num_corners(); ++t) {
-        const double* x = c.cell.corner(t);
-        if (dist3(x, W) > p.dist(x) - tau) return true;
-    }
+    for (size_t t = 0; t < c.cell.num_corners(); ++t)
+        if (!far_enough(c.cell.corner(t))) return true;
     return false;
 }
 
@@ -201,7 +242,7 @@ inline uint64_t pair_key(int64_t v, bool face, int64_t id) {
 }
 
 void flood(const MeshData& m, const CellStore& cs, const Table& t, const Primitive& p, int64_t pid, double tau,
-           ThreadCtx& c) {
+           double dmax, bool base_empty, ThreadCtx& c) {
     if (++c.cur == 0) {
         std::fill(c.stamp.begin(), c.stamp.end(), 0u);
         c.cur = 1;
@@ -215,7 +256,7 @@ void flood(const MeshData& m, const CellStore& cs, const Table& t, const Primiti
         int32_t w = c.queue[head];
         bool own = false;
         for (int i = 0; i < p.nverts; ++i) own |= (p.verts[i] == w);
-        bool hit = own || intercepts(m, cs, w, p, tau, c);  // Theorem 2 for the primitive's own vertices
+        bool hit = own || intercepts(m, cs, w, p, tau, dmax, base_empty, c);  // Theorem 2 for own vertices
         if (!hit) continue;
         ++c.hits;
         c.pairs.push_back(pair_key(w, p.face, pid));
@@ -308,6 +349,10 @@ bool build_table(const MeshData& m, const TableOptions& o, Table& t, TableStats&
 
     // 3. inspection
     t0 = Clock::now();
+    // every distance inside the (tau-grown) domain is below its diagonal
+    double dmax = 0.0;
+    for (int k = 0; k < 3; ++k) dmax += (bhi[k] - blo[k]) * (bhi[k] - blo[k]);
+    dmax = std::sqrt(dmax);
     std::vector<ThreadCtx> ctx((size_t)nth);
     const int64_t nprim = m.ne + m.nf;
 #pragma omp parallel num_threads(nth)
@@ -318,6 +363,10 @@ bool build_table(const MeshData& m, const TableOptions& o, Table& t, TableStats&
 #endif
         ThreadCtx& c = ctx[(size_t)tid];
         c.stamp.assign((size_t)nv, 0u);
+        for (int k = 0; k < 3; ++k) {
+            c.blo_[k] = blo[k];
+            c.bhi_[k] = bhi[k];
+        }
         Primitive p;
 #pragma omp for schedule(dynamic, 64)
         for (int64_t q = 0; q < nprim; ++q) {
@@ -325,13 +374,15 @@ bool build_table(const MeshData& m, const TableOptions& o, Table& t, TableStats&
             int64_t id = face ? q - m.ne : q;
             if (face) make_face(m, id, o.tau, p);
             else make_edge(m, id, o.tau, p);
+            bool base_empty = false;
+            make_base(p, blo, bhi, c, base_empty);
             if (o.mode == TABLE_FLOODING) {
-                flood(m, cs, t, p, id, o.tau, c);
+                flood(m, cs, t, p, id, o.tau, dmax, base_empty, c);
             } else {
                 for (int64_t w = 0; w < nv; ++w) {
                     bool own = false;
                     for (int i = 0; i < p.nverts; ++i) own |= (p.verts[i] == w);
-                    if (o.mode == TABLE_EVERYTHING || own || intercepts(m, cs, w, p, o.tau, c))
+                    if (o.mode == TABLE_EVERYTHING || own || intercepts(m, cs, w, p, o.tau, dmax, base_empty, c))
                         c.pairs.push_back(pair_key(w, face, id));
                 }
             }

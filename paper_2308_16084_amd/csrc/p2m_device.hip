@@ -15,6 +15,7 @@
 #include "device_common.hpp"
 #include "p2m_internal.hpp"
 #include "query_core.hpp"
+#include "wave_kdtree.hpp"
 
 namespace p2m {
 
@@ -152,20 +153,37 @@ __global__ void k_morton(const float* __restrict__ q, int64_t n, float lox, floa
     vals[i] = (int32_t)i;
 }
 
-template <bool kWriteExtras>
-__global__ __launch_bounds__(256) void k_query(MeshView m, const float* __restrict__ q,
+// kWave: the wavefront-coherent tree walk (dense, Morton-ordered batches);
+// otherwise every lane searches the tree on its own.
+template <bool kWriteExtras, bool kWave>
+__global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const float* __restrict__ q,
                                                 const int32_t* __restrict__ perm, int64_t n, int64_t chunk,
                                                 int32_t* __restrict__ prim, float* __restrict__ closest,
                                                 float* __restrict__ dist, uint8_t* __restrict__ status,
                                                 float* __restrict__ bary, int32_t* __restrict__ pvid) {
     const int64_t tile = xcd_tile(blockIdx.x, chunk);
     const int64_t j = tile * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const int64_t i = perm ? (int64_t)perm[j] : j;
-    const float qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
-    uint8_t st;
+    int64_t i = j < n ? (perm ? (int64_t)perm[j] : j) : -1;
+    if (i >= n) i = -1;
+    float qx = 0.f, qy = 0.f, qz = 0.f;
+    if (i >= 0) {
+        qx = q[3 * i];
+        qy = q[3 * i + 1];
+        qz = q[3 * i + 2];
+    }
+    const bool fin = finite3(qx, qy, qz);
     ScanCounters c;
-    const Answer a = p2m_query_point(m, qx, qy, qz, st, c);
+    Nearest nv;
+    if (kWave) {
+        // every lane of the wavefront takes part in the shared tree walk
+        nv = kdt_nearest_wave(m.node, m.nv, qx, qy, qz, i >= 0 && fin);
+        if (i < 0) return;
+    } else {
+        if (i < 0) return;
+        if (fin) nv = kdt_nearest(m.node, m.nv, qx, qy, qz, c.nodes);
+    }
+    uint8_t st = fin ? domain_status(m, qx, qy, qz) : (uint8_t)2;
+    const Answer a = fin ? p2m_answer(m, qx, qy, qz, nv, c) : nonfinite_answer();
     prim[i] = a.prim;
     closest[3 * i] = a.cx;
     closest[3 * i + 1] = a.cy;
@@ -180,20 +198,28 @@ __global__ __launch_bounds__(256) void k_query(MeshView m, const float* __restri
     }
 }
 
+template <bool kWave>
 __global__ __launch_bounds__(256) void k_nearest(MeshView m, const float* __restrict__ q, int64_t n,
                                                   int32_t* __restrict__ vid, float* __restrict__ d2) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
-    if (!(isfinite(qx) && isfinite(qy) && isfinite(qz))) {
-        vid[i] = -1;
-        if (d2) d2[i] = NAN;
-        return;
+    float qx = 0.f, qy = 0.f, qz = 0.f;
+    if (i < n) {
+        qx = q[3 * i];
+        qy = q[3 * i + 1];
+        qz = q[3 * i + 2];
     }
-    uint64_t visits = 0;
-    const Nearest b = kdt_nearest(m.node, m.nv, qx, qy, qz, visits);
-    vid[i] = b.vid;
-    if (d2) d2[i] = b.d2;
+    const bool fin = finite3(qx, qy, qz);
+    Nearest b;
+    if (kWave) {
+        b = kdt_nearest_wave(m.node, m.nv, qx, qy, qz, i < n && fin);
+        if (i >= n) return;
+    } else {
+        if (i >= n) return;
+        uint64_t visits = 0;
+        if (fin) b = kdt_nearest(m.node, m.nv, qx, qy, qz, visits);
+    }
+    vid[i] = fin ? b.vid : -1;
+    if (d2) d2[i] = fin ? b.d2 : NAN;
 }
 
 __global__ __launch_bounds__(256) void k_backward(const float* __restrict__ q, int64_t n,
@@ -359,13 +385,15 @@ p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, flo
     if (!q || !prim || !closest || !dist) return fail(P2M_ERR_ARG, "NULL query or output pointer");
     if ((bary == nullptr) != (pvid == nullptr)) return fail(P2M_ERR_ARG, "bary and pvid must both be set or both NULL");
     if (n > (int64_t)INT32_MAX) return fail(P2M_ERR_ARG, "more than 2^31-1 queries in one call");
-    int sort = 1, block = 256, profile = 0;
+    int sort = 1, block = 256, profile = 0, traversal = 0;
     if (opts) {
         profile = opts->profile;
+        traversal = opts->traversal;
+        if (traversal < 0 || traversal > 2) return fail(P2M_ERR_ARG, "traversal must be 0, 1 or 2");
         if (opts->sort_queries >= 0) sort = opts->sort_queries ? 1 : 0;
         if (opts->block_size != 0) {
-            if (opts->block_size < 64 || opts->block_size > 1024 || opts->block_size % 64)
-                return fail(P2M_ERR_ARG, "block_size must be a multiple of 64 in [64, 1024]");
+            if (opts->block_size < 64 || opts->block_size > kQueryMaxBlock || opts->block_size % 64)
+                return fail(P2M_ERR_ARG, "block_size must be a multiple of 64 in [64, 256]");
             block = opts->block_size;
         }
     }
@@ -388,10 +416,14 @@ p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, flo
     const int64_t tiles = (n + block - 1) / block;
     const int64_t chunk = (tiles + kXcds - 1) / kXcds;
     const unsigned grid = (unsigned)(chunk * kXcds);
-    if (bary)
-        k_query<true><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid);
-    else
-        k_query<false><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid);
+    const bool wave = traversal == 2 || (traversal == 0 && sort && n >= kWaveMinQueries);
+    if (bary) {
+        if (wave) k_query<true, true><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid);
+        else k_query<true, false><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid);
+    } else {
+        if (wave) k_query<false, true><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid);
+        else k_query<false, false><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid);
+    }
     p2m_status r = check_launch("query kernel");
     if (r == P2M_OK && profile) {
         (void)hipEventRecord((hipEvent_t)s.dev.ev[2], st);
@@ -416,16 +448,22 @@ p2m_status p2m_query_profile(p2m_mesh* mh, float* order_ms, float* query_ms) {
     return P2M_OK;
 }
 
-p2m_status p2m_nearest_vertex(p2m_mesh* mh, const float* q, int64_t n, int32_t* vid, float* d2, void* stream) {
+p2m_status p2m_nearest_vertex(p2m_mesh* mh, const float* q, int64_t n, int32_t* vid, float* d2, int traversal,
+                              void* stream) {
     if (!mh) return fail(P2M_ERR_ARG, "mesh is NULL");
     MeshState& s = mh->s;
     if (n < 0) return fail(P2M_ERR_ARG, "negative query count");
     if (s.dev.device < 0) return fail(P2M_ERR_STATE, "p2m_nearest_vertex before p2m_upload");
     if (n == 0) return P2M_OK;
     if (!q || !vid) return fail(P2M_ERR_ARG, "NULL pointer");
+    if (traversal < 0 || traversal > 2) return fail(P2M_ERR_ARG, "traversal must be 0, 1 or 2");
     DeviceGuard g(s.dev.device);
     const MeshView v = device_view(s);
-    k_nearest<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(v, q, n, vid, d2);
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    if (traversal == 2 || (traversal == 0 && n >= kWaveMinQueries))
+        k_nearest<true><<<grid, 256, 0, (hipStream_t)stream>>>(v, q, n, vid, d2);
+    else
+        k_nearest<false><<<grid, 256, 0, (hipStream_t)stream>>>(v, q, n, vid, d2);
     return check_launch("nearest-vertex kernel");
 }
 

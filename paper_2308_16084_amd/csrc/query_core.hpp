@@ -73,7 +73,9 @@ P2M_HD double d2_f64(float qx, float qy, float qz, float px, float py, float pz)
 P2M_HD void consider(Nearest& b, float qx, float qy, float qz, float d2, const float4& p) {
     const int32_t vid = as_int(p.w);
     bool take;
-    if (d2 < b.d2 * kTieLo) {
+    if (b.vid < 0) {
+        take = true;  // first candidate
+    } else if (d2 < b.d2 * kTieLo) {
         take = true;
     } else if (d2 <= b.d2 * kTieHi) {
         double D = d2_f64(qx, qy, qz, p.x, p.y, p.z);
@@ -117,7 +119,7 @@ P2M_HD Nearest kdt_nearest(const KdNode* __restrict__ node, int32_t n, float qx,
     Nearest b;
     b.d2 = INFINITY;
     b.px = b.py = b.pz = 0.f;
-    b.vid = 0x7fffffff;
+    b.vid = -1;
     int32_t st_node[kMaxDepth];
     float st_d[kMaxDepth];
     int sp = 0;
@@ -134,12 +136,12 @@ P2M_HD Nearest kdt_nearest(const KdNode* __restrict__ node, int32_t n, float qx,
             const int32_t c0 = 2 * cur + (left_first ? 1 : 2), c1 = 2 * cur + (left_first ? 2 : 1);
             const float d0 = left_first ? dl : dr, d1 = left_first ? dr : dl;
             const float lim = b.d2 * kTieHi;
-            if (d1 <= lim && sp < kMaxDepth) {
+            if (c1 < n && d1 <= lim && sp < kMaxDepth) {
                 st_node[sp] = c1;
                 st_d[sp] = d1;
                 ++sp;
             }
-            cur = d0 <= lim ? c0 : -1;
+            cur = (c0 < n && d0 <= lim) ? c0 : -1;
         }
         while (sp > 0) {
             --sp;
@@ -170,61 +172,82 @@ P2M_HD float seg_d2(float qx, float qy, float qz, const float4& a, const float4&
     return cx * cx + cy * cy + cz * cz;
 }
 
+struct SegHit {
+    float d2, t;
+    int region;
+};
+
+P2M_HD SegHit seg_hit(float qx, float qy, float qz, const float4& a, const float4& b) {
+    SegHit h;
+    h.d2 = seg_d2(qx, qy, qz, a, b, h.t, h.region);
+    return h;
+}
+
 // Closest point on the closed triangle (a,b,c).
 // region: 0 inside; 1,2,3 on side ab, bc, ca; 4,5,6 at corner a, b, c.
-// w: barycentric weights of the closest point.
-P2M_HD float tri_d2(float qx, float qy, float qz, const float4& a, const float4& b, const float4& c, float w[3],
-                    int& region) {
+// w: barycentric weights of the closest point; (cx,cy,cz): the point.
+// The foot of q on the plane is formed first and the inside test and weights
+// use short vectors from the foot to the corners: the same signs as with q
+// (the difference is along the normal) without the cancellation of long,
+// nearly parallel vectors from a far query.
+P2M_HD float tri_d2(float qx, float qy, float qz, const float4& a, const float4& b, const float4& c, float& w0,
+                    float& w1, float& w2, int& region, float& cx, float& cy, float& cz) {
     const float abx = b.x - a.x, aby = b.y - a.y, abz = b.z - a.z;
     const float acx = c.x - a.x, acy = c.y - a.y, acz = c.z - a.z;
     const float nx = aby * acz - abz * acy, ny = abz * acx - abx * acz, nz = abx * acy - aby * acx;
     const float nn = nx * nx + ny * ny + nz * nz;
-    const float aqx = qx - a.x, aqy = qy - a.y, aqz = qz - a.z;
-    const float bqx = qx - b.x, bqy = qy - b.y, bqz = qz - b.z;
-    const float cqx = qx - c.x, cqy = qy - c.y, cqz = qz - c.z;
+    const float inv = 1.f / nn;
+    const float h = (qx - a.x) * nx + (qy - a.y) * ny + (qz - a.z) * nz;
+    const float s = h * inv;
+    const float px = qx - s * nx, py = qy - s * ny, pz = qz - s * nz;  // foot on the plane
+    const float pax = a.x - px, pay = a.y - py, paz = a.z - pz;
+    const float pbx = b.x - px, pby = b.y - py, pbz = b.z - pz;
+    const float pcx = c.x - px, pcy = c.y - py, pcz = c.z - pz;
     // signed areas of the sub-triangles seen along the normal (scaled by nn)
-    const float ua = (bqy * cqz - bqz * cqy) * nx + (bqz * cqx - bqx * cqz) * ny + (bqx * cqy - bqy * cqx) * nz;
-    const float ub = (cqy * aqz - cqz * aqy) * nx + (cqz * aqx - cqx * aqz) * ny + (cqx * aqy - cqy * aqx) * nz;
-    const float uc = (aqy * bqz - aqz * bqy) * nx + (aqz * bqx - aqx * bqz) * ny + (aqx * bqy - aqy * bqx) * nz;
+    const float ua = (pby * pcz - pbz * pcy) * nx + (pbz * pcx - pbx * pcz) * ny + (pbx * pcy - pby * pcx) * nz;
+    const float ub = (pcy * paz - pcz * pay) * nx + (pcz * pax - pcx * paz) * ny + (pcx * pay - pcy * pax) * nz;
+    const float uc = (pay * pbz - paz * pby) * nx + (paz * pbx - pax * pbz) * ny + (pax * pby - pay * pbx) * nz;
     if (ua >= 0.f && ub >= 0.f && uc >= 0.f) {
-        const float h = aqx * nx + aqy * ny + aqz * nz;
-        const float inv = 1.f / nn;
-        w[0] = ua * inv;
-        w[1] = ub * inv;
-        w[2] = uc * inv;
+        w0 = ua * inv;
+        w1 = ub * inv;
+        w2 = uc * inv;
         region = 0;
-        return h * h * inv;
+        cx = px;
+        cy = py;
+        cz = pz;
+        return h * s;
     }
-    float t0, t1, t2;
-    int r0, r1, r2;
-    const float d0 = seg_d2(qx, qy, qz, a, b, t0, r0);
-    const float d1 = seg_d2(qx, qy, qz, b, c, t1, r1);
-    const float d2 = seg_d2(qx, qy, qz, c, a, t2, r2);
-    float d = d0, t = t0;
-    int side = 0, r = r0;
-    if (d1 < d) {
-        d = d1;
-        t = t1;
-        side = 1;
-        r = r1;
+    const SegHit h0 = seg_hit(qx, qy, qz, a, b);
+    const SegHit h1 = seg_hit(qx, qy, qz, b, c);
+    const SegHit h2 = seg_hit(qx, qy, qz, c, a);
+    const bool s1 = h1.d2 < h0.d2;
+    const float d01 = s1 ? h1.d2 : h0.d2;
+    const bool s2 = h2.d2 < d01;
+    const float d = s2 ? h2.d2 : d01;
+    const float t = s2 ? h2.t : (s1 ? h1.t : h0.t);
+    const int r = s2 ? h2.region : (s1 ? h1.region : h0.region);
+    const int side = s2 ? 2 : (s1 ? 1 : 0);
+    // side s runs from corner s to corner s+1 (mod 3); no run-time array
+    // indexing here, so everything stays in registers
+    const float Ax = side == 0 ? a.x : (side == 1 ? b.x : c.x), Bx = side == 0 ? b.x : (side == 1 ? c.x : a.x);
+    const float Ay = side == 0 ? a.y : (side == 1 ? b.y : c.y), By = side == 0 ? b.y : (side == 1 ? c.y : a.y);
+    const float Az = side == 0 ? a.z : (side == 1 ? b.z : c.z), Bz = side == 0 ? b.z : (side == 1 ? c.z : a.z);
+    cx = Ax + t * (Bx - Ax);
+    cy = Ay + t * (By - Ay);
+    cz = Az + t * (Bz - Az);
+    float wa = 1.f - t, wb = t;  // weights of A and B
+    if (r == 1) {
+        wa = 1.f;
+        wb = 0.f;
+    } else if (r == 2) {
+        wa = 0.f;
+        wb = 1.f;
     }
-    if (d2 < d) {
-        d = d2;
-        t = t2;
-        side = 2;
-        r = r2;
-    }
-    w[0] = w[1] = w[2] = 0.f;
-    const int i0 = side, i1 = (side + 1) % 3;
-    if (r == 0) {
-        w[i0] = 1.f - t;
-        w[i1] = t;
-        region = 1 + side;
-    } else {
-        const int corner = r == 1 ? i0 : i1;
-        w[corner] = 1.f;
-        region = 4 + corner;
-    }
+    w0 = side == 0 ? wa : (side == 2 ? wb : 0.f);
+    w1 = side == 1 ? wa : (side == 0 ? wb : 0.f);
+    w2 = side == 2 ? wa : (side == 1 ? wb : 0.f);
+    const int corner = r == 1 ? side : (side == 2 ? 0 : side + 1);
+    region = r == 0 ? 1 + side : 4 + corner;
     return d;
 }
 
@@ -241,21 +264,22 @@ struct ScanCounters {
     uint64_t nodes = 0, edges = 0, faces = 0;
 };
 
-// The whole query for one point.
-P2M_HD Answer p2m_query_point(const MeshView& m, float qx, float qy, float qz, uint8_t& status, ScanCounters& cnt) {
+P2M_HD Answer nonfinite_answer() {
     Answer a;
-    status = 0;
-    if (!finite3(qx, qy, qz)) {
-        status = 2;
-        a.prim = make_prim(KIND_NONE, 0);
-        a.cx = a.cy = a.cz = a.dist = NAN;
-        a.w[0] = a.w[1] = a.w[2] = 0.f;
-        a.pv[0] = a.pv[1] = a.pv[2] = -1;
-        return a;
-    }
-    if (qx < m.dlo[0] || qy < m.dlo[1] || qz < m.dlo[2] || qx > m.dhi[0] || qy > m.dhi[1] || qz > m.dhi[2])
-        status = 1;
-    const Nearest nv = kdt_nearest(m.node, m.nv, qx, qy, qz, cnt.nodes);
+    a.prim = make_prim(KIND_NONE, 0);
+    a.cx = a.cy = a.cz = a.dist = NAN;
+    a.w[0] = a.w[1] = a.w[2] = 0.f;
+    a.pv[0] = a.pv[1] = a.pv[2] = -1;
+    return a;
+}
+
+P2M_HD uint8_t domain_status(const MeshView& m, float qx, float qy, float qz) {
+    return (qx < m.dlo[0] || qy < m.dlo[1] || qz < m.dlo[2] || qx > m.dhi[0] || qy > m.dhi[1] || qz > m.dhi[2]) ? 1 : 0;
+}
+
+// Steps 2-3 given the nearest vertex: list scan and the resolved answer.
+P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const Nearest& nv, ScanCounters& cnt) {
+    Answer a;
     // running minimum over v and v's list; kind/id/code of the best
     float best = nv.d2;
     int best_kind = KIND_VERTEX;
@@ -276,9 +300,9 @@ P2M_HD Answer p2m_query_point(const MeshView& m, float qx, float qy, float qz, u
     for (uint32_t k = f0; k < f1; ++k) {
         const int32_t f = m.ent[k];
         const float4 A = m.tri[3 * f], B = m.tri[3 * f + 1], C = m.tri[3 * f + 2];
-        float w[3];
+        float w0, w1, w2, cx, cy, cz;
         int r;
-        const float d = tri_d2(qx, qy, qz, A, B, C, w, r);
+        const float d = tri_d2(qx, qy, qz, A, B, C, w0, w1, w2, r, cx, cy, cz);
         if (d < best) {
             best = d;
             best_kind = KIND_FACE;
@@ -313,44 +337,56 @@ P2M_HD Answer p2m_query_point(const MeshView& m, float qx, float qy, float qz, u
             a.pv[0] = as_int(A.w);
             a.pv[1] = as_int(B.w);
         } else {
-            const float4& P = r == 1 ? A : B;
-            a.prim = make_prim(KIND_VERTEX, as_int(P.w));
-            a.cx = P.x;
-            a.cy = P.y;
-            a.cz = P.z;
-            a.pv[0] = as_int(P.w);
+            const int32_t pid = as_int(r == 1 ? A.w : B.w);
+            a.prim = make_prim(KIND_VERTEX, pid);
+            a.cx = r == 1 ? A.x : B.x;
+            a.cy = r == 1 ? A.y : B.y;
+            a.cz = r == 1 ? A.z : B.z;
+            a.pv[0] = pid;
         }
     } else {
-        const float4 C3[3] = {m.tri[3 * best_id], m.tri[3 * best_id + 1], m.tri[3 * best_id + 2]};
-        float w[3];
+        const float4 A = m.tri[3 * best_id], B = m.tri[3 * best_id + 1], C = m.tri[3 * best_id + 2];
+        float w0, w1, w2;
         int r;
-        tri_d2(qx, qy, qz, C3[0], C3[1], C3[2], w, r);
-        a.cx = w[0] * C3[0].x + w[1] * C3[1].x + w[2] * C3[2].x;
-        a.cy = w[0] * C3[0].y + w[1] * C3[1].y + w[2] * C3[2].y;
-        a.cz = w[0] * C3[0].z + w[1] * C3[1].z + w[2] * C3[2].z;
+        tri_d2(qx, qy, qz, A, B, C, w0, w1, w2, r, a.cx, a.cy, a.cz);
+        const int32_t ia = as_int(A.w), ib = as_int(B.w), ic = as_int(C.w);
         if (r == 0) {
             a.prim = make_prim(KIND_FACE, best_id);
-            for (int i = 0; i < 3; ++i) {
-                a.w[i] = w[i];
-                a.pv[i] = as_int(C3[i].w);
-            }
+            a.w[0] = w0;
+            a.w[1] = w1;
+            a.w[2] = w2;
+            a.pv[0] = ia;
+            a.pv[1] = ib;
+            a.pv[2] = ic;
         } else if (r <= 3) {
-            const int s = r - 1, i0 = s, i1 = (s + 1) % 3;
-            a.prim = make_prim(KIND_EDGE, m.fedge[4 * best_id + s]);
-            a.w[0] = w[i0];
-            a.w[1] = w[i1];
-            a.pv[0] = as_int(C3[i0].w);
-            a.pv[1] = as_int(C3[i1].w);
+            const int side = r - 1;  // from corner side to corner side+1
+            a.prim = make_prim(KIND_EDGE, m.fedge[4 * best_id + side]);
+            a.w[0] = side == 0 ? w0 : (side == 1 ? w1 : w2);
+            a.w[1] = side == 0 ? w1 : (side == 1 ? w2 : w0);
+            a.pv[0] = side == 0 ? ia : (side == 1 ? ib : ic);
+            a.pv[1] = side == 0 ? ib : (side == 1 ? ic : ia);
         } else {
-            const int c = r - 4;
-            a.prim = make_prim(KIND_VERTEX, as_int(C3[c].w));
-            a.cx = C3[c].x;
-            a.cy = C3[c].y;
-            a.cz = C3[c].z;
-            a.pv[0] = as_int(C3[c].w);
+            const int corner = r - 4;
+            const int32_t pid = corner == 0 ? ia : (corner == 1 ? ib : ic);
+            a.prim = make_prim(KIND_VERTEX, pid);
+            a.cx = corner == 0 ? A.x : (corner == 1 ? B.x : C.x);
+            a.cy = corner == 0 ? A.y : (corner == 1 ? B.y : C.y);
+            a.cz = corner == 0 ? A.z : (corner == 1 ? B.z : C.z);
+            a.pv[0] = pid;
         }
     }
     return a;
+}
+
+// The whole query for one point (per-lane KD-tree search).
+P2M_HD Answer p2m_query_point(const MeshView& m, float qx, float qy, float qz, uint8_t& status, ScanCounters& cnt) {
+    if (!finite3(qx, qy, qz)) {
+        status = 2;
+        return nonfinite_answer();
+    }
+    status = domain_status(m, qx, qy, qz);
+    const Nearest nv = kdt_nearest(m.node, m.nv, qx, qy, qz, cnt.nodes);
+    return p2m_answer(m, qx, qy, qz, nv, cnt);
 }
 
 }  // namespace p2m

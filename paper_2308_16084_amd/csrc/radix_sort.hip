@@ -132,8 +132,10 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
         if (valid) {
             uint32_t pos = base[d] + rank;
             for (int k = 0; k < w; ++k) pos += wc[k][d];
-            kout[pos] = key;
-            vout[pos] = val;
+            if (pos < (uint64_t)n) {
+                kout[pos] = key;
+                vout[pos] = val;
+            }
         }
         __syncthreads();
         uint32_t tot = 0;

@@ -58,7 +58,8 @@ def test_c1_unsorted_and_block_sizes_identical(c1):
     """Ordering and launch shape change which lane runs a query, never its answer."""
     w, m, om, ans = c1
     ref = _run(m, w.Q)
-    for kw in ({"sort": False}, {"block_size": 64}, {"block_size": 1024, "sort": False}):
+    for kw in ({"sort": False}, {"block_size": 64}, {"block_size": 128, "sort": False}, {"traversal": 1},
+               {"traversal": 2}, {"traversal": 2, "sort": False}):
         print("case: c1", kw, flush=True)
         out = _run(m, w.Q, **kw)
         for k in ("prim", "closest", "dist"):
@@ -125,15 +126,22 @@ def test_order_bit_exact(c1, n):
     assert np.array_equal(perm.cpu().numpy(), rp)
 
 
-def test_nearest_vertex_brute_force(c1):
+@pytest.mark.parametrize("traversal", [1, 2])
+@pytest.mark.parametrize("ordered", [False, True])
+def test_nearest_vertex_brute_force(c1, traversal, ordered):
+    """Both tree walks return the exact nearest vertex, on scattered and on
+    Morton-ordered batches."""
     torch = _torch()
     w, m, om, _ = c1
-    vid, d2 = m.nearest_vertex(torch.from_numpy(w.Q).cuda())
+    Q = w.Q
+    if ordered:
+        Q = Q[OM.order(Q, w.domain_lo, w.domain_hi)[1]]
+    vid, d2 = m.nearest_vertex(torch.from_numpy(np.ascontiguousarray(Q)).cuda(), traversal=traversal)
     torch.cuda.synchronize()
     vid = vid.cpu().numpy()
-    D = ((w.Q.astype(np.float64)[:, None, :] - om.V[None]) ** 2).sum(-1)
+    D = ((Q.astype(np.float64)[:, None, :] - om.V[None]) ** 2).sum(-1)
     best = D.min(1)
-    got = D[np.arange(len(w.Q)), vid]
+    got = D[np.arange(len(Q)), vid]
     # exact nearest, or a tie within float64 rounding of the squared distance
     assert np.all(got <= best * (1 + 1e-12) + 1e-300)
 
@@ -154,6 +162,8 @@ def test_edge_cases(c1):
     assert out["dist"][3] >= a["dist"][1] - 1e-5 * om.diag  # an upper bound outside the domain
     with pytest.raises(TypeError):
         m.query(torch.zeros((4, 3), dtype=torch.float64, device="cuda"))
+    with pytest.raises(P.P2MError):
+        m.query(torch.zeros((4, 3), dtype=torch.float32, device="cuda"), block_size=1024)
     with pytest.raises(P.P2MError):
         P.Mesh(TETRA_V, TETRA_F).upload(0)  # before precompute
 
@@ -187,5 +197,10 @@ def test_c2_full_size_sampled(c2_full):
     print("case: c2 sampled parity", flush=True)
     fails, out = _sampled_parity(w, m, 1500, 77)
     assert fails == []
+    out1 = _run(m, w.Q[:200_000], traversal=1)
+    out2 = _run(m, w.Q[:200_000], traversal=2)
+    # the two tree walks agree on the nearest vertex up to float64 ties
+    assert np.mean(out1["prim"] == out2["prim"]) > 0.9999
+    assert np.max(np.abs(out1["dist"] - out2["dist"])) <= 1e-5 * 3.8
     assert np.all(np.isfinite(out["dist"])) and np.all(out["dist"] >= 0)
     assert np.all(out["status"] == 0)

@@ -208,9 +208,11 @@ def test_table_completeness_dense_sampling():
 
 def test_out_of_domain_and_nonfinite_flags():
     m, _, dom = _mesh(TETRA_V, TETRA_F, scale=2.0)
-    Q = np.array([[0.2, 0.2, 0.2], [50, 0, 0], [np.nan, 0, 0]], np.float32)
+    Q = np.array([[0.2, 0.2, 0.2], [50, 0, 0], [np.nan, 0, 0], [1e20, 0, 0]], np.float32)
     h = m.query_host(Q)
-    assert h["status"].tolist() == [0, P.OUT_OF_DOMAIN, P.NONFINITE]
+    assert h["status"].tolist() == [0, P.OUT_OF_DOMAIN, P.NONFINITE, P.OUT_OF_DOMAIN]
+    # squared distances overflow float32 here; the answer is still a vertex
+    assert P.prim_type(h["prim"][3]) == P.VERTEX
     assert np.isnan(h["dist"][2]) and P.prim_type(h["prim"][2]) == P.NONE
     assert abs(h["dist"][1] - 49.0) < 1e-4  # still a valid distance (to vertex (1,0,0))
 
