@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--queries", type=int, default=10_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
+    ap.add_argument("--batched-full", action="store_true",
+                    help="batched leg on all 256 meshes (default: the first 64 of the same seeded plan)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB-in / 1 GiB-out elementwise copy kernel (counter calibration)")
     ap.add_argument("--cache", default=os.environ.get("P2M_CACHE_DIR", ""),
@@ -229,6 +232,68 @@ def main():
         result["fwd_bwd"] = {"value": round(n5 / (ms_fb / 1e3), 1), "unit": "queries/s", "ms_per_step": round(ms_fb, 4),
                              "workload": "same mesh, 1e6 near-surface queries, loss = sum d^2, grads wrt q [1e6,3] and V [655362,3]"}
         log(f"[bench] fwd+bwd: {ms_fb:.3f} ms/step, {n5 / (ms_fb / 1e3) / 1e9:.3f} Gq/s")
+
+    if not args.no_batched:
+        count = 256 if args.batched_full else 64
+        t0 = time.time()
+        plan = C.c4_plan()[:count]
+        works = [C.c4_mesh(e) for e in plan]
+        t_gen = time.time() - t0
+        t0 = time.time()
+        meshes = P.precompute_many([(x.V, x.F, (x.domain_lo, x.domain_hi)) for x in works], args.cache or None)
+        t_pre4 = time.time() - t0
+        Qb = np.concatenate([x.Q for x in works])
+        offb = np.concatenate([[0], np.cumsum([len(x.Q) for x in works])]).astype(np.int64)
+        nb = int(offb[-1])
+        qb = torch.from_numpy(Qb).to(dev)
+        batch = P.Batch(meshes, 0)
+        outb = batch.query(qb, offb, graph=False)
+        torch.cuda.synchronize()
+        shape = batch.autotune(qb, offb, out=outb)
+        for _ in range(args.warmup):
+            batch.query(qb, offb, out=outb)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            batch.query(qb, offb, out=outb)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_b = e0.elapsed_time(e1) / args.steps
+        # the same work as one plain launch sequence per mesh
+        for m_ in meshes:
+            m_.upload(0)
+        outs = [{"prim": outb["prim"][offb[k]:offb[k + 1]], "closest": outb["closest"][offb[k]:offb[k + 1]],
+                 "dist": outb["dist"][offb[k]:offb[k + 1]]} for k in range(count)]
+        qsl = [qb[offb[k]:offb[k + 1]] for k in range(count)]
+
+        def plain_all():
+            for k in range(count):
+                if offb[k + 1] > offb[k]:
+                    meshes[k].query(qsl[k], out=outs[k])
+
+        for _ in range(args.warmup):
+            plain_all()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            plain_all()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_p = e0.elapsed_time(e1) / args.steps
+        ntri = int(sum(len(x.F) for x in works))
+        result["batched"] = {"value": round(nb / (ms_b / 1e3), 1), "unit": "queries/s", "ms_per_step": round(ms_b, 4),
+                             "plain_launches": {"value": round(nb / (ms_p / 1e3), 1), "ms_per_step": round(ms_p, 4),
+                                                "launches": count},
+                             "speedup_vs_plain": round(ms_p / ms_b, 3),
+                             "shape": {"block": shape[0], "queries_per_lane": shape[1],
+                                       "traversal": "wave" if shape[2] == 2 else "per-lane"},
+                             "workload": (f"{'all' if args.batched_full else 'first'} {count} meshes of the seeded 256-mesh plan "
+                                          f"(displaced geodesic spheres / heightfields, log-uniform sizes): {ntri} triangles, "
+                                          f"{nb} queries (log-uniform per mesh, mixed uniform/near-surface); one graph launch"),
+                             "host_precompute_s": round(t_pre4, 1), "generate_s": round(t_gen, 1)}
+        log(f"[bench] batched ({count} meshes, {ntri} tris, {nb} queries): {ms_b:.3f} ms graph vs {ms_p:.3f} ms "
+            f"for {count} plain launches; shape {shape}; precompute {t_pre4:.1f}s")
+        del batch, meshes, qb, outb, outs, qsl
 
     if not args.no_cpu:
         import oracle

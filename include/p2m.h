@@ -194,26 +194,40 @@ p2m_status p2m_query_backward(p2m_mesh* m, const float* q_dev, int64_t n, const 
 
 /* ------------------------------------------------------------- batching */
 
-/* Pack uploaded-or-not meshes (each precomputed, all for `device`) into one
- * device arena for a single persistent launch over all of them.  The
- * meshes must outlive the batch. */
+/* Pack precomputed meshes (not necessarily uploaded) into one device arena
+ * on `device` for a single persistent launch over all of them.  The copies
+ * are complete when the call returns; the meshes may be destroyed after. */
 p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, void* stream, p2m_batch** out);
 void p2m_batch_destroy(p2m_batch* b);
 
-/* Query all meshes in one launch: q_dev float [N*3] holds the queries of
- * mesh k at rows q_offsets_host[k] .. q_offsets_host[k+1] (host int64
- * [count+1], q_offsets_host[0] = 0, N = q_offsets_host[count]).  Outputs as
- * p2m_query, in the same row order.  The first call for a given offset
- * layout captures the launch sequence into a HIP graph on `stream`; later
- * calls with the same layout replay it. */
+/* Query all meshes in one persistent launch: q_dev float [N*3] holds the
+ * queries of mesh k at rows q_offsets_host[k] .. q_offsets_host[k+1] (host
+ * int64 [count+1], q_offsets_host[0] = 0, non-decreasing, N =
+ * q_offsets_host[count]).  Outputs (device) as p2m_query, in the same row
+ * order; primitive ids are local to each mesh.  The launch sequence
+ * (ordering keys and sort, work-counter reset, persistent kernel) is
+ * captured into a HIP graph on first use and replayed while the offsets,
+ * pointers and launch shape stay the same.  A new offset layout uploads a
+ * tile list and waits for that copy.  Calls on one batch must not overlap. */
 p2m_status p2m_batch_query(p2m_batch* b, const float* q_dev, const int64_t* q_offsets_host, int32_t* prim_dev,
                            float* closest_dev, float* dist_dev, void* stream);
 
-/* Time candidate launch shapes (block size, queries per lane) of the batched
- * kernel on the given queries and keep the fastest; *best_block and
- * *best_qpl (may be NULL) report the choice.  Synchronises the stream. */
+/* The same work enqueued directly on `stream` (no graph). */
+p2m_status p2m_batch_query_eager(p2m_batch* b, const float* q_dev, const int64_t* q_offsets_host, int32_t* prim_dev,
+                                 float* closest_dev, float* dist_dev, void* stream);
+
+/* Launch shape of the persistent kernel: workgroup size (64, 128, 192 or
+ * 256), queries per lane in a tile (1..16), KD-tree walk (1 per lane, 2
+ * wavefront-coherent). */
+p2m_status p2m_batch_set_shape(p2m_batch* b, int block, int queries_per_lane, int traversal);
+p2m_status p2m_batch_get_shape(const p2m_batch* b, int* block, int* queries_per_lane, int* traversal);
+
+/* Time every launch shape in {64,128,256} x {1,2,4} x {1,2} on these queries
+ * (eager launches, two timed runs after a warm-up each) and keep the fastest;
+ * the best_* outputs (may be NULL) report it.  Synchronises the stream. */
 p2m_status p2m_batch_autotune(p2m_batch* b, const float* q_dev, const int64_t* q_offsets_host, int32_t* prim_dev,
-                              float* closest_dev, float* dist_dev, void* stream, int* best_block, int* best_qpl);
+                              float* closest_dev, float* dist_dev, void* stream, int* best_block,
+                              int* best_queries_per_lane, int* best_traversal);
 
 #ifdef __cplusplus
 }

@@ -63,7 +63,10 @@ _SIGS = {
     "p2m_batch_create": (INT, [P, I32, INT, P, P]),
     "p2m_batch_destroy": (None, [P]),
     "p2m_batch_query": (INT, [P, P, P, P, P, P, P]),
-    "p2m_batch_autotune": (INT, [P, P, P, P, P, P, P, P, P]),
+    "p2m_batch_query_eager": (INT, [P, P, P, P, P, P, P]),
+    "p2m_batch_set_shape": (INT, [P, INT, INT, INT]),
+    "p2m_batch_get_shape": (INT, [P, P, P, P]),
+    "p2m_batch_autotune": (INT, [P, P, P, P, P, P, P, P, P, P]),
 }
 
 STATUS = {0: "P2M_OK", -1: "P2M_ERR_ARG", -2: "P2M_ERR_MESH", -3: "P2M_ERR_STATE", -4: "P2M_ERR_OOM",
@@ -87,8 +90,6 @@ def lib():
                                "(there is no fallback path)")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
-            if not hasattr(L, name):
-                continue
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args

@@ -256,6 +256,87 @@ class Mesh:
         return gq, grad_V
 
 
+class Batch:
+    """Many precomputed meshes in one device arena, queried in one launch."""
+
+    def __init__(self, meshes, device: int = 0, stream=None):
+        self._h = ctypes.c_void_p(0)
+        self.meshes = list(meshes)
+        arr = (ctypes.c_void_p * len(self.meshes))(*[m.handle.value for m in self.meshes])
+        check(lib().p2m_batch_create(arr, len(self.meshes), int(device), _stream(stream), ctypes.byref(self._h)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().p2m_batch_destroy(h)
+            except Exception:
+                pass
+            self._h = ctypes.c_void_p(0)
+
+    @staticmethod
+    def _offsets(q_offsets):
+        off = np.ascontiguousarray(np.asarray(q_offsets, dtype=np.int64))
+        return off
+
+    def _outs(self, q, out):
+        torch = _torch()
+        n = q.shape[0]
+        if out is None:
+            out = {"prim": torch.empty(n, dtype=torch.int32, device=q.device),
+                   "closest": torch.empty((n, 3), dtype=torch.float32, device=q.device),
+                   "dist": torch.empty(n, dtype=torch.float32, device=q.device)}
+        return out
+
+    def query(self, q, q_offsets, out: dict | None = None, graph: bool = True, stream=None) -> dict:
+        torch = _torch()
+        q = _dev_tensor(q, torch.float32, (3,), "q")
+        off = self._offsets(q_offsets)
+        if off.shape[0] != len(self.meshes) + 1 or off[-1] != q.shape[0]:
+            raise ValueError("q_offsets must have len(meshes)+1 entries ending at len(q)")
+        out = self._outs(q, out)
+        fn = lib().p2m_batch_query if graph else lib().p2m_batch_query_eager
+        check(fn(self._h, _ptr(q), _ptr(off), _ptr(out["prim"]), _ptr(out["closest"]), _ptr(out["dist"]),
+                 _stream(stream)))
+        return out
+
+    def set_shape(self, block: int, queries_per_lane: int, traversal: int) -> None:
+        check(lib().p2m_batch_set_shape(self._h, int(block), int(queries_per_lane), int(traversal)))
+
+    def shape(self) -> tuple[int, int, int]:
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib().p2m_batch_get_shape(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def autotune(self, q, q_offsets, out: dict | None = None, stream=None) -> tuple[int, int, int]:
+        torch = _torch()
+        q = _dev_tensor(q, torch.float32, (3,), "q")
+        off = self._offsets(q_offsets)
+        out = self._outs(q, out)
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib().p2m_batch_autotune(self._h, _ptr(q), _ptr(off), _ptr(out["prim"]), _ptr(out["closest"]),
+                                       _ptr(out["dist"]), _stream(stream), ctypes.byref(a), ctypes.byref(b),
+                                       ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+
+def precompute_many(items, cache_dir: str | None = None, workers: int = 0, **kw) -> list:
+    """Precompute several meshes concurrently (one host thread each; the C
+    calls release the interpreter lock).  items: (V, F, domain) tuples.
+    Returns the Mesh objects in the same order."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    if workers <= 0:
+        workers = max(1, len(os.sched_getaffinity(0)))
+
+    def one(it):
+        V, F, dom = it
+        return Mesh.cached(V, F, dom, cache_dir, threads=1, **kw)[0]
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(one, items))
+
+
 def _make_function():
     torch = _torch()
 
@@ -299,5 +380,5 @@ def p2m_distance(q, V, mesh):
     return _P2MDistance.apply(q, V, mesh)
 
 
-__all__ = ["Mesh", "p2m_distance", "P2MError", "prim_type", "prim_id", "VERTEX", "EDGE", "FACE", "NONE",
+__all__ = ["Mesh", "Batch", "precompute_many", "p2m_distance", "P2MError", "prim_type", "prim_id", "VERTEX", "EDGE", "FACE", "NONE",
            "OUT_OF_DOMAIN", "NONFINITE", "TABLE_FLOODING", "TABLE_ALL_PAIRS", "TABLE_EVERYTHING", "_lib"]

@@ -16,7 +16,7 @@ ARCH = "gfx950"
 
 HOST_SOURCES = ["predicates.cpp", "delaunay.cpp", "convex_cell.cpp", "mesh.cpp", "kdtree.cpp",
                 "interception.cpp", "p2m_host.cpp"]
-DEVICE_SOURCES = ["p2m_device.hip", "radix_sort.hip"]
+DEVICE_SOURCES = ["p2m_device.hip", "radix_sort.hip", "p2m_batch.hip"]
 
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-parameter",
               "-ffp-contract=off"]

@@ -1,0 +1,522 @@
+// Batched P2M queries: many meshes of uneven size with uneven query counts
+// served by one persistent launch over a packed arena, captured in a HIP
+// graph, with the launch shape chosen by a small autotuner.
+//
+// Ordering: key = mesh index in the high bits, then a Morton code of the
+// query inside that mesh's domain box; one stable radix sort groups each
+// mesh's queries (already contiguous) and orders them spatially.
+// Work list: tiles (mesh, first sorted position, count) of block x qpl
+// queries, meshes with the most work first; each workgroup of the
+// persistent kernel takes the next tile from an atomic counter until the
+// list is exhausted, so every workgroup reaches the exit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "device_common.hpp"
+#include "p2m_internal.hpp"
+#include "query_core.hpp"
+#include "wave_kdtree.hpp"
+
+namespace p2m {
+
+void pack_mesh(MeshState& s);
+MeshView host_view(const MeshState& s);
+
+struct BatchMesh {
+    int64_t node, off, ent, seg, tri, fedge;  // element offsets into the typed arenas
+    int32_t nv;
+    int32_t pad;
+    float dlo[3], dhi[3];  // domain rounded outward (status flag)
+    float mlo[3], msc[3];  // Morton quantisation of the domain
+};
+
+struct Tile {
+    int32_t mesh, start, count, pad;
+};
+
+}  // namespace p2m
+
+struct p2m_batch {
+    int device = -1;
+    int32_t count = 0;
+    int key_bits = 0;  // Morton bits per axis
+    void* base = nullptr;
+    int64_t bytes = 0;
+    p2m::KdNode* node = nullptr;
+    uint32_t* off = nullptr;
+    int32_t* ent = nullptr;
+    float4* seg = nullptr;
+    float4* tri = nullptr;
+    int32_t* fedge = nullptr;
+    p2m::BatchMesh* desc = nullptr;
+    std::vector<double> cost;  // per-mesh cost weight (log of vertex count)
+    // per query layout
+    std::vector<int64_t> layout;
+    int64_t n = 0;
+    void* work = nullptr;  // qoff int64 [count+1], tiles, counter, sort scratch
+    int64_t work_bytes = 0;
+    int64_t* qoff = nullptr;
+    p2m::Tile* tiles = nullptr;
+    int64_t ntiles = 0;
+    uint32_t* counter = nullptr;
+    void* scratch = nullptr;
+    int tile_block = 0, tile_qpl = 0;
+    // launch shape
+    int block = 256, qpl = 1, traversal = 2;
+    int grid = 0;
+    // captured graph
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* g_ptrs[4] = {nullptr, nullptr, nullptr, nullptr};
+    int g_shape[3] = {0, 0, 0};
+};
+
+namespace p2m {
+
+namespace {
+
+int64_t up256(int64_t x) { return (x + 255) / 256 * 256; }
+
+__global__ void k_batch_keys(const float* __restrict__ q, int64_t n, const int64_t* __restrict__ qoff, int32_t count,
+                             const BatchMesh* __restrict__ desc, int bits, uint32_t* __restrict__ keys,
+                             int32_t* __restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // mesh k with qoff[k] <= i < qoff[k+1]
+    int32_t lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (qoff[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    const BatchMesh& d = desc[lo];
+    const float qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
+    const uint32_t full = morton30(qx, qy, qz, d.mlo[0], d.mlo[1], d.mlo[2], d.msc[0], d.msc[1], d.msc[2]);
+    const uint32_t code = full >> (30 - 3 * bits);  // keep the top `bits` bits per axis
+    keys[i] = ((uint32_t)lo << (3 * bits)) | code;
+    vals[i] = (int32_t)i;
+}
+
+__global__ void k_reset(uint32_t* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0u;
+}
+
+template <bool kWave>
+__global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
+    const KdNode* __restrict__ node, const uint32_t* __restrict__ off, const int32_t* __restrict__ ent,
+    const float4* __restrict__ seg, const float4* __restrict__ tri, const int32_t* __restrict__ fedge,
+    const BatchMesh* __restrict__ desc, const Tile* __restrict__ tiles, int64_t ntiles, uint32_t* counter, int qpl,
+    const float* __restrict__ q, const int32_t* __restrict__ perm, int64_t n, int32_t* __restrict__ prim,
+    float* __restrict__ closest, float* __restrict__ dist) {
+    __shared__ int64_t s_tile;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int64_t t = s_tile;
+        __syncthreads();
+        if (t >= ntiles) break;  // uniform across the workgroup
+        const Tile T = tiles[t];
+        const BatchMesh& d = desc[T.mesh];
+        MeshView v;
+        v.node = node + d.node;
+        v.nv = d.nv;
+        v.off = off + d.off;
+        v.ent = ent + d.ent;
+        v.seg = seg + d.seg;
+        v.tri = tri + d.tri;
+        v.fedge = fedge + d.fedge;
+        for (int k = 0; k < 3; ++k) {
+            v.dlo[k] = d.dlo[k];
+            v.dhi[k] = d.dhi[k];
+        }
+        for (int r = 0; r < qpl; ++r) {
+            const int64_t local = (int64_t)r * blockDim.x + threadIdx.x;
+            const int64_t j = (int64_t)T.start + local;
+            int64_t i = (local < T.count && j < n) ? (int64_t)perm[j] : -1;
+            if (i >= n) i = -1;
+            float qx = 0.f, qy = 0.f, qz = 0.f;
+            if (i >= 0) {
+                qx = q[3 * i];
+                qy = q[3 * i + 1];
+                qz = q[3 * i + 2];
+            }
+            const bool fin = finite3(qx, qy, qz);
+            Nearest nv;
+            ScanCounters c;
+            if (kWave) {
+                nv = kdt_nearest_wave(v.node, v.nv, qx, qy, qz, i >= 0 && fin);
+            } else if (i >= 0 && fin) {
+                nv = kdt_nearest(v.node, v.nv, qx, qy, qz, c.nodes);
+            }
+            if (i >= 0) {
+                const Answer a = fin ? p2m_answer(v, qx, qy, qz, nv, c) : nonfinite_answer();
+                prim[i] = a.prim;
+                closest[3 * i] = a.cx;
+                closest[3 * i + 1] = a.cy;
+                closest[3 * i + 2] = a.cz;
+                dist[i] = a.dist;
+            }
+        }
+    }
+}
+
+void drop_graph(p2m_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+p2m_status hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? P2M_ERR_OOM : P2M_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Work buffers and tile list for a query layout and launch shape.
+p2m_status prepare(p2m_batch* b, const int64_t* qoff_host, hipStream_t st) {
+    std::vector<int64_t> layout(qoff_host, qoff_host + b->count + 1);
+    if (layout[0] != 0) return fail(P2M_ERR_ARG, "q_offsets[0] must be 0");
+    for (int32_t k = 0; k < b->count; ++k)
+        if (layout[(size_t)k + 1] < layout[(size_t)k]) return fail(P2M_ERR_ARG, "q_offsets must be non-decreasing");
+    const int64_t n = layout.back();
+    if (n > (int64_t)INT32_MAX) return fail(P2M_ERR_ARG, "more than 2^31-1 queries in one batch");
+    const bool same_layout = layout == b->layout;
+    if (same_layout && b->tile_block == b->block && b->tile_qpl == b->qpl) return P2M_OK;
+    drop_graph(b);
+    RadixPlan plan = radix_plan(std::max<int64_t>(n, 1));
+    const int64_t tsize = (int64_t)b->block * b->qpl;
+    std::vector<int64_t> order((size_t)b->count);
+    std::iota(order.begin(), order.end(), 0);
+    // most work first: queries x log(vertices)
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+        double wx = (double)(layout[(size_t)x + 1] - layout[(size_t)x]) * b->cost[(size_t)x];
+        double wy = (double)(layout[(size_t)y + 1] - layout[(size_t)y]) * b->cost[(size_t)y];
+        return wx > wy;
+    });
+    std::vector<Tile> tiles;
+    for (int64_t k : order)
+        for (int64_t s = layout[(size_t)k]; s < layout[(size_t)k + 1]; s += tsize)
+            tiles.push_back(Tile{(int32_t)k, (int32_t)s, (int32_t)std::min(tsize, layout[(size_t)k + 1] - s), 0});
+    const int64_t need = up256(8 * (int64_t)(b->count + 1)) + up256((int64_t)sizeof(Tile) * std::max<size_t>(1, tiles.size())) +
+                         256 + plan.bytes;
+    if (need > b->work_bytes) {
+        if (b->work) (void)hipFree(b->work);
+        b->work = nullptr;
+        b->work_bytes = 0;
+        hipError_t e = hipMalloc(&b->work, (size_t)need);
+        if (e != hipSuccess) return hip_fail(e, "batch work buffers");
+        b->work_bytes = need;
+    }
+    char* p = (char*)b->work;
+    b->qoff = (int64_t*)p;
+    p += up256(8 * (int64_t)(b->count + 1));
+    b->tiles = (Tile*)p;
+    p += up256((int64_t)sizeof(Tile) * std::max<size_t>(1, tiles.size()));
+    b->counter = (uint32_t*)p;
+    p += 256;
+    b->scratch = p;
+    hipError_t e = hipMemcpyAsync(b->qoff, layout.data(), 8 * layout.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !tiles.empty())
+        e = hipMemcpyAsync(b->tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // host staging goes out of scope
+    if (e != hipSuccess) return hip_fail(e, "batch layout upload");
+    b->layout = layout;
+    b->n = n;
+    b->ntiles = (int64_t)tiles.size();
+    b->tile_block = b->block;
+    b->tile_qpl = b->qpl;
+    return P2M_OK;
+}
+
+// Enqueue the whole batched query (keys, sort, counter reset, persistent kernel).
+p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, float* dist, hipStream_t st) {
+    const int64_t n = b->n;
+    if (n == 0) return P2M_OK;
+    RadixPlan plan = radix_plan(n);
+    RadixBuffers rb = radix_buffers(plan, b->scratch);
+    k_batch_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(q, n, b->qoff, b->count, b->desc, b->key_bits,
+                                                              rb.keys[0], rb.vals[0]);
+    const int cur = radix_sort_pairs(plan, rb, 32, st);
+    k_reset<<<1, 64, 0, st>>>(b->counter);
+    int grid = b->grid;
+    if (b->traversal == 2)
+        k_batch_query<true><<<grid, b->block, 0, st>>>(b->node, b->off, b->ent, b->seg, b->tri, b->fedge, b->desc,
+                                                       b->tiles, b->ntiles, b->counter, b->qpl, q, rb.vals[cur], n,
+                                                       prim, closest, dist);
+    else
+        k_batch_query<false><<<grid, b->block, 0, st>>>(b->node, b->off, b->ent, b->seg, b->tri, b->fedge, b->desc,
+                                                        b->tiles, b->ntiles, b->counter, b->qpl, q, rb.vals[cur], n,
+                                                        prim, closest, dist);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "batched query launch");
+    return P2M_OK;
+}
+
+p2m_status set_grid(p2m_batch* b) {
+    int dev = b->device, cus = 0, per = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "device attribute");
+    if (b->traversal == 2)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_batch_query<true>, b->block, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_batch_query<false>, b->block, 0);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    b->grid = std::max(1, cus * std::max(1, per));
+    return P2M_OK;
+}
+
+struct Guard {
+    int old = -1;
+    explicit Guard(int dev) {
+        if (hipGetDevice(&old) != hipSuccess) old = -1;
+        (void)hipSetDevice(dev);
+    }
+    ~Guard() {
+        if (old >= 0) (void)hipSetDevice(old);
+    }
+};
+
+}  // namespace
+
+}  // namespace p2m
+
+using namespace p2m;
+
+extern "C" {
+
+p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, void* stream, p2m_batch** out) {
+    if (!out) return fail(P2M_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!meshes || count < 1) return fail(P2M_ERR_ARG, "need at least one mesh");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(P2M_ERR_HIP, "no HIP device");
+    if (device < 0 || device >= ndev) return fail(P2M_ERR_ARG, "device index out of range");
+    for (int32_t k = 0; k < count; ++k) {
+        if (!meshes[k]) return fail(P2M_ERR_ARG, "NULL mesh in the batch");
+        if (!meshes[k]->s.precomputed) return fail(P2M_ERR_STATE, "batch mesh not precomputed");
+    }
+    int mesh_bits = 0;
+    while ((1 << mesh_bits) < count) ++mesh_bits;
+    if (mesh_bits > 26) return fail(P2M_ERR_ARG, "too many meshes in one batch");
+    Guard g(device);
+    p2m_batch* b = new p2m_batch();
+    b->device = device;
+    b->count = count;
+    b->key_bits = std::min(10, (32 - mesh_bits) / 3);
+    // host staging of the arena
+    std::vector<float> node, seg, tri;
+    std::vector<uint32_t> off;
+    std::vector<int32_t> ent, fedge;
+    std::vector<BatchMesh> desc((size_t)count);
+    b->cost.resize((size_t)count);
+    for (int32_t k = 0; k < count; ++k) {
+        MeshState& s = meshes[k]->s;
+        pack_mesh(s);
+        BatchMesh& d = desc[(size_t)k];
+        d.node = (int64_t)node.size() / 16;
+        d.off = (int64_t)off.size();
+        d.ent = (int64_t)ent.size();
+        d.seg = (int64_t)seg.size() / 4;
+        d.tri = (int64_t)tri.size() / 4;
+        d.fedge = (int64_t)fedge.size();
+        d.nv = (int32_t)s.m.nv;
+        d.pad = 0;
+        const MeshView hv = host_view(s);
+        float lo[3], sc[3];
+        morton_params(s.dlo, s.dhi, lo, sc);
+        for (int c = 0; c < 3; ++c) {
+            d.dlo[c] = hv.dlo[c];
+            d.dhi[c] = hv.dhi[c];
+            d.mlo[c] = lo[c];
+            d.msc[c] = sc[c];
+        }
+        node.insert(node.end(), s.pk_node.begin(), s.pk_node.end());
+        off.insert(off.end(), s.t.off.begin(), s.t.off.end());
+        ent.insert(ent.end(), s.t.ent.begin(), s.t.ent.end());
+        seg.insert(seg.end(), s.pk_seg.begin(), s.pk_seg.end());
+        tri.insert(tri.end(), s.pk_tri.begin(), s.pk_tri.end());
+        fedge.insert(fedge.end(), s.pk_fedge.begin(), s.pk_fedge.end());
+        b->cost[(size_t)k] = std::log2((double)s.m.nv + 2.0);
+    }
+    if (ent.size() >= (size_t)UINT32_MAX) {
+        delete b;
+        return fail(P2M_ERR_ARG, "batch tables exceed 2^32 entries");
+    }
+    const size_t sizes[7] = {4 * node.size(), 4 * off.size(), 4 * std::max<size_t>(1, ent.size()), 4 * seg.size(),
+                             4 * tri.size(), 4 * fedge.size(), sizeof(BatchMesh) * desc.size()};
+    size_t total = 0;
+    for (size_t x : sizes) total += (size_t)up256((int64_t)x);
+    hipError_t e = hipMalloc(&b->base, total);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "batch arena");
+    }
+    b->bytes = (int64_t)total;
+    char* p = (char*)b->base;
+    void* dst[7];
+    for (int i = 0; i < 7; ++i) {
+        dst[i] = p;
+        p += up256((int64_t)sizes[i]);
+    }
+    b->node = (KdNode*)dst[0];
+    b->off = (uint32_t*)dst[1];
+    b->ent = (int32_t*)dst[2];
+    b->seg = (float4*)dst[3];
+    b->tri = (float4*)dst[4];
+    b->fedge = (int32_t*)dst[5];
+    b->desc = (BatchMesh*)dst[6];
+    const void* src[7] = {node.data(), off.data(), ent.data(), seg.data(), tri.data(), fedge.data(), desc.data()};
+    const size_t nbytes[7] = {sizes[0], sizes[1], 4 * ent.size(), sizes[3], sizes[4], sizes[5], sizes[6]};
+    hipStream_t st = (hipStream_t)stream;
+    for (int i = 0; i < 7 && e == hipSuccess; ++i)
+        if (nbytes[i]) e = hipMemcpyAsync(dst[i], src[i], nbytes[i], hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // staging vectors are local
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        p2m_batch_destroy(b);
+        return hip_fail(e, "batch upload");
+    }
+    p2m_status r = set_grid(b);
+    if (r != P2M_OK) {
+        p2m_batch_destroy(b);
+        return r;
+    }
+    *out = b;
+    return P2M_OK;
+}
+
+void p2m_batch_destroy(p2m_batch* b) {
+    if (!b) return;
+    Guard g(b->device);
+    drop_graph(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->work) (void)hipFree(b->work);
+    if (b->base) (void)hipFree(b->base);
+    delete b;
+}
+
+p2m_status p2m_batch_set_shape(p2m_batch* b, int block, int qpl, int traversal) {
+    if (!b) return fail(P2M_ERR_ARG, "batch is NULL");
+    if (block < 64 || block > kQueryMaxBlock || block % 64) return fail(P2M_ERR_ARG, "block must be 64, 128, 192 or 256");
+    if (qpl < 1 || qpl > 16) return fail(P2M_ERR_ARG, "queries per lane must be in [1, 16]");
+    if (traversal != 1 && traversal != 2) return fail(P2M_ERR_ARG, "traversal must be 1 or 2");
+    Guard g(b->device);
+    if (b->block != block || b->qpl != qpl || b->traversal != traversal) drop_graph(b);
+    b->block = block;
+    b->qpl = qpl;
+    b->traversal = traversal;
+    return set_grid(b);
+}
+
+p2m_status p2m_batch_get_shape(const p2m_batch* b, int* block, int* qpl, int* traversal) {
+    if (!b) return fail(P2M_ERR_ARG, "batch is NULL");
+    if (block) *block = b->block;
+    if (qpl) *qpl = b->qpl;
+    if (traversal) *traversal = b->traversal;
+    return P2M_OK;
+}
+
+p2m_status p2m_batch_query(p2m_batch* b, const float* q, const int64_t* qoff, int32_t* prim, float* closest,
+                           float* dist, void* stream) {
+    if (!b) return fail(P2M_ERR_ARG, "batch is NULL");
+    if (!qoff) return fail(P2M_ERR_ARG, "q_offsets is NULL");
+    Guard g(b->device);
+    hipStream_t st = (hipStream_t)stream;
+    p2m_status r = prepare(b, qoff, st);
+    if (r != P2M_OK) return r;
+    if (b->n == 0) return P2M_OK;
+    if (!q || !prim || !closest || !dist) return fail(P2M_ERR_ARG, "NULL query or output pointer");
+    const void* ptrs[4] = {q, prim, closest, dist};
+    const int shape[3] = {b->block, b->qpl, b->traversal};
+    if (!b->exec || std::memcmp(ptrs, b->g_ptrs, sizeof(ptrs)) != 0 || std::memcmp(shape, b->g_shape, sizeof(shape)) != 0) {
+        drop_graph(b);
+        hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "graph capture begin");
+        r = enqueue(b, q, prim, closest, dist, b->cap_stream);
+        hipGraph_t gr = nullptr;
+        e = hipStreamEndCapture(b->cap_stream, &gr);
+        if (r != P2M_OK) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return r;
+        }
+        if (e != hipSuccess) return hip_fail(e, "graph capture end");
+        b->graph = gr;
+        e = hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(b);
+            return hip_fail(e, "graph instantiate");
+        }
+        std::memcpy(b->g_ptrs, ptrs, sizeof(ptrs));
+        std::memcpy(b->g_shape, shape, sizeof(shape));
+    }
+    hipError_t e = hipGraphLaunch(b->exec, st);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return P2M_OK;
+}
+
+p2m_status p2m_batch_query_eager(p2m_batch* b, const float* q, const int64_t* qoff, int32_t* prim, float* closest,
+                                 float* dist, void* stream) {
+    if (!b) return fail(P2M_ERR_ARG, "batch is NULL");
+    if (!qoff) return fail(P2M_ERR_ARG, "q_offsets is NULL");
+    Guard g(b->device);
+    hipStream_t st = (hipStream_t)stream;
+    p2m_status r = prepare(b, qoff, st);
+    if (r != P2M_OK) return r;
+    if (b->n == 0) return P2M_OK;
+    if (!q || !prim || !closest || !dist) return fail(P2M_ERR_ARG, "NULL query or output pointer");
+    return enqueue(b, q, prim, closest, dist, st);
+}
+
+p2m_status p2m_batch_autotune(p2m_batch* b, const float* q, const int64_t* qoff, int32_t* prim, float* closest,
+                              float* dist, void* stream, int* best_block, int* best_qpl, int* best_traversal) {
+    if (!b) return fail(P2M_ERR_ARG, "batch is NULL");
+    Guard g(b->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(P2M_ERR_HIP, "hipEventCreate");
+    const int blocks[3] = {64, 128, 256};
+    const int qpls[3] = {1, 2, 4};
+    const int travs[2] = {1, 2};
+    float best = INFINITY;
+    int bb = b->block, bq = b->qpl, bt = b->traversal;
+    p2m_status r = P2M_OK;
+    for (int tv : travs)
+        for (int bl : blocks)
+            for (int qp : qpls) {
+                if ((r = p2m_batch_set_shape(b, bl, qp, tv)) != P2M_OK) break;
+                float tot = 0.f;
+                for (int rep = 0; rep < 3 && r == P2M_OK; ++rep) {
+                    (void)hipEventRecord(e0, st);
+                    r = p2m_batch_query_eager(b, q, qoff, prim, closest, dist, stream);
+                    (void)hipEventRecord(e1, st);
+                    float ms = 0.f;
+                    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                        r = fail(P2M_ERR_HIP, "autotune timing");
+                    if (rep > 0) tot += ms;  // first run warms caches
+                }
+                if (r != P2M_OK) break;
+                if (tot < best) {
+                    best = tot;
+                    bb = bl;
+                    bq = qp;
+                    bt = tv;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r != P2M_OK) return r;
+    r = p2m_batch_set_shape(b, bb, bq, bt);
+    if (best_block) *best_block = bb;
+    if (best_qpl) *best_qpl = bq;
+    if (best_traversal) *best_traversal = bt;
+    return r;
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+"""Batched P2M: many meshes of uneven size in one persistent, graph-captured
+launch, against the oracle and against one plain launch per mesh."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import configs as C
+from tests._accept import check_answers
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def batch_setup():
+    import torch
+
+    import paper_2308_16084_amd as P
+    plan = C.c4_plan(count=12, tri_hi=2e4, q_hi=2e4)
+    works = [C.c4_mesh(e) for e in plan]
+    works[3].Q = works[3].Q[:0]            # a mesh with no queries
+    meshes = []
+    for w in works:
+        m = P.Mesh(w.V, w.F)
+        m.precompute(domain=(w.domain_lo, w.domain_hi))
+        meshes.append(m)
+    b = P.Batch(meshes, 0)
+    Q = np.concatenate([w.Q for w in works])
+    off = np.concatenate([[0], np.cumsum([len(w.Q) for w in works])]).astype(np.int64)
+    q = torch.from_numpy(Q).cuda()
+    return works, meshes, b, Q, off, q
+
+
+def _np(out):
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def test_batch_against_oracle(batch_setup):
+    import torch
+    works, meshes, b, Q, off, q = batch_setup
+    out = _np(b.query(q, off))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    for k, w in enumerate(works):
+        if len(w.Q) == 0:
+            continue
+        print(f"case: batch mesh {k} ({w.name}, {len(w.Q)} queries)", flush=True)
+        idx = np.sort(rng.choice(len(w.Q), size=min(64, len(w.Q)), replace=False))
+        rows = off[k] + idx
+        om = oracle.OracleMesh(w.V, w.F)
+        ans = om.query(w.Q[idx])
+        assert check_answers(om, w.Q[idx], ans, out["prim"][rows], out["closest"][rows], out["dist"][rows]) == []
+
+
+def test_batch_equals_plain_launches(batch_setup):
+    import torch
+    works, meshes, b, Q, off, q = batch_setup
+    ref = _np(b.query(q, off))
+    for k, (w, m) in enumerate(zip(works, meshes)):
+        if len(w.Q) == 0:
+            continue
+        m.upload(0)
+        o = _np(m.query(q[off[k]:off[k + 1]].contiguous(), traversal=1))
+        sl = slice(off[k], off[k + 1])
+        assert np.mean(o["prim"] == ref["prim"][sl]) > 0.999
+        assert np.max(np.abs(o["dist"] - ref["dist"][sl])) <= 1e-5 * w.diag
+
+
+def test_graph_replays_match_eager(batch_setup):
+    """Replay the captured graph several times, with eager work and
+    synchronisation in between; every replay equals the eager result."""
+    import torch
+    works, meshes, b, Q, off, q = batch_setup
+    eager = _np(b.query(q, off, graph=False))
+    torch.cuda.synchronize()
+    out = None
+    for r in range(4):
+        out = b.query(q, off, out=out)
+        torch.cuda.synchronize()
+        got = _np(out)
+        for key in ("prim", "closest", "dist"):
+            assert np.array_equal(got[key], eager[key]), (r, key)
+        junk = torch.randn(1 << 20, device="cuda") * 2.0   # unrelated eager work between replays
+        junk.sum().item()
+        for v in out.values():
+            v.fill_(-1)
+
+
+@pytest.mark.parametrize("shape", [(64, 1, 1), (128, 2, 2), (256, 4, 1), (192, 3, 2)])
+def test_launch_shapes_give_same_answers(batch_setup, shape):
+    works, meshes, b, Q, off, q = batch_setup
+    b.set_shape(256, 1, 2)
+    ref = _np(b.query(q, off))
+    b.set_shape(*shape)
+    got = _np(b.query(q, off))
+    assert np.mean(got["prim"] == ref["prim"]) > 0.999
+    assert np.max(np.abs(got["dist"] - ref["dist"])) <= 1e-5 * max(w.diag for w in works)
+
+
+def test_autotune_and_layout_change(batch_setup):
+    import torch
+    works, meshes, b, Q, off, q = batch_setup
+    ref = _np(b.query(q, off))
+    shape = b.autotune(q, off)
+    assert shape[0] in (64, 128, 256) and shape[1] in (1, 2, 4) and shape[2] in (1, 2)
+    got = _np(b.query(q, off))
+    assert np.mean(got["prim"] == ref["prim"]) > 0.999
+    # a different split of the same rows between meshes: only mesh 0 and 1 swap sizes
+    half = np.concatenate([[0], np.cumsum([len(w.Q) // 2 for w in works])]).astype(np.int64)
+    q2 = torch.cat([q[off[k]:off[k] + len(works[k].Q) // 2] for k in range(len(works))]).contiguous()
+    out2 = _np(b.query(q2, half))
+    for k in range(len(works)):
+        n2 = len(works[k].Q) // 2
+        assert np.array_equal(out2["dist"][half[k]:half[k] + n2], got["dist"][off[k]:off[k] + n2]) or \
+            np.max(np.abs(out2["dist"][half[k]:half[k] + n2] - got["dist"][off[k]:off[k] + n2])) <= 1e-6
