@@ -1,0 +1,111 @@
+"""Full-size workloads on the GPU: C3 (needle heightfield, 10^7 queries) and
+the batched C4 plan (first 64 meshes, as benchmarked), sampled against the
+FP64 oracle; C5 (10^6 near-surface queries on the C2 mesh) forward and
+backward against the oracle's closest points and gradients."""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import grad as OG
+from synth import configs as C
+from tests._accept import check_answers
+
+pytestmark = pytest.mark.gpu
+
+CACHE = os.environ.get("P2M_CACHE_DIR") or None
+
+
+def _np(out):
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def test_c3_full_size_sampled():
+    """Heightfield 1024 x 1024 with compressed rows (needles), 10^7 queries in
+    one sorted launch; 1,200 sampled rows against the oracle."""
+    import torch
+
+    import paper_2308_16084_amd as P
+    print("case: c3 build", flush=True)
+    w = C.c3()
+    m, _ = P.Mesh.cached(w.V, w.F, (w.domain_lo, w.domain_hi), CACHE)
+    m.upload(0)
+    q = torch.from_numpy(w.Q).cuda()
+    out = _np(m.query(q))
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(out["dist"])) and np.all(out["status"] == 0)
+    print("case: c3 oracle sample", flush=True)
+    rng = np.random.default_rng(33)
+    idx = np.sort(rng.choice(len(w.Q), size=1200, replace=False))
+    om = oracle.OracleMesh(w.V, w.F)
+    ans = om.query(w.Q[idx])
+    assert check_answers(om, w.Q[idx], ans, out["prim"][idx], out["closest"][idx], out["dist"][idx], idx=idx) == []
+
+
+def test_c4_subset_batched_sampled():
+    """First 64 meshes of the seeded C4 plan in one graph launch; 48 sampled
+    queries per mesh against the oracle."""
+    import torch
+
+    import paper_2308_16084_amd as P
+    print("case: c4 build", flush=True)
+    works = [C.c4_mesh(e) for e in C.c4_plan()[:64]]
+    meshes = P.precompute_many([(x.V, x.F, (x.domain_lo, x.domain_hi)) for x in works], CACHE)
+    b = P.Batch(meshes, 0)
+    Q = np.concatenate([x.Q for x in works])
+    off = np.concatenate([[0], np.cumsum([len(x.Q) for x in works])]).astype(np.int64)
+    out = _np(b.query(torch.from_numpy(Q).cuda(), off))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(44)
+    for k, x in enumerate(works):
+        idx = np.sort(rng.choice(len(x.Q), size=min(48, len(x.Q)), replace=False))
+        rows = off[k] + idx
+        om = oracle.OracleMesh(x.V, x.F)
+        fails = check_answers(om, x.Q[idx], om.query(x.Q[idx]), out["prim"][rows], out["closest"][rows],
+                              out["dist"][rows], idx=rows)
+        assert fails == [], (k, x.name, fails)
+
+
+def test_c5_forward_backward_vs_oracle():
+    """C5: the C2 mesh, 10^6 near-surface queries, loss = sum of d^2.  On 1,000
+    sampled queries: forward accepted by the oracle, grad_q = 2(q - c*) and
+    the vertex gradient of the sampled subset equal to the oracle gradient."""
+    import torch
+
+    import paper_2308_16084_amd as P
+    print("case: c5 build", flush=True)
+    w = C.c5()
+    m, _ = P.Mesh.cached(w.V, w.F, (w.domain_lo, w.domain_hi), CACHE)
+    m.upload(0)
+    q = torch.from_numpy(w.Q).cuda().requires_grad_(True)
+    Vt = torch.from_numpy(w.V).cuda().requires_grad_(True)
+    d, prim, c = P.p2m_distance(q, Vt, m)
+    (d * d).sum().backward()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(55)
+    S = np.sort(rng.choice(len(w.Q), size=1000, replace=False))
+    om = oracle.OracleMesh(w.V, w.F)
+    print("case: c5 oracle sample", flush=True)
+    ans = om.query(w.Q[S])
+    dn, pn, cn = d.detach().cpu().numpy(), prim.cpu().numpy(), c.detach().cpu().numpy()
+    assert check_answers(om, w.Q[S], ans, pn[S], cn[S], dn[S], idx=S) == []
+    tol = 1e-5 * om.diag
+    gq = q.grad.cpu().numpy().astype(np.float64)[S]
+    ogq, _ = OG.gradients(om, w.Q[S], ans, 2.0 * ans["dist"])
+    assert np.max(np.abs(gq - ogq)) <= 4 * tol
+    # vertex gradient of the subset loss: upstream gradient masked to S
+    q2 = torch.from_numpy(w.Q).cuda().requires_grad_(True)
+    V2 = torch.from_numpy(w.V).cuda().requires_grad_(True)
+    d2, _, _ = P.p2m_distance(q2, V2, m)
+    mask = torch.zeros(len(w.Q), device="cuda")
+    mask[torch.from_numpy(S).cuda()] = 1.0
+    (d2 * d2 * mask).sum().backward()
+    gV = V2.grad.cpu().numpy().astype(np.float64)
+    _, ogV = OG.gradients(om, w.Q[S], ans, 2.0 * ans["dist"])
+    # near-ties (a face vs. its side) may pick either primitive; the gradient
+    # is continuous across them, so the whole vertex gradient is compared
+    rel = np.linalg.norm(gV - ogV) / np.linalg.norm(ogV)
+    assert rel <= 5e-3, rel
