@@ -64,11 +64,13 @@ def measured_traffic(n_queries: int):
     return float(vals["hbm_bytes_per_launch"])
 
 
-def b_alg(nodes: float, edges: float, faces: float) -> float:
-    """Algorithmic bytes per query: query in (12) + results out (20) + 16 per
-    KD-tree node + 8 for the list offsets + per edge (id 4 + endpoints' ids 8
-    + coordinates 24) + per face (id 4 + vertex ids 12 + coordinates 36)."""
-    return 12 + 20 + 16 * nodes + 8 + 36 * edges + 52 * faces
+def b_alg(visits: float, steps: float, edges: float, faces: float) -> float:
+    """Algorithmic bytes per query: query in (12) + results out (20) + the
+    nearest-vertex walk (seed id 4 + seed vertex 16, per step the neighbour
+    list offsets 8, per neighbour its id 4 + position 16) + 8 for the
+    interception-list offsets + per edge (id 4 + endpoints' ids 8 +
+    coordinates 24) + per face (id 4 + vertex ids 12 + coordinates 36)."""
+    return 12 + 20 + 20 + 8 * steps + 20 * visits + 8 + 36 * edges + 52 * faces
 
 
 def main():
@@ -156,41 +158,43 @@ def main():
     order_avg, query_avg = float(np.mean(order_ms)), float(np.mean(query_ms))
     log(f"[bench] stage times: ordering {order_avg:.3f} ms, query kernel {query_avg:.3f} ms")
 
-    # cost breakdown: KD-tree nearest vertex alone vs the whole query kernel,
-    # both on the Morton-ordered batch without the ordering step
+    # cost breakdown: nearest vertex alone vs the whole query kernel, both on
+    # the Morton-ordered batch without the ordering step, default traversal
     _, perm = mesh.order_queries(q)
     qs = q[perm.long()].contiguous()
-    kd_ms, full_ms = [], []
-    trav = 2 if n >= (1 << 22) else 1  # the walk the sorted step uses
+    nv_ms, full_ms = [], []
     for _ in range(args.steps):
         e0.record()
-        mesh.nearest_vertex(qs, traversal=trav)
+        mesh.nearest_vertex(qs)
         e1.record()
         torch.cuda.synchronize()
-        kd_ms.append(e0.elapsed_time(e1))
+        nv_ms.append(e0.elapsed_time(e1))
         e0.record()
-        mesh.query(qs, out=out, sort=False, traversal=trav)
+        mesh.query(qs, out=out, sort=False)
         e1.record()
         torch.cuda.synchronize()
         full_ms.append(e0.elapsed_time(e1))
     del qs, perm
-    breakdown = {"kdtree_only_ms": round(float(np.mean(kd_ms)), 4), "query_presorted_ms": round(float(np.mean(full_ms)), 4)}
-    log(f"[bench] breakdown on pre-sorted queries: KD tree {breakdown['kdtree_only_ms']:.3f} ms, whole query {breakdown['query_presorted_ms']:.3f} ms")
+    breakdown = {"nearest_vertex_only_ms": round(float(np.mean(nv_ms)), 4),
+                 "query_presorted_ms": round(float(np.mean(full_ms)), 4)}
+    log(f"[bench] breakdown on pre-sorted queries: nearest vertex {breakdown['nearest_vertex_only_ms']:.3f} ms, "
+        f"whole query {breakdown['query_presorted_ms']:.3f} ms")
 
-    # algorithmic bytes per query from the same tree/table (host model counts)
+    # algorithmic bytes per query from the same structures (host model counts)
     rng = np.random.default_rng(123)
     sub = w.Q[rng.choice(n, size=min(n, 200_000), replace=False)]
     hs = mesh.query_host(sub)
-    nodes, edges, faces = hs["nodes"] / len(sub), hs["edges"] / len(sub), hs["faces"] / len(sub)
-    balg = b_alg(nodes, edges, faces)
+    visits, steps = hs["nodes"] / len(sub), hs["steps"] / len(sub)
+    edges, faces = hs["edges"] / len(sub), hs["faces"] / len(sub)
+    balg = b_alg(visits, steps, edges, faces)
     achieved = balg * n / (query_avg / 1e3) / 1e9
     traffic = measured_traffic(n)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_query", "kernel_ms": round(query_avg, 4),
                 "b_alg_bytes_per_query": round(balg, 1),
-                "per_query": {"kdtree_nodes": round(nodes, 2), "edges_tested": round(edges, 2),
-                              "faces_tested": round(faces, 2)}}
+                "per_query": {"walk_vertices": round(visits, 2), "walk_steps": round(steps, 2),
+                              "edges_tested": round(edges, 2), "faces_tested": round(faces, 2)}}
 
     result = {"metric": "P2M queries/sec at 1.3M tris (fwd, fwd+bwd, batched); % of HBM peak",
               "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -286,7 +290,7 @@ def main():
                                                 "launches": count},
                              "speedup_vs_plain": round(ms_p / ms_b, 3),
                              "shape": {"block": shape[0], "queries_per_lane": shape[1],
-                                       "traversal": "wave" if shape[2] == 2 else "per-lane"},
+                                       "traversal": {1: "kd per-lane", 2: "kd wavefront", 3: "voronoi walk"}[shape[2]]},
                              "workload": (f"{'all' if args.batched_full else 'first'} {count} meshes of the seeded 256-mesh plan "
                                           f"(displaced geodesic spheres / heightfields, log-uniform sizes): {ntri} triangles, "
                                           f"{nb} queries (log-uniform per mesh, mixed uniform/near-surface); one graph launch"),
@@ -313,7 +317,7 @@ def main():
         mesh.query_host(sub2, threads=nth)
         dt = time.perf_counter() - t0
         result["cpu_p2m"] = {"value": round(len(sub2) / dt, 1), "unit": "queries/s", "threads": nth,
-                             "kind": "multi-threaded CPU P2M query, same KD tree and table, float32",
+                             "kind": "multi-threaded CPU P2M query, same structures and float32 code as the default device path",
                              "sample": "first 1e6 queries of the workload"}
         log(f"[bench] CPU P2M: {len(sub2) / dt:.0f} q/s")
 

@@ -90,10 +90,15 @@ typedef struct {
     int block_size;     /* 0 default (256); else 64, 128, 192 or 256 */
     int profile;        /* nonzero: record HIP events around the ordering and
                            query kernels (read with p2m_query_profile) */
-    int traversal;      /* KD-tree walk: 0 automatic (wavefront-coherent for
-                           sorted batches of >= 2^22 queries), 1 one search per
-                           lane, 2 wavefront-coherent; every choice returns
-                           each query's exact nearest vertex */
+    int traversal;      /* nearest-vertex search: 0 default (3), 1 one
+                           KD-tree search per lane, 2 wavefront-coherent
+                           KD-tree walk, 3 greedy walk over the Voronoi
+                           neighbour graph (the graph Algorithm 1 floods)
+                           from a grid seed, exact in D, with the
+                           wavefront tree walk for queries outside D; every
+                           choice returns each query's exact nearest vertex
+                           (equal distances: the smallest id, up to float64
+                           rounding of the squared distance) */
     int reserved[4];    /* must be 0 */
 } p2m_query_opts;
 
@@ -133,13 +138,16 @@ p2m_status p2m_mesh_kdtree(const p2m_mesh* m, float* xyz, int32_t* vid);
 p2m_status p2m_save(const p2m_mesh* m, const char* path);
 p2m_status p2m_load(const char* path, p2m_mesh** out);
 
-/* Plain multi-threaded CPU P2M query over the same KD tree and table with
- * the same float32 arithmetic as the device kernel (host arrays).  A
- * reported baseline, never used by the device path.  counters (may be NULL)
- * receive sums over queries: [0] KD-tree nodes visited, [1] edges tested,
- * [2] faces tested. */
+/* Plain multi-threaded CPU P2M query over the same structures with the
+ * same float32 arithmetic as the device kernel's default traversal (host
+ * arrays): Voronoi walk from the grid seed in D, KD-tree search outside D.
+ * A reported baseline, never used by the device path.  The first call builds
+ * a host copy of the seed grid.  counters (may be NULL) receive sums over
+ * queries: [0] nearest-vertex candidates evaluated (walk: neighbour
+ * vertices; tree: nodes), [1] edges tested, [2] faces tested, [3] walk
+ * steps (neighbour lists read). */
 p2m_status p2m_query_host(const p2m_mesh* m, const float* q, int64_t n, int32_t* prim, float* closest,
-                          float* dist, uint8_t* status, int num_threads, int64_t counters[3]);
+                          float* dist, uint8_t* status, int num_threads, int64_t counters[4]);
 
 const char* p2m_last_error(void);
 
@@ -217,12 +225,12 @@ p2m_status p2m_batch_query_eager(p2m_batch* b, const float* q_dev, const int64_t
                                  float* closest_dev, float* dist_dev, void* stream);
 
 /* Launch shape of the persistent kernel: workgroup size (64, 128, 192 or
- * 256), queries per lane in a tile (1..16), KD-tree walk (1 per lane, 2
- * wavefront-coherent). */
+ * 256), queries per lane in a tile (1..16), nearest-vertex traversal (1, 2
+ * or 3 as in p2m_query_opts; 3 when the batch is created). */
 p2m_status p2m_batch_set_shape(p2m_batch* b, int block, int queries_per_lane, int traversal);
 p2m_status p2m_batch_get_shape(const p2m_batch* b, int* block, int* queries_per_lane, int* traversal);
 
-/* Time every launch shape in {64,128,256} x {1,2,4} x {1,2} on these queries
+/* Time every launch shape in {64,128,256} x {1,2,4} x {1,2,3} on these queries
  * (eager launches, two timed runs after a warm-up each) and keep the fastest;
  * the best_* outputs (may be NULL) report it.  Synchronises the stream. */
 p2m_status p2m_batch_autotune(p2m_batch* b, const float* q_dev, const int64_t* q_offsets_host, int32_t* prim_dev,

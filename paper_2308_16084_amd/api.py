@@ -181,11 +181,11 @@ class Mesh:
         closest = np.zeros((n, 3), np.float32)
         dist = np.zeros(n, np.float32)
         status = np.zeros(n, np.uint8)
-        cnt = np.zeros(3, np.int64)
+        cnt = np.zeros(4, np.int64)
         check(lib().p2m_query_host(self._h, _ptr(q), n, _ptr(prim), _ptr(closest), _ptr(dist), _ptr(status),
                                    int(threads), _ptr(cnt)))
         return {"prim": prim, "closest": closest, "dist": dist, "status": status,
-                "nodes": int(cnt[0]), "edges": int(cnt[1]), "faces": int(cnt[2])}
+                "nodes": int(cnt[0]), "edges": int(cnt[1]), "faces": int(cnt[2]), "steps": int(cnt[3])}
 
     # ----------------------------------------------------------- device
     def upload(self, device: int = 0, stream=None) -> int:

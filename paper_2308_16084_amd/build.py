@@ -13,14 +13,15 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libp2m.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 HOST_SOURCES = ["predicates.cpp", "delaunay.cpp", "convex_cell.cpp", "mesh.cpp", "kdtree.cpp",
                 "interception.cpp", "p2m_host.cpp"]
 DEVICE_SOURCES = ["p2m_device.hip", "radix_sort.hip", "p2m_batch.hip"]
 
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-parameter",
-              "-ffp-contract=off"]
-HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
+              "-ffp-contract=off", f"-I{INCLUDE}"]
+HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", f"-I{INCLUDE}",
              # packed FP32 instructions are kept out of every HIP build
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -9,10 +9,6 @@ namespace p2m {
 
 constexpr int kXcds = 8;  // MI355X: 8 XCDs, blocks dispatched round-robin
 constexpr int kQueryMaxBlock = 256;  // launch bound of the query kernels
-// Automatic traversal choice: the wavefront-coherent walk pays off when
-// Morton-adjacent queries are close compared with their nearest-vertex
-// distances, which the batch size stands in for.
-constexpr int64_t kWaveMinQueries = int64_t(1) << 22;
 
 // 30-bit Morton key: 10 bits per axis, cell = clamp(floor((q-lo)*s), 0, 1023)
 // in float32 (one subtract, one multiply); x takes the top bit of each triple.

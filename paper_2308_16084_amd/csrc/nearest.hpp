@@ -1,0 +1,49 @@
+// Nearest-vertex step of the query (Algorithm A.2): the three device
+// traversals and the seed grid of the Voronoi walk.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "query_core.hpp"
+#include "wave_kdtree.hpp"
+
+namespace p2m {
+
+// Nearest-vertex search used by a query kernel.
+enum Walk { WALK_LANE = 0, WALK_WAVE = 1, WALK_VORONOI = 2 };
+
+// WALK_LANE: every lane searches the KD tree on its own.  WALK_WAVE: the
+// wavefront-coherent tree walk (dense, Morton-ordered batches).
+// WALK_VORONOI: greedy walk over the Voronoi neighbour graph from the grid
+// seed for queries in D (where it is exact); the queries of a wavefront that
+// lie outside D then take the wavefront tree walk together, so that every
+// traversal returns the same vertex.  All lanes of the wavefront must call
+// this (inactive ones with active = false).
+template <int kWalk>
+__device__ __forceinline__ Nearest nearest_vertex(const MeshView& m, float qx, float qy, float qz, bool active,
+                                                  uint64_t& visits, uint64_t& steps) {
+    Nearest b;
+    b.d2 = INFINITY;
+    b.px = b.py = b.pz = 0.f;
+    b.vid = -1;
+    if (kWalk == WALK_WAVE) return kdt_nearest_wave(m.node, m.nv, qx, qy, qz, active);
+    if (kWalk == WALK_LANE) return active ? kdt_nearest(m.node, m.nv, qx, qy, qz, visits) : b;
+    const bool inside = active && domain_status(m, qx, qy, qz) == 0;
+    if (inside) b = voronoi_walk(m, qx, qy, qz, visits, steps);
+    const bool outside = active && !inside;
+    if (__any(outside)) {
+        const Nearest t = kdt_nearest_wave(m.node, m.nv, qx, qy, qz, outside);
+        if (outside) b = t;
+    }
+    return b;
+}
+
+// Side of the seed grid of the Voronoi walk: about 8 cells per vertex over
+// D, between 8^3 and 256^3 cells.
+int32_t walk_grid_side(int64_t nv);
+
+// Fills m.grid^3 seeds (nearest vertex of every cell centre) on `st`; m
+// points to device arrays (its seed field is ignored).
+hipError_t launch_seed_grid(const MeshView& m, int32_t* seed, hipStream_t st);
+
+}  // namespace p2m

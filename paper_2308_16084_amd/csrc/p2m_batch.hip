@@ -20,8 +20,8 @@
 
 #include "device_common.hpp"
 #include "p2m_internal.hpp"
+#include "nearest.hpp"
 #include "query_core.hpp"
-#include "wave_kdtree.hpp"
 
 namespace p2m {
 
@@ -30,11 +30,41 @@ MeshView host_view(const MeshState& s);
 
 struct BatchMesh {
     int64_t node, off, ent, seg, tri, fedge;  // element offsets into the typed arenas
+    int64_t vpos, nboff, nb, seed;            // Voronoi walk arrays (local ids inside)
     int32_t nv;
-    int32_t pad;
+    int32_t grid;          // seed grid side
     float dlo[3], dhi[3];  // domain rounded outward (status flag)
     float mlo[3], msc[3];  // Morton quantisation of the domain
+    float gscale[3];       // seed grid cells per unit length (grid origin = dlo)
+    int32_t pad;
 };
+
+// View of mesh d inside the arena.
+__host__ __device__ inline MeshView arena_view(const BatchMesh& d, const KdNode* node, const uint32_t* off,
+                                               const int32_t* ent, const float4* seg, const float4* tri,
+                                               const int32_t* fedge, const float4* vpos, const uint32_t* nboff,
+                                               const int32_t* nb, const int32_t* seed) {
+    MeshView v;
+    v.node = node + d.node;
+    v.nv = d.nv;
+    v.off = off + d.off;
+    v.ent = ent + d.ent;
+    v.seg = seg + d.seg;
+    v.tri = tri + d.tri;
+    v.fedge = fedge + d.fedge;
+    v.vpos = vpos + d.vpos;
+    v.nboff = nboff + d.nboff;
+    v.nb = nb + d.nb;
+    v.seed = seed + d.seed;
+    v.grid = d.grid;
+    for (int k = 0; k < 3; ++k) {
+        v.dlo[k] = d.dlo[k];
+        v.dhi[k] = d.dhi[k];
+        v.glo[k] = d.dlo[k];
+        v.gscale[k] = d.gscale[k];
+    }
+    return v;
+}
 
 struct Tile {
     int32_t mesh, start, count, pad;
@@ -54,6 +84,10 @@ struct p2m_batch {
     float4* seg = nullptr;
     float4* tri = nullptr;
     int32_t* fedge = nullptr;
+    float4* vpos = nullptr;
+    uint32_t* nboff = nullptr;
+    int32_t* nb = nullptr;
+    int32_t* seed = nullptr;
     p2m::BatchMesh* desc = nullptr;
     std::vector<double> cost;  // per-mesh cost weight (log of vertex count)
     // per query layout
@@ -68,7 +102,7 @@ struct p2m_batch {
     void* scratch = nullptr;
     int tile_block = 0, tile_qpl = 0;
     // launch shape
-    int block = 256, qpl = 1, traversal = 2;
+    int block = 256, qpl = 1, traversal = 3;
     int grid = 0;
     // captured graph
     hipStream_t cap_stream = nullptr;
@@ -108,11 +142,24 @@ __global__ void k_reset(uint32_t* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0u;
 }
 
-template <bool kWave>
+// Arena arrays of a batch, passed by value to the kernel.
+struct Arena {
+    const KdNode* node;
+    const uint32_t* off;
+    const int32_t* ent;
+    const float4* seg;
+    const float4* tri;
+    const int32_t* fedge;
+    const float4* vpos;
+    const uint32_t* nboff;
+    const int32_t* nb;
+    const int32_t* seed;
+    const BatchMesh* desc;
+};
+
+template <int kWalk>
 __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
-    const KdNode* __restrict__ node, const uint32_t* __restrict__ off, const int32_t* __restrict__ ent,
-    const float4* __restrict__ seg, const float4* __restrict__ tri, const int32_t* __restrict__ fedge,
-    const BatchMesh* __restrict__ desc, const Tile* __restrict__ tiles, int64_t ntiles, uint32_t* counter, int qpl,
+    Arena A, const Tile* __restrict__ tiles, int64_t ntiles, uint32_t* counter, int qpl,
     const float* __restrict__ q, const int32_t* __restrict__ perm, int64_t n, int32_t* __restrict__ prim,
     float* __restrict__ closest, float* __restrict__ dist) {
     __shared__ int64_t s_tile;
@@ -123,19 +170,8 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
         __syncthreads();
         if (t >= ntiles) break;  // uniform across the workgroup
         const Tile T = tiles[t];
-        const BatchMesh& d = desc[T.mesh];
-        MeshView v;
-        v.node = node + d.node;
-        v.nv = d.nv;
-        v.off = off + d.off;
-        v.ent = ent + d.ent;
-        v.seg = seg + d.seg;
-        v.tri = tri + d.tri;
-        v.fedge = fedge + d.fedge;
-        for (int k = 0; k < 3; ++k) {
-            v.dlo[k] = d.dlo[k];
-            v.dhi[k] = d.dhi[k];
-        }
+        const MeshView v = arena_view(A.desc[T.mesh], A.node, A.off, A.ent, A.seg, A.tri, A.fedge, A.vpos, A.nboff,
+                                      A.nb, A.seed);
         for (int r = 0; r < qpl; ++r) {
             const int64_t local = (int64_t)r * blockDim.x + threadIdx.x;
             const int64_t j = (int64_t)T.start + local;
@@ -148,13 +184,9 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
                 qz = q[3 * i + 2];
             }
             const bool fin = finite3(qx, qy, qz);
-            Nearest nv;
             ScanCounters c;
-            if (kWave) {
-                nv = kdt_nearest_wave(v.node, v.nv, qx, qy, qz, i >= 0 && fin);
-            } else if (i >= 0 && fin) {
-                nv = kdt_nearest(v.node, v.nv, qx, qy, qz, c.nodes);
-            }
+            // every lane of the wavefront calls this (see nearest_vertex)
+            const Nearest nv = nearest_vertex<kWalk>(v, qx, qy, qz, i >= 0 && fin, c.nodes, c.steps);
             if (i >= 0) {
                 const Answer a = fin ? p2m_answer(v, qx, qy, qz, nv, c) : nonfinite_answer();
                 prim[i] = a.prim;
@@ -244,15 +276,15 @@ p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, 
                                                               rb.keys[0], rb.vals[0]);
     const int cur = radix_sort_pairs(plan, rb, 32, st);
     k_reset<<<1, 64, 0, st>>>(b->counter);
-    int grid = b->grid;
-    if (b->traversal == 2)
-        k_batch_query<true><<<grid, b->block, 0, st>>>(b->node, b->off, b->ent, b->seg, b->tri, b->fedge, b->desc,
-                                                       b->tiles, b->ntiles, b->counter, b->qpl, q, rb.vals[cur], n,
-                                                       prim, closest, dist);
-    else
-        k_batch_query<false><<<grid, b->block, 0, st>>>(b->node, b->off, b->ent, b->seg, b->tri, b->fedge, b->desc,
-                                                        b->tiles, b->ntiles, b->counter, b->qpl, q, rb.vals[cur], n,
-                                                        prim, closest, dist);
+    const int grid = b->grid;
+    const Arena A{b->node, b->off, b->ent, b->seg, b->tri, b->fedge, b->vpos, b->nboff, b->nb, b->seed, b->desc};
+#define P2M_LAUNCH_BATCH(W)                                                                                  \
+    k_batch_query<W><<<grid, b->block, 0, st>>>(A, b->tiles, b->ntiles, b->counter, b->qpl, q, rb.vals[cur], n, \
+                                                prim, closest, dist)
+    if (b->traversal == 1) P2M_LAUNCH_BATCH(WALK_LANE);
+    else if (b->traversal == 2) P2M_LAUNCH_BATCH(WALK_WAVE);
+    else P2M_LAUNCH_BATCH(WALK_VORONOI);
+#undef P2M_LAUNCH_BATCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batched query launch");
     return P2M_OK;
@@ -262,10 +294,10 @@ p2m_status set_grid(p2m_batch* b) {
     int dev = b->device, cus = 0, per = 0;
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_fail(e, "device attribute");
-    if (b->traversal == 2)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_batch_query<true>, b->block, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_batch_query<false>, b->block, 0);
+    const void* k = b->traversal == 1   ? (const void*)k_batch_query<WALK_LANE>
+                    : b->traversal == 2 ? (const void*)k_batch_query<WALK_WAVE>
+                                        : (const void*)k_batch_query<WALK_VORONOI>;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, b->block, 0);
     if (e != hipSuccess) return hip_fail(e, "occupancy query");
     b->grid = std::max(1, cus * std::max(1, per));
     return P2M_OK;
@@ -310,9 +342,10 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
     b->count = count;
     b->key_bits = std::min(10, (32 - mesh_bits) / 3);
     // host staging of the arena
-    std::vector<float> node, seg, tri;
-    std::vector<uint32_t> off;
-    std::vector<int32_t> ent, fedge;
+    std::vector<float> node, seg, tri, vpos;
+    std::vector<uint32_t> off, nboff;
+    std::vector<int32_t> ent, fedge, nb;
+    int64_t seeds = 0;
     std::vector<BatchMesh> desc((size_t)count);
     b->cost.resize((size_t)count);
     for (int32_t k = 0; k < count; ++k) {
@@ -325,9 +358,15 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
         d.seg = (int64_t)seg.size() / 4;
         d.tri = (int64_t)tri.size() / 4;
         d.fedge = (int64_t)fedge.size();
+        d.vpos = (int64_t)vpos.size() / 4;
+        d.nboff = (int64_t)nboff.size();
+        d.nb = (int64_t)nb.size();
+        d.seed = seeds;
         d.nv = (int32_t)s.m.nv;
         d.pad = 0;
         const MeshView hv = host_view(s);
+        d.grid = hv.grid;
+        seeds += (int64_t)hv.grid * hv.grid * hv.grid;
         float lo[3], sc[3];
         morton_params(s.dlo, s.dhi, lo, sc);
         for (int c = 0; c < 3; ++c) {
@@ -335,6 +374,7 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
             d.dhi[c] = hv.dhi[c];
             d.mlo[c] = lo[c];
             d.msc[c] = sc[c];
+            d.gscale[c] = hv.gscale[c];
         }
         node.insert(node.end(), s.pk_node.begin(), s.pk_node.end());
         off.insert(off.end(), s.t.off.begin(), s.t.off.end());
@@ -342,14 +382,20 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
         seg.insert(seg.end(), s.pk_seg.begin(), s.pk_seg.end());
         tri.insert(tri.end(), s.pk_tri.begin(), s.pk_tri.end());
         fedge.insert(fedge.end(), s.pk_fedge.begin(), s.pk_fedge.end());
+        vpos.insert(vpos.end(), s.pk_vpos.begin(), s.pk_vpos.end());
+        nboff.insert(nboff.end(), s.pk_nboff.begin(), s.pk_nboff.end());
+        nb.insert(nb.end(), s.t.nb.begin(), s.t.nb.end());
         b->cost[(size_t)k] = std::log2((double)s.m.nv + 2.0);
     }
-    if (ent.size() >= (size_t)UINT32_MAX) {
+    if (ent.size() >= (size_t)UINT32_MAX || nb.size() >= (size_t)UINT32_MAX) {
         delete b;
         return fail(P2M_ERR_ARG, "batch tables exceed 2^32 entries");
     }
-    const size_t sizes[7] = {4 * node.size(), 4 * off.size(), 4 * std::max<size_t>(1, ent.size()), 4 * seg.size(),
-                             4 * tri.size(), 4 * fedge.size(), sizeof(BatchMesh) * desc.size()};
+    constexpr int kArrays = 11;
+    const size_t sizes[kArrays] = {4 * node.size(), 4 * off.size(), 4 * std::max<size_t>(1, ent.size()),
+                                   4 * seg.size(), 4 * tri.size(), 4 * fedge.size(), sizeof(BatchMesh) * desc.size(),
+                                   4 * vpos.size(), 4 * nboff.size(), 4 * std::max<size_t>(1, nb.size()),
+                                   4 * (size_t)seeds};
     size_t total = 0;
     for (size_t x : sizes) total += (size_t)up256((int64_t)x);
     hipError_t e = hipMalloc(&b->base, total);
@@ -359,8 +405,8 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
     }
     b->bytes = (int64_t)total;
     char* p = (char*)b->base;
-    void* dst[7];
-    for (int i = 0; i < 7; ++i) {
+    void* dst[kArrays];
+    for (int i = 0; i < kArrays; ++i) {
         dst[i] = p;
         p += up256((int64_t)sizes[i]);
     }
@@ -371,11 +417,22 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
     b->tri = (float4*)dst[4];
     b->fedge = (int32_t*)dst[5];
     b->desc = (BatchMesh*)dst[6];
-    const void* src[7] = {node.data(), off.data(), ent.data(), seg.data(), tri.data(), fedge.data(), desc.data()};
-    const size_t nbytes[7] = {sizes[0], sizes[1], 4 * ent.size(), sizes[3], sizes[4], sizes[5], sizes[6]};
+    b->vpos = (float4*)dst[7];
+    b->nboff = (uint32_t*)dst[8];
+    b->nb = (int32_t*)dst[9];
+    b->seed = (int32_t*)dst[10];
+    // the seed grids are filled on the device below
+    const void* src[kArrays - 1] = {node.data(), off.data(), ent.data(), seg.data(), tri.data(), fedge.data(),
+                                    desc.data(), vpos.data(), nboff.data(), nb.data()};
+    const size_t nbytes[kArrays - 1] = {sizes[0], sizes[1], 4 * ent.size(), sizes[3], sizes[4],
+                                        sizes[5], sizes[6], sizes[7], sizes[8], 4 * nb.size()};
     hipStream_t st = (hipStream_t)stream;
-    for (int i = 0; i < 7 && e == hipSuccess; ++i)
+    for (int i = 0; i < kArrays - 1 && e == hipSuccess; ++i)
         if (nbytes[i]) e = hipMemcpyAsync(dst[i], src[i], nbytes[i], hipMemcpyHostToDevice, st);
+    for (int32_t k = 0; k < count && e == hipSuccess; ++k)
+        e = launch_seed_grid(arena_view(desc[(size_t)k], b->node, b->off, b->ent, b->seg, b->tri, b->fedge, b->vpos,
+                                        b->nboff, b->nb, b->seed),
+                             b->seed + desc[(size_t)k].seed, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // staging vectors are local
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -405,7 +462,7 @@ p2m_status p2m_batch_set_shape(p2m_batch* b, int block, int qpl, int traversal) 
     if (!b) return fail(P2M_ERR_ARG, "batch is NULL");
     if (block < 64 || block > kQueryMaxBlock || block % 64) return fail(P2M_ERR_ARG, "block must be 64, 128, 192 or 256");
     if (qpl < 1 || qpl > 16) return fail(P2M_ERR_ARG, "queries per lane must be in [1, 16]");
-    if (traversal != 1 && traversal != 2) return fail(P2M_ERR_ARG, "traversal must be 1 or 2");
+    if (traversal < 1 || traversal > 3) return fail(P2M_ERR_ARG, "traversal must be 1, 2 or 3");
     Guard g(b->device);
     if (b->block != block || b->qpl != qpl || b->traversal != traversal) drop_graph(b);
     b->block = block;
@@ -483,7 +540,7 @@ p2m_status p2m_batch_autotune(p2m_batch* b, const float* q, const int64_t* qoff,
         return fail(P2M_ERR_HIP, "hipEventCreate");
     const int blocks[3] = {64, 128, 256};
     const int qpls[3] = {1, 2, 4};
-    const int travs[2] = {1, 2};
+    const int travs[3] = {1, 2, 3};
     float best = INFINITY;
     int bb = b->block, bq = b->qpl, bt = b->traversal;
     p2m_status r = P2M_OK;

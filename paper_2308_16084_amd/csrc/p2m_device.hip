@@ -14,8 +14,8 @@
 
 #include "device_common.hpp"
 #include "p2m_internal.hpp"
+#include "nearest.hpp"
 #include "query_core.hpp"
-#include "wave_kdtree.hpp"
 
 namespace p2m {
 
@@ -94,6 +94,16 @@ void pack_mesh(MeshState& s) {
         }
         s.pk_fedge[(size_t)(4 * f + 3)] = -1;
     }
+    // Voronoi walk: vertex positions with ids, 32-bit neighbour offsets
+    s.pk_vpos.resize((size_t)(4 * n));
+    for (int64_t v = 0; v < n; ++v) {
+        float* d = &s.pk_vpos[(size_t)(4 * v)];
+        for (int k = 0; k < 3; ++k) d[k] = m.V[3 * (size_t)v + k];
+        d[3] = bits_as_float((int32_t)v);
+    }
+    s.pk_nboff.resize(s.t.nb_off.size());
+    for (size_t k = 0; k < s.t.nb_off.size(); ++k) s.pk_nboff[k] = (uint32_t)s.t.nb_off[k];
+    s.pk_seed.clear();
     s.packed = true;
 }
 
@@ -110,7 +120,24 @@ MeshView host_view(const MeshState& s) {
         v.dlo[k] = float_down(s.dlo[k]);
         v.dhi[k] = float_up(s.dhi[k]);
     }
+    v.vpos = nullptr;
+    v.nboff = nullptr;
+    v.nb = nullptr;
+    v.seed = s.pk_seed.empty() ? nullptr : s.pk_seed.data();
+    v.grid = walk_grid_side(s.m.nv);
+    for (int k = 0; k < 3; ++k) {
+        v.glo[k] = v.dlo[k];
+        v.gscale[k] = (float)((double)v.grid / ((double)v.dhi[k] - (double)v.dlo[k]));
+    }
+    v.vpos = (const float4*)s.pk_vpos.data();
+    v.nboff = s.pk_nboff.data();
+    v.nb = s.t.nb.data();
     return v;
+}
+
+int32_t walk_grid_side(int64_t nv) {
+    const double g = std::ceil(2.0 * std::cbrt((double)std::max<int64_t>(nv, 1)));
+    return (int32_t)std::min(256.0, std::max(8.0, g));
 }
 
 MeshView device_view(const MeshState& s) {
@@ -121,6 +148,10 @@ MeshView device_view(const MeshState& s) {
     v.seg = (const float4*)s.dev.seg;
     v.tri = (const float4*)s.dev.tri;
     v.fedge = (const int32_t*)s.dev.fedge;
+    v.vpos = (const float4*)s.dev.vpos;
+    v.nboff = (const uint32_t*)s.dev.nboff;
+    v.nb = (const int32_t*)s.dev.nb;
+    v.seed = (const int32_t*)s.dev.seed;
     return v;
 }
 
@@ -153,9 +184,7 @@ __global__ void k_morton(const float* __restrict__ q, int64_t n, float lox, floa
     vals[i] = (int32_t)i;
 }
 
-// kWave: the wavefront-coherent tree walk (dense, Morton-ordered batches);
-// otherwise every lane searches the tree on its own.
-template <bool kWriteExtras, bool kWave>
+template <bool kWriteExtras, int kWalk>
 __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const float* __restrict__ q,
                                                 const int32_t* __restrict__ perm, int64_t n, int64_t chunk,
                                                 int32_t* __restrict__ prim, float* __restrict__ closest,
@@ -173,15 +202,9 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const floa
     }
     const bool fin = finite3(qx, qy, qz);
     ScanCounters c;
-    Nearest nv;
-    if (kWave) {
-        // every lane of the wavefront takes part in the shared tree walk
-        nv = kdt_nearest_wave(m.node, m.nv, qx, qy, qz, i >= 0 && fin);
-        if (i < 0) return;
-    } else {
-        if (i < 0) return;
-        if (fin) nv = kdt_nearest(m.node, m.nv, qx, qy, qz, c.nodes);
-    }
+    // with WALK_WAVE every lane of the wavefront takes part in the shared walk
+    const Nearest nv = nearest_vertex<kWalk>(m, qx, qy, qz, i >= 0 && fin, c.nodes, c.steps);
+    if (i < 0) return;
     uint8_t st = fin ? domain_status(m, qx, qy, qz) : (uint8_t)2;
     const Answer a = fin ? p2m_answer(m, qx, qy, qz, nv, c) : nonfinite_answer();
     prim[i] = a.prim;
@@ -198,7 +221,7 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const floa
     }
 }
 
-template <bool kWave>
+template <int kWalk>
 __global__ __launch_bounds__(256) void k_nearest(MeshView m, const float* __restrict__ q, int64_t n,
                                                   int32_t* __restrict__ vid, float* __restrict__ d2) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,17 +232,57 @@ __global__ __launch_bounds__(256) void k_nearest(MeshView m, const float* __rest
         qz = q[3 * i + 2];
     }
     const bool fin = finite3(qx, qy, qz);
-    Nearest b;
-    if (kWave) {
-        b = kdt_nearest_wave(m.node, m.nv, qx, qy, qz, i < n && fin);
-        if (i >= n) return;
-    } else {
-        if (i >= n) return;
-        uint64_t visits = 0;
-        if (fin) b = kdt_nearest(m.node, m.nv, qx, qy, qz, visits);
-    }
+    uint64_t visits = 0, steps = 0;
+    const Nearest b = nearest_vertex<kWalk>(m, qx, qy, qz, i < n && fin, visits, steps);
+    if (i >= n) return;
     vid[i] = fin ? b.vid : -1;
     if (d2) d2[i] = fin ? b.d2 : NAN;
+}
+
+// Seed grid of the Voronoi walk: nearest vertex of every cell centre.
+__global__ __launch_bounds__(256) void k_seed_grid(MeshView m, int32_t* __restrict__ seed) {
+    const int64_t G = m.grid;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= G * G * G) return;
+    const int64_t ix = i % G, iy = (i / G) % G, iz = i / (G * G);
+    const float cx = m.glo[0] + ((float)ix + 0.5f) / m.gscale[0];
+    const float cy = m.glo[1] + ((float)iy + 0.5f) / m.gscale[1];
+    const float cz = m.glo[2] + ((float)iz + 0.5f) / m.gscale[2];
+    uint64_t visits = 0;
+    seed[i] = kdt_nearest(m.node, m.nv, cx, cy, cz, visits).vid;
+}
+
+// Host copy of the seed grid for the host query, same definition as the
+// device kernel above.
+static void host_seed_grid(MeshState& s, int nt) {
+    const MeshView v = host_view(s);
+    const int64_t G = v.grid, cells = G * G * G;
+    s.pk_seed.assign((size_t)cells, 0);
+    std::atomic<int64_t> cursor{0};
+    auto work = [&]() {
+        for (;;) {
+            const int64_t b = cursor.fetch_add(4096);
+            if (b >= cells) break;
+            for (int64_t i = b; i < std::min(cells, b + 4096); ++i) {
+                const int64_t ix = i % G, iy = (i / G) % G, iz = i / (G * G);
+                const float cx = v.glo[0] + ((float)ix + 0.5f) / v.gscale[0];
+                const float cy = v.glo[1] + ((float)iy + 0.5f) / v.gscale[1];
+                const float cz = v.glo[2] + ((float)iz + 0.5f) / v.gscale[2];
+                uint64_t visits = 0;
+                s.pk_seed[(size_t)i] = kdt_nearest(v.node, v.nv, cx, cy, cz, visits).vid;
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(work);
+    work();
+    for (auto& x : th) x.join();
+}
+
+hipError_t launch_seed_grid(const MeshView& m, int32_t* seed, hipStream_t st) {
+    const int64_t cells = (int64_t)m.grid * m.grid * m.grid;
+    k_seed_grid<<<(unsigned)((cells + 255) / 256), 256, 0, st>>>(m, seed);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_backward(const float* __restrict__ q, int64_t n,
@@ -257,6 +320,18 @@ __global__ __launch_bounds__(256) void k_backward(const float* __restrict__ q, i
 }
 
 // ------------------------------------------------------------ launches
+
+// traversal option (0 default, 1 per-lane tree, 2 wavefront tree, 3 Voronoi
+// walk) -> Walk.  The Voronoi walk reads a few dozen vertices per query
+// where the tree searches read hundreds of nodes, on ordered and unordered
+// batches alike, so it is the default.
+static int pick_walk(int traversal) {
+    switch (traversal) {
+        case 1: return WALK_LANE;
+        case 2: return WALK_WAVE;
+        default: return WALK_VORONOI;
+    }
+}
 
 struct DeviceGuard {
     int old = -1;
@@ -339,7 +414,16 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
     const size_t b_seg = sizeof(float) * s.pk_seg.size();
     const size_t b_tri = sizeof(float) * s.pk_tri.size();
     const size_t b_fe = sizeof(int32_t) * s.pk_fedge.size();
-    const size_t total = up(b_node) + up(b_off) + up(b_ent) + up(b_seg) + up(b_tri) + up(b_fe);
+    // Voronoi walk: vertex positions, neighbour CSR (32-bit offsets), seed grid
+    if (s.t.nb.size() >= (size_t)UINT32_MAX || s.t.nb_off.size() != (size_t)s.m.nv + 1)
+        return fail(P2M_ERR_INTERNAL, "Voronoi neighbour graph missing or too large");
+    const int32_t G = walk_grid_side(s.m.nv);
+    const size_t b_vpos = sizeof(float) * s.pk_vpos.size();
+    const size_t b_nboff = sizeof(uint32_t) * s.pk_nboff.size();
+    const size_t b_nb = sizeof(int32_t) * std::max<size_t>(1, s.t.nb.size());
+    const size_t b_seed = sizeof(int32_t) * (size_t)G * (size_t)G * (size_t)G;
+    const size_t total = up(b_node) + up(b_off) + up(b_ent) + up(b_seg) + up(b_tri) + up(b_fe) + up(b_vpos) +
+                         up(b_nboff) + up(b_nb) + up(b_seed);
     void* base = nullptr;
     hipError_t e = hipMalloc(&base, total);
     if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? P2M_ERR_OOM : P2M_ERR_HIP, "device arena allocation");
@@ -358,6 +442,14 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
     s.dev.tri = p;
     p += up(b_tri);
     s.dev.fedge = p;
+    p += up(b_fe);
+    s.dev.vpos = p;
+    p += up(b_vpos);
+    s.dev.nboff = p;
+    p += up(b_nboff);
+    s.dev.nb = p;
+    p += up(b_nb);
+    s.dev.seed = p;
     hipStream_t st = (hipStream_t)stream;
     struct Cp {
         void* dst;
@@ -365,11 +457,21 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
         size_t n;
     } cps[] = {{s.dev.node, s.pk_node.data(), b_node}, {s.dev.off, s.t.off.data(), b_off},
                {s.dev.ent, s.t.ent.data(), s.t.ent.size() * sizeof(int32_t)}, {s.dev.seg, s.pk_seg.data(), b_seg},
-               {s.dev.tri, s.pk_tri.data(), b_tri}, {s.dev.fedge, s.pk_fedge.data(), b_fe}};
+               {s.dev.tri, s.pk_tri.data(), b_tri}, {s.dev.fedge, s.pk_fedge.data(), b_fe},
+               {s.dev.vpos, s.pk_vpos.data(), b_vpos}, {s.dev.nboff, s.pk_nboff.data(), b_nboff},
+               {s.dev.nb, s.t.nb.data(), s.t.nb.size() * sizeof(int32_t)}};
     for (const Cp& c : cps) {
         if (c.n == 0) continue;
         e = hipMemcpyAsync(c.dst, c.src, c.n, hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return fail(P2M_ERR_HIP, std::string("upload copy: ") + hipGetErrorString(e));
+        if (e != hipSuccess) {
+            device_release(s);
+            return fail(P2M_ERR_HIP, std::string("upload copy: ") + hipGetErrorString(e));
+        }
+    }
+    e = launch_seed_grid(device_view(s), (int32_t*)s.dev.seed, st);
+    if (e != hipSuccess) {
+        device_release(s);
+        return fail(P2M_ERR_HIP, std::string("seed grid kernel: ") + hipGetErrorString(e));
     }
     if (bytes) *bytes = (int64_t)total;
     return P2M_OK;
@@ -389,7 +491,7 @@ p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, flo
     if (opts) {
         profile = opts->profile;
         traversal = opts->traversal;
-        if (traversal < 0 || traversal > 2) return fail(P2M_ERR_ARG, "traversal must be 0, 1 or 2");
+        if (traversal < 0 || traversal > 3) return fail(P2M_ERR_ARG, "traversal must be 0, 1, 2 or 3");
         if (opts->sort_queries >= 0) sort = opts->sort_queries ? 1 : 0;
         if (opts->block_size != 0) {
             if (opts->block_size < 64 || opts->block_size > kQueryMaxBlock || opts->block_size % 64)
@@ -416,14 +518,19 @@ p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, flo
     const int64_t tiles = (n + block - 1) / block;
     const int64_t chunk = (tiles + kXcds - 1) / kXcds;
     const unsigned grid = (unsigned)(chunk * kXcds);
-    const bool wave = traversal == 2 || (traversal == 0 && sort && n >= kWaveMinQueries);
+    const int walk = pick_walk(traversal);
+#define P2M_LAUNCH_QUERY(X, W) \
+    k_query<X, W><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid)
     if (bary) {
-        if (wave) k_query<true, true><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid);
-        else k_query<true, false><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid);
+        if (walk == WALK_WAVE) P2M_LAUNCH_QUERY(true, WALK_WAVE);
+        else if (walk == WALK_VORONOI) P2M_LAUNCH_QUERY(true, WALK_VORONOI);
+        else P2M_LAUNCH_QUERY(true, WALK_LANE);
     } else {
-        if (wave) k_query<false, true><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid);
-        else k_query<false, false><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid);
+        if (walk == WALK_WAVE) P2M_LAUNCH_QUERY(false, WALK_WAVE);
+        else if (walk == WALK_VORONOI) P2M_LAUNCH_QUERY(false, WALK_VORONOI);
+        else P2M_LAUNCH_QUERY(false, WALK_LANE);
     }
+#undef P2M_LAUNCH_QUERY
     p2m_status r = check_launch("query kernel");
     if (r == P2M_OK && profile) {
         (void)hipEventRecord((hipEvent_t)s.dev.ev[2], st);
@@ -456,14 +563,15 @@ p2m_status p2m_nearest_vertex(p2m_mesh* mh, const float* q, int64_t n, int32_t* 
     if (s.dev.device < 0) return fail(P2M_ERR_STATE, "p2m_nearest_vertex before p2m_upload");
     if (n == 0) return P2M_OK;
     if (!q || !vid) return fail(P2M_ERR_ARG, "NULL pointer");
-    if (traversal < 0 || traversal > 2) return fail(P2M_ERR_ARG, "traversal must be 0, 1 or 2");
+    if (traversal < 0 || traversal > 3) return fail(P2M_ERR_ARG, "traversal must be 0, 1, 2 or 3");
     DeviceGuard g(s.dev.device);
     const MeshView v = device_view(s);
     const unsigned grid = (unsigned)((n + 255) / 256);
-    if (traversal == 2 || (traversal == 0 && n >= kWaveMinQueries))
-        k_nearest<true><<<grid, 256, 0, (hipStream_t)stream>>>(v, q, n, vid, d2);
-    else
-        k_nearest<false><<<grid, 256, 0, (hipStream_t)stream>>>(v, q, n, vid, d2);
+    const int walk = pick_walk(traversal);
+    hipStream_t st = (hipStream_t)stream;
+    if (walk == WALK_WAVE) k_nearest<WALK_WAVE><<<grid, 256, 0, st>>>(v, q, n, vid, d2);
+    else if (walk == WALK_VORONOI) k_nearest<WALK_VORONOI><<<grid, 256, 0, st>>>(v, q, n, vid, d2);
+    else k_nearest<WALK_LANE><<<grid, 256, 0, st>>>(v, q, n, vid, d2);
     return check_launch("nearest-vertex kernel");
 }
 
@@ -506,15 +614,16 @@ p2m_status p2m_query_backward(p2m_mesh* mh, const float* q, int64_t n, const flo
 }
 
 p2m_status p2m_query_host(const p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, float* closest, float* dist,
-                          uint8_t* status, int num_threads, int64_t counters[3]) {
+                          uint8_t* status, int num_threads, int64_t counters[4]) {
     if (!mh) return fail(P2M_ERR_ARG, "mesh is NULL");
     MeshState& s = const_cast<MeshState&>(mh->s);
     if (!s.precomputed) return fail(P2M_ERR_STATE, "p2m_query_host before p2m_precompute");
     if (n < 0) return fail(P2M_ERR_ARG, "negative query count");
     if (n > 0 && (!q || !prim || !closest || !dist)) return fail(P2M_ERR_ARG, "NULL pointer");
     pack_mesh(s);
-    const MeshView v = host_view(s);
     int nt = num_threads > 0 ? num_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    if (s.pk_seed.empty()) host_seed_grid(s, nt);
+    const MeshView v = host_view(s);
     nt = (int)std::min<int64_t>(nt, std::max<int64_t>(1, n / 1024));
     std::vector<ScanCounters> cnt((size_t)nt);
     std::atomic<int64_t> cursor{0};
@@ -541,11 +650,12 @@ p2m_status p2m_query_host(const p2m_mesh* mh, const float* q, int64_t n, int32_t
     work(0);
     for (auto& x : th) x.join();
     if (counters) {
-        counters[0] = counters[1] = counters[2] = 0;
+        counters[0] = counters[1] = counters[2] = counters[3] = 0;
         for (auto& c : cnt) {
             counters[0] += c.nodes;
             counters[1] += c.edges;
             counters[2] += c.faces;
+            counters[3] += c.steps;
         }
     }
     return P2M_OK;

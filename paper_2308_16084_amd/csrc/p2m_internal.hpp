@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/p2m.h"
+#include "p2m.h"
 #include "interception.hpp"
 #include "kdtree.hpp"
 #include "mesh.hpp"
@@ -32,6 +32,12 @@ struct DeviceMesh {
     void* seg = nullptr;
     void* tri = nullptr;
     void* fedge = nullptr;
+    // Voronoi-neighbour walk: vpos float4[nv], nboff uint32[nv+1], nb int32[],
+    // seed int32[grid^3] (nearest vertex of each cell centre of a grid on D)
+    void* vpos = nullptr;
+    void* nboff = nullptr;
+    void* nb = nullptr;
+    void* seed = nullptr;
     // ordering scratch (keys/values, double-buffered), grown on demand
     void* scratch = nullptr;
     int64_t scratch_bytes = 0;
@@ -56,6 +62,9 @@ struct MeshState {
     std::vector<float> pk_node;                  // 16 floats per KD-tree node
     std::vector<float> pk_seg, pk_tri;           // 4 floats per entry
     std::vector<int32_t> pk_fedge;               // 4 ints per face
+    std::vector<float> pk_vpos;                  // 4 floats per vertex (Voronoi walk)
+    std::vector<uint32_t> pk_nboff;              // 32-bit neighbour offsets
+    std::vector<int32_t> pk_seed;                // host copy of the seed grid (host query only)
     DeviceMesh dev;
 };
 

@@ -41,6 +41,13 @@ struct MeshView {
     const float4* tri;      // [3nf]
     const int32_t* fedge;   // [4nf]
     float dlo[3], dhi[3];   // query domain rounded outward to float
+    // Voronoi-neighbour walk (optional; null when absent)
+    const float4* vpos;     // [nv] vertex x, y, z, id bits
+    const uint32_t* nboff;  // [nv+1] Voronoi neighbours of each vertex
+    const int32_t* nb;
+    const int32_t* seed;    // [grid^3] nearest vertex of each grid-cell centre
+    int32_t grid;
+    float glo[3], gscale[3];  // cell = floor((q - glo) * gscale), clamped
 };
 
 P2M_HD int depth_of(int32_t node) { return 31 - __builtin_clz((unsigned)(node + 1)); }
@@ -154,6 +161,48 @@ P2M_HD Nearest kdt_nearest(const KdNode* __restrict__ node, int32_t n, float qx,
     return b;
 }
 
+// Nearest vertex by a greedy walk over the Voronoi (Delaunay) neighbour
+// graph of the vertices -- the graph the flooding inspection walks
+// (Algorithm 1).  Start at the nearest vertex of q's grid cell centre and
+// move to the best of the current vertex's neighbours while one is better
+// (same float32 + float64-tie comparison as the tree search).  For q inside
+// the query domain the walk stops only at the nearest vertex: if q is
+// outside Cell(v), it violates the bisector half-space of some Voronoi
+// neighbour of v, which is then closer.  The order is strict, so the walk
+// cannot cycle; `cap` bounds it regardless.
+P2M_HD Nearest voronoi_walk(const MeshView& m, float qx, float qy, float qz, uint64_t& visits, uint64_t& steps) {
+    const int32_t G = m.grid;
+    auto cell = [&](float x, float lo, float s) {
+        const float t = (x - lo) * s;
+        return t >= 0.f ? (t < (float)G ? (int32_t)t : G - 1) : 0;
+    };
+    const int32_t c = (cell(qz, m.glo[2], m.gscale[2]) * G + cell(qy, m.glo[1], m.gscale[1])) * G +
+                      cell(qx, m.glo[0], m.gscale[0]);
+    Nearest b;
+    b.d2 = INFINITY;
+    b.px = b.py = b.pz = 0.f;
+    b.vid = -1;
+    float4 p = m.vpos[m.seed[c]];
+    {
+        const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
+        consider(b, qx, qy, qz, dx * dx + dy * dy + dz * dz, p);
+    }
+    const int cap = 1 << 16;
+    for (int it = 0; it < cap; ++it) {
+        const int32_t v = b.vid;
+        ++steps;
+        const uint32_t k1 = m.nboff[v + 1];
+        for (uint32_t k = m.nboff[v]; k < k1; ++k) {
+            p = m.vpos[m.nb[k]];
+            ++visits;
+            const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
+            consider(b, qx, qy, qz, dx * dx + dy * dy + dz * dz, p);
+        }
+        if (b.vid == v) break;
+    }
+    return b;
+}
+
 // Closest point on the closed segment (a,b).  region: 0 inside, 1 at a, 2 at b.
 P2M_HD float seg_d2(float qx, float qy, float qz, const float4& a, const float4& b, float& t, int& region) {
     const float ex = b.x - a.x, ey = b.y - a.y, ez = b.z - a.z;
@@ -261,7 +310,7 @@ struct Answer {
 P2M_HD int32_t make_prim(int kind, int32_t id) { return (int32_t)(((uint32_t)kind << 30) | (uint32_t)id); }
 
 struct ScanCounters {
-    uint64_t nodes = 0, edges = 0, faces = 0;
+    uint64_t nodes = 0, edges = 0, faces = 0, steps = 0;  // nodes: nearest-vertex candidates
 };
 
 P2M_HD Answer nonfinite_answer() {
@@ -385,7 +434,8 @@ P2M_HD Answer p2m_query_point(const MeshView& m, float qx, float qy, float qz, u
         return nonfinite_answer();
     }
     status = domain_status(m, qx, qy, qz);
-    const Nearest nv = kdt_nearest(m.node, m.nv, qx, qy, qz, cnt.nodes);
+    const Nearest nv = status == 0 && m.seed ? voronoi_walk(m, qx, qy, qz, cnt.nodes, cnt.steps)
+                                             : kdt_nearest(m.node, m.nv, qx, qy, qz, cnt.nodes);
     return p2m_answer(m, qx, qy, qz, nv, cnt);
 }
 

@@ -59,7 +59,8 @@ def test_c1_unsorted_and_block_sizes_identical(c1):
     w, m, om, ans = c1
     ref = _run(m, w.Q)
     for kw in ({"sort": False}, {"block_size": 64}, {"block_size": 128, "sort": False}, {"traversal": 1},
-               {"traversal": 2}, {"traversal": 2, "sort": False}):
+               {"traversal": 2}, {"traversal": 2, "sort": False}, {"traversal": 3},
+               {"traversal": 3, "sort": False, "block_size": 64}):
         print("case: c1", kw, flush=True)
         out = _run(m, w.Q, **kw)
         for k in ("prim", "closest", "dist"):
@@ -88,8 +89,10 @@ def test_tiny_meshes(mode):
         m = _build(V, F, dom, mode)
         Q = rng.uniform(dom[0], dom[1], size=(5000, 3)).astype(np.float32)
         om = oracle.OracleMesh(V, F)
-        out = _run(m, Q)
-        assert check_answers(om, Q, om.query(Q), out["prim"], out["closest"], out["dist"]) == []
+        ans = om.query(Q)
+        for kw in ({}, {"traversal": 3}):
+            out = _run(m, Q, **kw)
+            assert check_answers(om, Q, ans, out["prim"], out["closest"], out["dist"]) == [], kw
 
 
 def test_golden_points_on_device():
@@ -126,14 +129,17 @@ def test_order_bit_exact(c1, n):
     assert np.array_equal(perm.cpu().numpy(), rp)
 
 
-@pytest.mark.parametrize("traversal", [1, 2])
+@pytest.mark.parametrize("traversal", [1, 2, 3])
 @pytest.mark.parametrize("ordered", [False, True])
 def test_nearest_vertex_brute_force(c1, traversal, ordered):
-    """Both tree walks return the exact nearest vertex, on scattered and on
-    Morton-ordered batches."""
+    """Every traversal returns the exact nearest vertex, on scattered and on
+    Morton-ordered batches, inside and outside the query domain."""
     torch = _torch()
     w, m, om, _ = c1
-    Q = w.Q
+    rng = np.random.default_rng(11)
+    lo, hi = w.domain_lo, w.domain_hi
+    Q = np.concatenate([w.Q, rng.uniform(lo - 0.5 * (hi - lo), hi + 0.5 * (hi - lo), size=(3000, 3)),
+                        np.array([lo, hi, [lo[0], hi[1], lo[2]]])]).astype(np.float32)
     if ordered:
         Q = Q[OM.order(Q, w.domain_lo, w.domain_hi)[1]]
     vid, d2 = m.nearest_vertex(torch.from_numpy(np.ascontiguousarray(Q)).cuda(), traversal=traversal)
@@ -198,9 +204,10 @@ def test_c2_full_size_sampled(c2_full):
     fails, out = _sampled_parity(w, m, 1500, 77)
     assert fails == []
     out1 = _run(m, w.Q[:200_000], traversal=1)
-    out2 = _run(m, w.Q[:200_000], traversal=2)
-    # the two tree walks agree on the nearest vertex up to float64 ties
-    assert np.mean(out1["prim"] == out2["prim"]) > 0.9999
-    assert np.max(np.abs(out1["dist"] - out2["dist"])) <= 1e-5 * 3.8
+    # the traversals agree on the nearest vertex up to float64 ties
+    for t in (2, 3):
+        out2 = _run(m, w.Q[:200_000], traversal=t)
+        assert np.mean(out1["prim"] == out2["prim"]) > 0.9999, t
+        assert np.max(np.abs(out1["dist"] - out2["dist"])) <= 1e-5 * 3.8, t
     assert np.all(np.isfinite(out["dist"])) and np.all(out["dist"] >= 0)
     assert np.all(out["status"] == 0)

@@ -87,10 +87,10 @@ def test_graph_replays_match_eager(batch_setup):
             v.fill_(-1)
 
 
-@pytest.mark.parametrize("shape", [(64, 1, 1), (128, 2, 2), (256, 4, 1), (192, 3, 2)])
+@pytest.mark.parametrize("shape", [(64, 1, 1), (128, 2, 2), (256, 4, 1), (192, 3, 2), (64, 2, 3), (256, 1, 3)])
 def test_launch_shapes_give_same_answers(batch_setup, shape):
     works, meshes, b, Q, off, q = batch_setup
-    b.set_shape(256, 1, 2)
+    b.set_shape(256, 1, 1)
     ref = _np(b.query(q, off))
     b.set_shape(*shape)
     got = _np(b.query(q, off))
@@ -103,7 +103,7 @@ def test_autotune_and_layout_change(batch_setup):
     works, meshes, b, Q, off, q = batch_setup
     ref = _np(b.query(q, off))
     shape = b.autotune(q, off)
-    assert shape[0] in (64, 128, 256) and shape[1] in (1, 2, 4) and shape[2] in (1, 2)
+    assert shape[0] in (64, 128, 256) and shape[1] in (1, 2, 4) and shape[2] in (1, 2, 3)
     got = _np(b.query(q, off))
     assert np.mean(got["prim"] == ref["prim"]) > 0.999
     # a different split of the same rows between meshes: only mesh 0 and 1 swap sizes

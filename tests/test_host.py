@@ -117,6 +117,43 @@ def test_voronoi_neighbours_match_qhull():
     assert all((int(a), int(b)) in mine for a, b in ii)
 
 
+@pytest.mark.parametrize("name", ["tetra", "cube", "sphere", "heightfield", "c1"])
+def test_voronoi_walk_reaches_nearest_vertex(name):
+    """Greedy descent over the neighbour graph (the device's Voronoi-walk
+    traversal) ends at an exact nearest vertex from any start, for every
+    point of D: a point outside Cell(v) is closer to some neighbour of v."""
+    rng = np.random.default_rng(5)
+    if name == "tetra":
+        V, F = TETRA_V, TETRA_F
+    elif name == "cube":
+        V, F = CUBE_V, CUBE_F
+    elif name == "c1":
+        w = C.c1()
+        V, F = w.V, w.F
+    else:
+        V, F = random_tiny_mesh(rng, name)
+    m, st, (lo, hi) = _mesh(V, F, scale=3.0)
+    off, nb = m.neighbors()
+    Vd = V.astype(np.float64)
+    X = rng.uniform(lo, hi, size=(3000, 3))
+    X[:8] = np.array([[lo[0], lo[1], lo[2]], [hi[0], hi[1], hi[2]], [lo[0], hi[1], lo[2]], [hi[0], lo[1], hi[2]],
+                      [lo[0], lo[1], hi[2]], [hi[0], hi[1], lo[2]], [lo[0], hi[1], hi[2]], [hi[0], lo[1], lo[2]]])
+    start = rng.integers(0, len(V), size=len(X))
+    for x, v in zip(X, start):
+        dv = ((x - Vd[v]) ** 2).sum()
+        while True:
+            ns = nb[off[v]:off[v + 1]]
+            if len(ns) == 0:
+                break
+            d = ((x - Vd[ns]) ** 2).sum(1)
+            k = int(d.argmin())
+            if d[k] >= dv:
+                break
+            v, dv = int(ns[k]), d[k]
+        best = ((x - Vd) ** 2).sum(1).min()
+        assert dv <= best * (1 + 1e-12), (name, x)
+
+
 def test_table_contains_incident_primitives():
     """Theorem 2: every vertex intercepts its incident edges and faces."""
     rng = np.random.default_rng(3)
