@@ -40,7 +40,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("query_core.hpp", "p2m_device.hip"):
+    for f in ("query_core.hpp", "nearest.hpp", "wave_kdtree.hpp", "device_common.hpp", "p2m_device.hip"):
         with open(os.path.join(ROOT, "paper_2308_16084_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -64,13 +64,14 @@ def measured_traffic(n_queries: int):
     return float(vals["hbm_bytes_per_launch"])
 
 
-def b_alg(visits: float, steps: float, edges: float, faces: float) -> float:
+def b_alg(visits: float, steps: float, entries: float, edge_forms: float, face_forms: float) -> float:
     """Algorithmic bytes per query: query in (12) + results out (20) + the
     nearest-vertex walk (seed id 4 + seed vertex 16, per step the neighbour
     list offsets 8, per neighbour its id 4 + position 16) + 8 for the
-    interception-list offsets + per edge (id 4 + endpoints' ids 8 +
-    coordinates 24) + per face (id 4 + vertex ids 12 + coordinates 36)."""
-    return 12 + 20 + 20 + 8 * steps + 20 * visits + 8 + 36 * edges + 52 * faces
+    interception-list offsets + 16 per list entry (id + box) + per entry
+    whose box holds q its forms (edge 32, face 48) + the winner's exact
+    re-evaluation (48)."""
+    return 12 + 20 + 20 + 8 * steps + 20 * visits + 8 + 16 * entries + 32 * edge_forms + 48 * face_forms + 48
 
 
 def main():
@@ -84,6 +85,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
     ap.add_argument("--batched-full", action="store_true",
                     help="batched leg on all 256 meshes (default: the first 64 of the same seeded plan)")
+    ap.add_argument("--breakdown", action="store_true",
+                    help="also time the nearest-vertex step alone and the query kernel on pre-sorted queries "
+                         "(extra launches of the same kernel; off by default so profiles average the step only)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB-in / 1 GiB-out elementwise copy kernel (counter calibration)")
     ap.add_argument("--cache", default=os.environ.get("P2M_CACHE_DIR", ""),
@@ -160,41 +164,44 @@ def main():
 
     # cost breakdown: nearest vertex alone vs the whole query kernel, both on
     # the Morton-ordered batch without the ordering step, default traversal
-    _, perm = mesh.order_queries(q)
-    qs = q[perm.long()].contiguous()
-    nv_ms, full_ms = [], []
-    for _ in range(args.steps):
-        e0.record()
-        mesh.nearest_vertex(qs)
-        e1.record()
-        torch.cuda.synchronize()
-        nv_ms.append(e0.elapsed_time(e1))
-        e0.record()
-        mesh.query(qs, out=out, sort=False)
-        e1.record()
-        torch.cuda.synchronize()
-        full_ms.append(e0.elapsed_time(e1))
-    del qs, perm
-    breakdown = {"nearest_vertex_only_ms": round(float(np.mean(nv_ms)), 4),
-                 "query_presorted_ms": round(float(np.mean(full_ms)), 4)}
-    log(f"[bench] breakdown on pre-sorted queries: nearest vertex {breakdown['nearest_vertex_only_ms']:.3f} ms, "
-        f"whole query {breakdown['query_presorted_ms']:.3f} ms")
+    breakdown = None
+    if args.breakdown:
+        _, perm = mesh.order_queries(q)
+        qs = q[perm.long()].contiguous()
+        nv_ms, full_ms = [], []
+        for _ in range(args.steps):
+            e0.record()
+            mesh.nearest_vertex(qs)
+            e1.record()
+            torch.cuda.synchronize()
+            nv_ms.append(e0.elapsed_time(e1))
+            e0.record()
+            mesh.query(qs, out=out, sort=False)
+            e1.record()
+            torch.cuda.synchronize()
+            full_ms.append(e0.elapsed_time(e1))
+        del qs, perm
+        breakdown = {"nearest_vertex_only_ms": round(float(np.mean(nv_ms)), 4),
+                     "query_presorted_ms": round(float(np.mean(full_ms)), 4)}
+        log(f"[bench] breakdown on pre-sorted queries: nearest vertex {breakdown['nearest_vertex_only_ms']:.3f} ms, "
+            f"whole query {breakdown['query_presorted_ms']:.3f} ms")
 
     # algorithmic bytes per query from the same structures (host model counts)
     rng = np.random.default_rng(123)
     sub = w.Q[rng.choice(n, size=min(n, 200_000), replace=False)]
     hs = mesh.query_host(sub)
-    visits, steps = hs["nodes"] / len(sub), hs["steps"] / len(sub)
-    edges, faces = hs["edges"] / len(sub), hs["faces"] / len(sub)
-    balg = b_alg(visits, steps, edges, faces)
+    per = {k: hs[k] / len(sub) for k in ("nodes", "steps", "edges", "faces", "edge_forms", "face_forms")}
+    balg = b_alg(per["nodes"], per["steps"], per["edges"] + per["faces"], per["edge_forms"], per["face_forms"])
     achieved = balg * n / (query_avg / 1e3) / 1e9
     traffic = measured_traffic(n)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_query", "kernel_ms": round(query_avg, 4),
                 "b_alg_bytes_per_query": round(balg, 1),
-                "per_query": {"walk_vertices": round(visits, 2), "walk_steps": round(steps, 2),
-                              "edges_tested": round(edges, 2), "faces_tested": round(faces, 2)}}
+                "per_query": {"walk_vertices": round(per["nodes"], 2), "walk_steps": round(per["steps"], 2),
+                              "edge_entries": round(per["edges"], 2), "face_entries": round(per["faces"], 2),
+                              "edge_forms_read": round(per["edge_forms"], 2),
+                              "face_forms_read": round(per["face_forms"], 2)}}
 
     result = {"metric": "P2M queries/sec at 1.3M tris (fwd, fwd+bwd, batched); % of HBM peak",
               "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -208,8 +215,9 @@ def main():
                          "avg_list": round(float(stats.get("avg_list", 0.0)), 2),
                          "device_bytes": dev_bytes},
               "roofline": roofline,
-              "stages_ms": {"ordering": round(order_avg, 4), "query": round(query_avg, 4)},
-              "breakdown": breakdown}
+              "stages_ms": {"ordering": round(order_avg, 4), "query": round(query_avg, 4)}}
+    if breakdown:
+        result["breakdown"] = breakdown
 
     if not args.no_bwd:
         w5 = C.c5()

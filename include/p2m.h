@@ -131,6 +131,14 @@ p2m_status p2m_precompute(p2m_mesh* m, const p2m_build_opts* opts, p2m_build_sta
  * KD tree: node coordinates xyz float [nv*3] and vertex ids vid int32 [nv] in
  * implicit left-balanced order (children of node i: 2i+1, 2i+2). */
 p2m_status p2m_mesh_table(const p2m_mesh* m, int64_t* nnz, uint32_t* off, int32_t* ent);
+/* Entry boxes of the table (host uint16 [nnz*6], in table order): for each
+ * entry (v, p), lower x, y, z then upper x, y, z of a box holding
+ * ConvexPoly(v,p) = Cell(v) n Space-perp(p) n D (Sec. 4.6 bounds Region(v,p)
+ * <= ConvexPoly(v,p) by its box for the per-list R-tree), in the 16-bit
+ * frame of D: u = (x - lo) * 65535 / (hi - lo), rounded outward and clamped
+ * to [0, 65535]; lower 65535 and upper 0 on every axis for an empty
+ * polytope.  The query tests an entry only when q lies in its box. */
+p2m_status p2m_mesh_table_boxes(const p2m_mesh* m, uint16_t* boxes);
 p2m_status p2m_mesh_neighbors(const p2m_mesh* m, int64_t* nnz, int64_t* nb_off, int32_t* nb);
 p2m_status p2m_mesh_kdtree(const p2m_mesh* m, float* xyz, int32_t* vid);
 
@@ -144,10 +152,11 @@ p2m_status p2m_load(const char* path, p2m_mesh** out);
  * A reported baseline, never used by the device path.  The first call builds
  * a host copy of the seed grid.  counters (may be NULL) receive sums over
  * queries: [0] nearest-vertex candidates evaluated (walk: neighbour
- * vertices; tree: nodes), [1] edges tested, [2] faces tested, [3] walk
- * steps (neighbour lists read). */
+ * vertices; tree: nodes), [1] edge entries and [2] face entries scanned,
+ * [3] walk steps (neighbour lists read), [4] edge and [5] face entries whose
+ * box held q (their forms read and tested). */
 p2m_status p2m_query_host(const p2m_mesh* m, const float* q, int64_t n, int32_t* prim, float* closest,
-                          float* dist, uint8_t* status, int num_threads, int64_t counters[4]);
+                          float* dist, uint8_t* status, int num_threads, int64_t counters[6]);
 
 const char* p2m_last_error(void);
 

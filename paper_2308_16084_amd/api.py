@@ -155,6 +155,13 @@ class Mesh:
         check(lib().p2m_mesh_table(self._h, ctypes.byref(nnz), _ptr(off), _ptr(ent)))
         return off, ent[:nnz.value]
 
+    def table_boxes(self) -> np.ndarray:
+        """Entry boxes uint16 [nnz, 6] (lower xyz, upper xyz in D's 16-bit frame)."""
+        off, _ = self.table()
+        boxes = np.zeros((max(1, int(off[-1])), 6), np.uint16)
+        check(lib().p2m_mesh_table_boxes(self._h, _ptr(boxes)))
+        return boxes[:int(off[-1])]
+
     def neighbors(self) -> tuple[np.ndarray, np.ndarray]:
         nnz = ctypes.c_int64()
         check(lib().p2m_mesh_neighbors(self._h, ctypes.byref(nnz), None, None))
@@ -181,11 +188,12 @@ class Mesh:
         closest = np.zeros((n, 3), np.float32)
         dist = np.zeros(n, np.float32)
         status = np.zeros(n, np.uint8)
-        cnt = np.zeros(4, np.int64)
+        cnt = np.zeros(6, np.int64)
         check(lib().p2m_query_host(self._h, _ptr(q), n, _ptr(prim), _ptr(closest), _ptr(dist), _ptr(status),
                                    int(threads), _ptr(cnt)))
         return {"prim": prim, "closest": closest, "dist": dist, "status": status,
-                "nodes": int(cnt[0]), "edges": int(cnt[1]), "faces": int(cnt[2]), "steps": int(cnt[3])}
+                "nodes": int(cnt[0]), "edges": int(cnt[1]), "faces": int(cnt[2]), "steps": int(cnt[3]),
+                "edge_forms": int(cnt[4]), "face_forms": int(cnt[5])}
 
     # ----------------------------------------------------------- device
     def upload(self, device: int = 0, stream=None) -> int:

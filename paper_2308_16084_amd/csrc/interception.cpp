@@ -169,15 +169,61 @@ void make_edge(const MeshData& m, int64_t e, double tau, Primitive& p) {
     }
 }
 
+// A table entry before packing: key (vertex, kind, id) and the entry's box.
+struct PairRec {
+    uint64_t key;
+    uint16_t box[6];
+};
+
 struct ThreadCtx {
     ConvexCell cell, base;
     double blo_[3], bhi_[3];
+    double qlo_[3], qscale_[3];  // 16-bit frame of D for the entry boxes
     std::vector<uint32_t> stamp;
     uint32_t cur = 0;
     std::vector<int32_t> queue;
-    std::vector<uint64_t> pairs;
+    std::vector<PairRec> pairs;
     int64_t tests = 0, hits = 0, quick = 0, skipped = 0;
 };
+
+// Entry box (Sec. 4.6: the bounding box of Region(w,p), here of the larger
+// ConvexPoly(w,p) = Cell(w) n Space-perp(p) n D with every half-space moved
+// out by tau) in the 16-bit frame of D, rounded outward by one more unit.
+// Lower corner 65535 and upper 0 on every axis: an empty polytope.
+void quantize_box(const ThreadCtx& c, const double lo[3], const double hi[3], uint16_t out[6]) {
+    for (int k = 0; k < 3; ++k) {
+        const double a = std::floor((lo[k] - c.qlo_[k]) * c.qscale_[k]) - 1.0;
+        const double b = std::ceil((hi[k] - c.qlo_[k]) * c.qscale_[k]) + 1.0;
+        out[k] = (uint16_t)std::min(65535.0, std::max(0.0, a));
+        out[3 + k] = (uint16_t)std::min(65535.0, std::max(0.0, b));
+    }
+}
+
+void cell_box(const ThreadCtx& c, const ConvexCell& cell, uint16_t out[6]) {
+    if (cell.empty() || cell.num_corners() == 0) {
+        for (int k = 0; k < 3; ++k) {
+            out[k] = 65535;
+            out[3 + k] = 0;
+        }
+        return;
+    }
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (size_t t = 0; t < cell.num_corners(); ++t) {
+        const double* x = cell.corner(t);
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], x[k]);
+            hi[k] = std::max(hi[k], x[k]);
+        }
+    }
+    quantize_box(c, lo, hi, out);
+}
+
+void full_box(uint16_t out[6]) {
+    for (int k = 0; k < 3; ++k) {
+        out[k] = 0;
+        out[3 + k] = 65535;
+    }
+}
 
 // Space-perp(p) n D (all half-spaces moved outward by tau), built once per
 // primitive; ConvexPoly(w,p) is then this polytope cut by w's cell planes.
@@ -192,16 +238,47 @@ void make_base(const Primitive& p, const double blo[3], const double bhi[3], Thr
     }
 }
 
+// ConvexPoly(w,p) into c.cell: the base polytope cut by w's cell planes.
+// False when it is empty.
+bool clip_to_cell(const CellStore& cs, int64_t w, ThreadCtx& c) {
+    c.cell = c.base;
+    uint32_t np = 0;
+    const double* H = cs.plane_data(w, np);
+    for (uint32_t i = 0; i < np; ++i) {
+        HalfSpace h{{H[4 * i], H[4 * i + 1], H[4 * i + 2]}, H[4 * i + 3]};
+        // the cell's domain-box faces are already faces of the base polytope
+        const int axes = (h.n[0] != 0.0) + (h.n[1] != 0.0) + (h.n[2] != 0.0);
+        if (axes == 1 && (std::fabs(h.n[0]) == 1.0 || std::fabs(h.n[1]) == 1.0 || std::fabs(h.n[2]) == 1.0)) {
+            const int k = h.n[0] != 0.0 ? 0 : (h.n[1] != 0.0 ? 1 : 2);
+            if ((h.n[k] > 0 && h.off == c.bhi_[k]) || (h.n[k] < 0 && h.off == -c.blo_[k])) continue;
+        }
+        ConvexCell::ClipResult r = c.cell.clip(h);
+        if (r == ConvexCell::EMPTY) return false;
+        if (r == ConvexCell::SKIPPED) ++c.skipped;
+    }
+    return true;
+}
+
+// Box of ConvexPoly(w,p) for a vertex of p itself (Theorem 2 keeps it in
+// the list without the filter).
+void own_box(const CellStore& cs, int64_t w, bool base_empty, ThreadCtx& c, uint16_t out[6]) {
+    if (base_empty || !clip_to_cell(cs, w, c)) {
+        c.cell = ConvexCell();
+        cell_box(c, c.cell, out);
+        return;
+    }
+    cell_box(c, c.cell, out);
+}
+
 // Convexity filter (Theorems 5/6) on ConvexPoly(w,p) = Cell(w) n Space-perp(p).
 // A corner x keeps w out when |x-w| <= Dist(x,p) - tau; with Dist <= dmax this
 // follows from the squared test |x-w|^2 + 2 tau dmax <= Dist^2, used here.
+// On a hit, box receives the entry box of (w,p).
 bool intercepts(const MeshData& m, const CellStore& cs, int64_t w, const Primitive& p, double tau, double dmax,
-                bool base_empty, ThreadCtx& c) {
+                bool base_empty, ThreadCtx& c, uint16_t box[6]) {
     ++c.tests;
     const double* W = &m.Vd[3 * (size_t)w];
     const double slack = 2.0 * tau * dmax;
-    const double* blo_ = c.blo_;
-    const double* bhi_ = c.bhi_;
     auto far_enough = [&](const double* x) {
         double d[3] = {x[0] - W[0], x[1] - W[1], x[2] - W[2]};
         return dot3(d, d) + slack <= p.dist2(x);
@@ -217,23 +294,12 @@ bool intercepts(const MeshData& m, const CellStore& cs, int64_t w, const Primiti
         return false;
     }
     if (base_empty) return false;
-    c.cell = c.base;
-    uint32_t np = 0;
-    const double* H = cs.plane_data(w, np);
-    for (uint32_t i = 0; i < np; ++i) {
-        HalfSpace h{{H[4 * i], H[4 * i + 1], H[4 * i + 2]}, H[4 * i + 3]};
-        // the cell's domain-box faces are already faces of the base polytope
-        const int axes = (h.n[0] != 0.0) + (h.n[1] != 0.0) + (h.n[2] != 0.0);
-        if (axes == 1 && (std::fabs(h.n[0]) == 1.0 || std::fabs(h.n[1]) == 1.0 || std::fabs(h.n[2]) == 1.0)) {
-            const int k = h.n[0] != 0.0 ? 0 : (h.n[1] != 0.0 ? 1 : 2);
-            if ((h.n[k] > 0 && h.off == bhi_[k]) || (h.n[k] < 0 && h.off == -blo_[k])) continue;
-        }
-        ConvexCell::ClipResult r = c.cell.clip(h);
-        if (r == ConvexCell::EMPTY) return false;
-        if (r == ConvexCell::SKIPPED) ++c.skipped;
-    }
+    if (!clip_to_cell(cs, w, c)) return false;
     for (size_t t = 0; t < c.cell.num_corners(); ++t)
-        if (!far_enough(c.cell.corner(t))) return true;
+        if (!far_enough(c.cell.corner(t))) {
+            cell_box(c, c.cell, box);
+            return true;
+        }
     return false;
 }
 
@@ -256,10 +322,18 @@ void flood(const MeshData& m, const CellStore& cs, const Table& t, const Primiti
         int32_t w = c.queue[head];
         bool own = false;
         for (int i = 0; i < p.nverts; ++i) own |= (p.verts[i] == w);
-        bool hit = own || intercepts(m, cs, w, p, tau, dmax, base_empty, c);  // Theorem 2 for own vertices
+        PairRec rec;
+        rec.key = pair_key(w, p.face, pid);
+        bool hit;
+        if (own) {  // Theorem 2
+            own_box(cs, w, base_empty, c, rec.box);
+            hit = true;
+        } else {
+            hit = intercepts(m, cs, w, p, tau, dmax, base_empty, c, rec.box);
+        }
         if (!hit) continue;
         ++c.hits;
-        c.pairs.push_back(pair_key(w, p.face, pid));
+        c.pairs.push_back(rec);
         for (int64_t k = t.nb_off[(size_t)w]; k < t.nb_off[(size_t)w + 1]; ++k) {
             int32_t u = t.nb[(size_t)k];
             if (c.stamp[(size_t)u] == c.cur) continue;
@@ -366,6 +440,8 @@ bool build_table(const MeshData& m, const TableOptions& o, Table& t, TableStats&
         for (int k = 0; k < 3; ++k) {
             c.blo_[k] = blo[k];
             c.bhi_[k] = bhi[k];
+            c.qlo_[k] = o.lo[k];
+            c.qscale_[k] = 65535.0 / (o.hi[k] - o.lo[k]);
         }
         Primitive p;
 #pragma omp for schedule(dynamic, 64)
@@ -382,20 +458,25 @@ bool build_table(const MeshData& m, const TableOptions& o, Table& t, TableStats&
                 for (int64_t w = 0; w < nv; ++w) {
                     bool own = false;
                     for (int i = 0; i < p.nverts; ++i) own |= (p.verts[i] == w);
-                    if (o.mode == TABLE_EVERYTHING || own || intercepts(m, cs, w, p, o.tau, dmax, base_empty, c))
-                        c.pairs.push_back(pair_key(w, face, id));
+                    PairRec rec;
+                    rec.key = pair_key(w, face, id);
+                    bool hit = true;
+                    if (o.mode == TABLE_EVERYTHING) full_box(rec.box);
+                    else if (own) own_box(cs, w, base_empty, c, rec.box);
+                    else hit = intercepts(m, cs, w, p, o.tau, dmax, base_empty, c, rec.box);
+                    if (hit) c.pairs.push_back(rec);
                 }
             }
         }
     }
-    std::vector<uint64_t> pairs;
+    std::vector<PairRec> pairs;
     {
         size_t tot = 0;
         for (auto& c : ctx) tot += c.pairs.size();
         pairs.reserve(tot);
         for (auto& c : ctx) {
             pairs.insert(pairs.end(), c.pairs.begin(), c.pairs.end());
-            std::vector<uint64_t>().swap(c.pairs);
+            std::vector<PairRec>().swap(c.pairs);
             st.flood_tests += c.tests;
             st.flood_hits += c.hits;
             st.quick_rejects += c.quick;
@@ -406,10 +487,11 @@ bool build_table(const MeshData& m, const TableOptions& o, Table& t, TableStats&
 
     // 4. CSR: per vertex, edge ids then face ids, each ascending
     t0 = Clock::now();
+    auto by_key = [](const PairRec& a, const PairRec& b) { return a.key < b.key; };
 #ifdef _OPENMP
-    __gnu_parallel::sort(pairs.begin(), pairs.end());
+    __gnu_parallel::sort(pairs.begin(), pairs.end(), by_key);
 #else
-    std::sort(pairs.begin(), pairs.end());
+    std::sort(pairs.begin(), pairs.end(), by_key);
 #endif
     if (pairs.size() >= (size_t)UINT32_MAX) {
         err = "interception table exceeds 2^32 entries";
@@ -417,9 +499,11 @@ bool build_table(const MeshData& m, const TableOptions& o, Table& t, TableStats&
     }
     t.off.assign((size_t)(2 * nv + 1), 0u);
     t.ent.resize(pairs.size());
+    t.box.resize(6 * pairs.size());
     std::vector<uint32_t> ecount((size_t)nv, 0), fcount((size_t)nv, 0);
     for (size_t i = 0; i < pairs.size(); ++i) {
-        uint64_t k = pairs[i];
+        std::memcpy(&t.box[6 * i], pairs[i].box, sizeof(pairs[i].box));
+        uint64_t k = pairs[i].key;
         int64_t v = (int64_t)(k >> 32);
         uint32_t code = (uint32_t)(k & 0xffffffffu);
         t.ent[i] = (int32_t)(code & 0x7fffffffu);

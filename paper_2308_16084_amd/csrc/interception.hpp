@@ -47,6 +47,13 @@ struct Table {
     // ent[off[2v+1] .. off[2v+2]), each ascending.
     std::vector<uint32_t> off;  // [2*nv+1]
     std::vector<int32_t> ent;
+    // Entry boxes, 6 per entry (lower x,y,z then upper x,y,z) in the 16-bit
+    // frame of D: u = (x - lo) * 65535 / (hi - lo), rounded outward by one
+    // unit beyond the floor / ceiling and clamped to [0, 65535].  The box
+    // holds ConvexPoly(v,p) = Cell(v) n Space-perp(p) n D (Sec. 4.6 bounds
+    // Region(v,p), a subset, the same way); a query in D outside it is not in
+    // Space-perp(p) and p is not its answer.
+    std::vector<uint16_t> box;
     // Voronoi (Delaunay) neighbours, kept for inspection.
     std::vector<int64_t> nb_off;
     std::vector<int32_t> nb;

@@ -38,6 +38,93 @@ static float bits_as_float(int32_t i) {
     return f;
 }
 
+// List-scan forms (see query_core.hpp, step 3), built in float64 in
+// coordinates relative to the domain centre rounded to float, then rounded.
+// mu = 2^-20 of the domain diagonal: the float32 error of a form evaluated
+// at a query in D is a few 2^-24 of the domain size, well inside mu.
+static void pack_scan_forms(MeshState& s) {
+    const MeshData& m = s.m;
+    double c[3], diag2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        s.ctr[k] = (float)(0.5 * (s.dlo[k] + s.dhi[k]));
+        c[k] = (double)s.ctr[k];
+        diag2 += (s.dhi[k] - s.dlo[k]) * (s.dhi[k] - s.dlo[k]);
+    }
+    const double mu = std::ldexp(std::sqrt(diag2), -20);
+    s.mu = (float)mu;
+    auto P = [&](int32_t v, double o[3]) {
+        for (int k = 0; k < 3; ++k) o[k] = (double)m.V[3 * (size_t)v + k] - c[k];
+    };
+    auto cross = [](const double a[3], const double b[3], double o[3]) {
+        o[0] = a[1] * b[2] - a[2] * b[1];
+        o[1] = a[2] * b[0] - a[0] * b[2];
+        o[2] = a[0] * b[1] - a[1] * b[0];
+    };
+    auto dot = [](const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+    s.pk_erec.assign((size_t)(8 * m.ne), 0.f);
+    for (int64_t e = 0; e < m.ne; ++e) {
+        double a[3], b[3], u[3];
+        P(m.E[(size_t)(2 * e)], a);
+        P(m.E[(size_t)(2 * e + 1)], b);
+        for (int k = 0; k < 3; ++k) u[k] = b[k] - a[k];
+        const double L = std::sqrt(dot(u, u));
+        float* d = &s.pk_erec[(size_t)(8 * e)];
+        for (int k = 0; k < 3; ++k) {
+            d[k] = (float)a[k];
+            d[4 + k] = (float)(u[k] / L);
+        }
+        d[3] = (float)L;
+    }
+    s.pk_frec.assign((size_t)(12 * m.nf), 0.f);
+    for (int64_t f = 0; f < m.nf; ++f) {
+        double p[3][3];
+        for (int k = 0; k < 3; ++k) P(m.F[(size_t)(3 * f + k)], p[k]);
+        double e1[3], e2[3], n[3];
+        for (int k = 0; k < 3; ++k) {
+            e1[k] = p[1][k] - p[0][k];
+            e2[k] = p[2][k] - p[0][k];
+        }
+        cross(e1, e2, n);
+        const double twice_area = std::sqrt(dot(n, n));
+        for (int k = 0; k < 3; ++k) n[k] /= twice_area;
+        float* d = &s.pk_frec[(size_t)(12 * f)];
+        for (int k = 0; k < 3; ++k) d[k] = (float)n[k];
+        d[3] = (float)dot(n, p[0]);
+        // Barycentric weight of corner i as an affine form r.x - o (the
+        // signed area of x and the opposite side over the face's): r =
+        // n x (p[i+2] - p[i+1]) / 2A, |r| = 1 / height_i.  The corner opposite
+        // the longest side (smallest height) is not stored: its weight is 1
+        // minus the other two, whose rounding, in distance units, is then at
+        // most twice that of a stored form.  Each weight may go down to
+        // -mu / height_i (the foot within mu outside that side).
+        double len[3];
+        for (int i = 0; i < 3; ++i) {
+            double ed[3];
+            for (int k = 0; k < 3; ++k) ed[k] = p[(i + 2) % 3][k] - p[(i + 1) % 3][k];
+            len[i] = std::sqrt(dot(ed, ed));
+        }
+        const int skip = len[0] >= len[1] ? (len[0] >= len[2] ? 0 : 2) : (len[1] >= len[2] ? 1 : 2);
+        // The stored forms give w_i + mu / h_i; the third weight may go down to
+        // -mu / h_skip when their sum is at most 1 + mu (len_0 + len_1 + len_2)
+        // / 2A (this lets it go a further mu (1/h_1 + 1/h_2) <= 2 mu / h_skip,
+        // so its side's margin is at most 3 mu); both forms are divided by that
+        // bound so the test reads <= 1.
+        const double scale = 1.0 / (1.0 + mu * (len[0] + len[1] + len[2]) / twice_area);
+        for (int j = 0; j < 2; ++j) {
+            const int i = (skip + 1 + j) % 3;
+            const double* b = p[(i + 1) % 3];
+            const double* cc = p[(i + 2) % 3];
+            double ed[3], r[3], bc[3];
+            for (int k = 0; k < 3; ++k) ed[k] = cc[k] - b[k];
+            cross(n, ed, r);
+            cross(b, cc, bc);
+            float* o = d + 4 * (j + 1);
+            for (int k = 0; k < 3; ++k) o[k] = (float)(r[k] / twice_area * scale);
+            o[3] = (float)((-dot(n, bc) - mu * len[i]) / twice_area * scale);
+        }
+    }
+}
+
 void pack_mesh(MeshState& s) {
     if (s.packed) return;
     const MeshData& m = s.m;
@@ -94,6 +181,17 @@ void pack_mesh(MeshState& s) {
         }
         s.pk_fedge[(size_t)(4 * f + 3)] = -1;
     }
+    pack_scan_forms(s);
+    // list entries: id + entry box packed into 16 bytes
+    s.pk_lent.resize(4 * s.t.ent.size());
+    for (size_t k = 0; k < s.t.ent.size(); ++k) {
+        const uint16_t* b = &s.t.box[6 * k];
+        uint32_t* o = &s.pk_lent[4 * k];
+        o[0] = (uint32_t)s.t.ent[k];
+        o[1] = (uint32_t)b[0] | ((uint32_t)b[1] << 16);
+        o[2] = (uint32_t)b[2] | ((uint32_t)b[3] << 16);
+        o[3] = (uint32_t)b[4] | ((uint32_t)b[5] << 16);
+    }
     // Voronoi walk: vertex positions with ids, 32-bit neighbour offsets
     s.pk_vpos.resize((size_t)(4 * n));
     for (int64_t v = 0; v < n; ++v) {
@@ -112,10 +210,18 @@ MeshView host_view(const MeshState& s) {
     v.node = (const KdNode*)s.pk_node.data();
     v.nv = (int32_t)s.m.nv;
     v.off = s.t.off.data();
-    v.ent = s.t.ent.data();
+    v.lent = (const uint4*)s.pk_lent.data();
     v.seg = (const float4*)s.pk_seg.data();
     v.tri = (const float4*)s.pk_tri.data();
     v.fedge = s.pk_fedge.data();
+    v.frec = (const float4*)s.pk_frec.data();
+    v.erec = (const float4*)s.pk_erec.data();
+    for (int k = 0; k < 3; ++k) v.ctr[k] = s.ctr[k];
+    v.mu = s.mu;
+    for (int k = 0; k < 3; ++k) {
+        v.qlo[k] = (float)s.dlo[k];
+        v.qs[k] = (float)(65535.0 / (s.dhi[k] - s.dlo[k]));
+    }
     for (int k = 0; k < 3; ++k) {
         v.dlo[k] = float_down(s.dlo[k]);
         v.dhi[k] = float_up(s.dhi[k]);
@@ -144,10 +250,12 @@ MeshView device_view(const MeshState& s) {
     MeshView v = host_view(s);
     v.node = (const KdNode*)s.dev.node;
     v.off = (const uint32_t*)s.dev.off;
-    v.ent = (const int32_t*)s.dev.ent;
+    v.lent = (const uint4*)s.dev.lent;
     v.seg = (const float4*)s.dev.seg;
     v.tri = (const float4*)s.dev.tri;
     v.fedge = (const int32_t*)s.dev.fedge;
+    v.frec = (const float4*)s.dev.frec;
+    v.erec = (const float4*)s.dev.erec;
     v.vpos = (const float4*)s.dev.vpos;
     v.nboff = (const uint32_t*)s.dev.nboff;
     v.nb = (const int32_t*)s.dev.nb;
@@ -410,7 +518,7 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
     auto up = [&](size_t x) { return (x + a - 1) / a * a; };
     const size_t b_node = sizeof(float) * s.pk_node.size();
     const size_t b_off = sizeof(uint32_t) * s.t.off.size();
-    const size_t b_ent = sizeof(int32_t) * std::max<size_t>(1, s.t.ent.size());
+    const size_t b_ent = sizeof(uint32_t) * std::max<size_t>(4, s.pk_lent.size());
     const size_t b_seg = sizeof(float) * s.pk_seg.size();
     const size_t b_tri = sizeof(float) * s.pk_tri.size();
     const size_t b_fe = sizeof(int32_t) * s.pk_fedge.size();
@@ -422,8 +530,10 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
     const size_t b_nboff = sizeof(uint32_t) * s.pk_nboff.size();
     const size_t b_nb = sizeof(int32_t) * std::max<size_t>(1, s.t.nb.size());
     const size_t b_seed = sizeof(int32_t) * (size_t)G * (size_t)G * (size_t)G;
+    const size_t b_frec = sizeof(float) * s.pk_frec.size();
+    const size_t b_erec = sizeof(float) * std::max<size_t>(1, s.pk_erec.size());
     const size_t total = up(b_node) + up(b_off) + up(b_ent) + up(b_seg) + up(b_tri) + up(b_fe) + up(b_vpos) +
-                         up(b_nboff) + up(b_nb) + up(b_seed);
+                         up(b_nboff) + up(b_nb) + up(b_seed) + up(b_frec) + up(b_erec);
     void* base = nullptr;
     hipError_t e = hipMalloc(&base, total);
     if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? P2M_ERR_OOM : P2M_ERR_HIP, "device arena allocation");
@@ -435,7 +545,7 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
     p += up(b_node);
     s.dev.off = p;
     p += up(b_off);
-    s.dev.ent = p;
+    s.dev.lent = p;
     p += up(b_ent);
     s.dev.seg = p;
     p += up(b_seg);
@@ -450,16 +560,22 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
     s.dev.nb = p;
     p += up(b_nb);
     s.dev.seed = p;
+    p += up(b_seed);
+    s.dev.frec = p;
+    p += up(b_frec);
+    s.dev.erec = p;
     hipStream_t st = (hipStream_t)stream;
     struct Cp {
         void* dst;
         const void* src;
         size_t n;
     } cps[] = {{s.dev.node, s.pk_node.data(), b_node}, {s.dev.off, s.t.off.data(), b_off},
-               {s.dev.ent, s.t.ent.data(), s.t.ent.size() * sizeof(int32_t)}, {s.dev.seg, s.pk_seg.data(), b_seg},
+               {s.dev.lent, s.pk_lent.data(), s.pk_lent.size() * sizeof(uint32_t)}, {s.dev.seg, s.pk_seg.data(), b_seg},
                {s.dev.tri, s.pk_tri.data(), b_tri}, {s.dev.fedge, s.pk_fedge.data(), b_fe},
                {s.dev.vpos, s.pk_vpos.data(), b_vpos}, {s.dev.nboff, s.pk_nboff.data(), b_nboff},
-               {s.dev.nb, s.t.nb.data(), s.t.nb.size() * sizeof(int32_t)}};
+               {s.dev.nb, s.t.nb.data(), s.t.nb.size() * sizeof(int32_t)},
+               {s.dev.frec, s.pk_frec.data(), b_frec},
+               {s.dev.erec, s.pk_erec.data(), s.pk_erec.size() * sizeof(float)}};
     for (const Cp& c : cps) {
         if (c.n == 0) continue;
         e = hipMemcpyAsync(c.dst, c.src, c.n, hipMemcpyHostToDevice, st);
@@ -614,7 +730,7 @@ p2m_status p2m_query_backward(p2m_mesh* mh, const float* q, int64_t n, const flo
 }
 
 p2m_status p2m_query_host(const p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, float* closest, float* dist,
-                          uint8_t* status, int num_threads, int64_t counters[4]) {
+                          uint8_t* status, int num_threads, int64_t counters[6]) {
     if (!mh) return fail(P2M_ERR_ARG, "mesh is NULL");
     MeshState& s = const_cast<MeshState&>(mh->s);
     if (!s.precomputed) return fail(P2M_ERR_STATE, "p2m_query_host before p2m_precompute");
@@ -650,12 +766,14 @@ p2m_status p2m_query_host(const p2m_mesh* mh, const float* q, int64_t n, int32_t
     work(0);
     for (auto& x : th) x.join();
     if (counters) {
-        counters[0] = counters[1] = counters[2] = counters[3] = 0;
+        for (int k = 0; k < 6; ++k) counters[k] = 0;
         for (auto& c : cnt) {
             counters[0] += c.nodes;
             counters[1] += c.edges;
             counters[2] += c.faces;
             counters[3] += c.steps;
+            counters[4] += c.edge_forms;
+            counters[5] += c.face_forms;
         }
     }
     return P2M_OK;

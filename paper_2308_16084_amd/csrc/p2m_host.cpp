@@ -169,6 +169,13 @@ p2m_status p2m_mesh_table(const p2m_mesh* m, int64_t* nnz, uint32_t* off, int32_
     return P2M_OK;
 }
 
+p2m_status p2m_mesh_table_boxes(const p2m_mesh* m, uint16_t* boxes) {
+    if (!m || !boxes) return fail(P2M_ERR_ARG, "NULL argument");
+    if (!m->s.precomputed) return fail(P2M_ERR_STATE, "mesh not precomputed");
+    std::memcpy(boxes, m->s.t.box.data(), sizeof(uint16_t) * m->s.t.box.size());
+    return P2M_OK;
+}
+
 p2m_status p2m_mesh_neighbors(const p2m_mesh* m, int64_t* nnz, int64_t* nb_off, int32_t* nb) {
     if (!m || !nnz) return fail(P2M_ERR_ARG, "NULL argument");
     if (!m->s.precomputed) return fail(P2M_ERR_STATE, "mesh not precomputed");
@@ -199,11 +206,11 @@ p2m_status p2m_mesh_kdtree(const p2m_mesh* m, float* xyz, int32_t* vid) {
 //
 // File: magic, version, payload length, payload, FNV-1a of the payload.
 // Payload: domain (6 doubles), tau, then length-prefixed arrays V, F, KD-tree
-// x, y, z, vid, table off, ent, neighbour off, nb.
+// x, y, z, vid, table off, ent, entry boxes, neighbour off, nb.
 
 namespace {
 const char kMagic[8] = {'P', '2', 'M', 'M', 'E', 'S', 'H', '1'};
-const uint32_t kVersion = 2;
+const uint32_t kVersion = 3;
 
 uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
     const unsigned char* p = (const unsigned char*)data;
@@ -269,6 +276,7 @@ p2m_status p2m_save(const p2m_mesh* m, const char* path) {
     w.vec(s.kd.vid);
     w.vec(s.t.off);
     w.vec(s.t.ent);
+    w.vec(s.t.box);
     w.vec(s.t.nb_off);
     w.vec(s.t.nb);
     uint64_t len = w.b.size(), h = fnv1a(w.b.data(), w.b.size());
@@ -326,12 +334,13 @@ p2m_status p2m_load(const char* path, p2m_mesh** out) {
     r.vec(s.kd.vid);
     r.vec(s.t.off);
     r.vec(s.t.ent);
+    r.vec(s.t.box);
     r.vec(s.t.nb_off);
     r.vec(s.t.nb);
     const size_t nv = (size_t)s.m.nv;
     ok = r.ok && r.pos == buf.size() && s.kd.x.size() == nv && s.kd.y.size() == nv && s.kd.z.size() == nv &&
          s.kd.vid.size() == nv && s.t.off.size() == 2 * nv + 1 && s.t.off.back() == s.t.ent.size() &&
-         s.t.nb_off.size() == nv + 1;
+         s.t.box.size() == 6 * s.t.ent.size() && s.t.nb_off.size() == nv + 1;
     for (size_t v = 0; ok && v < nv; ++v) {
         ok = s.kd.vid[v] >= 0 && (size_t)s.kd.vid[v] < nv && s.t.off[2 * v] <= s.t.off[2 * v + 1] &&
              s.t.off[2 * v + 1] <= s.t.off[2 * v + 2];

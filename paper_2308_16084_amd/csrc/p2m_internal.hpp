@@ -28,7 +28,7 @@ struct DeviceMesh {
     int64_t bytes = 0;
     void* node = nullptr;
     void* off = nullptr;
-    void* ent = nullptr;
+    void* lent = nullptr;  // list entries with boxes, uint4 [nnz]
     void* seg = nullptr;
     void* tri = nullptr;
     void* fedge = nullptr;
@@ -38,6 +38,9 @@ struct DeviceMesh {
     void* nboff = nullptr;
     void* nb = nullptr;
     void* seed = nullptr;
+    // list-scan forms: frec float4[3nf], erec float4[2ne]
+    void* frec = nullptr;
+    void* erec = nullptr;
     // ordering scratch (keys/values, double-buffered), grown on demand
     void* scratch = nullptr;
     int64_t scratch_bytes = 0;
@@ -65,6 +68,10 @@ struct MeshState {
     std::vector<float> pk_vpos;                  // 4 floats per vertex (Voronoi walk)
     std::vector<uint32_t> pk_nboff;              // 32-bit neighbour offsets
     std::vector<int32_t> pk_seed;                // host copy of the seed grid (host query only)
+    std::vector<float> pk_frec, pk_erec;         // list-scan forms: 12 floats per face, 8 per edge
+    std::vector<uint32_t> pk_lent;               // list entries: id + packed box, 4 words each
+    float ctr[3] = {0.f, 0.f, 0.f};              // origin of the forms
+    float mu = 0.f;                              // gate margin
     DeviceMesh dev;
 };
 

@@ -1,20 +1,24 @@
 // Per-query arithmetic of the P2M query (Appendix, Algorithm A.2), shared by
 // the device kernels and the host CPU baseline (compiled by hipcc only).
 //
-//  1. nearest vertex v by the KD tree (float32 distances; candidates whose
-//     squared distances agree to within 2^-20 relative are decided in
-//     float64, then by vertex id; subtrees are pruned only when their lower
-//     bound exceeds the best squared distance by more than 2^-20 relative);
+//  1. nearest vertex v (float32 distances; candidates whose squared
+//     distances agree to within 2^-20 relative are decided in float64, then
+//     by vertex id): a greedy walk over the Voronoi neighbour graph, or a
+//     KD-tree search (subtrees pruned only when their lower bound exceeds
+//     the best squared distance by more than 2^-20 relative);
 //  2. d_min <- d(q, v);
-//  3. for every edge and face in v's interception list, the distance to the
-//     closed segment / triangle.  The paper gates each primitive by
-//     Space-perp and then takes the line / plane distance; the clamped test
-//     returns the same value whenever the gate passes and otherwise a
-//     distance to a point of the primitive's boundary, which never
-//     undercuts the true minimum.  So the minimum is unchanged in exact
-//     arithmetic, and rounding in a gate cannot drop the true answer.  The
-//     clamp region tells whether the closest point is inside the face, on
-//     one of its sides or at a corner, which names the primitive returned.
+//  3. scan of v's interception list with the paper's tests: an edge counts
+//     only if the foot of q on its line lies on the edge (q in Space-perp(e))
+//     and then gives the distance to the line; a face counts only if the
+//     foot on its plane lies in the face (q in Space-perp(f)) and gives the
+//     plane distance.  Each gate is evaluated from precomputed affine forms
+//     (plane, barycentric rows, edge direction) with every boundary moved
+//     outward by mu (a 2^-20 fraction of the domain diagonal, several times
+//     the float32 error of the forms), so rounding cannot drop the true
+//     answer and a primitive passes only if q's foot is within mu of it;
+//  4. the winner alone is re-evaluated with the exact closed segment /
+//     triangle distance, whose clamp region (inside, on a side, at a corner)
+//     names the primitive returned, its closest point and weights.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,6 +33,7 @@ namespace p2m {
 constexpr float kTieLo = 0.99999904632568359375f;  // 1 - 2^-20
 constexpr float kTieHi = 1.00000095367431640625f;  // 1 + 2^-20
 constexpr int kMaxDepth = 32;
+constexpr int kScanUnroll = 4;  // list entries evaluated per scan step
 
 enum : int { KIND_VERTEX = 0, KIND_EDGE = 1, KIND_FACE = 2, KIND_NONE = 3 };
 
@@ -36,10 +41,22 @@ struct MeshView {
     const struct KdNode* node;  // [nv] KD-tree nodes (point + child boxes)
     int32_t nv;
     const uint32_t* off;    // [2nv+1]
-    const int32_t* ent;     // [nnz]
+    // list entries: x = primitive id, y..w = entry box in D's 16-bit frame
+    // (y = lo.x | lo.y << 16, z = lo.z | hi.x << 16, w = hi.y | hi.z << 16)
+    const uint4* lent;      // [nnz]
     const float4* seg;      // [2ne]
     const float4* tri;      // [3nf]
     const int32_t* fedge;   // [4nf]
+    // list-scan forms, in coordinates relative to ctr (see step 3 above):
+    // face f: frec[3f] = (unit normal, offset), frec[3f+1..3f+2] = forms of
+    // two barycentric weights (scaled, offsets moved by mu; the third weight
+    // is tested as 1 minus their sum);
+    // edge e: erec[2e] = (a - ctr, length), erec[2e+1] = (unit direction, 0)
+    const float4* frec;     // [3nf]
+    const float4* erec;     // [2ne]
+    float ctr[3];           // centre of the domain box, rounded to float
+    float mu;               // gate margin
+    float qlo[3], qs[3];    // 16-bit frame of D for the entry boxes
     float dlo[3], dhi[3];   // query domain rounded outward to float
     // Voronoi-neighbour walk (optional; null when absent)
     const float4* vpos;     // [nv] vertex x, y, z, id bits
@@ -311,6 +328,7 @@ P2M_HD int32_t make_prim(int kind, int32_t id) { return (int32_t)(((uint32_t)kin
 
 struct ScanCounters {
     uint64_t nodes = 0, edges = 0, faces = 0, steps = 0;  // nodes: nearest-vertex candidates
+    uint64_t edge_forms = 0, face_forms = 0;              // entries whose box held q
 };
 
 P2M_HD Answer nonfinite_answer() {
@@ -327,41 +345,97 @@ P2M_HD uint8_t domain_status(const MeshView& m, float qx, float qy, float qz) {
 }
 
 // Steps 2-3 given the nearest vertex: list scan and the resolved answer.
+// Gated squared distance to the line of edge e (infinite when q's foot is
+// more than mu beyond an end); r* = q - ctr.
+P2M_HD float edge_gate_d2(const MeshView& m, int32_t e, float rx, float ry, float rz) {
+    const float4 A = m.erec[2 * e], U = m.erec[2 * e + 1];
+    const float wx = rx - A.x, wy = ry - A.y, wz = rz - A.z;
+    const float t = wx * U.x + wy * U.y + wz * U.z;
+    const float cx = wx - t * U.x, cy = wy - t * U.y, cz = wz - t * U.z;
+    const float d = cx * cx + cy * cy + cz * cz;
+    const bool in = (t >= -m.mu) & (t <= A.w + m.mu);  // no short-circuit: branch-free
+    return in ? d : INFINITY;
+}
+
+// Gated squared distance to the plane of face f (infinite when q's foot is
+// more than mu outside the face).
+P2M_HD float face_gate_d2(const MeshView& m, int32_t f, float rx, float ry, float rz) {
+    const float4 N = m.frec[3 * f], L1 = m.frec[3 * f + 1], L2 = m.frec[3 * f + 2];
+    const float h = N.x * rx + N.y * ry + N.z * rz - N.w;
+    const float l1 = L1.x * rx + L1.y * ry + L1.z * rz - L1.w;
+    const float l2 = L2.x * rx + L2.y * ry + L2.z * rz - L2.w;
+    const bool in = (l1 >= 0.f) & (l2 >= 0.f) & (l1 + l2 <= 1.f);
+    return in ? h * h : INFINITY;
+}
+
+// q (in D's 16-bit frame) inside the box of list entry e.
+P2M_HD bool in_box(const uint4& e, float ux, float uy, float uz) {
+    const float lx = (float)(e.y & 0xffffu), ly = (float)(e.y >> 16), lz = (float)(e.z & 0xffffu);
+    const float hx = (float)(e.z >> 16), hy = (float)(e.w & 0xffffu), hz = (float)(e.w >> 16);
+    return (ux >= lx) & (ux <= hx) & (uy >= ly) & (uy <= hy) & (uz >= lz) & (uz <= hz);
+}
+
 P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const Nearest& nv, ScanCounters& cnt) {
     Answer a;
-    // running minimum over v and v's list; kind/id/code of the best
+    // running minimum over v and v's list; kind/id of the best
     float best = nv.d2;
     int best_kind = KIND_VERTEX;
     int32_t best_id = nv.vid;
+    const float rx = qx - m.ctr[0], ry = qy - m.ctr[1], rz = qz - m.ctr[2];
     const uint32_t e0 = m.off[2 * nv.vid], f0 = m.off[2 * nv.vid + 1], f1 = m.off[2 * nv.vid + 2];
-    for (uint32_t k = e0; k < f0; ++k) {
-        const int32_t e = m.ent[k];
-        const float4 A = m.seg[2 * e], B = m.seg[2 * e + 1];
-        float t;
-        int r;
-        const float d = seg_d2(qx, qy, qz, A, B, t, r);
-        if (d < best) {
-            best = d;
-            best_kind = KIND_EDGE;
-            best_id = e;
+    // Entry boxes first (Sec. 4.6): an entry whose box does not hold q is
+    // skipped without reading its forms.  q in the 16-bit frame of D,
+    // clamped to it (a query outside D is answered as an upper bound).
+    const float ux = fminf(fmaxf((qx - m.qlo[0]) * m.qs[0], 0.f), 65535.f);
+    const float uy = fminf(fmaxf((qy - m.qlo[1]) * m.qs[1], 0.f), 65535.f);
+    const float uz = fminf(fmaxf((qz - m.qlo[2]) * m.qs[2], 0.f), 65535.f);
+    // kScanUnroll entries per step: all their entry records, then the forms
+    // of those whose box holds q, are loaded before any is evaluated, so a
+    // lane keeps several independent loads in flight; slots past the end
+    // re-read the step's first entry and are discarded.
+    for (uint32_t k = e0; k < f0; k += kScanUnroll) {
+        uint4 en[kScanUnroll];
+#pragma unroll
+        for (int u = 0; u < kScanUnroll; ++u) en[u] = m.lent[k + u < f0 ? k + u : k];
+        float d[kScanUnroll];
+#pragma unroll
+        for (int u = 0; u < kScanUnroll; ++u) {
+            const bool hit = k + u < f0 && in_box(en[u], ux, uy, uz);
+            cnt.edge_forms += hit;
+            d[u] = hit ? edge_gate_d2(m, (int32_t)en[u].x, rx, ry, rz) : INFINITY;
         }
+#pragma unroll
+        for (int u = 0; u < kScanUnroll; ++u)
+            if (d[u] < best) {
+                best = d[u];
+                best_kind = KIND_EDGE;
+                best_id = (int32_t)en[u].x;
+            }
     }
-    for (uint32_t k = f0; k < f1; ++k) {
-        const int32_t f = m.ent[k];
-        const float4 A = m.tri[3 * f], B = m.tri[3 * f + 1], C = m.tri[3 * f + 2];
-        float w0, w1, w2, cx, cy, cz;
-        int r;
-        const float d = tri_d2(qx, qy, qz, A, B, C, w0, w1, w2, r, cx, cy, cz);
-        if (d < best) {
-            best = d;
-            best_kind = KIND_FACE;
-            best_id = f;
+    for (uint32_t k = f0; k < f1; k += kScanUnroll) {
+        uint4 en[kScanUnroll];
+#pragma unroll
+        for (int u = 0; u < kScanUnroll; ++u) en[u] = m.lent[k + u < f1 ? k + u : k];
+        float d[kScanUnroll];
+#pragma unroll
+        for (int u = 0; u < kScanUnroll; ++u) {
+            const bool hit = k + u < f1 && in_box(en[u], ux, uy, uz);
+            cnt.face_forms += hit;
+            d[u] = hit ? face_gate_d2(m, (int32_t)en[u].x, rx, ry, rz) : INFINITY;
         }
+#pragma unroll
+        for (int u = 0; u < kScanUnroll; ++u)
+            if (d[u] < best) {
+                best = d[u];
+                best_kind = KIND_FACE;
+                best_id = (int32_t)en[u].x;
+            }
     }
     cnt.edges += f0 - e0;
     cnt.faces += f1 - f0;
-    // resolve the winner: closest point, weights, reported primitive
-    a.dist = sqrtf(best);
+    // resolve the winner exactly: distance, closest point, weights and the
+    // reported primitive from the closed segment / triangle
+    float exact = nv.d2;
     a.w[0] = 1.f;
     a.w[1] = a.w[2] = 0.f;
     a.pv[1] = a.pv[2] = -1;
@@ -375,7 +449,7 @@ P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const 
         const float4 A = m.seg[2 * best_id], B = m.seg[2 * best_id + 1];
         float t;
         int r;
-        seg_d2(qx, qy, qz, A, B, t, r);
+        exact = seg_d2(qx, qy, qz, A, B, t, r);
         a.cx = A.x + t * (B.x - A.x);
         a.cy = A.y + t * (B.y - A.y);
         a.cz = A.z + t * (B.z - A.z);
@@ -397,7 +471,7 @@ P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const 
         const float4 A = m.tri[3 * best_id], B = m.tri[3 * best_id + 1], C = m.tri[3 * best_id + 2];
         float w0, w1, w2;
         int r;
-        tri_d2(qx, qy, qz, A, B, C, w0, w1, w2, r, a.cx, a.cy, a.cz);
+        exact = tri_d2(qx, qy, qz, A, B, C, w0, w1, w2, r, a.cx, a.cy, a.cz);
         const int32_t ia = as_int(A.w), ib = as_int(B.w), ic = as_int(C.w);
         if (r == 0) {
             a.prim = make_prim(KIND_FACE, best_id);
@@ -424,6 +498,20 @@ P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const 
             a.pv[0] = pid;
         }
     }
+    // a primitive that passed its gate within the margin but is farther than
+    // v in the exact test gives way to v
+    if (best_kind != KIND_VERTEX && !(exact <= nv.d2)) {
+        exact = nv.d2;
+        a.prim = make_prim(KIND_VERTEX, nv.vid);
+        a.cx = nv.px;
+        a.cy = nv.py;
+        a.cz = nv.pz;
+        a.w[0] = 1.f;
+        a.w[1] = a.w[2] = 0.f;
+        a.pv[0] = nv.vid;
+        a.pv[1] = a.pv[2] = -1;
+    }
+    a.dist = sqrtf(exact);
     return a;
 }
 

@@ -154,6 +154,66 @@ def test_voronoi_walk_reaches_nearest_vertex(name):
         assert dv <= best * (1 + 1e-12), (name, x)
 
 
+@pytest.mark.parametrize("name", ["tetra", "cube", "sphere", "heightfield", "c1"])
+def test_entry_boxes_hold_their_polytopes(name):
+    """Every entry (v,p) whose Space-perp(p) holds a point x of D with nearest
+    vertex v has x inside its box (the box bounds Cell(v) n Space-perp(p) n
+    D); boxes of the table lie inside the 16-bit frame and are not all full."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(13)
+    if name == "tetra":
+        V, F = TETRA_V, TETRA_F
+    elif name == "cube":
+        V, F = CUBE_V, CUBE_F
+    elif name == "c1":
+        w = C.c1()
+        V, F = w.V, w.F
+    else:
+        V, F = random_tiny_mesh(rng, name)
+    m, st, (lo, hi) = _mesh(V, F, scale=2.0)
+    off, ent = m.table()
+    box = m.table_boxes().astype(np.int64)
+    assert box.shape == (len(ent), 6)
+    assert np.all(box[:, :3] <= box[:, 3:]) and np.any(box[:, :3] > 0)
+    E = m.edges()
+    Vd = V.astype(np.float64)
+    lo, hi = np.asarray(lo, np.float64), np.asarray(hi, np.float64)
+    # Space-perp(e) (Eq. 4): the foot on the line inside e, and q not on the
+    # face side of the plane through e perpendicular to an adjacent face
+    adj = {}
+    for f, tri in enumerate(F):
+        for i in range(3):
+            a, b = sorted((int(tri[i]), int(tri[(i + 1) % 3])))
+            adj.setdefault((a, b), []).append(int(tri[(i + 2) % 3]))
+    X = rng.uniform(lo, hi, size=(1000 if name == "c1" else 3000, 3))
+    _, nn = cKDTree(Vd).query(X)
+    U = (X - lo) * (65535.0 / (hi - lo))
+    checked = 0
+    for x, u, v in zip(X, U, nn):
+        for k in range(off[2 * v], off[2 * v + 2]):
+            pid = ent[k]
+            if k < off[2 * v + 1]:
+                a, b = Vd[E[pid, 0]], Vd[E[pid, 1]]
+                t = (x - a) @ (b - a) / ((b - a) @ (b - a))
+                inside = 0 < t < 1
+                for c in adj[(int(E[pid, 0]), int(E[pid, 1]))]:
+                    nf = np.cross(b - a, Vd[c] - a)
+                    mm = np.cross(b - a, nf)
+                    if mm @ (Vd[c] - a) < 0:
+                        mm = -mm
+                    inside &= mm @ (x - a) < 0
+            else:
+                a, b, c = Vd[F[pid]]
+                n = np.cross(b - a, c - a)
+                p = x - ((x - a) @ n) / (n @ n) * n
+                w = [np.cross(c - b, p - b) @ n, np.cross(a - c, p - c) @ n, np.cross(b - a, p - a) @ n]
+                inside = min(w) > 0
+            if inside:
+                checked += 1
+                assert np.all(u >= box[k, :3]) and np.all(u <= box[k, 3:]), (name, x, v, k)
+    assert checked > 100
+
+
 def test_table_contains_incident_primitives():
     """Theorem 2: every vertex intercepts its incident edges and faces."""
     rng = np.random.default_rng(3)
@@ -217,6 +277,47 @@ def test_host_query_c1_all_queries():
     h = m.query_host(w.Q)
     assert check_answers(om, w.Q, om.query(w.Q), h["prim"], h["closest"], h["dist"]) == []
     assert st["nv"] == 2562 and st["nf"] == 5120 and st["ne"] == 7680
+
+
+@pytest.mark.parametrize("name", ["c1", "needles"])
+def test_host_query_gate_boundaries(name):
+    """Points where the list scan's gates decide: on edges (midpoints and
+    near the ends), at vertices, on faces, pushed off the surface by tiny
+    and by large amounts, and the far corners of the domain; on C1 and on a
+    heightfield with needle rows."""
+    from synth import mesh as M
+    rng = np.random.default_rng(9)
+    if name == "c1":
+        w = C.c1()
+        V, F = w.V, w.F
+    else:
+        V, F = M.heightfield(24, 77)
+        V, F = V.astype(np.float32), F.astype(np.int32)
+    m, st, (lo, hi) = _mesh(V, F, scale=1.5)
+    om = oracle.OracleMesh(V, F)
+    Vd = V.astype(np.float64)
+    E = om.E
+    tri = Vd[F]
+    n = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    pts = []
+    ke = rng.integers(0, len(E), 400)
+    for t in (0.5, 1e-4, 1 - 1e-4, 0.0):
+        pts.append(Vd[E[ke, 0]] * (1 - t) + Vd[E[ke, 1]] * t)
+    kf = rng.integers(0, len(F), 400)
+    b = rng.dirichlet([1, 1, 1], 400)
+    on_face = (tri[kf] * b[:, :, None]).sum(1)
+    pts.append(on_face)
+    diag = float(np.linalg.norm(hi - lo))
+    for h in (1e-7, 1e-4, 0.05, 0.3):
+        pts.append(on_face + h * diag * n[kf])
+        pts.append(pts[0] + h * diag * rng.normal(size=(400, 3)))
+    corners = np.array([[x, y, z] for x in (lo[0], hi[0]) for y in (lo[1], hi[1]) for z in (lo[2], hi[2])])
+    pts.append(corners)
+    Q = np.clip(np.concatenate(pts), lo, hi).astype(np.float32)
+    h = m.query_host(Q)
+    assert np.all(h["status"] == 0)
+    assert check_answers(om, Q, om.query(Q), h["prim"], h["closest"], h["dist"]) == []
 
 
 def test_table_completeness_dense_sampling():
