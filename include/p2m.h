@@ -86,7 +86,9 @@ typedef struct {
 } p2m_build_stats;
 
 typedef struct {
-    int sort_queries;   /* <0 default (on), 0 off, 1 Morton-order the batch */
+    int sort_queries;   /* <0 default (on), 0 off, 1 Morton-order the batch:
+                           a stable sort by the top 24 bits of the key of
+                           p2m_order_queries (8 per axis: a 256^3 grid on D) */
     int block_size;     /* 0 default (256); else 64, 128, 192 or 256 */
     int profile;        /* nonzero: record HIP events around the ordering and
                            query kernels (read with p2m_query_profile) */
@@ -168,15 +170,18 @@ const char* p2m_last_error(void);
  * device arena size. */
 p2m_status p2m_upload(p2m_mesh* m, int device, void* stream, int64_t* bytes);
 
-/* P2M query of n points q_dev float [n*3] (Algorithm A.2 with exact clamped
- * point-segment / point-triangle tests).  Outputs (device): prim int32 [n],
- * closest float [n*3], dist float [n]; status uint8 [n] (may be NULL).  For
- * the backward pass, bary float [n*3] and pvid int32 [n*3] (both NULL or
- * both set) receive the closest point's barycentric weights over the
- * primitive's vertices (unused slots: weight 0, id -1).  Non-finite queries
- * give P2M_NONE, NaN distance and P2M_Q_NONFINITE.  n = 0 is a no-op.
- * Scratch device memory for ordering is owned by the mesh and reused;
- * concurrent calls on the same mesh from different streams race. */
+/* P2M query of n points q_dev float [n*3] (Algorithm A.2: nearest vertex,
+ * then the gated tests of its interception list, Sec. 4.6 entry boxes
+ * first; the winner re-evaluated with the exact closed segment / triangle
+ * distance).  Outputs (device): prim int32 [n], closest float [n*3], dist
+ * float [n]; status uint8 [n] (may be NULL).  For the backward pass, bary
+ * float [n*3] and pvid int32 [n*3] (both NULL or both set) receive the
+ * closest point's barycentric weights over the primitive's vertices (unused
+ * slots: weight 0, id -1).  Non-finite queries give P2M_NONE, NaN distance
+ * and P2M_Q_NONFINITE.  n = 0 is a no-op.  Scratch device memory (ordering,
+ * and 32 bytes per query of staged answers for an ordered batch) is owned
+ * by the mesh, grown on demand and reused; concurrent calls on the same
+ * mesh from different streams race. */
 p2m_status p2m_query(p2m_mesh* m, const float* q_dev, int64_t n, int32_t* prim_dev, float* closest_dev,
                      float* dist_dev, uint8_t* status_dev, float* bary_dev, int32_t* pvid_dev,
                      const p2m_query_opts* opts, void* stream);

@@ -65,8 +65,9 @@ constexpr int64_t kRadixTile = kRadixThreads * kRadixItems;
 
 RadixPlan radix_plan(int64_t n);
 RadixBuffers radix_buffers(const RadixPlan& p, void* scratch);
-// Sorts keys[0]/vals[0] by the low `bits` bits; returns which buffer (0/1)
-// holds the result.  All work is enqueued on `st`.
-int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int bits, hipStream_t st);
+// Stable sort of keys[0]/vals[0] by bits [lo_bit, hi_bit) of the key (8 bits
+// per pass; the span is a multiple of 8); returns which buffer (0/1) holds
+// the result.  All work is enqueued on `st`.
+int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit, hipStream_t st);
 
 }  // namespace p2m

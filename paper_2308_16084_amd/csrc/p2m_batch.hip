@@ -287,7 +287,7 @@ p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, 
     RadixBuffers rb = radix_buffers(plan, b->scratch);
     k_batch_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(q, n, b->qoff, b->count, b->desc, b->key_bits,
                                                               rb.keys[0], rb.vals[0]);
-    const int cur = radix_sort_pairs(plan, rb, 32, st);
+    const int cur = radix_sort_pairs(plan, rb, 0, 32, st);
     k_reset<<<1, 64, 0, st>>>(b->counter);
     const int grid = b->grid;
     const Arena A{b->node, b->off,  b->lent, b->seg,  b->tri,  b->fedge, b->vpos,

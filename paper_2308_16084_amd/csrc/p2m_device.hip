@@ -292,12 +292,18 @@ __global__ void k_morton(const float* __restrict__ q, int64_t n, float lox, floa
     vals[i] = (int32_t)i;
 }
 
+// stage (ordered batches): query i's answer goes to stage[2i], stage[2i+1]
+// as (prim, closest) and (dist, status) -- one aligned 32-byte record per
+// query instead of four partial cache lines in the output arrays; k_split
+// then writes those arrays with coalesced stores.  Without stage the
+// answer goes to the output arrays directly.
 template <bool kWriteExtras, int kWalk>
 __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const float* __restrict__ q,
                                                 const int32_t* __restrict__ perm, int64_t n, int64_t chunk,
                                                 int32_t* __restrict__ prim, float* __restrict__ closest,
                                                 float* __restrict__ dist, uint8_t* __restrict__ status,
-                                                float* __restrict__ bary, int32_t* __restrict__ pvid) {
+                                                float* __restrict__ bary, int32_t* __restrict__ pvid,
+                                                float4* __restrict__ stage) {
     const int64_t tile = xcd_tile(blockIdx.x, chunk);
     const int64_t j = tile * blockDim.x + threadIdx.x;
     int64_t i = j < n ? (perm ? (int64_t)perm[j] : j) : -1;
@@ -315,18 +321,37 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const floa
     if (i < 0) return;
     uint8_t st = fin ? domain_status(m, qx, qy, qz) : (uint8_t)2;
     const Answer a = fin ? p2m_answer(m, qx, qy, qz, nv, c) : nonfinite_answer();
-    prim[i] = a.prim;
-    closest[3 * i] = a.cx;
-    closest[3 * i + 1] = a.cy;
-    closest[3 * i + 2] = a.cz;
-    dist[i] = a.dist;
-    if (status) status[i] = st;
+    if (stage) {
+        stage[2 * i] = make_float4(__int_as_float(a.prim), a.cx, a.cy, a.cz);
+        stage[2 * i + 1] = make_float4(a.dist, __int_as_float((int)st), 0.f, 0.f);
+    } else {
+        prim[i] = a.prim;
+        closest[3 * i] = a.cx;
+        closest[3 * i + 1] = a.cy;
+        closest[3 * i + 2] = a.cz;
+        dist[i] = a.dist;
+        if (status) status[i] = st;
+    }
     if (kWriteExtras) {
         for (int k = 0; k < 3; ++k) {
             bary[3 * i + k] = a.w[k];
             pvid[3 * i + k] = a.pv[k];
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_split(const float4* __restrict__ stage, int64_t n, int32_t* __restrict__ prim,
+                                               float* __restrict__ closest, float* __restrict__ dist,
+                                               uint8_t* __restrict__ status) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 a = stage[2 * i], b = stage[2 * i + 1];
+    prim[i] = __float_as_int(a.x);
+    closest[3 * i] = a.y;
+    closest[3 * i + 1] = a.z;
+    closest[3 * i + 2] = a.w;
+    dist[i] = b.x;
+    if (status) status[i] = (uint8_t)__float_as_int(b.y);
 }
 
 template <int kWalk>
@@ -429,6 +454,11 @@ __global__ __launch_bounds__(256) void k_backward(const float* __restrict__ q, i
 
 // ------------------------------------------------------------ launches
 
+// The query orders its batch by the top 24 bits of the Morton key (a 256^3
+// grid over D): three sort passes instead of four; within a grid cell the
+// input order is kept.
+constexpr int kQuerySortLoBit = 6;
+
 // traversal option (0 default, 1 per-lane tree, 2 wavefront tree, 3 Voronoi
 // walk) -> Walk.  The Voronoi walk reads a few dozen vertices per query
 // where the tree searches read hundreds of nodes, on ordered and unordered
@@ -476,11 +506,15 @@ static p2m_status ensure_scratch(MeshState& s, int64_t bytes) {
     return P2M_OK;
 }
 
-// Morton keys + stable sort into scratch; returns the permutation pointer.
-static p2m_status order_into_scratch(MeshState& s, const float* q, int64_t n, hipStream_t st, uint32_t** keys_out,
-                                     int32_t** perm_out) {
+// Morton keys + stable sort by key bits [lo_bit, 30) into scratch; returns
+// the permutation pointer.  `extra` bytes of scratch after the sort's own
+// (256-byte aligned) are returned in *extra_out.
+static p2m_status order_into_scratch(MeshState& s, const float* q, int64_t n, int lo_bit, hipStream_t st,
+                                     uint32_t** keys_out, int32_t** perm_out, int64_t extra = 0,
+                                     void** extra_out = nullptr) {
     RadixPlan plan = radix_plan(n);
-    p2m_status r = ensure_scratch(s, plan.bytes);
+    const int64_t sort_bytes = (plan.bytes + 255) / 256 * 256;
+    p2m_status r = ensure_scratch(s, sort_bytes + extra);
     if (r != P2M_OK) return r;
     RadixBuffers b = radix_buffers(plan, s.dev.scratch);
     float lo[3], sc[3];
@@ -489,11 +523,12 @@ static p2m_status order_into_scratch(MeshState& s, const float* q, int64_t n, hi
     k_morton<<<(unsigned)blocks, 256, 0, st>>>(q, n, lo[0], lo[1], lo[2], sc[0], sc[1], sc[2], b.keys[0], b.vals[0]);
     r = check_launch("morton keys");
     if (r != P2M_OK) return r;
-    int cur = radix_sort_pairs(plan, b, 30, st);
+    int cur = radix_sort_pairs(plan, b, lo_bit, 30, st);
     r = check_launch("radix sort");
     if (r != P2M_OK) return r;
     *keys_out = b.keys[cur];
     *perm_out = b.vals[cur];
+    if (extra_out) *extra_out = (char*)s.dev.scratch + sort_bytes;
     return P2M_OK;
 }
 
@@ -624,10 +659,13 @@ p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, flo
         (void)hipEventRecord((hipEvent_t)s.dev.ev[0], st);
     }
     int32_t* perm = nullptr;
+    float4* stage = nullptr;
     if (sort) {
         uint32_t* keys = nullptr;
-        p2m_status r = order_into_scratch(s, q, n, st, &keys, &perm);
+        void* x = nullptr;
+        p2m_status r = order_into_scratch(s, q, n, kQuerySortLoBit, st, &keys, &perm, 32 * n, &x);
         if (r != P2M_OK) return r;
+        stage = (float4*)x;
     }
     if (profile) (void)hipEventRecord((hipEvent_t)s.dev.ev[1], st);
     const MeshView v = device_view(s);
@@ -636,7 +674,7 @@ p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, flo
     const unsigned grid = (unsigned)(chunk * kXcds);
     const int walk = pick_walk(traversal);
 #define P2M_LAUNCH_QUERY(X, W) \
-    k_query<X, W><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid)
+    k_query<X, W><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid, stage)
     if (bary) {
         if (walk == WALK_WAVE) P2M_LAUNCH_QUERY(true, WALK_WAVE);
         else if (walk == WALK_VORONOI) P2M_LAUNCH_QUERY(true, WALK_VORONOI);
@@ -648,6 +686,10 @@ p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, flo
     }
 #undef P2M_LAUNCH_QUERY
     p2m_status r = check_launch("query kernel");
+    if (r == P2M_OK && stage) {
+        k_split<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(stage, n, prim, closest, dist, status);
+        r = check_launch("output split kernel");
+    }
     if (r == P2M_OK && profile) {
         (void)hipEventRecord((hipEvent_t)s.dev.ev[2], st);
         s.dev.ev_recorded = true;
@@ -704,7 +746,7 @@ p2m_status p2m_order_queries(p2m_mesh* mh, const float* q, int64_t n, uint32_t* 
     hipStream_t st = (hipStream_t)stream;
     uint32_t* keys = nullptr;
     int32_t* perm = nullptr;
-    p2m_status r = order_into_scratch(s, q, n, st, &keys, &perm);
+    p2m_status r = order_into_scratch(s, q, n, 0, st, &keys, &perm);
     if (r != P2M_OK) return r;
     hipError_t e = hipMemcpyAsync(keys_out, keys, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess)

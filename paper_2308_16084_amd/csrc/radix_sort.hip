@@ -2,11 +2,14 @@
 //
 // Per 8-bit digit pass: (1) every tile of 4096 keys counts its digits in
 // LDS; (2) an exclusive scan over the digit-major count matrix gives each
-// (digit, tile) its output offset; (3) every tile re-reads its keys in
-// order, 256 at a time, ranks each key among equal digits with wave-wide
-// ballots (stable within a wave), adds the counts of earlier waves and of
-// earlier chunks of the tile, and writes the pair to its place.
+// (digit, tile) its output offset; (3) every tile re-reads its keys, ranks
+// each key among equal digits with wave-wide ballots (stable within a
+// wave), adds the counts of earlier waves and of earlier chunks of the
+// tile, places the pair in LDS in digit order and finally writes each
+// digit's run of the tile to its output offset with coalesced stores.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "device_common.hpp"
 
@@ -98,27 +101,70 @@ __global__ __launch_bounds__(kT) void k_scan_add(uint32_t* __restrict__ a, int64
         if (base + k < n) a[base + k] += add;
 }
 
+// Scatter of one tile: the tile's 4096 pairs are first placed in LDS in
+// digit order (stable: by digit, then by position in the tile), then written
+// out so that consecutive threads write consecutive places of each digit's
+// run -- coalesced runs of ~16 keys instead of one cache line per key.
 __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
                                                       int64_t n, int shift, const uint32_t* __restrict__ offs,
                                                       int64_t tiles, uint32_t* __restrict__ kout,
                                                       int32_t* __restrict__ vout) {
-    __shared__ uint32_t base[256];
+    __shared__ uint32_t gbase[256];  // global start of each digit's run of this tile
+    __shared__ uint32_t lstart[256];  // start of each digit in the tile's LDS order
+    __shared__ uint32_t run[256];     // pairs of each digit placed so far
     __shared__ uint32_t wc[kWaves][256];
+    __shared__ uint32_t lk[kRadixTile];
+    __shared__ int32_t lv[kRadixTile];
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int w = t >> 6;
-    base[t] = offs[(int64_t)t * tiles + blockIdx.x];
+    const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
+    const int cnt = (int)std::min<int64_t>(kRadixTile, n - tile0);
+    gbase[t] = offs[(int64_t)t * tiles + blockIdx.x];
+    run[t] = 0;
+    // digit histogram of the tile and its exclusive scan
+    lstart[t] = 0;
+    __syncthreads();
+    uint32_t key[kI];
+    int32_t val[kI];
+#pragma unroll
+    for (int it = 0; it < kI; ++it) {
+        const int i = it * kT + t;
+        key[it] = i < cnt ? kin[tile0 + i] : 0u;
+        val[it] = i < cnt ? vin[tile0 + i] : 0;
+        if (i < cnt) atomicAdd(&lstart[(key[it] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    {
+        // exclusive scan of 256 counts by the first wave (4 per lane)
+        uint32_t c[4], s = 0;
+        if (w == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                c[k] = lstart[4 * lane + k];
+                s += c[k];
+            }
+            uint32_t incl = s;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t x = __shfl_up(incl, d);
+                if (lane >= d) incl += x;
+            }
+            uint32_t e = incl - s;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                lstart[4 * lane + k] = e;
+                e += c[k];
+            }
+        }
+    }
 #pragma unroll
     for (int k = 0; k < kWaves; ++k) wc[k][t] = 0;
     __syncthreads();
-    const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int it = 0; it < kI; ++it) {
-        const int64_t i = tile0 + (int64_t)it * kT + t;
-        const bool valid = i < n;
-        const uint32_t key = valid ? kin[i] : 0u;
-        const int32_t val = valid ? vin[i] : 0;
-        const uint32_t d = (key >> shift) & 255u;
+        const bool valid = it * kT + t < cnt;
+        const uint32_t d = (key[it] >> shift) & 255u;
         unsigned long long mask = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -130,12 +176,10 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
         if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(mask);
         __syncthreads();
         if (valid) {
-            uint32_t pos = base[d] + rank;
+            uint32_t pos = lstart[d] + run[d] + rank;
             for (int k = 0; k < w; ++k) pos += wc[k][d];
-            if (pos < (uint64_t)n) {
-                kout[pos] = key;
-                vout[pos] = val;
-            }
+            lk[pos] = key[it];
+            lv[pos] = val[it];
         }
         __syncthreads();
         uint32_t tot = 0;
@@ -144,8 +188,18 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
             tot += wc[k][t];
             wc[k][t] = 0;
         }
-        base[t] += tot;
+        run[t] += tot;
         __syncthreads();
+    }
+    // coalesced write-out: LDS place p of digit d goes to gbase[d] + p - lstart[d]
+    for (int p = t; p < cnt; p += kT) {
+        const uint32_t k = lk[p];
+        const uint32_t d = (k >> shift) & 255u;
+        const uint32_t pos = gbase[d] + (uint32_t)p - lstart[d];
+        if (pos < (uint64_t)n) {
+            kout[pos] = k;
+            vout[pos] = lv[p];
+        }
     }
 }
 
@@ -176,10 +230,10 @@ RadixBuffers radix_buffers(const RadixPlan& p, void* scratch) {
     return b;
 }
 
-int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int bits, hipStream_t st) {
+int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit, hipStream_t st) {
     int cur = 0;
     if (p.n <= 1) return cur;
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int shift = lo_bit; shift < hi_bit; shift += 8) {
         k_radix_hist<<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], p.n, shift, b.counts, p.tiles);
         k_scan_local<<<(unsigned)p.scan_blocks, kT, 0, st>>>(b.counts, p.counts, b.sums);
         k_scan_sums<<<1, kT, 0, st>>>(b.sums, p.scan_blocks);
