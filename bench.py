@@ -153,14 +153,16 @@ def main():
     log(f"[bench] forward: {ms_step:.3f} ms/step ({wall / args.steps * 1e3:.3f} ms wall), {qps / 1e9:.3f} Gq/s")
 
     # live per-kernel timing of the dominant (query) kernel over profiled steps
-    order_ms, query_ms = [], []
+    order_ms, query_ms, finish_ms = [], [], []
     for _ in range(args.steps):
         step(profile=True)
-        a, b = mesh.query_profile()
+        a, b, c = mesh.query_profile()
         order_ms.append(a)
         query_ms.append(b)
-    order_avg, query_avg = float(np.mean(order_ms)), float(np.mean(query_ms))
-    log(f"[bench] stage times: ordering {order_avg:.3f} ms, query kernel {query_avg:.3f} ms")
+        finish_ms.append(c)
+    order_avg, query_avg, finish_avg = (float(np.mean(x)) for x in (order_ms, query_ms, finish_ms))
+    log(f"[bench] stage times: ordering {order_avg:.3f} ms, query kernel {query_avg:.3f} ms, "
+        f"answer write-out {finish_avg:.3f} ms")
 
     # cost breakdown: nearest vertex alone vs the whole query kernel, both on
     # the Morton-ordered batch without the ordering step, default traversal
@@ -215,7 +217,8 @@ def main():
                          "avg_list": round(float(stats.get("avg_list", 0.0)), 2),
                          "device_bytes": dev_bytes},
               "roofline": roofline,
-              "stages_ms": {"ordering": round(order_avg, 4), "query": round(query_avg, 4)}}
+              "stages_ms": {"ordering": round(order_avg, 4), "query": round(query_avg, 4),
+                            "write_out": round(finish_avg, 4)}}
     if breakdown:
         result["breakdown"] = breakdown
 

@@ -186,10 +186,12 @@ p2m_status p2m_query(p2m_mesh* m, const float* q_dev, int64_t n, int32_t* prim_d
                      float* dist_dev, uint8_t* status_dev, float* bary_dev, int32_t* pvid_dev,
                      const p2m_query_opts* opts, void* stream);
 
-/* Stage times of the last p2m_query on this mesh that set opts->profile:
- * ordering (Morton keys + sort) and query kernel, in milliseconds, from HIP
- * events recorded on the call's stream.  Waits for those events. */
-p2m_status p2m_query_profile(p2m_mesh* m, float* order_ms, float* query_ms);
+/* Stage times of the last p2m_query on this mesh that set opts->profile, in
+ * milliseconds, from HIP events recorded on the call's stream: ordering
+ * (Morton keys + sort), the query kernel, and the pass that writes staged
+ * answers to the output arrays (0 for an unordered batch).  Any pointer may
+ * be NULL.  Waits for those events. */
+p2m_status p2m_query_profile(p2m_mesh* m, float* order_ms, float* query_ms, float* finish_ms);
 
 /* KD-tree nearest vertex only (the first step of Algorithm A.2): vid int32
  * [n] and squared distance d2 float [n] (may be NULL).  traversal as in

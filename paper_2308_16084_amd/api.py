@@ -228,11 +228,11 @@ class Mesh:
                               ctypes.byref(o), _stream(stream)))
         return out
 
-    def query_profile(self) -> tuple[float, float]:
-        """(ordering ms, query-kernel ms) of the last profiled query."""
-        a, b = ctypes.c_float(), ctypes.c_float()
-        check(lib().p2m_query_profile(self._h, ctypes.byref(a), ctypes.byref(b)))
-        return a.value, b.value
+    def query_profile(self) -> tuple[float, float, float]:
+        """(ordering, query kernel, answer write-out) ms of the last profiled query."""
+        a, b, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+        check(lib().p2m_query_profile(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def nearest_vertex(self, q, traversal: int = 0, stream=None):
         torch = _torch()

@@ -686,30 +686,33 @@ p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, flo
     }
 #undef P2M_LAUNCH_QUERY
     p2m_status r = check_launch("query kernel");
+    if (profile) (void)hipEventRecord((hipEvent_t)s.dev.ev[2], st);
     if (r == P2M_OK && stage) {
         k_split<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(stage, n, prim, closest, dist, status);
         r = check_launch("output split kernel");
     }
     if (r == P2M_OK && profile) {
-        (void)hipEventRecord((hipEvent_t)s.dev.ev[2], st);
+        (void)hipEventRecord((hipEvent_t)s.dev.ev[3], st);
         s.dev.ev_recorded = true;
         s.dev.ev_sorted = sort != 0;
     }
     return r;
 }
 
-p2m_status p2m_query_profile(p2m_mesh* mh, float* order_ms, float* query_ms) {
+p2m_status p2m_query_profile(p2m_mesh* mh, float* order_ms, float* query_ms, float* finish_ms) {
     if (!mh) return fail(P2M_ERR_ARG, "mesh is NULL");
     MeshState& s = mh->s;
     if (!s.dev.ev_recorded) return fail(P2M_ERR_STATE, "no profiled p2m_query on this mesh");
     DeviceGuard g(s.dev.device);
-    float a = 0.f, b = 0.f;
-    hipError_t e = hipEventSynchronize((hipEvent_t)s.dev.ev[2]);
+    float a = 0.f, b = 0.f, c = 0.f;
+    hipError_t e = hipEventSynchronize((hipEvent_t)s.dev.ev[3]);
     if (e == hipSuccess) e = hipEventElapsedTime(&a, (hipEvent_t)s.dev.ev[0], (hipEvent_t)s.dev.ev[1]);
     if (e == hipSuccess) e = hipEventElapsedTime(&b, (hipEvent_t)s.dev.ev[1], (hipEvent_t)s.dev.ev[2]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&c, (hipEvent_t)s.dev.ev[2], (hipEvent_t)s.dev.ev[3]);
     if (e != hipSuccess) return fail(P2M_ERR_HIP, std::string("profile events: ") + hipGetErrorString(e));
     if (order_ms) *order_ms = s.dev.ev_sorted ? a : 0.f;
     if (query_ms) *query_ms = b;
+    if (finish_ms) *finish_ms = s.dev.ev_sorted ? c : 0.f;
     return P2M_OK;
 }
 

@@ -45,7 +45,7 @@ struct DeviceMesh {
     void* scratch = nullptr;
     int64_t scratch_bytes = 0;
     // profiling events (hipEvent_t): start, after ordering, after query
-    void* ev[3] = {nullptr, nullptr, nullptr};
+    void* ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool ev_recorded = false;
     bool ev_sorted = false;
 };
