@@ -42,8 +42,8 @@ __device__ __forceinline__ Nearest nearest_vertex(const MeshView& m, float qx, f
 // D, between 8^3 and 256^3 cells.
 int32_t walk_grid_side(int64_t nv);
 
-// Fills m.grid^3 seeds (nearest vertex of every cell centre) on `st`; m
-// points to device arrays (its seed field is ignored).
-hipError_t launch_seed_grid(const MeshView& m, int32_t* seed, hipStream_t st);
+// Fills m.grid^3 seeds (nearest vertex of every cell centre: position, id
+// bits) on `st`; m points to device arrays (its seed field is ignored).
+hipError_t launch_seed_grid(const MeshView& m, float4* seed, hipStream_t st);
 
 }  // namespace p2m

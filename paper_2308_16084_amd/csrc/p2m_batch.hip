@@ -30,7 +30,7 @@ MeshView host_view(const MeshState& s);
 
 struct BatchMesh {
     int64_t node, off, ent, seg, tri, fedge;  // element offsets into the typed arenas
-    int64_t vpos, nboff, nb, seed;            // Voronoi walk arrays (local ids inside)
+    int64_t nboff, nbrec, seed;               // Voronoi walk arrays (local ids inside)
     int64_t frec, erec;                       // list-scan forms
     int32_t nv;
     int32_t grid;          // seed grid side
@@ -44,8 +44,8 @@ struct BatchMesh {
 // View of mesh d inside the arena.
 __host__ __device__ inline MeshView arena_view(const BatchMesh& d, const KdNode* node, const uint32_t* off,
                                                const uint4* lent, const float4* seg, const float4* tri,
-                                               const int32_t* fedge, const float4* vpos, const uint32_t* nboff,
-                                               const int32_t* nb, const int32_t* seed, const float4* frec,
+                                               const int32_t* fedge, const uint32_t* nboff, const float4* nbrec,
+                                               const float4* seed, const float4* frec,
                                                const float4* erec) {
     MeshView v;
     v.node = node + d.node;
@@ -55,9 +55,8 @@ __host__ __device__ inline MeshView arena_view(const BatchMesh& d, const KdNode*
     v.seg = seg + d.seg;
     v.tri = tri + d.tri;
     v.fedge = fedge + d.fedge;
-    v.vpos = vpos + d.vpos;
     v.nboff = nboff + d.nboff;
-    v.nb = nb + d.nb;
+    v.nbrec = nbrec + d.nbrec;
     v.seed = seed + d.seed;
     v.frec = frec + d.frec;
     v.erec = erec + d.erec;
@@ -93,10 +92,9 @@ struct p2m_batch {
     float4* seg = nullptr;
     float4* tri = nullptr;
     int32_t* fedge = nullptr;
-    float4* vpos = nullptr;
     uint32_t* nboff = nullptr;
-    int32_t* nb = nullptr;
-    int32_t* seed = nullptr;
+    float4* nbrec = nullptr;
+    float4* seed = nullptr;
     float4* frec = nullptr;
     float4* erec = nullptr;
     p2m::BatchMesh* desc = nullptr;
@@ -161,10 +159,9 @@ struct Arena {
     const float4* seg;
     const float4* tri;
     const int32_t* fedge;
-    const float4* vpos;
     const uint32_t* nboff;
-    const int32_t* nb;
-    const int32_t* seed;
+    const float4* nbrec;
+    const float4* seed;
     const float4* frec;
     const float4* erec;
     const BatchMesh* desc;
@@ -183,8 +180,8 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
         __syncthreads();
         if (t >= ntiles) break;  // uniform across the workgroup
         const Tile T = tiles[t];
-        const MeshView v = arena_view(A.desc[T.mesh], A.node, A.off, A.lent, A.seg, A.tri, A.fedge, A.vpos, A.nboff,
-                                      A.nb, A.seed, A.frec, A.erec);
+        const MeshView v = arena_view(A.desc[T.mesh], A.node, A.off, A.lent, A.seg, A.tri, A.fedge, A.nboff, A.nbrec,
+                                      A.seed, A.frec, A.erec);
         for (int r = 0; r < qpl; ++r) {
             const int64_t local = (int64_t)r * blockDim.x + threadIdx.x;
             const int64_t j = (int64_t)T.start + local;
@@ -290,8 +287,8 @@ p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, 
     const int cur = radix_sort_pairs(plan, rb, 0, 32, st);
     k_reset<<<1, 64, 0, st>>>(b->counter);
     const int grid = b->grid;
-    const Arena A{b->node, b->off,  b->lent, b->seg,  b->tri,  b->fedge, b->vpos,
-                  b->nboff, b->nb, b->seed, b->frec, b->erec, b->desc};
+    const Arena A{b->node,  b->off,   b->lent, b->seg,  b->tri,  b->fedge,
+                  b->nboff, b->nbrec, b->seed, b->frec, b->erec, b->desc};
 #define P2M_LAUNCH_BATCH(W)                                                                                  \
     k_batch_query<W><<<grid, b->block, 0, st>>>(A, b->tiles, b->ntiles, b->counter, b->qpl, q, rb.vals[cur], n, \
                                                 prim, closest, dist)
@@ -356,10 +353,10 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
     b->count = count;
     b->key_bits = std::min(10, (32 - mesh_bits) / 3);
     // host staging of the arena
-    std::vector<float> node, seg, tri, vpos, frec, erec;
+    std::vector<float> node, seg, tri, nbrec, frec, erec;
     std::vector<uint32_t> off, nboff;
     std::vector<uint32_t> lent;
-    std::vector<int32_t> fedge, nb;
+    std::vector<int32_t> fedge;
     int64_t seeds = 0;
     std::vector<BatchMesh> desc((size_t)count);
     b->cost.resize((size_t)count);
@@ -373,9 +370,8 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
         d.seg = (int64_t)seg.size() / 4;
         d.tri = (int64_t)tri.size() / 4;
         d.fedge = (int64_t)fedge.size();
-        d.vpos = (int64_t)vpos.size() / 4;
         d.nboff = (int64_t)nboff.size();
-        d.nb = (int64_t)nb.size();
+        d.nbrec = (int64_t)nbrec.size() / 4;
         d.seed = seeds;
         d.frec = (int64_t)frec.size() / 4;
         d.erec = (int64_t)erec.size() / 4;
@@ -402,22 +398,21 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
         seg.insert(seg.end(), s.pk_seg.begin(), s.pk_seg.end());
         tri.insert(tri.end(), s.pk_tri.begin(), s.pk_tri.end());
         fedge.insert(fedge.end(), s.pk_fedge.begin(), s.pk_fedge.end());
-        vpos.insert(vpos.end(), s.pk_vpos.begin(), s.pk_vpos.end());
         nboff.insert(nboff.end(), s.pk_nboff.begin(), s.pk_nboff.end());
-        nb.insert(nb.end(), s.t.nb.begin(), s.t.nb.end());
+        nbrec.insert(nbrec.end(), s.pk_nbrec.begin(), s.pk_nbrec.end());
         frec.insert(frec.end(), s.pk_frec.begin(), s.pk_frec.end());
         erec.insert(erec.end(), s.pk_erec.begin(), s.pk_erec.end());
         b->cost[(size_t)k] = std::log2((double)s.m.nv + 2.0);
     }
-    if (lent.size() / 4 >= (size_t)UINT32_MAX || nb.size() >= (size_t)UINT32_MAX) {
+    if (lent.size() / 4 >= (size_t)UINT32_MAX || nbrec.size() / 4 >= (size_t)UINT32_MAX) {
         delete b;
         return fail(P2M_ERR_ARG, "batch tables exceed 2^32 entries");
     }
-    constexpr int kArrays = 13;
+    constexpr int kArrays = 12;
     const size_t sizes[kArrays] = {4 * node.size(), 4 * off.size(), 4 * std::max<size_t>(4, lent.size()),
                                    4 * seg.size(), 4 * tri.size(), 4 * fedge.size(), sizeof(BatchMesh) * desc.size(),
-                                   4 * vpos.size(), 4 * nboff.size(), 4 * std::max<size_t>(1, nb.size()),
-                                   4 * frec.size(), 4 * std::max<size_t>(1, erec.size()), 4 * (size_t)seeds};
+                                   4 * nboff.size(), 4 * std::max<size_t>(4, nbrec.size()),
+                                   4 * frec.size(), 4 * std::max<size_t>(4, erec.size()), 16 * (size_t)seeds};
     size_t total = 0;
     for (size_t x : sizes) total += (size_t)up256((int64_t)x);
     hipError_t e = hipMalloc(&b->base, total);
@@ -439,23 +434,22 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
     b->tri = (float4*)dst[4];
     b->fedge = (int32_t*)dst[5];
     b->desc = (BatchMesh*)dst[6];
-    b->vpos = (float4*)dst[7];
-    b->nboff = (uint32_t*)dst[8];
-    b->nb = (int32_t*)dst[9];
-    b->frec = (float4*)dst[10];
-    b->erec = (float4*)dst[11];
-    b->seed = (int32_t*)dst[12];
+    b->nboff = (uint32_t*)dst[7];
+    b->nbrec = (float4*)dst[8];
+    b->frec = (float4*)dst[9];
+    b->erec = (float4*)dst[10];
+    b->seed = (float4*)dst[11];
     // the seed grids (last array) are filled on the device below
     const void* src[kArrays - 1] = {node.data(),  off.data(),   lent.data(), seg.data(),  tri.data(), fedge.data(),
-                                    desc.data(), vpos.data(), nboff.data(), nb.data(), frec.data(), erec.data()};
+                                    desc.data(), nboff.data(), nbrec.data(), frec.data(), erec.data()};
     const size_t nbytes[kArrays - 1] = {sizes[0], sizes[1], 4 * lent.size(), sizes[3], sizes[4],  sizes[5],
-                                        sizes[6], sizes[7], sizes[8],       4 * nb.size(), sizes[10], 4 * erec.size()};
+                                        sizes[6], sizes[7], 4 * nbrec.size(), sizes[9], 4 * erec.size()};
     hipStream_t st = (hipStream_t)stream;
     for (int i = 0; i < kArrays - 1 && e == hipSuccess; ++i)
         if (nbytes[i]) e = hipMemcpyAsync(dst[i], src[i], nbytes[i], hipMemcpyHostToDevice, st);
     for (int32_t k = 0; k < count && e == hipSuccess; ++k)
-        e = launch_seed_grid(arena_view(desc[(size_t)k], b->node, b->off, b->lent, b->seg, b->tri, b->fedge, b->vpos,
-                                        b->nboff, b->nb, b->seed, b->frec, b->erec),
+        e = launch_seed_grid(arena_view(desc[(size_t)k], b->node, b->off, b->lent, b->seg, b->tri, b->fedge, b->nboff,
+                                        b->nbrec, b->seed, b->frec, b->erec),
                              b->seed + desc[(size_t)k].seed, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // staging vectors are local
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);

@@ -192,15 +192,18 @@ void pack_mesh(MeshState& s) {
         o[2] = (uint32_t)b[2] | ((uint32_t)b[3] << 16);
         o[3] = (uint32_t)b[4] | ((uint32_t)b[5] << 16);
     }
-    // Voronoi walk: vertex positions with ids, 32-bit neighbour offsets
-    s.pk_vpos.resize((size_t)(4 * n));
-    for (int64_t v = 0; v < n; ++v) {
-        float* d = &s.pk_vpos[(size_t)(4 * v)];
-        for (int k = 0; k < 3; ++k) d[k] = m.V[3 * (size_t)v + k];
-        d[3] = bits_as_float((int32_t)v);
-    }
+    // Voronoi walk: 32-bit neighbour offsets, and each neighbour's position
+    // with its id stored in the neighbour list itself (one 16-byte record per
+    // entry: a walk step reads one contiguous run, no id -> position gather)
     s.pk_nboff.resize(s.t.nb_off.size());
     for (size_t k = 0; k < s.t.nb_off.size(); ++k) s.pk_nboff[k] = (uint32_t)s.t.nb_off[k];
+    s.pk_nbrec.resize(4 * s.t.nb.size());
+    for (size_t k = 0; k < s.t.nb.size(); ++k) {
+        const int32_t w = s.t.nb[k];
+        float* d = &s.pk_nbrec[4 * k];
+        for (int c = 0; c < 3; ++c) d[c] = m.V[3 * (size_t)w + c];
+        d[3] = bits_as_float(w);
+    }
     s.pk_seed.clear();
     s.packed = true;
 }
@@ -226,18 +229,16 @@ MeshView host_view(const MeshState& s) {
         v.dlo[k] = float_down(s.dlo[k]);
         v.dhi[k] = float_up(s.dhi[k]);
     }
-    v.vpos = nullptr;
     v.nboff = nullptr;
-    v.nb = nullptr;
-    v.seed = s.pk_seed.empty() ? nullptr : s.pk_seed.data();
+    v.nbrec = nullptr;
+    v.seed = s.pk_seed.empty() ? nullptr : (const float4*)s.pk_seed.data();
     v.grid = walk_grid_side(s.m.nv);
     for (int k = 0; k < 3; ++k) {
         v.glo[k] = v.dlo[k];
         v.gscale[k] = (float)((double)v.grid / ((double)v.dhi[k] - (double)v.dlo[k]));
     }
-    v.vpos = (const float4*)s.pk_vpos.data();
     v.nboff = s.pk_nboff.data();
-    v.nb = s.t.nb.data();
+    v.nbrec = (const float4*)s.pk_nbrec.data();
     return v;
 }
 
@@ -256,10 +257,9 @@ MeshView device_view(const MeshState& s) {
     v.fedge = (const int32_t*)s.dev.fedge;
     v.frec = (const float4*)s.dev.frec;
     v.erec = (const float4*)s.dev.erec;
-    v.vpos = (const float4*)s.dev.vpos;
     v.nboff = (const uint32_t*)s.dev.nboff;
-    v.nb = (const int32_t*)s.dev.nb;
-    v.seed = (const int32_t*)s.dev.seed;
+    v.nbrec = (const float4*)s.dev.nbrec;
+    v.seed = (const float4*)s.dev.seed;
     return v;
 }
 
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(256) void k_nearest(MeshView m, const float* __rest
 }
 
 // Seed grid of the Voronoi walk: nearest vertex of every cell centre.
-__global__ __launch_bounds__(256) void k_seed_grid(MeshView m, int32_t* __restrict__ seed) {
+__global__ __launch_bounds__(256) void k_seed_grid(MeshView m, float4* __restrict__ seed) {
     const int64_t G = m.grid;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= G * G * G) return;
@@ -382,7 +382,8 @@ __global__ __launch_bounds__(256) void k_seed_grid(MeshView m, int32_t* __restri
     const float cy = m.glo[1] + ((float)iy + 0.5f) / m.gscale[1];
     const float cz = m.glo[2] + ((float)iz + 0.5f) / m.gscale[2];
     uint64_t visits = 0;
-    seed[i] = kdt_nearest(m.node, m.nv, cx, cy, cz, visits).vid;
+    const Nearest b = kdt_nearest(m.node, m.nv, cx, cy, cz, visits);
+    seed[i] = make_float4(b.px, b.py, b.pz, __int_as_float(b.vid));
 }
 
 // Host copy of the seed grid for the host query, same definition as the
@@ -390,7 +391,7 @@ __global__ __launch_bounds__(256) void k_seed_grid(MeshView m, int32_t* __restri
 static void host_seed_grid(MeshState& s, int nt) {
     const MeshView v = host_view(s);
     const int64_t G = v.grid, cells = G * G * G;
-    s.pk_seed.assign((size_t)cells, 0);
+    s.pk_seed.assign((size_t)(4 * cells), 0.f);
     std::atomic<int64_t> cursor{0};
     auto work = [&]() {
         for (;;) {
@@ -402,7 +403,12 @@ static void host_seed_grid(MeshState& s, int nt) {
                 const float cy = v.glo[1] + ((float)iy + 0.5f) / v.gscale[1];
                 const float cz = v.glo[2] + ((float)iz + 0.5f) / v.gscale[2];
                 uint64_t visits = 0;
-                s.pk_seed[(size_t)i] = kdt_nearest(v.node, v.nv, cx, cy, cz, visits).vid;
+                const Nearest b = kdt_nearest(v.node, v.nv, cx, cy, cz, visits);
+                float* d = &s.pk_seed[(size_t)(4 * i)];
+                d[0] = b.px;
+                d[1] = b.py;
+                d[2] = b.pz;
+                d[3] = bits_as_float(b.vid);
             }
         }
     };
@@ -412,7 +418,7 @@ static void host_seed_grid(MeshState& s, int nt) {
     for (auto& x : th) x.join();
 }
 
-hipError_t launch_seed_grid(const MeshView& m, int32_t* seed, hipStream_t st) {
+hipError_t launch_seed_grid(const MeshView& m, float4* seed, hipStream_t st) {
     const int64_t cells = (int64_t)m.grid * m.grid * m.grid;
     k_seed_grid<<<(unsigned)((cells + 255) / 256), 256, 0, st>>>(m, seed);
     return hipGetLastError();
@@ -561,14 +567,13 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
     if (s.t.nb.size() >= (size_t)UINT32_MAX || s.t.nb_off.size() != (size_t)s.m.nv + 1)
         return fail(P2M_ERR_INTERNAL, "Voronoi neighbour graph missing or too large");
     const int32_t G = walk_grid_side(s.m.nv);
-    const size_t b_vpos = sizeof(float) * s.pk_vpos.size();
     const size_t b_nboff = sizeof(uint32_t) * s.pk_nboff.size();
-    const size_t b_nb = sizeof(int32_t) * std::max<size_t>(1, s.t.nb.size());
-    const size_t b_seed = sizeof(int32_t) * (size_t)G * (size_t)G * (size_t)G;
+    const size_t b_nb = sizeof(float) * std::max<size_t>(4, s.pk_nbrec.size());
+    const size_t b_seed = sizeof(float4) * (size_t)G * (size_t)G * (size_t)G;
     const size_t b_frec = sizeof(float) * s.pk_frec.size();
     const size_t b_erec = sizeof(float) * std::max<size_t>(1, s.pk_erec.size());
-    const size_t total = up(b_node) + up(b_off) + up(b_ent) + up(b_seg) + up(b_tri) + up(b_fe) + up(b_vpos) +
-                         up(b_nboff) + up(b_nb) + up(b_seed) + up(b_frec) + up(b_erec);
+    const size_t total = up(b_node) + up(b_off) + up(b_ent) + up(b_seg) + up(b_tri) + up(b_fe) + up(b_nboff) +
+                         up(b_nb) + up(b_seed) + up(b_frec) + up(b_erec);
     void* base = nullptr;
     hipError_t e = hipMalloc(&base, total);
     if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? P2M_ERR_OOM : P2M_ERR_HIP, "device arena allocation");
@@ -588,11 +593,9 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
     p += up(b_tri);
     s.dev.fedge = p;
     p += up(b_fe);
-    s.dev.vpos = p;
-    p += up(b_vpos);
     s.dev.nboff = p;
     p += up(b_nboff);
-    s.dev.nb = p;
+    s.dev.nbrec = p;
     p += up(b_nb);
     s.dev.seed = p;
     p += up(b_seed);
@@ -607,8 +610,8 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
     } cps[] = {{s.dev.node, s.pk_node.data(), b_node}, {s.dev.off, s.t.off.data(), b_off},
                {s.dev.lent, s.pk_lent.data(), s.pk_lent.size() * sizeof(uint32_t)}, {s.dev.seg, s.pk_seg.data(), b_seg},
                {s.dev.tri, s.pk_tri.data(), b_tri}, {s.dev.fedge, s.pk_fedge.data(), b_fe},
-               {s.dev.vpos, s.pk_vpos.data(), b_vpos}, {s.dev.nboff, s.pk_nboff.data(), b_nboff},
-               {s.dev.nb, s.t.nb.data(), s.t.nb.size() * sizeof(int32_t)},
+               {s.dev.nboff, s.pk_nboff.data(), b_nboff},
+               {s.dev.nbrec, s.pk_nbrec.data(), s.pk_nbrec.size() * sizeof(float)},
                {s.dev.frec, s.pk_frec.data(), b_frec},
                {s.dev.erec, s.pk_erec.data(), s.pk_erec.size() * sizeof(float)}};
     for (const Cp& c : cps) {
@@ -619,7 +622,7 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
             return fail(P2M_ERR_HIP, std::string("upload copy: ") + hipGetErrorString(e));
         }
     }
-    e = launch_seed_grid(device_view(s), (int32_t*)s.dev.seed, st);
+    e = launch_seed_grid(device_view(s), (float4*)s.dev.seed, st);
     if (e != hipSuccess) {
         device_release(s);
         return fail(P2M_ERR_HIP, std::string("seed grid kernel: ") + hipGetErrorString(e));

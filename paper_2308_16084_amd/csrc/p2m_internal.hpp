@@ -32,11 +32,10 @@ struct DeviceMesh {
     void* seg = nullptr;
     void* tri = nullptr;
     void* fedge = nullptr;
-    // Voronoi-neighbour walk: vpos float4[nv], nboff uint32[nv+1], nb int32[],
-    // seed int32[grid^3] (nearest vertex of each cell centre of a grid on D)
-    void* vpos = nullptr;
+    // Voronoi-neighbour walk: nboff uint32[nv+1], nbrec float4[nnz] (neighbour
+    // position + id), seed float4[grid^3] (nearest vertex of each cell centre)
     void* nboff = nullptr;
-    void* nb = nullptr;
+    void* nbrec = nullptr;
     void* seed = nullptr;
     // list-scan forms: frec float4[3nf], erec float4[2ne]
     void* frec = nullptr;
@@ -65,9 +64,9 @@ struct MeshState {
     std::vector<float> pk_node;                  // 16 floats per KD-tree node
     std::vector<float> pk_seg, pk_tri;           // 4 floats per entry
     std::vector<int32_t> pk_fedge;               // 4 ints per face
-    std::vector<float> pk_vpos;                  // 4 floats per vertex (Voronoi walk)
     std::vector<uint32_t> pk_nboff;              // 32-bit neighbour offsets
-    std::vector<int32_t> pk_seed;                // host copy of the seed grid (host query only)
+    std::vector<float> pk_nbrec;                 // 4 floats per neighbour entry (position, id)
+    std::vector<float> pk_seed;                  // host copy of the seed grid, 4 floats per cell (host query only)
     std::vector<float> pk_frec, pk_erec;         // list-scan forms: 12 floats per face, 8 per edge
     std::vector<uint32_t> pk_lent;               // list entries: id + packed box, 4 words each
     float ctr[3] = {0.f, 0.f, 0.f};              // origin of the forms

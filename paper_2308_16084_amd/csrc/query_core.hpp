@@ -59,10 +59,9 @@ struct MeshView {
     float qlo[3], qs[3];    // 16-bit frame of D for the entry boxes
     float dlo[3], dhi[3];   // query domain rounded outward to float
     // Voronoi-neighbour walk (optional; null when absent)
-    const float4* vpos;     // [nv] vertex x, y, z, id bits
-    const uint32_t* nboff;  // [nv+1] Voronoi neighbours of each vertex
-    const int32_t* nb;
-    const int32_t* seed;    // [grid^3] nearest vertex of each grid-cell centre
+    const uint32_t* nboff;  // [nv+1] Voronoi neighbours of each vertex, CSR
+    const float4* nbrec;    // [nnz] neighbour position, id bits in .w
+    const float4* seed;     // [grid^3] nearest vertex of each grid-cell centre (position, id bits)
     int32_t grid;
     float glo[3], gscale[3];  // cell = floor((q - glo) * gscale), clamped
 };
@@ -199,7 +198,7 @@ P2M_HD Nearest voronoi_walk(const MeshView& m, float qx, float qy, float qz, uin
     b.d2 = INFINITY;
     b.px = b.py = b.pz = 0.f;
     b.vid = -1;
-    float4 p = m.vpos[m.seed[c]];
+    float4 p = m.seed[c];
     {
         const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
         consider(b, qx, qy, qz, dx * dx + dy * dy + dz * dz, p);
@@ -208,12 +207,19 @@ P2M_HD Nearest voronoi_walk(const MeshView& m, float qx, float qy, float qz, uin
     for (int it = 0; it < cap; ++it) {
         const int32_t v = b.vid;
         ++steps;
-        const uint32_t k1 = m.nboff[v + 1];
-        for (uint32_t k = m.nboff[v]; k < k1; ++k) {
-            p = m.vpos[m.nb[k]];
-            ++visits;
-            const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
-            consider(b, qx, qy, qz, dx * dx + dy * dy + dz * dz, p);
+        const uint32_t k0 = m.nboff[v], k1 = m.nboff[v + 1];
+        // four neighbour records loaded before any is compared; slots past
+        // the end re-read the first record of the group (no effect)
+        for (uint32_t k = k0; k < k1; k += 4) {
+            float4 r[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) r[u] = m.nbrec[k + u < k1 ? k + u : k];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float dx = qx - r[u].x, dy = qy - r[u].y, dz = qz - r[u].z;
+                consider(b, qx, qy, qz, dx * dx + dy * dy + dz * dz, r[u]);
+            }
+            visits += k1 - k < 4 ? k1 - k : 4;
         }
         if (b.vid == v) break;
     }
