@@ -38,7 +38,7 @@ __device__ __forceinline__ Nearest nearest_vertex(const MeshView& m, float qx, f
     return b;
 }
 
-// Side of the seed grid of the Voronoi walk: about 8 cells per vertex over
+// Side of the seed grid of the Voronoi walk: about 27 cells per vertex over
 // D, between 8^3 and 256^3 cells.
 int32_t walk_grid_side(int64_t nv);
 

@@ -29,7 +29,7 @@ void pack_mesh(MeshState& s);
 MeshView host_view(const MeshState& s);
 
 struct BatchMesh {
-    int64_t node, off, ent, seg, tri, fedge;  // element offsets into the typed arenas
+    int64_t node, head, ent, seg, tri, fedge;  // element offsets into the typed arenas
     int64_t nboff, nbrec, seed;               // Voronoi walk arrays (local ids inside)
     int64_t frec, erec;                       // list-scan forms
     int32_t nv;
@@ -42,7 +42,7 @@ struct BatchMesh {
 };
 
 // View of mesh d inside the arena.
-__host__ __device__ inline MeshView arena_view(const BatchMesh& d, const KdNode* node, const uint32_t* off,
+__host__ __device__ inline MeshView arena_view(const BatchMesh& d, const KdNode* node, const uint4* vhead,
                                                const uint4* lent, const float4* seg, const float4* tri,
                                                const int32_t* fedge, const uint32_t* nboff, const float4* nbrec,
                                                const float4* seed, const float4* frec,
@@ -50,7 +50,7 @@ __host__ __device__ inline MeshView arena_view(const BatchMesh& d, const KdNode*
     MeshView v;
     v.node = node + d.node;
     v.nv = d.nv;
-    v.off = off + d.off;
+    v.vhead = vhead + d.head;
     v.lent = lent + d.ent;
     v.seg = seg + d.seg;
     v.tri = tri + d.tri;
@@ -87,7 +87,7 @@ struct p2m_batch {
     void* base = nullptr;
     int64_t bytes = 0;
     p2m::KdNode* node = nullptr;
-    uint32_t* off = nullptr;
+    uint4* vhead = nullptr;
     uint4* lent = nullptr;
     float4* seg = nullptr;
     float4* tri = nullptr;
@@ -154,7 +154,7 @@ __global__ void k_reset(uint32_t* counter) {
 // Arena arrays of a batch, passed by value to the kernel.
 struct Arena {
     const KdNode* node;
-    const uint32_t* off;
+    const uint4* vhead;
     const uint4* lent;
     const float4* seg;
     const float4* tri;
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
         __syncthreads();
         if (t >= ntiles) break;  // uniform across the workgroup
         const Tile T = tiles[t];
-        const MeshView v = arena_view(A.desc[T.mesh], A.node, A.off, A.lent, A.seg, A.tri, A.fedge, A.nboff, A.nbrec,
+        const MeshView v = arena_view(A.desc[T.mesh], A.node, A.vhead, A.lent, A.seg, A.tri, A.fedge, A.nboff, A.nbrec,
                                       A.seed, A.frec, A.erec);
         for (int r = 0; r < qpl; ++r) {
             const int64_t local = (int64_t)r * blockDim.x + threadIdx.x;
@@ -287,7 +287,7 @@ p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, 
     const int cur = radix_sort_pairs(plan, rb, 0, 32, st);
     k_reset<<<1, 64, 0, st>>>(b->counter);
     const int grid = b->grid;
-    const Arena A{b->node,  b->off,   b->lent, b->seg,  b->tri,  b->fedge,
+    const Arena A{b->node,  b->vhead, b->lent, b->seg,  b->tri,  b->fedge,
                   b->nboff, b->nbrec, b->seed, b->frec, b->erec, b->desc};
 #define P2M_LAUNCH_BATCH(W)                                                                                  \
     k_batch_query<W><<<grid, b->block, 0, st>>>(A, b->tiles, b->ntiles, b->counter, b->qpl, q, rb.vals[cur], n, \
@@ -354,7 +354,7 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
     b->key_bits = std::min(10, (32 - mesh_bits) / 3);
     // host staging of the arena
     std::vector<float> node, seg, tri, nbrec, frec, erec;
-    std::vector<uint32_t> off, nboff;
+    std::vector<uint32_t> vhead, nboff;
     std::vector<uint32_t> lent;
     std::vector<int32_t> fedge;
     int64_t seeds = 0;
@@ -365,8 +365,8 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
         pack_mesh(s);
         BatchMesh& d = desc[(size_t)k];
         d.node = (int64_t)node.size() / 16;
-        d.off = (int64_t)off.size();
-        d.ent = (int64_t)lent.size() / 4;
+        d.head = (int64_t)vhead.size() / 4;
+        d.ent = (int64_t)lent.size() / 4;  // uint4 elements (two entries each)
         d.seg = (int64_t)seg.size() / 4;
         d.tri = (int64_t)tri.size() / 4;
         d.fedge = (int64_t)fedge.size();
@@ -393,7 +393,7 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
         }
         d.mu = hv.mu;
         node.insert(node.end(), s.pk_node.begin(), s.pk_node.end());
-        off.insert(off.end(), s.t.off.begin(), s.t.off.end());
+        vhead.insert(vhead.end(), s.pk_vhead.begin(), s.pk_vhead.end());
         lent.insert(lent.end(), s.pk_lent.begin(), s.pk_lent.end());
         seg.insert(seg.end(), s.pk_seg.begin(), s.pk_seg.end());
         tri.insert(tri.end(), s.pk_tri.begin(), s.pk_tri.end());
@@ -409,7 +409,7 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
         return fail(P2M_ERR_ARG, "batch tables exceed 2^32 entries");
     }
     constexpr int kArrays = 12;
-    const size_t sizes[kArrays] = {4 * node.size(), 4 * off.size(), 4 * std::max<size_t>(4, lent.size()),
+    const size_t sizes[kArrays] = {4 * node.size(), 4 * vhead.size(), 4 * std::max<size_t>(4, lent.size()),
                                    4 * seg.size(), 4 * tri.size(), 4 * fedge.size(), sizeof(BatchMesh) * desc.size(),
                                    4 * nboff.size(), 4 * std::max<size_t>(4, nbrec.size()),
                                    4 * frec.size(), 4 * std::max<size_t>(4, erec.size()), 16 * (size_t)seeds};
@@ -428,7 +428,7 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
         p += up256((int64_t)sizes[i]);
     }
     b->node = (KdNode*)dst[0];
-    b->off = (uint32_t*)dst[1];
+    b->vhead = (uint4*)dst[1];
     b->lent = (uint4*)dst[2];
     b->seg = (float4*)dst[3];
     b->tri = (float4*)dst[4];
@@ -440,7 +440,7 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
     b->erec = (float4*)dst[10];
     b->seed = (float4*)dst[11];
     // the seed grids (last array) are filled on the device below
-    const void* src[kArrays - 1] = {node.data(),  off.data(),   lent.data(), seg.data(),  tri.data(), fedge.data(),
+    const void* src[kArrays - 1] = {node.data(),  vhead.data(), lent.data(), seg.data(),  tri.data(), fedge.data(),
                                     desc.data(), nboff.data(), nbrec.data(), frec.data(), erec.data()};
     const size_t nbytes[kArrays - 1] = {sizes[0], sizes[1], 4 * lent.size(), sizes[3], sizes[4],  sizes[5],
                                         sizes[6], sizes[7], 4 * nbrec.size(), sizes[9], 4 * erec.size()};
@@ -448,7 +448,7 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
     for (int i = 0; i < kArrays - 1 && e == hipSuccess; ++i)
         if (nbytes[i]) e = hipMemcpyAsync(dst[i], src[i], nbytes[i], hipMemcpyHostToDevice, st);
     for (int32_t k = 0; k < count && e == hipSuccess; ++k)
-        e = launch_seed_grid(arena_view(desc[(size_t)k], b->node, b->off, b->lent, b->seg, b->tri, b->fedge, b->nboff,
+        e = launch_seed_grid(arena_view(desc[(size_t)k], b->node, b->vhead, b->lent, b->seg, b->tri, b->fedge, b->nboff,
                                         b->nbrec, b->seed, b->frec, b->erec),
                              b->seed + desc[(size_t)k].seed, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // staging vectors are local

@@ -125,6 +125,63 @@ static void pack_scan_forms(MeshState& s) {
     }
 }
 
+// List heads and 8-byte list entries (see MeshView::vhead, ::lent): each
+// entry box re-quantised to 5 bits per coordinate inside the list box (the
+// union of the list's entry boxes), rounded outward; runs padded to even
+// length with empty-box entries.
+static void pack_lists(MeshState& s) {
+    const Table& t = s.t;
+    const int64_t nv = s.m.nv;
+    const uint32_t kEmpty = 31u | 31u << 5 | 31u << 10;  // lower corner 31, upper 0
+    s.pk_vhead.assign((size_t)(8 * nv), 0u);
+    s.pk_lent.clear();
+    s.pk_lent.reserve(2 * t.ent.size() + 4 * (size_t)nv);
+    for (int64_t v = 0; v < nv; ++v) {
+        const uint32_t a = t.off[(size_t)(2 * v)], b = t.off[(size_t)(2 * v + 1)], c = t.off[(size_t)(2 * v + 2)];
+        uint32_t lo[3] = {65535u, 65535u, 65535u}, hi[3] = {0u, 0u, 0u};
+        for (uint32_t k = a; k < c; ++k) {
+            const uint16_t* bx = &t.box[6 * (size_t)k];
+            if (bx[0] > bx[3] || bx[1] > bx[4] || bx[2] > bx[5]) continue;  // empty
+            for (int i = 0; i < 3; ++i) {
+                lo[i] = std::min<uint32_t>(lo[i], bx[i]);
+                hi[i] = std::max<uint32_t>(hi[i], bx[3 + i]);
+            }
+        }
+        if (lo[0] > hi[0]) lo[0] = lo[1] = lo[2] = hi[0] = hi[1] = hi[2] = 0u;  // no entry holds any point
+        uint32_t* h = &s.pk_vhead[(size_t)(8 * v)];
+        h[4] = lo[0] | lo[1] << 16;
+        h[5] = lo[2] | hi[0] << 16;
+        h[6] = hi[1] | hi[2] << 16;
+        auto run = [&](uint32_t k0, uint32_t k1) {
+            for (uint32_t k = k0; k < k1; ++k) {
+                const uint16_t* bx = &t.box[6 * (size_t)k];
+                uint32_t code = kEmpty;
+                if (!(bx[0] > bx[3] || bx[1] > bx[4] || bx[2] > bx[5])) {
+                    code = 0u;
+                    for (int i = 0; i < 3; ++i) {
+                        const double span = (double)std::max<uint32_t>(hi[i] - lo[i], 1u);
+                        const double l = std::floor(((double)bx[i] - lo[i]) * 31.0 / span);
+                        const double u = std::ceil(((double)bx[3 + i] - lo[i]) * 31.0 / span);
+                        code |= (uint32_t)std::min(31.0, std::max(0.0, l)) << (5 * i);
+                        code |= (uint32_t)std::min(31.0, std::max(0.0, u)) << (15 + 5 * i);
+                    }
+                }
+                s.pk_lent.push_back((uint32_t)t.ent[k]);
+                s.pk_lent.push_back(code);
+            }
+            if ((k1 - k0) & 1u) {
+                s.pk_lent.push_back(0u);
+                s.pk_lent.push_back(kEmpty);
+            }
+        };
+        h[0] = (uint32_t)(s.pk_lent.size() / 2);
+        run(a, b);
+        h[1] = (uint32_t)(s.pk_lent.size() / 2);
+        run(b, c);
+        h[2] = (uint32_t)(s.pk_lent.size() / 2);
+    }
+}
+
 void pack_mesh(MeshState& s) {
     if (s.packed) return;
     const MeshData& m = s.m;
@@ -182,16 +239,7 @@ void pack_mesh(MeshState& s) {
         s.pk_fedge[(size_t)(4 * f + 3)] = -1;
     }
     pack_scan_forms(s);
-    // list entries: id + entry box packed into 16 bytes
-    s.pk_lent.resize(4 * s.t.ent.size());
-    for (size_t k = 0; k < s.t.ent.size(); ++k) {
-        const uint16_t* b = &s.t.box[6 * k];
-        uint32_t* o = &s.pk_lent[4 * k];
-        o[0] = (uint32_t)s.t.ent[k];
-        o[1] = (uint32_t)b[0] | ((uint32_t)b[1] << 16);
-        o[2] = (uint32_t)b[2] | ((uint32_t)b[3] << 16);
-        o[3] = (uint32_t)b[4] | ((uint32_t)b[5] << 16);
-    }
+    pack_lists(s);
     // Voronoi walk: 32-bit neighbour offsets, and each neighbour's position
     // with its id stored in the neighbour list itself (one 16-byte record per
     // entry: a walk step reads one contiguous run, no id -> position gather)
@@ -212,7 +260,7 @@ MeshView host_view(const MeshState& s) {
     MeshView v;
     v.node = (const KdNode*)s.pk_node.data();
     v.nv = (int32_t)s.m.nv;
-    v.off = s.t.off.data();
+    v.vhead = (const uint4*)s.pk_vhead.data();
     v.lent = (const uint4*)s.pk_lent.data();
     v.seg = (const float4*)s.pk_seg.data();
     v.tri = (const float4*)s.pk_tri.data();
@@ -243,14 +291,14 @@ MeshView host_view(const MeshState& s) {
 }
 
 int32_t walk_grid_side(int64_t nv) {
-    const double g = std::ceil(2.0 * std::cbrt((double)std::max<int64_t>(nv, 1)));
+    const double g = std::ceil(3.0 * std::cbrt((double)std::max<int64_t>(nv, 1)));
     return (int32_t)std::min(256.0, std::max(8.0, g));
 }
 
 MeshView device_view(const MeshState& s) {
     MeshView v = host_view(s);
     v.node = (const KdNode*)s.dev.node;
-    v.off = (const uint32_t*)s.dev.off;
+    v.vhead = (const uint4*)s.dev.vhead;
     v.lent = (const uint4*)s.dev.lent;
     v.seg = (const float4*)s.dev.seg;
     v.tri = (const float4*)s.dev.tri;
@@ -558,7 +606,7 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
     const size_t a = 256;
     auto up = [&](size_t x) { return (x + a - 1) / a * a; };
     const size_t b_node = sizeof(float) * s.pk_node.size();
-    const size_t b_off = sizeof(uint32_t) * s.t.off.size();
+    const size_t b_off = sizeof(uint32_t) * s.pk_vhead.size();
     const size_t b_ent = sizeof(uint32_t) * std::max<size_t>(4, s.pk_lent.size());
     const size_t b_seg = sizeof(float) * s.pk_seg.size();
     const size_t b_tri = sizeof(float) * s.pk_tri.size();
@@ -583,7 +631,7 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
     char* p = (char*)base;
     s.dev.node = p;
     p += up(b_node);
-    s.dev.off = p;
+    s.dev.vhead = p;
     p += up(b_off);
     s.dev.lent = p;
     p += up(b_ent);
@@ -607,7 +655,7 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
         void* dst;
         const void* src;
         size_t n;
-    } cps[] = {{s.dev.node, s.pk_node.data(), b_node}, {s.dev.off, s.t.off.data(), b_off},
+    } cps[] = {{s.dev.node, s.pk_node.data(), b_node}, {s.dev.vhead, s.pk_vhead.data(), b_off},
                {s.dev.lent, s.pk_lent.data(), s.pk_lent.size() * sizeof(uint32_t)}, {s.dev.seg, s.pk_seg.data(), b_seg},
                {s.dev.tri, s.pk_tri.data(), b_tri}, {s.dev.fedge, s.pk_fedge.data(), b_fe},
                {s.dev.nboff, s.pk_nboff.data(), b_nboff},

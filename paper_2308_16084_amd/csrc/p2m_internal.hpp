@@ -27,7 +27,7 @@ struct DeviceMesh {
     void* base = nullptr;
     int64_t bytes = 0;
     void* node = nullptr;
-    void* off = nullptr;
+    void* vhead = nullptr;  // list heads, uint4 [2nv]
     void* lent = nullptr;  // list entries with boxes, uint4 [nnz]
     void* seg = nullptr;
     void* tri = nullptr;
@@ -68,7 +68,8 @@ struct MeshState {
     std::vector<float> pk_nbrec;                 // 4 floats per neighbour entry (position, id)
     std::vector<float> pk_seed;                  // host copy of the seed grid, 4 floats per cell (host query only)
     std::vector<float> pk_frec, pk_erec;         // list-scan forms: 12 floats per face, 8 per edge
-    std::vector<uint32_t> pk_lent;               // list entries: id + packed box, 4 words each
+    std::vector<uint32_t> pk_vhead;              // list heads: 8 words per vertex
+    std::vector<uint32_t> pk_lent;               // list entries: id + 5-bit box, 2 words each, runs padded
     float ctr[3] = {0.f, 0.f, 0.f};              // origin of the forms
     float mu = 0.f;                              // gate margin
     DeviceMesh dev;

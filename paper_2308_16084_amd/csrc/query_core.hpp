@@ -33,17 +33,22 @@ namespace p2m {
 constexpr float kTieLo = 0.99999904632568359375f;  // 1 - 2^-20
 constexpr float kTieHi = 1.00000095367431640625f;  // 1 + 2^-20
 constexpr int kMaxDepth = 32;
-constexpr int kScanUnroll = 4;  // list entries evaluated per scan step
+constexpr int kWalkGroup = 8;   // neighbour records loaded per walk group
 
 enum : int { KIND_VERTEX = 0, KIND_EDGE = 1, KIND_FACE = 2, KIND_NONE = 3 };
 
 struct MeshView {
     const struct KdNode* node;  // [nv] KD-tree nodes (point + child boxes)
     int32_t nv;
-    const uint32_t* off;    // [2nv+1]
-    // list entries: x = primitive id, y..w = entry box in D's 16-bit frame
-    // (y = lo.x | lo.y << 16, z = lo.z | hi.x << 16, w = hi.y | hi.z << 16)
-    const uint4* lent;      // [nnz]
+    // list head of vertex v: vhead[2v] = (first edge entry, first face entry,
+    // end, 0); vhead[2v+1] = list box (union of the entry boxes) in D's
+    // 16-bit frame: (lo.x | lo.y << 16, lo.z | hi.x << 16, hi.y | hi.z << 16, 0)
+    const uint4* vhead;     // [2nv]
+    // list entries, two per element: (id, box) with the box in 5 bits per
+    // coordinate relative to the list box (lo.x, lo.y, lo.z, hi.x, hi.y,
+    // hi.z from bit 0 up); each vertex's edge and face runs start at an even
+    // entry and are padded to an even length with empty-box entries
+    const uint4* lent;      // [padded nnz / 2]
     const float4* seg;      // [2ne]
     const float4* tri;      // [3nf]
     const int32_t* fedge;   // [4nf]
@@ -208,18 +213,18 @@ P2M_HD Nearest voronoi_walk(const MeshView& m, float qx, float qy, float qz, uin
         const int32_t v = b.vid;
         ++steps;
         const uint32_t k0 = m.nboff[v], k1 = m.nboff[v + 1];
-        // four neighbour records loaded before any is compared; slots past
-        // the end re-read the first record of the group (no effect)
-        for (uint32_t k = k0; k < k1; k += 4) {
-            float4 r[4];
+        // kWalkGroup neighbour records loaded before any is compared; slots
+        // past the end re-read the first record of the group (no effect)
+        for (uint32_t k = k0; k < k1; k += kWalkGroup) {
+            float4 r[kWalkGroup];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) r[u] = m.nbrec[k + u < k1 ? k + u : k];
+            for (int u = 0; u < kWalkGroup; ++u) r[u] = m.nbrec[k + u < k1 ? k + u : k];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kWalkGroup; ++u) {
                 const float dx = qx - r[u].x, dy = qy - r[u].y, dz = qz - r[u].z;
                 consider(b, qx, qy, qz, dx * dx + dy * dy + dz * dz, r[u]);
             }
-            visits += k1 - k < 4 ? k1 - k : 4;
+            visits += k1 - k < (uint32_t)kWalkGroup ? k1 - k : (uint32_t)kWalkGroup;
         }
         if (b.vid == v) break;
     }
@@ -374,11 +379,22 @@ P2M_HD float face_gate_d2(const MeshView& m, int32_t f, float rx, float ry, floa
     return in ? h * h : INFINITY;
 }
 
-// q (in D's 16-bit frame) inside the box of list entry e.
-P2M_HD bool in_box(const uint4& e, float ux, float uy, float uz) {
-    const float lx = (float)(e.y & 0xffffu), ly = (float)(e.y >> 16), lz = (float)(e.z & 0xffffu);
-    const float hx = (float)(e.z >> 16), hy = (float)(e.w & 0xffffu), hz = (float)(e.w >> 16);
+// q (in the list box's 5-bit frame) inside an entry's box.
+P2M_HD bool in_box5(uint32_t b, float ux, float uy, float uz) {
+    const float lx = (float)(b & 31u), ly = (float)((b >> 5) & 31u), lz = (float)((b >> 10) & 31u);
+    const float hx = (float)((b >> 15) & 31u), hy = (float)((b >> 20) & 31u), hz = (float)((b >> 25) & 31u);
     return (ux >= lx) & (ux <= hx) & (uy >= ly) & (uy <= hy) & (uz >= lz) & (uz <= hz);
+}
+
+// Coordinate of q in the 5-bit frame of a list box side [lo, hi] (16-bit
+// units of D), clamped to [0, 31].  Inside the list box the entry boxes
+// keep a 16-bit unit of margin beyond their polytopes, far above the
+// rounding of this rescale, except where both the box and q were clamped
+// to D's edge; the clamp here keeps that case exact.  A q outside the list
+// box is moved onto it, which can only let more entries through.
+P2M_HD float frame5(float u, uint32_t lo, uint32_t hi) {
+    const float span = (float)(hi > lo ? hi - lo : 1u);
+    return fminf(fmaxf((u - (float)lo) * (31.f / span), 0.f), 31.f);
 }
 
 P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const Nearest& nv, ScanCounters& cnt) {
@@ -388,53 +404,57 @@ P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const 
     int best_kind = KIND_VERTEX;
     int32_t best_id = nv.vid;
     const float rx = qx - m.ctr[0], ry = qy - m.ctr[1], rz = qz - m.ctr[2];
-    const uint32_t e0 = m.off[2 * nv.vid], f0 = m.off[2 * nv.vid + 1], f1 = m.off[2 * nv.vid + 2];
+    const uint4 h0 = m.vhead[2 * nv.vid], h1 = m.vhead[2 * nv.vid + 1];
+    const uint32_t e0 = h0.x, f0 = h0.y, f1 = h0.z;
     // Entry boxes first (Sec. 4.6): an entry whose box does not hold q is
     // skipped without reading its forms.  q in the 16-bit frame of D,
-    // clamped to it (a query outside D is answered as an upper bound).
+    // clamped to it (a query outside D is answered as an upper bound), then
+    // in the 5-bit frame of the list box.
     const float ux = fminf(fmaxf((qx - m.qlo[0]) * m.qs[0], 0.f), 65535.f);
     const float uy = fminf(fmaxf((qy - m.qlo[1]) * m.qs[1], 0.f), 65535.f);
     const float uz = fminf(fmaxf((qz - m.qlo[2]) * m.qs[2], 0.f), 65535.f);
-    // kScanUnroll entries per step: all their entry records, then the forms
-    // of those whose box holds q, are loaded before any is evaluated, so a
-    // lane keeps several independent loads in flight; slots past the end
-    // re-read the step's first entry and are discarded.
-    for (uint32_t k = e0; k < f0; k += kScanUnroll) {
-        uint4 en[kScanUnroll];
+    const float sx = frame5(ux, h1.x & 0xffffu, h1.y >> 16);
+    const float sy = frame5(uy, h1.x >> 16, h1.z & 0xffffu);
+    const float sz = frame5(uz, h1.y & 0xffffu, h1.z >> 16);
+    // Four entries (two 16-byte loads) per step: all their boxes, then the
+    // forms of those whose box holds q, are loaded before any is evaluated,
+    // so a lane keeps several independent loads in flight.  Runs have even
+    // length; a second load past the run's end re-reads the first and its
+    // slots are discarded.
+    for (uint32_t k = e0; k < f0; k += 4) {
+        const uint4 A = m.lent[k >> 1], B = m.lent[(k + 2 < f0 ? k + 2 : k) >> 1];
+        const uint32_t id[4] = {A.x, A.z, B.x, B.z}, bx[4] = {A.y, A.w, B.y, B.w};
+        float d[4];
 #pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) en[u] = m.lent[k + u < f0 ? k + u : k];
-        float d[kScanUnroll];
-#pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) {
-            const bool hit = k + u < f0 && in_box(en[u], ux, uy, uz);
+        for (int u = 0; u < 4; ++u) {
+            const bool hit = k + u < f0 && in_box5(bx[u], sx, sy, sz);
             cnt.edge_forms += hit;
-            d[u] = hit ? edge_gate_d2(m, (int32_t)en[u].x, rx, ry, rz) : INFINITY;
+            d[u] = hit ? edge_gate_d2(m, (int32_t)id[u], rx, ry, rz) : INFINITY;
         }
 #pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u)
+        for (int u = 0; u < 4; ++u)
             if (d[u] < best) {
                 best = d[u];
                 best_kind = KIND_EDGE;
-                best_id = (int32_t)en[u].x;
+                best_id = (int32_t)id[u];
             }
     }
-    for (uint32_t k = f0; k < f1; k += kScanUnroll) {
-        uint4 en[kScanUnroll];
+    for (uint32_t k = f0; k < f1; k += 4) {
+        const uint4 A = m.lent[k >> 1], B = m.lent[(k + 2 < f1 ? k + 2 : k) >> 1];
+        const uint32_t id[4] = {A.x, A.z, B.x, B.z}, bx[4] = {A.y, A.w, B.y, B.w};
+        float d[4];
 #pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) en[u] = m.lent[k + u < f1 ? k + u : k];
-        float d[kScanUnroll];
-#pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) {
-            const bool hit = k + u < f1 && in_box(en[u], ux, uy, uz);
+        for (int u = 0; u < 4; ++u) {
+            const bool hit = k + u < f1 && in_box5(bx[u], sx, sy, sz);
             cnt.face_forms += hit;
-            d[u] = hit ? face_gate_d2(m, (int32_t)en[u].x, rx, ry, rz) : INFINITY;
+            d[u] = hit ? face_gate_d2(m, (int32_t)id[u], rx, ry, rz) : INFINITY;
         }
 #pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u)
+        for (int u = 0; u < 4; ++u)
             if (d[u] < best) {
                 best = d[u];
                 best_kind = KIND_FACE;
-                best_id = (int32_t)en[u].x;
+                best_id = (int32_t)id[u];
             }
     }
     cnt.edges += f0 - e0;
