@@ -66,12 +66,11 @@ def measured_traffic(n_queries: int):
 
 def b_alg(visits: float, steps: float, entries: float, edge_forms: float, face_forms: float) -> float:
     """Algorithmic bytes per query: query in (12) + results out (20) + the
-    nearest-vertex walk (seed id 4 + seed vertex 16, per step the neighbour
-    list offsets 8, per neighbour its id 4 + position 16) + 8 for the
-    interception-list offsets + 16 per list entry (id + box) + per entry
-    whose box holds q its forms (edge 32, face 48) + the winner's exact
-    re-evaluation (48)."""
-    return 12 + 20 + 20 + 8 * steps + 20 * visits + 8 + 16 * entries + 32 * edge_forms + 48 * face_forms + 48
+    nearest-vertex walk (seed record 16, per step the neighbour-list
+    offsets 8, per neighbour its record 16) + the list head (32) + 8 per list
+    entry (id + box; runs padded to even length) + per entry whose box holds
+    q its forms (edge 32, face 48) + the winner's exact re-evaluation (48)."""
+    return 12 + 20 + 16 + 8 * steps + 16 * visits + 32 + 8 * entries + 32 * edge_forms + 48 * face_forms + 48
 
 
 def main():

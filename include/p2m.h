@@ -179,7 +179,8 @@ p2m_status p2m_upload(p2m_mesh* m, int device, void* stream, int64_t* bytes);
  * closest point's barycentric weights over the primitive's vertices (unused
  * slots: weight 0, id -1).  Non-finite queries give P2M_NONE, NaN distance
  * and P2M_Q_NONFINITE.  n = 0 is a no-op.  Scratch device memory (ordering,
- * and 32 bytes per query of staged answers for an ordered batch) is owned
+ * and 32 bytes per query of staged answers for an ordered batch, 48 with
+ * bary/pvid) is owned
  * by the mesh, grown on demand and reused; concurrent calls on the same
  * mesh from different streams race. */
 p2m_status p2m_query(p2m_mesh* m, const float* q_dev, int64_t n, int32_t* prim_dev, float* closest_dev,
@@ -229,8 +230,9 @@ void p2m_batch_destroy(p2m_batch* b);
  * int64 [count+1], q_offsets_host[0] = 0, non-decreasing, N =
  * q_offsets_host[count]).  Outputs (device) as p2m_query, in the same row
  * order; primitive ids are local to each mesh.  The launch sequence
- * (ordering keys and sort, work-counter reset, persistent kernel) is
- * captured into a HIP graph on first use and replayed while the offsets,
+ * (ordering keys and sort, work-counter reset, persistent kernel, write-out
+ * of the staged 32-byte answers) is captured into a HIP graph on first use
+ * and replayed while the offsets,
  * pointers and launch shape stay the same.  A new offset layout uploads a
  * tile list and waits for that copy.  Calls on one batch must not overlap. */
 p2m_status p2m_batch_query(p2m_batch* b, const float* q_dev, const int64_t* q_offsets_host, int32_t* prim_dev,

@@ -41,6 +41,13 @@ inline void morton_params(const double dlo[3], const double dhi[3], float lo[3],
     }
 }
 
+// Writes staged answers to the output arrays with coalesced stores: per
+// query (prim bits, closest), (dist, status bits, w0, w1) and, when bary
+// is set, (w2, pv0, pv1, pv2); status may be NULL, bary and pvid both NULL
+// or both set.  Enqueued on `st`.
+hipError_t launch_split(const float4* stage, int64_t n, int32_t* prim, float* closest, float* dist, uint8_t* status,
+                        float* bary, int32_t* pvid, hipStream_t st);
+
 // ---------------------------------------------------------------- sort
 
 // Stable LSD radix sort of (uint32 key, int32 value) pairs, 8-bit digits.

@@ -109,6 +109,7 @@ struct p2m_batch {
     int64_t ntiles = 0;
     uint32_t* counter = nullptr;
     void* scratch = nullptr;
+    float4* stage = nullptr;  // 32-byte answer record per query
     int tile_block = 0, tile_qpl = 0;
     // launch shape
     int block = 256, qpl = 1, traversal = 3;
@@ -170,8 +171,7 @@ struct Arena {
 template <int kWalk>
 __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
     Arena A, const Tile* __restrict__ tiles, int64_t ntiles, uint32_t* counter, int qpl,
-    const float* __restrict__ q, const int32_t* __restrict__ perm, int64_t n, int32_t* __restrict__ prim,
-    float* __restrict__ closest, float* __restrict__ dist) {
+    const float* __restrict__ q, const int32_t* __restrict__ perm, int64_t n, float4* __restrict__ stage) {
     __shared__ int64_t s_tile;
     for (;;) {
         if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1u);
@@ -199,11 +199,9 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
             const Nearest nv = nearest_vertex<kWalk>(v, qx, qy, qz, i >= 0 && fin, c.nodes, c.steps);
             if (i >= 0) {
                 const Answer a = fin ? p2m_answer(v, qx, qy, qz, nv, c) : nonfinite_answer();
-                prim[i] = a.prim;
-                closest[3 * i] = a.cx;
-                closest[3 * i + 1] = a.cy;
-                closest[3 * i + 2] = a.cz;
-                dist[i] = a.dist;
+                // one 32-byte record per query; split into the outputs afterwards
+                stage[2 * i] = make_float4(__int_as_float(a.prim), a.cx, a.cy, a.cz);
+                stage[2 * i + 1] = make_float4(a.dist, 0.f, 0.f, 0.f);
             }
         }
     }
@@ -246,7 +244,7 @@ p2m_status prepare(p2m_batch* b, const int64_t* qoff_host, hipStream_t st) {
         for (int64_t s = layout[(size_t)k]; s < layout[(size_t)k + 1]; s += tsize)
             tiles.push_back(Tile{(int32_t)k, (int32_t)s, (int32_t)std::min(tsize, layout[(size_t)k + 1] - s), 0});
     const int64_t need = up256(8 * (int64_t)(b->count + 1)) + up256((int64_t)sizeof(Tile) * std::max<size_t>(1, tiles.size())) +
-                         256 + plan.bytes;
+                         256 + up256(plan.bytes) + 32 * std::max<int64_t>(n, 1);
     if (need > b->work_bytes) {
         if (b->work) (void)hipFree(b->work);
         b->work = nullptr;
@@ -263,6 +261,8 @@ p2m_status prepare(p2m_batch* b, const int64_t* qoff_host, hipStream_t st) {
     b->counter = (uint32_t*)p;
     p += 256;
     b->scratch = p;
+    p += up256(plan.bytes);
+    b->stage = (float4*)p;
     hipError_t e = hipMemcpyAsync(b->qoff, layout.data(), 8 * layout.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !tiles.empty())
         e = hipMemcpyAsync(b->tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, st);
@@ -276,7 +276,8 @@ p2m_status prepare(p2m_batch* b, const int64_t* qoff_host, hipStream_t st) {
     return P2M_OK;
 }
 
-// Enqueue the whole batched query (keys, sort, counter reset, persistent kernel).
+// Enqueue the whole batched query (keys, sort, counter reset, persistent
+// kernel, write-out of the staged answers).
 p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, float* dist, hipStream_t st) {
     const int64_t n = b->n;
     if (n == 0) return P2M_OK;
@@ -291,13 +292,15 @@ p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, 
                   b->nboff, b->nbrec, b->seed, b->frec, b->erec, b->desc};
 #define P2M_LAUNCH_BATCH(W)                                                                                  \
     k_batch_query<W><<<grid, b->block, 0, st>>>(A, b->tiles, b->ntiles, b->counter, b->qpl, q, rb.vals[cur], n, \
-                                                prim, closest, dist)
+                                                b->stage)
     if (b->traversal == 1) P2M_LAUNCH_BATCH(WALK_LANE);
     else if (b->traversal == 2) P2M_LAUNCH_BATCH(WALK_WAVE);
     else P2M_LAUNCH_BATCH(WALK_VORONOI);
 #undef P2M_LAUNCH_BATCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batched query launch");
+    e = launch_split(b->stage, n, prim, closest, dist, nullptr, nullptr, nullptr, st);
+    if (e != hipSuccess) return hip_fail(e, "batched answer write-out");
     return P2M_OK;
 }
 

@@ -340,11 +340,12 @@ __global__ void k_morton(const float* __restrict__ q, int64_t n, float lox, floa
     vals[i] = (int32_t)i;
 }
 
-// stage (ordered batches): query i's answer goes to stage[2i], stage[2i+1]
-// as (prim, closest) and (dist, status) -- one aligned 32-byte record per
-// query instead of four partial cache lines in the output arrays; k_split
-// then writes those arrays with coalesced stores.  Without stage the
-// answer goes to the output arrays directly.
+// stage (ordered batches): query i's answer goes to stage[S*i .. S*i+S-1]
+// (S = 2, or 3 with the backward extras) as (prim, closest), (dist, status,
+// w0, w1), (w2, pv0, pv1, pv2) -- one aligned record per query instead of
+// several partial cache lines in the output arrays; k_split then writes
+// those arrays with coalesced stores.  Without stage the answer goes to the
+// output arrays directly.
 template <bool kWriteExtras, int kWalk>
 __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const float* __restrict__ q,
                                                 const int32_t* __restrict__ perm, int64_t n, int64_t chunk,
@@ -370,16 +371,20 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const floa
     uint8_t st = fin ? domain_status(m, qx, qy, qz) : (uint8_t)2;
     const Answer a = fin ? p2m_answer(m, qx, qy, qz, nv, c) : nonfinite_answer();
     if (stage) {
-        stage[2 * i] = make_float4(__int_as_float(a.prim), a.cx, a.cy, a.cz);
-        stage[2 * i + 1] = make_float4(a.dist, __int_as_float((int)st), 0.f, 0.f);
-    } else {
-        prim[i] = a.prim;
-        closest[3 * i] = a.cx;
-        closest[3 * i + 1] = a.cy;
-        closest[3 * i + 2] = a.cz;
-        dist[i] = a.dist;
-        if (status) status[i] = st;
+        constexpr int S = kWriteExtras ? 3 : 2;
+        stage[S * i] = make_float4(__int_as_float(a.prim), a.cx, a.cy, a.cz);
+        stage[S * i + 1] = make_float4(a.dist, __int_as_float((int)st), a.w[0], a.w[1]);
+        if (kWriteExtras)
+            stage[S * i + 2] = make_float4(a.w[2], __int_as_float(a.pv[0]), __int_as_float(a.pv[1]),
+                                           __int_as_float(a.pv[2]));
+        return;
     }
+    prim[i] = a.prim;
+    closest[3 * i] = a.cx;
+    closest[3 * i + 1] = a.cy;
+    closest[3 * i + 2] = a.cz;
+    dist[i] = a.dist;
+    if (status) status[i] = st;
     if (kWriteExtras) {
         for (int k = 0; k < 3; ++k) {
             bary[3 * i + k] = a.w[k];
@@ -388,18 +393,38 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const floa
     }
 }
 
+template <bool kExtras>
 __global__ __launch_bounds__(256) void k_split(const float4* __restrict__ stage, int64_t n, int32_t* __restrict__ prim,
                                                float* __restrict__ closest, float* __restrict__ dist,
-                                               uint8_t* __restrict__ status) {
+                                               uint8_t* __restrict__ status, float* __restrict__ bary,
+                                               int32_t* __restrict__ pvid) {
+    constexpr int S = kExtras ? 3 : 2;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float4 a = stage[2 * i], b = stage[2 * i + 1];
+    const float4 a = stage[S * i], b = stage[S * i + 1];
     prim[i] = __float_as_int(a.x);
     closest[3 * i] = a.y;
     closest[3 * i + 1] = a.z;
     closest[3 * i + 2] = a.w;
     dist[i] = b.x;
     if (status) status[i] = (uint8_t)__float_as_int(b.y);
+    if (kExtras) {
+        const float4 c = stage[S * i + 2];
+        bary[3 * i] = b.z;
+        bary[3 * i + 1] = b.w;
+        bary[3 * i + 2] = c.x;
+        pvid[3 * i] = __float_as_int(c.y);
+        pvid[3 * i + 1] = __float_as_int(c.z);
+        pvid[3 * i + 2] = __float_as_int(c.w);
+    }
+}
+
+hipError_t launch_split(const float4* stage, int64_t n, int32_t* prim, float* closest, float* dist, uint8_t* status,
+                        float* bary, int32_t* pvid, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (bary) k_split<true><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(stage, n, prim, closest, dist, status, bary, pvid);
+    else k_split<false><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(stage, n, prim, closest, dist, status, bary, pvid);
+    return hipGetLastError();
 }
 
 template <int kWalk>
@@ -714,7 +739,7 @@ p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, flo
     if (sort) {
         uint32_t* keys = nullptr;
         void* x = nullptr;
-        p2m_status r = order_into_scratch(s, q, n, kQuerySortLoBit, st, &keys, &perm, 32 * n, &x);
+        p2m_status r = order_into_scratch(s, q, n, kQuerySortLoBit, st, &keys, &perm, (bary ? 48 : 32) * n, &x);
         if (r != P2M_OK) return r;
         stage = (float4*)x;
     }
@@ -739,8 +764,8 @@ p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, flo
     p2m_status r = check_launch("query kernel");
     if (profile) (void)hipEventRecord((hipEvent_t)s.dev.ev[2], st);
     if (r == P2M_OK && stage) {
-        k_split<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(stage, n, prim, closest, dist, status);
-        r = check_launch("output split kernel");
+        const hipError_t e = launch_split(stage, n, prim, closest, dist, status, bary, pvid, st);
+        if (e != hipSuccess) r = fail(P2M_ERR_HIP, std::string("answer write-out: ") + hipGetErrorString(e));
     }
     if (r == P2M_OK && profile) {
         (void)hipEventRecord((hipEvent_t)s.dev.ev[3], st);
