@@ -379,11 +379,27 @@ P2M_HD float face_gate_d2(const MeshView& m, int32_t f, float rx, float ry, floa
     return in ? h * h : INFINITY;
 }
 
-// q (in the list box's 5-bit frame) inside an entry's box.
-P2M_HD bool in_box5(uint32_t b, float ux, float uy, float uz) {
-    const float lx = (float)(b & 31u), ly = (float)((b >> 5) & 31u), lz = (float)((b >> 10) & 31u);
-    const float hx = (float)((b >> 15) & 31u), hy = (float)((b >> 20) & 31u), hz = (float)((b >> 25) & 31u);
-    return (ux >= lx) & (ux <= hx) & (uy >= ly) & (uy <= hy) & (uz >= lz) & (uz <= hz);
+// Integer bounds of q in the list box's 5-bit frame: for integer box
+// bounds, lo <= s exactly when lo <= floor(s), and s <= hi exactly when
+// ceil(s) <= hi, so the integer test equals the real one.
+struct Cell5 {
+    uint32_t fx, fy, fz, cx, cy, cz;
+};
+
+P2M_HD Cell5 cell5(float sx, float sy, float sz) {
+    Cell5 c;
+    c.fx = (uint32_t)floorf(sx);
+    c.fy = (uint32_t)floorf(sy);
+    c.fz = (uint32_t)floorf(sz);
+    c.cx = (uint32_t)ceilf(sx);
+    c.cy = (uint32_t)ceilf(sy);
+    c.cz = (uint32_t)ceilf(sz);
+    return c;
+}
+
+P2M_HD bool in_box5(uint32_t b, const Cell5& c) {
+    return ((b & 31u) <= c.fx) & (((b >> 5) & 31u) <= c.fy) & (((b >> 10) & 31u) <= c.fz) &
+           (((b >> 15) & 31u) >= c.cx) & (((b >> 20) & 31u) >= c.cy) & ((b >> 25) >= c.cz);
 }
 
 // Coordinate of q in the 5-bit frame of a list box side [lo, hi] (16-bit
@@ -416,6 +432,7 @@ P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const 
     const float sx = frame5(ux, h1.x & 0xffffu, h1.y >> 16);
     const float sy = frame5(uy, h1.x >> 16, h1.z & 0xffffu);
     const float sz = frame5(uz, h1.y & 0xffffu, h1.z >> 16);
+    const Cell5 qc = cell5(sx, sy, sz);
     // Four entries (two 16-byte loads) per step: all their boxes, then the
     // forms of those whose box holds q, are loaded before any is evaluated,
     // so a lane keeps several independent loads in flight.  Runs have even
@@ -427,7 +444,7 @@ P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const 
         float d[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const bool hit = k + u < f0 && in_box5(bx[u], sx, sy, sz);
+            const bool hit = k + u < f0 && in_box5(bx[u], qc);
             cnt.edge_forms += hit;
             d[u] = hit ? edge_gate_d2(m, (int32_t)id[u], rx, ry, rz) : INFINITY;
         }
@@ -445,7 +462,7 @@ P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const 
         float d[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const bool hit = k + u < f1 && in_box5(bx[u], sx, sy, sz);
+            const bool hit = k + u < f1 && in_box5(bx[u], qc);
             cnt.face_forms += hit;
             d[u] = hit ? face_gate_d2(m, (int32_t)id[u], rx, ry, rz) : INFINITY;
         }
