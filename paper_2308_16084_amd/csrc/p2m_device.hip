@@ -497,6 +497,94 @@ hipError_t launch_seed_grid(const MeshView& m, float4* seed, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Bucketed reduction of the vertex gradient for large meshes: every
+// (query, corner) contribution is emitted with its vertex id as key, one
+// radix pass on the key bits above kBucketShift groups them into buckets of
+// 2^kBucketShift consecutive vertices, and one workgroup per bucket sums its
+// contributions in LDS and adds them to grad_V with coalesced stores -- no
+// scattered global atomics.
+constexpr int kBucketShift = 12;
+constexpr int64_t kAtomicMaxVertices = 65536;  // below this the direct atomics stay in L2
+
+__global__ __launch_bounds__(256) void k_bwd_emit(const float* __restrict__ q, int64_t n,
+                                                   const float* __restrict__ closest, const float* __restrict__ dist,
+                                                   const float* __restrict__ bary, const int32_t* __restrict__ pvid,
+                                                   const float* __restrict__ gd, float* __restrict__ gq, int32_t nv,
+                                                   uint32_t* __restrict__ keys, int32_t* __restrict__ vals,
+                                                   float* __restrict__ contrib) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float d = dist[i];
+    const float g = gd[i];
+    float ux = 0.f, uy = 0.f, uz = 0.f;
+    if (d > 0.f && isfinite(d)) {
+        const float inv = 1.f / d;
+        ux = (q[3 * i] - closest[3 * i]) * inv;
+        uy = (q[3 * i + 1] - closest[3 * i + 1]) * inv;
+        uz = (q[3 * i + 2] - closest[3 * i + 2]) * inv;
+    }
+    if (gq) {
+        gq[3 * i] = g * ux;
+        gq[3 * i + 1] = g * uy;
+        gq[3 * i + 2] = g * uz;
+    }
+    const bool any = (ux != 0.f || uy != 0.f || uz != 0.f) && g != 0.f;
+    for (int k = 0; k < 3; ++k) {
+        const int64_t c = 3 * i + k;
+        const int32_t v = pvid[c];
+        const float w = bary[c];
+        const bool ok = any && v >= 0 && v < nv && w != 0.f;
+        const float s = -g * w;
+        keys[c] = ok ? (uint32_t)v : 0xffffffffu;
+        vals[c] = (int32_t)c;
+        contrib[3 * c] = ok ? s * ux : 0.f;
+        contrib[3 * c + 1] = ok ? s * uy : 0.f;
+        contrib[3 * c + 2] = ok ? s * uz : 0.f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ a, int64_t n, uint32_t x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = x;
+}
+
+// First and one-past-last sorted position of every bucket present.
+__global__ __launch_bounds__(256) void k_bucket_bounds(const uint32_t* __restrict__ keys, int64_t m, uint32_t nb,
+                                                       uint32_t* __restrict__ start, uint32_t* __restrict__ end) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t b = (keys[j] >> kBucketShift) & (nb - 1);
+    if (j == 0 || ((keys[j - 1] >> kBucketShift) & (nb - 1)) != b) start[b] = (uint32_t)j;
+    if (j == m - 1 || ((keys[j + 1] >> kBucketShift) & (nb - 1)) != b) end[b] = (uint32_t)(j + 1);
+}
+
+__global__ __launch_bounds__(512) void k_bwd_accum(const uint32_t* __restrict__ keys, const int32_t* __restrict__ vals,
+                                                   const float* __restrict__ contrib,
+                                                   const uint32_t* __restrict__ start, const uint32_t* __restrict__ end,
+                                                   float* __restrict__ gV, int32_t nv) {
+    __shared__ float acc[3 << kBucketShift];
+    const uint32_t b = blockIdx.x;
+    const uint32_t s0 = start[b], s1 = end[b];
+    if (s1 <= s0) return;  // uniform: empty bucket
+    for (int t = threadIdx.x; t < (3 << kBucketShift); t += blockDim.x) acc[t] = 0.f;
+    __syncthreads();
+    const int64_t v0 = (int64_t)b << kBucketShift;
+    for (uint32_t j = s0 + threadIdx.x; j < s1; j += blockDim.x) {
+        const uint32_t v = keys[j];
+        // keys outside this bucket or past nv carry no contribution
+        if (v >= (uint32_t)nv || ((int64_t)v >> kBucketShift) != (int64_t)b) continue;
+        const int64_t c = vals[j];
+        const int l = (int)(v - (uint32_t)v0);
+        atomicAdd(&acc[3 * l], contrib[3 * c]);
+        atomicAdd(&acc[3 * l + 1], contrib[3 * c + 1]);
+        atomicAdd(&acc[3 * l + 2], contrib[3 * c + 2]);
+    }
+    __syncthreads();
+    const int64_t lim = std::min<int64_t>((int64_t)3 << kBucketShift, 3 * ((int64_t)nv - v0));
+    for (int t = threadIdx.x; t < lim; t += blockDim.x)
+        if (acc[t] != 0.f) gV[3 * v0 + t] += acc[t];
+}
+
 __global__ __launch_bounds__(256) void k_backward(const float* __restrict__ q, int64_t n,
                                                    const float* __restrict__ closest, const float* __restrict__ dist,
                                                    const float* __restrict__ bary, const int32_t* __restrict__ pvid,
@@ -845,9 +933,36 @@ p2m_status p2m_query_backward(p2m_mesh* mh, const float* q, int64_t n, const flo
     if (!q || !closest || !dist || !gd) return fail(P2M_ERR_ARG, "NULL pointer");
     if (gV && (!bary || !pvid)) return fail(P2M_ERR_ARG, "grad_V needs bary and pvid from the forward");
     DeviceGuard g(s.dev.device);
-    k_backward<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(q, n, closest, dist, bary, pvid, gd,
-                                                                            gq, gV, (int32_t)s.m.nv);
-    return check_launch("backward kernel");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nv = s.m.nv;
+    if (!gV || nv <= kAtomicMaxVertices || 3 * n > (int64_t)INT32_MAX) {
+        k_backward<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(q, n, closest, dist, bary, pvid, gd, gq, gV,
+                                                                (int32_t)nv);
+        return check_launch("backward kernel");
+    }
+    // bucketed reduction: key bits [kBucketShift, kBucketShift + 8 * passes)
+    int bits = 0;
+    while (((int64_t)1 << bits) < nv) ++bits;
+    const int passes = (bits - kBucketShift + 7) / 8;
+    const int hi_bit = kBucketShift + 8 * passes;
+    const uint32_t nb = 1u << (8 * passes);
+    const int64_t m = 3 * n;
+    const RadixPlan plan = radix_plan(m);
+    const int64_t a = (plan.bytes + 255) / 256 * 256;
+    const int64_t b_contrib = (12 * m + 255) / 256 * 256;
+    p2m_status r = ensure_scratch(s, a + b_contrib + 8 * (int64_t)nb);
+    if (r != P2M_OK) return r;
+    RadixBuffers rb = radix_buffers(plan, s.dev.scratch);
+    float* contrib = (float*)((char*)s.dev.scratch + a);
+    uint32_t* bstart = (uint32_t*)((char*)s.dev.scratch + a + b_contrib);
+    uint32_t* bend = bstart + nb;
+    k_bwd_emit<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(q, n, closest, dist, bary, pvid, gd, gq, (int32_t)nv,
+                                                            rb.keys[0], rb.vals[0], contrib);
+    const int cur = radix_sort_pairs(plan, rb, kBucketShift, hi_bit, st);
+    k_fill_u32<<<(unsigned)((2 * nb + 255) / 256), 256, 0, st>>>(bstart, 2 * (int64_t)nb, 0u);
+    k_bucket_bounds<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(rb.keys[cur], m, nb, bstart, bend);
+    k_bwd_accum<<<nb, 512, 0, st>>>(rb.keys[cur], rb.vals[cur], contrib, bstart, bend, gV, (int32_t)nv);
+    return check_launch("backward kernels");
 }
 
 p2m_status p2m_query_host(const p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, float* closest, float* dist,

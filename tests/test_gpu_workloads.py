@@ -109,3 +109,35 @@ def test_c5_forward_backward_vs_oracle():
     # is continuous across them, so the whole vertex gradient is compared
     rel = np.linalg.norm(gV - ogV) / np.linalg.norm(ogV)
     assert rel <= 5e-3, rel
+
+
+def test_c5_vertex_gradient_reduction_dense():
+    """Full C5 loss: the vertex gradient (bucketed reduction on a mesh this
+    size) equals a float64 accumulation of the same per-query contributions
+    -(dL/dd) w_k (q - c)/d built on the host from the forward's outputs."""
+    import torch
+
+    import paper_2308_16084_amd as P
+    print("case: c5 dense vertex gradient", flush=True)
+    w = C.c5()
+    m, _ = P.Mesh.cached(w.V, w.F, (w.domain_lo, w.domain_hi), CACHE)
+    m.upload(0)
+    q = torch.from_numpy(w.Q).cuda()
+    fwd = m.query(q, for_backward=True, status=False)
+    g = 2.0 * fwd["dist"]
+    gV = torch.zeros((m.nv, 3), dtype=torch.float32, device="cuda")
+    gq, gV = m.query_backward(q, fwd, g, grad_q=True, grad_V=gV)
+    torch.cuda.synchronize()
+    Q = w.Q.astype(np.float64)
+    c = fwd["closest"].cpu().numpy().astype(np.float64)
+    d = fwd["dist"].cpu().numpy().astype(np.float64)
+    bary = fwd["bary"].cpu().numpy().astype(np.float64)
+    pvid = fwd["pvid"].cpu().numpy()
+    u = np.where(d[:, None] > 0, (Q - c) / np.maximum(d, 1e-30)[:, None], 0.0)
+    ref = np.zeros((m.nv, 3))
+    for k in range(3):
+        ok = (pvid[:, k] >= 0) & (bary[:, k] != 0)
+        np.add.at(ref, pvid[ok, k], -(2.0 * d[ok] * bary[ok, k])[:, None] * u[ok])
+    got = gV.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+    assert np.allclose(gq.cpu().numpy(), 2.0 * d[:, None] * u, atol=1e-5)
