@@ -82,6 +82,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-primitive (triangles + segments) leg")
     ap.add_argument("--batched-full", action="store_true",
                     help="batched leg on all 256 meshes (default: the first 64 of the same seeded plan)")
     ap.add_argument("--breakdown", action="store_true",
@@ -246,6 +247,32 @@ def main():
         result["fwd_bwd"] = {"value": round(n5 / (ms_fb / 1e3), 1), "unit": "queries/s", "ms_per_step": round(ms_fb, 4),
                              "workload": "same mesh, 1e6 near-surface queries, loss = sum d^2, grads wrt q [1e6,3] and V [655362,3]"}
         log(f"[bench] fwd+bwd: {ms_fb:.3f} ms/step, {n5 / (ms_fb / 1e3) / 1e9:.3f} Gq/s")
+
+    if not args.no_mixed:
+        t0 = time.time()
+        w6 = C.c6()
+        m6, _ = P.Mesh.cached(w6.V, w6.F, (w6.domain_lo, w6.domain_hi), args.cache or None, segments=w6.S)
+        t_pre6 = time.time() - t0
+        m6.upload(0)
+        q6 = torch.from_numpy(w6.Q).to(dev)
+        out6 = m6.query(q6)
+        for _ in range(args.warmup):
+            m6.query(q6, out=out6)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            m6.query(q6, out=out6)
+        e1.record()
+        torch.cuda.synchronize()
+        ms6 = e0.elapsed_time(e1) / args.steps
+        n6 = q6.shape[0]
+        result["mixed"] = {"value": round(n6 / (ms6 / 1e3), 1), "unit": "queries/s", "ms_per_step": round(ms6, 4),
+                           "workload": f"mixed primitive set: {len(w6.F)} triangles + {len(w6.S)} free segments "
+                                       f"({len(w6.V)} V), {n6} queries (half uniform in 1.5x AABB, half near "
+                                       f"the triangles / segments)",
+                           "host_precompute_s": round(t_pre6, 1)}
+        log(f"[bench] mixed (triangles + segments): {ms6:.3f} ms/step, {n6 / (ms6 / 1e3) / 1e9:.3f} Gq/s")
+        del m6, q6, out6
 
     if not args.no_batched:
         count = 256 if args.batched_full else 64

@@ -112,6 +112,16 @@ typedef struct {
  * statement assumes one copy per vertex, Sec. 4.1), nv or nf < 1, or more
  * than 2^30-1 vertices, edges or faces. */
 p2m_status p2m_mesh_create(const float* V, int64_t nv, const int32_t* F, int64_t nf, p2m_mesh** out);
+
+/* A mixed set of triangles and segments (Sec. 5.5): as p2m_mesh_create plus
+ * free segments S host int32 [ns*2] (vertex index pairs; F may be NULL when
+ * nf = 0, S when ns = 0; at least one face or segment).  The edges of the
+ * mesh are the distinct vertex pairs of the face sides and the segments,
+ * numbered by their (min, max) pair in lexicographic order; a segment that
+ * is also a face side is that edge.  Rejects a segment index out of range
+ * or a segment that repeats a vertex, besides the checks above. */
+p2m_status p2m_mesh_create_mixed(const float* V, int64_t nv, const int32_t* F, int64_t nf, const int32_t* S,
+                                 int64_t ns, p2m_mesh** out);
 void p2m_mesh_destroy(p2m_mesh* m);
 
 /* Vertex, edge and face counts (any pointer may be NULL). */

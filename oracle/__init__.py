@@ -78,20 +78,28 @@ def _p(a: np.ndarray):
 class OracleMesh:
     """A mesh promoted exactly to FP64, with its canonical edge list."""
 
-    def __init__(self, V, F, library=None, promote: bool = True):
+    def __init__(self, V, F, library=None, promote: bool = True, segments=None):
         """promote=True rounds V to float32 first (the product's input type)
-        and widens exactly; promote=False takes float64 coordinates as given."""
+        and widens exactly; promote=False takes float64 coordinates as given.
+        segments: extra free segments (vertex pairs) of a mixed primitive set
+        (Sec. 5.5); the edges are then the distinct pairs of the face sides
+        and the segments, in lexicographic (min, max) order."""
         self._L = library if library is not None else lib()
         self._promote = promote
         self.V = np.ascontiguousarray(self._widen(V))
-        self.F = np.ascontiguousarray(np.asarray(F, dtype=np.int32))
+        self.F = np.ascontiguousarray(np.asarray(F, dtype=np.int32).reshape(-1, 3))
         self.nv = self.V.shape[0]
         self.nf = self.F.shape[0]
         L = self._L
-        ne = L.p2mo_edges(self.nv, _p(self.F), self.nf, None)
-        self.E = np.zeros((ne, 2), dtype=np.int32)
-        L.p2mo_edges(self.nv, _p(self.F), self.nf, _p(self.E))
-        self.ne = ne
+        ne = L.p2mo_edges(self.nv, _p(self.F), self.nf, None) if self.nf else 0
+        E = np.zeros((ne, 2), dtype=np.int32)
+        if ne:
+            L.p2mo_edges(self.nv, _p(self.F), self.nf, _p(E))
+        if segments is not None:
+            S = np.sort(np.asarray(segments, dtype=np.int32).reshape(-1, 2), axis=1)
+            E = np.unique(np.concatenate([E, S]), axis=0).astype(np.int32)
+        self.E = np.ascontiguousarray(E)
+        self.ne = self.E.shape[0]
         lo, hi = self.V.min(0), self.V.max(0)
         self.diag = float(np.linalg.norm(hi - lo))
 

@@ -49,6 +49,7 @@ _SIGS = {
     "p2m_precompute": (INT, [P, P, P]),
     "p2m_mesh_table": (INT, [P, P, P, P]),
     "p2m_mesh_table_boxes": (INT, [P, P]),
+    "p2m_mesh_create_mixed": (INT, [P, I64, P, I64, P, I64, P]),
     "p2m_mesh_neighbors": (INT, [P, P, P, P]),
     "p2m_mesh_kdtree": (INT, [P, P, P]),
     "p2m_save": (INT, [P, ctypes.c_char_p]),

@@ -58,17 +58,23 @@ def _dev_tensor(x, dtype, shape_tail, name):
 
 
 class Mesh:
-    """A triangle mesh with its precomputed KD tree and interception table."""
+    """A triangle mesh (optionally with free segments: a mixed primitive set)
+    with its precomputed KD tree, Voronoi graph and interception table."""
 
-    def __init__(self, V=None, F=None, _handle=None):
+    def __init__(self, V=None, F=None, segments=None, _handle=None):
         self._h = ctypes.c_void_p(0)
         self.device = None
         if _handle is not None:
             self._h = _handle
             return
         V = np.ascontiguousarray(np.asarray(V, dtype=np.float32).reshape(-1, 3))
-        F = np.ascontiguousarray(np.asarray(F, dtype=np.int32).reshape(-1, 3))
-        check(lib().p2m_mesh_create(_ptr(V), V.shape[0], _ptr(F), F.shape[0], ctypes.byref(self._h)))
+        F = np.ascontiguousarray(np.asarray(F if F is not None else np.zeros((0, 3)), dtype=np.int32).reshape(-1, 3))
+        if segments is None:
+            check(lib().p2m_mesh_create(_ptr(V), V.shape[0], _ptr(F), F.shape[0], ctypes.byref(self._h)))
+        else:
+            S = np.ascontiguousarray(np.asarray(segments, dtype=np.int32).reshape(-1, 2))
+            check(lib().p2m_mesh_create_mixed(_ptr(V), V.shape[0], _ptr(F) if len(F) else None, F.shape[0],
+                                              _ptr(S) if len(S) else None, S.shape[0], ctypes.byref(self._h)))
         self.nv, self.nf = V.shape[0], F.shape[0]
 
     @classmethod
@@ -82,7 +88,7 @@ class Mesh:
         return m
 
     @classmethod
-    def cached(cls, V, F, domain, cache_dir: str | None, **precompute_kw) -> tuple["Mesh", dict]:
+    def cached(cls, V, F, domain, cache_dir: str | None, segments=None, **precompute_kw) -> tuple["Mesh", dict]:
         """Precompute, or load the structures saved by an earlier call with
         the same mesh, domain and options from cache_dir (None: no cache)."""
         import hashlib
@@ -92,6 +98,9 @@ class Mesh:
         h = hashlib.sha256()
         h.update(V.tobytes())
         h.update(F.tobytes())
+        if segments is not None:
+            h.update(b"segments")
+            h.update(np.ascontiguousarray(np.asarray(segments, dtype=np.int32)).tobytes())
         h.update(np.asarray(domain, dtype=np.float64).tobytes())
         h.update(repr(sorted(precompute_kw.items())).encode())
         path = os.path.join(cache_dir, f"mesh_{h.hexdigest()[:24]}.p2m") if cache_dir else None
@@ -100,7 +109,7 @@ class Mesh:
                 return cls.load(path), {"loaded_from": path}
             except P2MError:
                 pass
-        m = cls(V, F)
+        m = cls(V, F, segments=segments)
         st = m.precompute(domain=domain, **precompute_kw)
         if path:
             os.makedirs(cache_dir, exist_ok=True)

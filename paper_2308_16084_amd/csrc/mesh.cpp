@@ -22,12 +22,15 @@ void psort(It b, It e, Cmp c) {
 }
 }  // namespace
 
-std::string build_mesh(const float* V, int64_t nv, const int32_t* F, int64_t nf, MeshData& m) {
-    if (!V || !F) return "null vertex or face array";
-    if (nv < 1 || nf < 1) return "mesh needs at least one vertex and one face";
-    if (nv > kMaxPrimitives || nf > kMaxPrimitives) return "more than 2^30-1 vertices or faces";
+std::string build_mesh(const float* V, int64_t nv, const int32_t* F, int64_t nf, const int32_t* S, int64_t ns,
+                       MeshData& m) {
+    if (nf < 0 || ns < 0) return "negative face or segment count";
+    if (!V || (nf > 0 && !F) || (ns > 0 && !S)) return "null vertex, face or segment array";
+    if (nv < 1 || nf + ns < 1) return "mesh needs at least one vertex and one face or segment";
+    if (nv > kMaxPrimitives || nf > kMaxPrimitives || ns > kMaxPrimitives) return "more than 2^30-1 vertices, faces or segments";
     m.nv = nv;
     m.nf = nf;
+    m.ns = ns;
     m.V.assign(V, V + 3 * nv);
     m.Vd.resize((size_t)(3 * nv));
     for (int k = 0; k < 3; ++k) {
@@ -41,6 +44,13 @@ std::string build_mesh(const float* V, int64_t nv, const int32_t* F, int64_t nf,
         m.hi[i % 3] = std::max(m.hi[i % 3], m.Vd[(size_t)i]);
     }
     m.F.assign(F, F + 3 * nf);
+    m.S.assign(S, S + 2 * ns);
+    for (int64_t k = 0; k < ns; ++k) {
+        const int32_t a = S[2 * k], b = S[2 * k + 1];
+        if (a < 0 || b < 0 || a >= nv || b >= nv)
+            return "segment " + std::to_string(k) + " has a vertex index out of range";
+        if (a == b) return "segment " + std::to_string(k) + " repeats a vertex";
+    }
     for (int64_t f = 0; f < nf; ++f) {
         int32_t a = F[3 * f], b = F[3 * f + 1], c = F[3 * f + 2];
         if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv)
@@ -73,7 +83,7 @@ std::string build_mesh(const float* V, int64_t nv, const int32_t* F, int64_t nf,
                        std::to_string(std::max(idx[(size_t)i - 1], idx[(size_t)i])) + " coincide";
         }
     }
-    // canonical edges: sort (min,max) keys of all sides
+    // canonical edges: sort (min,max) keys of all face sides and segments
     std::vector<uint64_t> keys((size_t)(3 * nf));
     for (int64_t f = 0; f < nf; ++f)
         for (int s = 0; s < 3; ++s) {
@@ -82,6 +92,11 @@ std::string build_mesh(const float* V, int64_t nv, const int32_t* F, int64_t nf,
             keys[(size_t)(3 * f + s)] = (a << 32) | b;
         }
     std::vector<uint64_t> uk = keys;
+    for (int64_t k = 0; k < ns; ++k) {
+        uint64_t a = (uint32_t)S[2 * k], b = (uint32_t)S[2 * k + 1];
+        if (a > b) std::swap(a, b);
+        uk.push_back((a << 32) | b);
+    }
     psort(uk.begin(), uk.end(), std::less<uint64_t>());
     uk.erase(std::unique(uk.begin(), uk.end()), uk.end());
     m.ne = (int64_t)uk.size();

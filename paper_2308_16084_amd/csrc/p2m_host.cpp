@@ -37,10 +37,20 @@ p2m_status p2m_mesh_create(const float* V, int64_t nv, const int32_t* F, int64_t
     *out = nullptr;
     if (!V || !F) return fail(P2M_ERR_ARG, "V or F is NULL");
     if (nv < 0 || nf < 0) return fail(P2M_ERR_ARG, "negative count");
+    if (nv < 1 || nf < 1) return fail(P2M_ERR_MESH, "mesh needs at least one vertex and one face");
+    return p2m_mesh_create_mixed(V, nv, F, nf, nullptr, 0, out);
+}
+
+p2m_status p2m_mesh_create_mixed(const float* V, int64_t nv, const int32_t* F, int64_t nf, const int32_t* S,
+                                 int64_t ns, p2m_mesh** out) {
+    if (!out) return fail(P2M_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!V || (nf > 0 && !F) || (ns > 0 && !S)) return fail(P2M_ERR_ARG, "V, F or S is NULL");
+    if (nv < 0 || nf < 0 || ns < 0) return fail(P2M_ERR_ARG, "negative count");
     try {
         auto t0 = Clock::now();
         p2m_mesh* m = new p2m_mesh();
-        std::string err = build_mesh(V, nv, F, nf, m->s.m);
+        std::string err = build_mesh(V, nv, F, nf, S, ns, m->s.m);
         if (!err.empty()) {
             delete m;
             return fail(P2M_ERR_MESH, err);
@@ -205,12 +215,12 @@ p2m_status p2m_mesh_kdtree(const p2m_mesh* m, float* xyz, int32_t* vid) {
 // ---------------------------------------------------------------- save/load
 //
 // File: magic, version, payload length, payload, FNV-1a of the payload.
-// Payload: domain (6 doubles), tau, then length-prefixed arrays V, F, KD-tree
+// Payload: domain (6 doubles), tau, then length-prefixed arrays V, F, S, KD-tree
 // x, y, z, vid, table off, ent, entry boxes, neighbour off, nb.
 
 namespace {
 const char kMagic[8] = {'P', '2', 'M', 'M', 'E', 'S', 'H', '1'};
-const uint32_t kVersion = 3;
+const uint32_t kVersion = 4;
 
 uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
     const unsigned char* p = (const unsigned char*)data;
@@ -270,6 +280,7 @@ p2m_status p2m_save(const p2m_mesh* m, const char* path) {
     w.raw(&s.tau, sizeof(s.tau));
     w.vec(s.m.V);
     w.vec(s.m.F);
+    w.vec(s.m.S);
     w.vec(s.kd.x);
     w.vec(s.kd.y);
     w.vec(s.kd.z);
@@ -323,9 +334,13 @@ p2m_status p2m_load(const char* path, p2m_mesh** out) {
     r.raw(&tau, sizeof(tau));
     r.vec(V);
     r.vec(F);
-    if (!r.ok || V.size() % 3 || F.size() % 3) return fail(P2M_ERR_IO, std::string("corrupt p2m mesh file: ") + path);
+    std::vector<int32_t> S;
+    r.vec(S);
+    if (!r.ok || V.size() % 3 || F.size() % 3 || S.size() % 2)
+        return fail(P2M_ERR_IO, std::string("corrupt p2m mesh file: ") + path);
     p2m_mesh* m = nullptr;
-    p2m_status st = p2m_mesh_create(V.data(), (int64_t)V.size() / 3, F.data(), (int64_t)F.size() / 3, &m);
+    p2m_status st = p2m_mesh_create_mixed(V.data(), (int64_t)V.size() / 3, F.data(), (int64_t)F.size() / 3, S.data(),
+                                          (int64_t)S.size() / 2, &m);
     if (st != P2M_OK) return st;
     MeshState& s = m->s;
     r.vec(s.kd.x);

@@ -1,4 +1,4 @@
-"""The five synthetic workloads (seeded), as plain arrays.
+"""The synthetic workloads (seeded), as plain arrays.
 
 C1  icosphere level 4 (2,562 V / 5,120 F), radial U[-0.05,0.05] noise,
     10^4 queries uniform in the 1.2x AABB.
@@ -11,6 +11,12 @@ C3  1024 x 1024 heightfield (1,048,576 V / 2,093,058 F), fbm heights
 C4  256 displaced spheres / heightfields, triangle counts log-uniform in
     [1e3, 2e5], query counts log-uniform in [1e3, 1e6] (mixed as C2).
 C5  the C2 mesh with 10^6 near-surface queries (loss = sum of d^2).
+C6  a mixed primitive set: the triangles of a displaced icosphere level 6
+    (40,962 V / 81,920 F) and, as free segments, the edge wireframe of a
+    displaced icosphere level 5 of radius 0.6 centred at (0.55, 0.1, -0.05)
+    (10,242 V / 30,720 segments), intersecting it; 10^6 queries: half uniform
+    in the 1.5x AABB, a quarter near the triangles and a quarter near the
+    segments (sigma = 1% of the AABB diagonal).
 
 Each workload also fixes the query domain box D that the precompute clips
 Voronoi cells to: the box the queries are drawn from.
@@ -37,6 +43,7 @@ class Workload:
     domain_lo: np.ndarray    # float64 [3]
     domain_hi: np.ndarray    # float64 [3]
     meta: dict = field(default_factory=dict)
+    S: np.ndarray | None = None  # int32 [ns,2] free segments (mixed primitive sets)
 
     @property
     def diag(self) -> float:
@@ -142,3 +149,27 @@ def c4_mesh(entry: dict, query_scale: float = 1.0) -> Workload:
 
 def c4(count: int = 256, query_scale: float = 1.0, tri_hi: float = 2e5) -> list[Workload]:
     return [c4_mesh(e, query_scale) for e in c4_plan(count, tri_hi=tri_hi)]
+
+
+def c6(n_queries: int = 1_000_000, level: int = 6, wire_level: int = 5) -> Workload:
+    """Mixed primitive set: triangles of one displaced sphere, the edge
+    wireframe of another (free segments) crossing it."""
+    V1, F1 = sphere_mesh(level, "fbm", MESH_SEED + 6)
+    V2u, F2 = M.icosphere(wire_level)
+    V2 = (0.6 * M.displace_fbm(V2u, 0.1, MESH_SEED + 7) + np.array([0.55, 0.1, -0.05])).astype(np.float32)
+    S2 = np.unique(np.sort(np.concatenate([F2[:, [0, 1]], F2[:, [1, 2]], F2[:, [2, 0]]]), axis=1), axis=0)
+    V = np.concatenate([V1, V2]).astype(np.float32)
+    S = (S2 + len(V1)).astype(np.int32)
+    lo, hi = Q.aabb(V)
+    dlo, dhi = Q.scaled_box(lo, hi, 1.5)
+    diag = float(np.linalg.norm(hi - lo))
+    rng = np.random.default_rng(QUERY_SEED + 6)
+    nu = n_queries // 2
+    nt = (n_queries - nu) // 2
+    Qp = np.concatenate([Q.uniform_in_box(nu, dlo, dhi, rng),
+                         Q.near_surface(V, F1, nt, 0.01 * diag, rng),
+                         Q.near_segments(V, S, n_queries - nu - nt, 0.01 * diag, rng)])
+    Qp = Qp[rng.permutation(n_queries)]
+    w = _finish(f"c6_mixed_icosphere{level}_wire{wire_level}", V, F1, Qp, dlo, dhi)
+    w.S = S
+    return w

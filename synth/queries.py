@@ -57,6 +57,19 @@ def near_surface(V: np.ndarray, F: np.ndarray, n: int, sigma: float,
     return (P + rng.normal(0.0, sigma, size=P.shape)).astype(np.float32)
 
 
+def near_segments(V: np.ndarray, S: np.ndarray, n: int, sigma: float, rng: np.random.Generator) -> np.ndarray:
+    """Length-weighted uniform samples on segments plus isotropic Gaussian offsets."""
+    V = np.asarray(V, dtype=np.float64)
+    a, b = V[S[:, 0]], V[S[:, 1]]
+    cdf = np.cumsum(np.linalg.norm(b - a, axis=1))
+    cdf /= cdf[-1]
+    k = np.searchsorted(cdf, rng.random(n), side="right")
+    k = np.minimum(k, len(S) - 1)
+    t = rng.random(n)[:, None]
+    P = a[k] * (1.0 - t) + b[k] * t
+    return (P + rng.normal(0.0, sigma, size=P.shape)).astype(np.float32)
+
+
 def mixed(V: np.ndarray, F: np.ndarray, n: int, box_scale: float, sigma_rel: float,
           rng: np.random.Generator) -> np.ndarray:
     """Half uniform in the scaled AABB, half near-surface, shuffled."""

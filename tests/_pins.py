@@ -209,4 +209,60 @@ def pin_near_set_contains_best_and_ties(library=None):
     assert (2, 0) in ns
 
 
+_NOF = np.zeros((0, 3), np.int32)
+
+
+def pin_single_segment_closed_form(library=None):
+    """One free segment (Sec. 5.5's mixed sets): distance to the closed
+    segment by projection and clamping; the end vertex when clamped."""
+    rng = np.random.default_rng(31)
+    V = np.array([[0.1, -0.2, 0.3], [0.9, 0.4, -0.1]], np.float32)
+    om = oracle.OracleMesh(V, _NOF, library, segments=[[0, 1]])
+    Q = rng.uniform(-1.0, 2.0, size=(400, 3)).astype(np.float32)
+    ans = om.query(Q)
+    a, b = V.astype(np.float64)
+    e = b - a
+    for i, q in enumerate(Q.astype(np.float64)):
+        t = (q - a) @ e / (e @ e)
+        c = a + min(max(t, 0.0), 1.0) * e
+        assert abs(ans["dist"][i] - np.linalg.norm(q - c)) <= 1e-12
+        assert ans["type"][i] == (1 if 0.0 < t < 1.0 else 0), (q, t, ans["type"][i])
+
+
+def pin_wireframe_cube_closed_form(library=None):
+    """The 12 edges of the unit cube as free segments: the nearest edge
+    parallel to axis k is at squared distance sum over j != k of
+    min(x_j^2, (x_j - 1)^2), plus the clamp along k."""
+    rng = np.random.default_rng(32)
+    S = np.array([[a, b] for a in range(8) for b in range(a + 1, 8)
+                  if np.abs(CUBE_V[a] - CUBE_V[b]).sum() == 1.0], np.int32)
+    assert len(S) == 12
+    om = oracle.OracleMesh(CUBE_V, _NOF, library, segments=S)
+    Q = rng.uniform(-0.5, 1.5, size=(600, 3))
+    ans = om.query(Q.astype(np.float32))
+    Qd = Q.astype(np.float32).astype(np.float64)
+    near = np.minimum(Qd ** 2, (Qd - 1.0) ** 2)
+    along = (Qd - np.clip(Qd, 0.0, 1.0)) ** 2
+    d = np.sqrt(np.min([near.sum(1) - near[:, k] + along[:, k] for k in range(3)], axis=0))
+    assert np.max(np.abs(ans["dist"] - d)) <= 1e-12
+    assert set(np.unique(ans["type"])) <= {0, 1}
+
+
+def pin_mixed_set_is_min_of_parts(library=None):
+    """A mixed set's distance is the smaller of its triangles' and its
+    segments' distances (the primitive set is their union)."""
+    rng = np.random.default_rng(33)
+    V1, F1 = random_tiny_mesh(rng, "sphere")
+    V2, F2 = random_tiny_mesh(rng, "sphere")
+    V2 = (0.5 * V2 + np.array([0.6, 0.1, 0.0], np.float32)).astype(np.float32)
+    S2 = np.unique(np.sort(np.concatenate([F2[:, [0, 1]], F2[:, [1, 2]], F2[:, [2, 0]]]), axis=1), axis=0)
+    V = np.concatenate([V1, V2])
+    mixed = oracle.OracleMesh(V, F1, library, segments=S2 + len(V1))
+    tri = oracle.OracleMesh(V1, F1, library)
+    seg = oracle.OracleMesh(V2, _NOF, library, segments=S2)
+    Q = rng.uniform(-1.5, 1.5, size=(500, 3)).astype(np.float32)
+    d = mixed.query(Q)["dist"]
+    assert np.array_equal(d, np.minimum(tri.query(Q)["dist"], seg.query(Q)["dist"]))
+
+
 PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -141,3 +141,39 @@ def test_c5_vertex_gradient_reduction_dense():
     got = gV.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
     assert np.allclose(gq.cpu().numpy(), 2.0 * d[:, None] * u, atol=1e-5)
+
+
+def test_c6_mixed_primitives_sampled():
+    """C6 (Sec. 5.5 mixed set: triangles + a crossing wireframe of free
+    segments), 10^6 queries in one ordered launch: 1,500 sampled rows
+    against the oracle over the same primitive set; the other traversals
+    give the same answers; served as one mesh of a batch with a triangle
+    mesh, it gives the plain launch's answers."""
+    import torch
+
+    import paper_2308_16084_amd as P
+    print("case: c6 build", flush=True)
+    w = C.c6()
+    m, _ = P.Mesh.cached(w.V, w.F, (w.domain_lo, w.domain_hi), CACHE, segments=w.S)
+    m.upload(0)
+    q = torch.from_numpy(w.Q).cuda()
+    out = {k: v.cpu().numpy() for k, v in m.query(q).items()}
+    rng = np.random.default_rng(66)
+    S = np.sort(rng.choice(len(w.Q), size=1500, replace=False))
+    om = oracle.OracleMesh(w.V, w.F, segments=w.S)
+    ans = om.query(w.Q[S])
+    assert check_answers(om, w.Q[S], ans, out["prim"][S], out["closest"][S], out["dist"][S], idx=S) == []
+    assert np.all(out["status"] == 0)
+    for t in (1, 2):
+        o = {k: v.cpu().numpy() for k, v in m.query(q[:200_000], traversal=t).items()}
+        assert np.mean(o["prim"] == out["prim"][:200_000]) > 0.9999, t
+    w1 = C.c1()
+    m1 = P.Mesh(w1.V, w1.F)
+    m1.precompute(domain=(w1.domain_lo, w1.domain_hi))
+    b = P.Batch([m1, m], 0)
+    qb = torch.cat([torch.from_numpy(w1.Q).cuda(), q[:300_000]]).contiguous()
+    off = np.array([0, len(w1.Q), len(w1.Q) + 300_000], np.int64)
+    ob = {k: v.cpu().numpy() for k, v in b.query(qb, off).items()}
+    sl = slice(len(w1.Q), None)
+    assert np.mean(ob["prim"][sl] == out["prim"][:300_000]) > 0.9999
+    assert np.max(np.abs(ob["dist"][sl] - out["dist"][:300_000])) <= 1e-5 * om.diag

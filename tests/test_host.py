@@ -373,3 +373,80 @@ def test_save_load_roundtrip():
             fh.write(b"\x00\x01\x02\x03")
         with pytest.raises(P.P2MError):
             P.Mesh.load(path)
+
+
+# ------------------------------------------------ mixed primitive sets (Sec. 5.5)
+
+def _wire(F):
+    return np.unique(np.sort(np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]]), axis=1), axis=0)
+
+
+@pytest.mark.parametrize("S,msg", [
+    ([[0, 9]], "out of range"),
+    ([[2, 2]], "repeats"),
+    ([[-1, 0]], "out of range"),
+])
+def test_mixed_validation(S, msg):
+    with pytest.raises(P.P2MError, match=msg):
+        P.Mesh(TETRA_V, TETRA_F, segments=S)
+
+
+def test_mixed_needs_a_primitive():
+    with pytest.raises(P.P2MError, match="at least one"):
+        P.Mesh(TETRA_V, np.zeros((0, 3), np.int32), segments=np.zeros((0, 2), np.int32))
+
+
+def test_mixed_edges_union_and_duplicates():
+    """A segment that is also a face side is that edge; the others are new
+    edges, all numbered in lexicographic (min, max) order."""
+    m = P.Mesh(TETRA_V, TETRA_F[:1], segments=[[3, 0], [2, 0], [1, 3]])
+    E = m.edges()
+    assert [tuple(e) for e in E.tolist()] == sorted({(0, 1), (0, 2), (1, 2), (0, 3), (1, 3)})
+
+
+@pytest.mark.parametrize("name", ["wireframe", "c6"])
+def test_mixed_host_query(name):
+    """Segment-only and mixed sets through the host model of the kernel:
+    every answer accepted by the FP64 oracle over the same primitive set,
+    including points on segments, near their ends and pushed off them."""
+    from synth import mesh as M
+    rng = np.random.default_rng(71)
+    if name == "wireframe":
+        V, F0 = random_tiny_mesh(rng, "sphere")
+        F, S = np.zeros((0, 3), np.int32), _wire(F0)
+        m, st, (lo, hi) = None, None, SQ.scaled_box(*SQ.aabb(V), 1.5)
+        Q = [rng.uniform(lo, hi, size=(2000, 3))]
+    else:
+        w = C.c6(n_queries=3000)
+        V, F, S = w.V, w.F, w.S
+        lo, hi = w.domain_lo, w.domain_hi
+        Q = [w.Q.astype(np.float64)]
+    m = P.Mesh(V, F, segments=S)
+    m.precompute(domain=(lo, hi))
+    Vd = V.astype(np.float64)
+    k = rng.integers(0, len(S), 300)
+    for t in (0.5, 1e-4, 1 - 1e-4, 0.0):
+        P0 = Vd[S[k, 0]] * (1 - t) + Vd[S[k, 1]] * t
+        Q.append(P0)
+        Q.append(P0 + 1e-3 * rng.normal(size=P0.shape))
+    Q = np.clip(np.concatenate(Q), lo, hi).astype(np.float32)
+    om = oracle.OracleMesh(V, F, segments=S)
+    h = m.query_host(Q)
+    assert check_answers(om, Q, om.query(Q), h["prim"], h["closest"], h["dist"]) == []
+
+
+def test_mixed_save_load_roundtrip():
+    rng = np.random.default_rng(72)
+    V, F0 = random_tiny_mesh(rng, "sphere")
+    S = _wire(F0)[::2]
+    m = P.Mesh(V, F0[: len(F0) // 2], segments=S)
+    lo, hi = SQ.scaled_box(*SQ.aabb(V), 1.5)
+    m.precompute(domain=(lo, hi))
+    Q = rng.uniform(lo, hi, size=(500, 3)).astype(np.float32)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "mixed.p2m")
+        m.save(path)
+        m2 = P.Mesh.load(path)
+    assert np.array_equal(m.edges(), m2.edges())
+    a, b = m.query_host(Q), m2.query_host(Q)
+    assert np.array_equal(a["prim"], b["prim"]) and np.array_equal(a["dist"], b["dist"])
