@@ -83,6 +83,9 @@ def main():
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-primitive (triangles + segments) leg")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also run the near/far sweep: the C2 mesh precomputed for D = 10x AABB, 1e6 uniform "
+                         "queries in boxes of 1x..10x AABB (not part of the default run)")
     ap.add_argument("--batched-full", action="store_true",
                     help="batched leg on all 256 meshes (default: the first 64 of the same seeded plan)")
     ap.add_argument("--breakdown", action="store_true",
@@ -273,6 +276,41 @@ def main():
                            "host_precompute_s": round(t_pre6, 1)}
         log(f"[bench] mixed (triangles + segments): {ms6:.3f} ms/step, {n6 / (ms6 / 1e3) / 1e9:.3f} Gq/s")
         del m6, q6, out6
+
+    if args.sweep:
+        t0 = time.time()
+        lo2, hi2 = SQ.aabb(w.V)
+        d10 = SQ.scaled_box(lo2, hi2, 10.0)
+        m10, st10 = P.Mesh.cached(w.V, w.F, d10, args.cache or None)
+        t_pre10 = time.time() - t0
+        m10.upload(0)
+        rows = []
+        for scale in (1.0, 1.5, 2.0, 3.0, 5.0, 10.0):
+            blo, bhi = SQ.scaled_box(lo2, hi2, scale)
+            Qs = SQ.uniform_in_box(1_000_000, blo, bhi, np.random.default_rng(2100 + int(10 * scale)))
+            qs_t = torch.from_numpy(Qs).to(dev)
+            o = m10.query(qs_t)
+            for _ in range(args.warmup):
+                m10.query(qs_t, out=o)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                m10.query(qs_t, out=o)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            hc = m10.query_host(Qs[:100_000])
+            k = 100_000
+            rows.append({"box_scale": scale, "queries_per_s": round(1e6 / (ms / 1e3), 1), "ms_per_1e6": round(ms, 4),
+                         "walk_vertices": round(hc["nodes"] / k, 2), "walk_steps": round(hc["steps"] / k, 2),
+                         "list_entries": round((hc["edges"] + hc["faces"]) / k, 2),
+                         "forms_read": round((hc["edge_forms"] + hc["face_forms"]) / k, 2)})
+            log(f"[bench] sweep box {scale}x: {ms:.3f} ms per 1e6, entries {rows[-1]['list_entries']}, "
+                f"forms {rows[-1]['forms_read']}")
+        off10, _ = m10.table()
+        result["near_far_sweep"] = {"domain": "10x AABB", "host_precompute_s": round(t_pre10, 1),
+                                    "avg_list": round(float(off10[-1]) / m10.nv, 2), "rows": rows}
+        del m10
 
     if not args.no_batched:
         count = 256 if args.batched_full else 64
