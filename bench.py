@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-primitive (triangles + segments) leg")
+    ap.add_argument("--no-precompute", action="store_true",
+                    help="skip the device-inspection leg (the C2 table built with the filter and flooding on the GPU)")
     ap.add_argument("--sweep", action="store_true",
                     help="also run the near/far sweep: the C2 mesh precomputed for D = 10x AABB, 1e6 uniform "
                          "queries in boxes of 1x..10x AABB (not part of the default run)")
@@ -276,6 +278,35 @@ def main():
                            "host_precompute_s": round(t_pre6, 1)}
         log(f"[bench] mixed (triangles + segments): {ms6:.3f} ms/step, {n6 / (ms6 / 1e3) / 1e9:.3f} Gq/s")
         del m6, q6, out6
+
+    if not args.no_precompute:
+        # The C2 table again, with the inspection (filter + flooding) on the
+        # device; it must equal the host-built table used above.
+        t0 = time.time()
+        md = P.Mesh(w.V, w.F)
+        sd = md.precompute((w.domain_lo, w.domain_hi), table_mode=P.TABLE_FLOODING_DEVICE)
+        t_dev = time.time() - t0
+        oh, eh = mesh.table()
+        od, ed = md.table()
+        same = bool(np.array_equal(oh, od) and np.array_equal(eh, ed) and
+                    np.array_equal(mesh.table_boxes(), md.table_boxes()))
+        host_stages = {k: round(stats[k], 3) for k in ("t_delaunay", "t_cells", "t_flood", "t_pack") if k in stats}
+        result["precompute_device"] = {
+            "total_s": round(t_dev, 2),
+            "stages_s": {"delaunay": round(sd["t_delaunay"], 3), "cells": round(sd["t_cells"], 3),
+                         "inspection": round(sd["t_flood"], 3), "upload": round(sd["t_dev_upload"], 3),
+                         "kernel": round(sd["t_dev_kernel"], 3), "download": round(sd["t_dev_download"], 3),
+                         "pack": round(sd["t_pack"], 3)},
+            "host_build_stages_s": host_stages or None,
+            "host_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+            "primitives_finished_on_host": int(sd["device_redo"]), "filter_tests": int(sd["flood_tests"]),
+            "identical_to_host_table": same,
+            "workload": "C2 mesh (655,362 V, 1,966,080 E, 1,310,720 F), D = 1.5x AABB"}
+        log(f"[bench] device inspection: total {t_dev:.1f}s, kernel {sd['t_dev_kernel']:.2f}s, inspection "
+            f"{sd['t_flood']:.2f}s (host build: {host_stages or 'loaded from cache'}), "
+            f"{int(sd['device_redo'])} primitives finished on the host, identical table: {same}")
+        assert same, "device-built interception table differs from the host-built one"
+        del md
 
     if args.sweep:
         t0 = time.time()

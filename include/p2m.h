@@ -61,7 +61,16 @@ typedef struct p2m_batch p2m_batch;
 enum {
     P2M_TABLE_FLOODING = 0,  /* convexity filter + flooding (Sec. 4.4-4.5) */
     P2M_TABLE_ALL_PAIRS = 1, /* convexity filter on every vertex-primitive pair (tiny meshes) */
-    P2M_TABLE_EVERYTHING = 2 /* every primitive in every list (tiny meshes; test aid) */
+    P2M_TABLE_EVERYTHING = 2, /* every primitive in every list (tiny meshes; test aid) */
+    /* P2M_TABLE_FLOODING with the filter and flooding (Sec. 4.4-4.5,
+     * Algorithm 1: the inspection, the bulk of the preprocessing per
+     * Table 2) run on the current HIP device, one primitive per lane, in
+     * FP64 with the host's operations and their order, so the table and its
+     * entry boxes are those of P2M_TABLE_FLOODING.  The Delaunay neighbours
+     * and the cells are still built on the host.  A primitive whose flood
+     * outgrows the lane's fixed buffers is finished on the host.  Needs a
+     * HIP device; fails with P2M_ERR_HIP otherwise. */
+    P2M_TABLE_FLOODING_DEVICE = 3
 };
 
 typedef struct {
@@ -74,6 +83,11 @@ typedef struct {
     int num_threads;        /* host threads for the precompute; 0 = all */
     double margin_rel;      /* conservative margin, times diag(D); 0 = 1e-9 */
     int table_mode;         /* P2M_TABLE_* */
+    int device_visit_cap;   /* P2M_TABLE_FLOODING_DEVICE: vertices one
+                               primitive's flood may visit on the device
+                               before the host takes the primitive over;
+                               0 = 512 (the most), 1..512 accepted (small
+                               values move work to the host; a test aid) */
 } p2m_build_opts;
 
 typedef struct {
@@ -83,6 +97,10 @@ typedef struct {
     int64_t flood_tests, flood_hits, quick_rejects, skipped_clips;
     int64_t nnz_edges, nnz_faces, max_list;
     double avg_list; /* (nnz_edges + nnz_faces) / nv */
+    /* P2M_TABLE_FLOODING_DEVICE: seconds spent uploading, in the kernel and
+     * downloading; primitives the host finished */
+    double t_dev_upload, t_dev_kernel, t_dev_download;
+    int64_t device_redo;
 } p2m_build_stats;
 
 typedef struct {

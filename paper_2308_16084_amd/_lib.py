@@ -21,7 +21,7 @@ INT = ctypes.c_int
 class BuildOpts(ctypes.Structure):
     _fields_ = [("domain_lo", ctypes.c_double * 3), ("domain_hi", ctypes.c_double * 3),
                 ("use_default_domain", INT), ("num_threads", INT), ("margin_rel", ctypes.c_double),
-                ("table_mode", INT)]
+                ("table_mode", INT), ("device_visit_cap", INT)]
 
 
 class BuildStats(ctypes.Structure):
@@ -30,7 +30,9 @@ class BuildStats(ctypes.Structure):
                [(n, I64) for n in ("nv", "ne", "nf", "delaunay_edges", "tets", "exact_predicates",
                                    "flood_tests", "flood_hits", "quick_rejects", "skipped_clips",
                                    "nnz_edges", "nnz_faces", "max_list")] + \
-               [("avg_list", ctypes.c_double)]
+               [("avg_list", ctypes.c_double)] + \
+               [(n, ctypes.c_double) for n in ("t_dev_upload", "t_dev_kernel", "t_dev_download")] + \
+               [("device_redo", I64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

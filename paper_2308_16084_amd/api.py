@@ -14,7 +14,7 @@ from ._lib import BuildOpts, BuildStats, P2MError, QueryOpts, check, lib
 
 VERTEX, EDGE, FACE, NONE = 0, 1, 2, 3
 OUT_OF_DOMAIN, NONFINITE = 1, 2
-TABLE_FLOODING, TABLE_ALL_PAIRS, TABLE_EVERYTHING = 0, 1, 2
+TABLE_FLOODING, TABLE_ALL_PAIRS, TABLE_EVERYTHING, TABLE_FLOODING_DEVICE = 0, 1, 2, 3
 
 
 def prim_type(prim):
@@ -140,7 +140,7 @@ class Mesh:
         return E
 
     def precompute(self, domain=None, threads: int = 0, margin_rel: float = 0.0,
-                   table_mode: int = TABLE_FLOODING) -> dict:
+                   table_mode: int = TABLE_FLOODING, device_visit_cap: int = 0) -> dict:
         o = BuildOpts()
         if domain is None:
             o.use_default_domain = 1
@@ -152,6 +152,7 @@ class Mesh:
         o.num_threads = int(threads)
         o.margin_rel = float(margin_rel)
         o.table_mode = int(table_mode)
+        o.device_visit_cap = int(device_visit_cap)
         st = BuildStats()
         check(lib().p2m_precompute(self._h, ctypes.byref(o), ctypes.byref(st)))
         return st.as_dict()
@@ -398,4 +399,4 @@ def p2m_distance(q, V, mesh):
 
 
 __all__ = ["Mesh", "Batch", "precompute_many", "p2m_distance", "P2MError", "prim_type", "prim_id", "VERTEX", "EDGE", "FACE", "NONE",
-           "OUT_OF_DOMAIN", "NONFINITE", "TABLE_FLOODING", "TABLE_ALL_PAIRS", "TABLE_EVERYTHING", "_lib"]
+           "OUT_OF_DOMAIN", "NONFINITE", "TABLE_FLOODING", "TABLE_ALL_PAIRS", "TABLE_EVERYTHING", "TABLE_FLOODING_DEVICE", "_lib"]

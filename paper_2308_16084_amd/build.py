@@ -17,7 +17,10 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 HOST_SOURCES = ["predicates.cpp", "delaunay.cpp", "convex_cell.cpp", "mesh.cpp", "kdtree.cpp",
                 "interception.cpp", "p2m_host.cpp"]
-DEVICE_SOURCES = ["p2m_device.hip", "radix_sort.hip", "p2m_batch.hip"]
+DEVICE_SOURCES = ["p2m_device.hip", "radix_sort.hip", "p2m_batch.hip", "p2m_flood.hip"]
+# The device inspection repeats the host builder's FP64 operations exactly:
+# no contraction into fused multiply-adds, as in the host build.
+EXTRA_FLAGS = {"p2m_flood.hip": ["-ffp-contract=off"]}
 
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-parameter",
               "-ffp-contract=off", f"-I{INCLUDE}"]
@@ -40,7 +43,8 @@ def build(verbose: bool = False) -> str:
     for s in HOST_SOURCES:
         jobs.append(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, s), "-o", os.path.join(BUILD, s + ".o")])
     for s in DEVICE_SOURCES:
-        jobs.append([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, s), "-o", os.path.join(BUILD, s + ".o")])
+        jobs.append([hipcc, *HIP_FLAGS, *EXTRA_FLAGS.get(s, []), "-c", os.path.join(CSRC, s), "-o",
+                     os.path.join(BUILD, s + ".o")])
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         outs = list(ex.map(_run, jobs))
     if verbose:

@@ -8,6 +8,7 @@
 
 #include "convex_cell.hpp"
 #include "delaunay.hpp"
+#include "flood_device.hpp"
 
 #ifdef _OPENMP
 #include <omp.h>
@@ -343,6 +344,112 @@ void flood(const MeshData& m, const CellStore& cs, const Table& t, const Primiti
     }
 }
 
+// Flat copies of the cells and the primitives' Space-perp half-spaces for
+// the device inspection, which returns every entry of the primitives it
+// finished and the list of those it hands back (their entries, if any, are
+// dropped here; the host floods them afterwards).
+bool inspect_on_device(const MeshData& m, const CellStore& cs, const Table& t, const TableOptions& o,
+                       const double blo[3], const double bhi[3], double dmax, int nth, std::vector<PairRec>& pairs,
+                       std::vector<int64_t>& redo, TableStats& st, std::string& err) {
+    const int64_t nv = m.nv, nprim = m.ne + m.nf;
+    FlatCells fc;
+    fc.poff.assign((size_t)nv + 1, 0);
+    fc.toff.assign((size_t)nv + 1, 0);
+    for (int64_t v = 0; v < nv; ++v) {
+        fc.poff[(size_t)v + 1] = fc.poff[(size_t)v] + cs.ref[(size_t)v].np;
+        fc.toff[(size_t)v + 1] = fc.toff[(size_t)v] + cs.ref[(size_t)v].nt;
+    }
+    fc.planes.resize(4 * (size_t)fc.poff[(size_t)nv]);
+    fc.pos.resize(3 * (size_t)fc.toff[(size_t)nv]);
+#pragma omp parallel for num_threads(nth) schedule(static, 4096)
+    for (int64_t v = 0; v < nv; ++v) {
+        uint32_t np = 0, nt = 0;
+        const double* P = cs.plane_data(v, np);
+        const double* X = cs.corners(v, nt);
+        std::memcpy(&fc.planes[4 * (size_t)fc.poff[(size_t)v]], P, sizeof(double) * 4 * np);
+        std::memcpy(&fc.pos[3 * (size_t)fc.toff[(size_t)v]], X, sizeof(double) * 3 * nt);
+    }
+    // half-spaces per primitive: a face has 3, an edge its 2 end planes and
+    // one per incident face, 8 at most (as make_edge keeps them)
+    std::vector<FloodPrim> prims((size_t)nprim);
+    std::vector<int64_t> poff((size_t)nprim + 1, 0);
+    for (int64_t q = 0; q < nprim; ++q) {
+        const int64_t np = q >= m.ne ? 3 : std::min<int64_t>(8, 2 + (m.ef_off[(size_t)q + 1] - m.ef_off[(size_t)q]));
+        poff[(size_t)q + 1] = poff[(size_t)q] + np;
+    }
+    std::vector<double> perp(4 * (size_t)std::max<int64_t>(1, poff[(size_t)nprim]));
+#pragma omp parallel num_threads(nth)
+    {
+        Primitive p;
+#pragma omp for schedule(static, 1024)
+        for (int64_t q = 0; q < nprim; ++q) {
+            const bool face = q >= m.ne;
+            const int64_t id = face ? q - m.ne : q;
+            if (face) make_face(m, id, o.tau, p);
+            else make_edge(m, id, o.tau, p);
+            FloodPrim& f = prims[(size_t)q];
+            std::memcpy(f.a, p.a, sizeof(f.a));
+            std::memcpy(f.dir, p.dir, sizeof(f.dir));
+            for (int k = 0; k < 3; ++k) f.verts[k] = k < p.nverts ? p.verts[k] : -1;
+            f.nverts = p.nverts;
+            f.face = face ? 1 : 0;
+            f.nperp = p.nperp;
+            f.perp_off = poff[(size_t)q];
+            f.id = id;
+            for (int k = 0; k < p.nperp; ++k) {
+                double* h = &perp[4 * (size_t)(poff[(size_t)q] + k)];
+                h[0] = p.perp[k].n[0];
+                h[1] = p.perp[k].n[1];
+                h[2] = p.perp[k].n[2];
+                h[3] = p.perp[k].off;
+            }
+        }
+    }
+    FloodInput in;
+    in.nv = nv;
+    in.nprim = nprim;
+    in.Vd = m.Vd.data();
+    in.nb_off = t.nb_off.data();
+    in.nb = t.nb.data();
+    in.cells = &fc;
+    in.prims = prims.data();
+    in.perp = perp.data();
+    in.nperp_total = poff[(size_t)nprim];
+    for (int k = 0; k < 3; ++k) {
+        in.blo[k] = blo[k];
+        in.bhi[k] = bhi[k];
+        in.qlo[k] = o.lo[k];
+        in.qscale[k] = 65535.0 / (o.hi[k] - o.lo[k]);
+    }
+    in.tau = o.tau;
+    in.dmax = dmax;
+    in.visit_cap = o.visit_cap;
+    FloodResult r;
+    if (!device_flood(in, r, err)) return false;
+    std::vector<uint8_t> back((size_t)nprim, 0);
+    for (int64_t q : r.redo) back[(size_t)q] = 1;
+    pairs.reserve(r.recs.size());
+    for (const FloodRec& f : r.recs) {
+        const int64_t q = (f.code & 0x80000000u) ? m.ne + (int64_t)(f.code & 0x7fffffffu) : (int64_t)f.code;
+        if (back[(size_t)q]) continue;
+        PairRec rec;
+        rec.key = ((uint64_t)f.v << 32) | (uint64_t)f.code;
+        std::memcpy(rec.box, f.box, sizeof(rec.box));
+        pairs.push_back(rec);
+    }
+    redo = std::move(r.redo);
+    std::sort(redo.begin(), redo.end());
+    st.flood_tests += r.tests;
+    st.flood_hits += r.hits;
+    st.quick_rejects += r.quick;
+    st.skipped_clips += r.skipped;
+    st.t_dev_upload = r.t_upload;
+    st.t_dev_kernel = r.t_kernel;
+    st.t_dev_download = r.t_download;
+    st.device_redo = (int64_t)redo.size();
+    return true;
+}
+
 }  // namespace
 
 bool build_table(const MeshData& m, const TableOptions& o, Table& t, TableStats& st, std::string& err) {
@@ -429,6 +536,11 @@ bool build_table(const MeshData& m, const TableOptions& o, Table& t, TableStats&
     dmax = std::sqrt(dmax);
     std::vector<ThreadCtx> ctx((size_t)nth);
     const int64_t nprim = m.ne + m.nf;
+    std::vector<PairRec> dev_pairs;
+    std::vector<int64_t> redo;
+    if (o.mode == TABLE_FLOODING_DEVICE) {
+        if (!inspect_on_device(m, cs, t, o, blo, bhi, dmax, nth, dev_pairs, redo, st, err)) return false;
+    }
 #pragma omp parallel num_threads(nth)
     {
         int tid = 0;
@@ -444,15 +556,18 @@ bool build_table(const MeshData& m, const TableOptions& o, Table& t, TableStats&
             c.qscale_[k] = 65535.0 / (o.hi[k] - o.lo[k]);
         }
         Primitive p;
+        const bool dev = o.mode == TABLE_FLOODING_DEVICE;
+        const int64_t nwork = dev ? (int64_t)redo.size() : nprim;
 #pragma omp for schedule(dynamic, 64)
-        for (int64_t q = 0; q < nprim; ++q) {
+        for (int64_t qi = 0; qi < nwork; ++qi) {
+            const int64_t q = dev ? redo[(size_t)qi] : qi;
             bool face = q >= m.ne;
             int64_t id = face ? q - m.ne : q;
             if (face) make_face(m, id, o.tau, p);
             else make_edge(m, id, o.tau, p);
             bool base_empty = false;
             make_base(p, blo, bhi, c, base_empty);
-            if (o.mode == TABLE_FLOODING) {
+            if (o.mode == TABLE_FLOODING || dev) {
                 flood(m, cs, t, p, id, o.tau, dmax, base_empty, c);
             } else {
                 for (int64_t w = 0; w < nv; ++w) {
@@ -470,8 +585,9 @@ bool build_table(const MeshData& m, const TableOptions& o, Table& t, TableStats&
         }
     }
     std::vector<PairRec> pairs;
+    pairs.swap(dev_pairs);
     {
-        size_t tot = 0;
+        size_t tot = pairs.size();
         for (auto& c : ctx) tot += c.pairs.size();
         pairs.reserve(tot);
         for (auto& c : ctx) {

@@ -25,17 +25,23 @@
 
 namespace p2m {
 
-enum TableMode { TABLE_FLOODING = 0, TABLE_ALL_PAIRS = 1, TABLE_EVERYTHING = 2 };
+// TABLE_FLOODING_DEVICE runs the filter and flooding on the current HIP
+// device with the host's arithmetic; the table is the TABLE_FLOODING one.
+enum TableMode { TABLE_FLOODING = 0, TABLE_ALL_PAIRS = 1, TABLE_EVERYTHING = 2, TABLE_FLOODING_DEVICE = 3 };
 
 struct TableOptions {
     double lo[3], hi[3];  // query domain D
     double tau;           // absolute margin
     int threads;          // 0: all
     int mode;             // TableMode
+    int visit_cap = 0;    // TABLE_FLOODING_DEVICE: flood size the device keeps (0: its most)
 };
 
 struct TableStats {
     double t_delaunay = 0, t_cells = 0, t_flood = 0, t_pack = 0;
+    // device inspection: upload, kernel, download; primitives left to the host
+    double t_dev_upload = 0, t_dev_kernel = 0, t_dev_download = 0;
+    int64_t device_redo = 0;
     int64_t delaunay_edges = 0, tets = 0;
     long long exact_predicates = 0;
     int64_t flood_tests = 0, flood_hits = 0, quick_rejects = 0, skipped_clips = 0;

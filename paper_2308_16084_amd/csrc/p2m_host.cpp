@@ -93,7 +93,8 @@ p2m_status p2m_precompute(p2m_mesh* m, const p2m_build_opts* opts, p2m_build_sta
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
     else o.use_default_domain = 1;
-    if (o.table_mode < 0 || o.table_mode > 2) return fail(P2M_ERR_ARG, "bad table_mode");
+    if (o.table_mode < 0 || o.table_mode > 3) return fail(P2M_ERR_ARG, "bad table_mode");
+    if (o.device_visit_cap < 0 || o.device_visit_cap > 512) return fail(P2M_ERR_ARG, "device_visit_cap outside 0..512");
     if (o.num_threads < 0) return fail(P2M_ERR_ARG, "negative num_threads");
     if (o.margin_rel < 0 || !std::isfinite(o.margin_rel)) return fail(P2M_ERR_ARG, "bad margin_rel");
     double lo[3], hi[3];
@@ -128,9 +129,11 @@ p2m_status p2m_precompute(p2m_mesh* m, const p2m_build_opts* opts, p2m_build_sta
         to.tau = margin * diag;
         to.threads = o.num_threads;
         to.mode = o.table_mode;
+        to.visit_cap = o.device_visit_cap;
         s.ts = TableStats();
         std::string err;
-        if (!build_table(s.m, to, s.t, s.ts, err)) return fail(P2M_ERR_MESH, err);
+        if (!build_table(s.m, to, s.t, s.ts, err))
+            return fail(err.rfind("device inspection", 0) == 0 ? P2M_ERR_HIP : P2M_ERR_MESH, err);
         for (int k = 0; k < 3; ++k) {
             s.dlo[k] = lo[k];
             s.dhi[k] = hi[k];
@@ -166,6 +169,10 @@ p2m_status p2m_precompute(p2m_mesh* m, const p2m_build_opts* opts, p2m_build_sta
         st.nnz_faces = s.ts.nnz_faces;
         st.max_list = s.ts.max_list;
         st.avg_list = (double)(s.ts.nnz_edges + s.ts.nnz_faces) / (double)s.m.nv;
+        st.t_dev_upload = s.ts.t_dev_upload;
+        st.t_dev_kernel = s.ts.t_dev_kernel;
+        st.t_dev_download = s.ts.t_dev_download;
+        st.device_redo = s.ts.device_redo;
     }
     return P2M_OK;
 }

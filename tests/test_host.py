@@ -450,3 +450,13 @@ def test_mixed_save_load_roundtrip():
     assert np.array_equal(m.edges(), m2.edges())
     a, b = m.query_host(Q), m2.query_host(Q)
     assert np.array_equal(a["prim"], b["prim"]) and np.array_equal(a["dist"], b["dist"])
+
+
+@pytest.mark.parametrize("kw,msg", [(dict(table_mode=4), "bad table_mode"),
+                                    (dict(table_mode=P.TABLE_FLOODING_DEVICE, device_visit_cap=513), "device_visit_cap"),
+                                    (dict(table_mode=P.TABLE_FLOODING_DEVICE, device_visit_cap=-1), "device_visit_cap")])
+def test_precompute_option_validation(kw, msg):
+    """Build options are checked before any work, on the host."""
+    m = P.Mesh(TETRA_V, TETRA_F)
+    with pytest.raises(P.P2MError, match=msg):
+        m.precompute(**kw)
