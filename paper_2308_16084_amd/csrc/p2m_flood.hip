@@ -125,21 +125,28 @@ __device__ bool corner_of(const Poly<Cap>& P, const PlaneSrc& S, int i, int j, c
     return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
 }
 
-// Cut P by the half-space (hn, hoff), recorded as plane source `s`.
+// Corners of P strictly outside the half-space (hn, hoff): bit t of out.
 template <int Cap>
-__device__ __noinline__ int clip(Poly<Cap>& P, const PlaneSrc& S, const double hn[3], double hoff, uint8_t s) {
-    if (P.empty) return UNCHANGED;
-    const int nt = P.nt;
-    uint64_t out[2] = {0ull, 0ull};
+__device__ __forceinline__ int outside(const Poly<Cap>& P, const double hn[3], double hoff, uint64_t out[2]) {
+    out[0] = 0ull;
+    out[1] = 0ull;
     int nout = 0;
-    for (int t = 0; t < nt; ++t) {
+    for (int t = 0; t < P.nt; ++t) {
         const double v = dot3(hn, P.pos[t]) - hoff;
         if (v > 0.0) {
             out[t >> 6] |= 1ull << (t & 63);
             ++nout;
         }
     }
-    if (nout == 0) return UNCHANGED;
+    return nout;
+}
+
+// Cut P by the half-space (hn, hoff), recorded as plane source `s`, given
+// the nout > 0 corners outside it (bits of out).
+template <int Cap>
+__device__ __noinline__ int cut(Poly<Cap>& P, const PlaneSrc& S, const double hn[3], double hoff, uint8_t s,
+                                const uint64_t out[2], int nout) {
+    const int nt = P.nt;
     if (nout == nt) {
         P.empty = true;
         P.nt = 0;
@@ -224,8 +231,16 @@ __device__ __noinline__ int clip(Poly<Cap>& P, const PlaneSrc& S, const double h
     return CLIPPED;
 }
 
+template <int Cap>
+__device__ int clip(Poly<Cap>& P, const PlaneSrc& S, const double hn[3], double hoff, uint8_t s) {
+    if (P.empty) return UNCHANGED;
+    uint64_t out[2];
+    const int nout = outside(P, hn, hoff, out);
+    if (nout == 0) return UNCHANGED;
+    return cut(P, S, hn, hoff, s, out, nout);
+}
+
 struct Ctx {
-    const FloodPrim* p;
     const double* perp;
     const double* blo;
     const double* bhi;
@@ -292,30 +307,69 @@ __device__ __noinline__ bool clip_to_cell(const Ctx& c, const Poly<kBaseCap>& B,
         W.pos[t][1] = B.pos[t][1];
         W.pos[t][2] = B.pos[t][2];
     }
+    if (W.empty) return true;
     const PlaneSrc S{c.blo, c.bhi, c.perp, cellp};
-    for (int i = 0; i < np; ++i) {
-        const double hn[3] = {cellp[4 * i], cellp[4 * i + 1], cellp[4 * i + 2]};
-        const double hoff = cellp[4 * i + 3];
-        const int axes = (hn[0] != 0.0) + (hn[1] != 0.0) + (hn[2] != 0.0);
-        if (axes == 1 && (fabs(hn[0]) == 1.0 || fabs(hn[1]) == 1.0 || fabs(hn[2]) == 1.0)) {
-            const int k = hn[0] != 0.0 ? 0 : (hn[1] != 0.0 ? 1 : 2);
-            if ((hn[k] > 0 && hoff == c.bhi[k]) || (hn[k] < 0 && hoff == -c.blo[k])) continue;
+    // Planes that leave W unchanged are passed over in a tight loop of their
+    // own, so the lanes of a wavefront reach their next real cut together.
+    int i = 0;
+    for (;;) {
+        uint64_t out[2] = {0ull, 0ull};
+        int nout = 0;
+        double hn[3], hoff = 0.0;
+        for (; i < np; ++i) {
+            hn[0] = cellp[4 * i];
+            hn[1] = cellp[4 * i + 1];
+            hn[2] = cellp[4 * i + 2];
+            hoff = cellp[4 * i + 3];
+            const int axes = (hn[0] != 0.0) + (hn[1] != 0.0) + (hn[2] != 0.0);
+            if (axes == 1 && (fabs(hn[0]) == 1.0 || fabs(hn[1]) == 1.0 || fabs(hn[2]) == 1.0)) {
+                const int k = hn[0] != 0.0 ? 0 : (hn[1] != 0.0 ? 1 : 2);
+                if ((hn[k] > 0 && hoff == c.bhi[k]) || (hn[k] < 0 && hoff == -c.blo[k])) continue;
+            }
+            nout = outside(W, hn, hoff, out);
+            if (nout > 0) break;
         }
-        const int r = clip(W, S, hn, hoff, (uint8_t)(8 + i));
+        if (i >= np) return true;
+        const int r = cut(W, S, hn, hoff, (uint8_t)(8 + i), out, nout);
         if (r == EMPTY) return false;
         if (r == SKIPPED) ++skipped;
         if (r == OVERFLOW) {
             ovf = true;
             return false;
         }
+        ++i;
     }
-    return true;
+}
+
+// Open-addressing set of visited vertices: true when u is new.  Never full:
+// it has twice the slots of the most vertices a flood may visit.
+__device__ __forceinline__ bool hash_visit(int32_t* hset, int32_t u) {
+    uint32_t h = ((uint32_t)u * 2654435761u) & (kHashCap - 1);
+    for (;;) {
+        if (hset[h] == u) return false;
+        if (hset[h] < 0) {
+            hset[h] = u;
+            return true;
+        }
+        h = (h + 1) & (kHashCap - 1);
+    }
+}
+
+// A point x keeps w out of p's list when |x-w|^2 + slack <= Dist(x,p)^2
+// (Theorems 5 and 6 with the margin).
+__device__ __forceinline__ bool far_enough(const FloodPrim& p, const double* Wv, const double* x, double slack) {
+    double d[3] = {x[0] - Wv[0], x[1] - Wv[1], x[2] - Wv[2]};
+    return dot3(d, d) + slack <= dist2(p, x);
 }
 
 struct Counters {
-    unsigned long long recs, redo, tests, hits, quick, skipped;
+    unsigned long long recs, redo, tests, hits, quick, skipped, next;
 };
 
+// Each lane takes primitives from a shared counter and runs one flood step
+// (one visited vertex) per trip of a single loop; a lane whose flood has
+// ended takes the next primitive at once instead of waiting for the longest
+// flood of its wavefront.
 __global__ __launch_bounds__(64) void k_flood(int64_t nprim, const FloodPrim* __restrict__ prims,
                                               const double* __restrict__ perp, const double* __restrict__ Vd,
                                               const int64_t* __restrict__ nb_off, const int32_t* __restrict__ nb,
@@ -325,98 +379,105 @@ __global__ __launch_bounds__(64) void k_flood(int64_t nprim, const FloodPrim* __
                                               FloodRec* __restrict__ recs, uint64_t rec_cap,
                                               int64_t* __restrict__ redo, Counters* __restrict__ cnt,
                                               int visit_cap) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nprim) return;
-    const FloodPrim p = prims[i];
     Ctx c;
-    c.p = &p;
-    c.perp = perp + 4 * p.perp_off;
     c.blo = dom;
     c.bhi = dom + 3;
     c.qlo = dom + 6;
     c.qscale = dom + 9;
-    const double tau = dom[12], dmax = dom[13];
-    c.slack = 2.0 * tau * dmax;
+    c.slack = 2.0 * dom[12] * dom[13];
+    // lane totals over the primitives it finished
+    unsigned long long t_tests = 0, t_hits = 0, t_quick = 0, t_skipped = 0;
+    // the current primitive
+    int64_t i = -1;
+    FloodPrim p;
+    uint32_t code = 0;
     int64_t tests = 0, hits = 0, quick = 0, skipped = 0;
-    bool ovf = false;
-
-    // base polytope Space-perp(p) n D
+    bool ovf = false, base_empty = false;
+    int head = 0, qn = 0;
     Poly<kBaseCap> B;
-    init_box(B, c.blo, c.bhi);
-    bool base_empty = false;
-    {
-        const PlaneSrc S{c.blo, c.bhi, c.perp, nullptr};
-        for (int j = 0; j < p.nperp && !base_empty && !ovf; ++j) {
-            const double hn[3] = {c.perp[4 * j], c.perp[4 * j + 1], c.perp[4 * j + 2]};
-            const int r = clip(B, S, hn, c.perp[4 * j + 3], (uint8_t)j);
-            if (r == EMPTY) base_empty = true;
-            if (r == SKIPPED) ++skipped;
-            if (r == OVERFLOW) ovf = true;
-        }
-    }
-
+    Poly<kTriCap> W;
     int32_t queue[kQueueCap];
     int32_t hset[kHashCap];
-    for (int k = 0; k < kHashCap; ++k) hset[k] = -1;
-    int qn = 0;
-    auto visit = [&](int32_t u) -> bool {  // true when u is new
-        uint32_t h = ((uint32_t)u * 2654435761u) & (kHashCap - 1);
-        for (;;) {
-            if (hset[h] == u) return false;
-            if (hset[h] < 0) {
-                hset[h] = u;
-                return true;
+    for (;;) {
+        if (ovf || head >= qn) {
+            // the current primitive is done: account for it, take the next
+            if (i >= 0) {
+                if (ovf) {
+                    const unsigned long long slot = atomicAdd(&cnt->redo, 1ull);
+                    redo[slot] = i;
+                } else {
+                    t_tests += (unsigned long long)tests;
+                    t_hits += (unsigned long long)hits;
+                    t_quick += (unsigned long long)quick;
+                    t_skipped += (unsigned long long)skipped;
+                }
             }
-            h = (h + 1) & (kHashCap - 1);
+            i = (int64_t)atomicAdd(&cnt->next, 1ull);
+            if (i >= nprim) break;
+            p = prims[i];
+            c.perp = perp + 4 * p.perp_off;
+            code = (p.face ? 0x80000000u : 0u) | (uint32_t)p.id;
+            tests = hits = quick = skipped = 0;
+            ovf = false;
+            // base polytope Space-perp(p) n D
+            init_box(B, c.blo, c.bhi);
+            base_empty = false;
+            {
+                const PlaneSrc S{c.blo, c.bhi, c.perp, nullptr};
+                for (int j = 0; j < p.nperp && !base_empty && !ovf; ++j) {
+                    const double hn[3] = {c.perp[4 * j], c.perp[4 * j + 1], c.perp[4 * j + 2]};
+                    const int r = clip(B, S, hn, c.perp[4 * j + 3], (uint8_t)j);
+                    if (r == EMPTY) base_empty = true;
+                    if (r == SKIPPED) ++skipped;
+                    if (r == OVERFLOW) ovf = true;
+                }
+            }
+            for (int k = 0; k < kHashCap; ++k) hset[k] = -1;
+            qn = 0;
+            head = 0;
+            for (int k = 0; k < p.nverts; ++k) {
+                hash_visit(hset, p.verts[k]);
+                queue[qn++] = p.verts[k];
+            }
+            continue;
         }
-    };
-    for (int k = 0; k < p.nverts; ++k) {
-        visit(p.verts[k]);
-        queue[qn++] = p.verts[k];
-    }
-    const uint32_t code = (p.face ? 0x80000000u : 0u) | (uint32_t)p.id;
-    Poly<kTriCap> W;
-    for (int head = 0; head < qn && !ovf; ++head) {
-        const int32_t w = queue[head];
+        // one flood step: the next queued vertex w
+        const int32_t w = queue[head++];
         bool own = false;
         for (int k = 0; k < p.nverts; ++k) own |= (p.verts[k] == w);
         const double* cellp = cplanes + 4 * cpoff[w];
         const int cnp = (int)(cpoff[w + 1] - cpoff[w]);
         if (cnp > kPlaneCap - 8 - 8) {
             ovf = true;
-            break;
+            continue;
         }
         uint16_t box[6];
         bool hit;
         if (own) {  // Theorem 2
             if (base_empty || !clip_to_cell(c, B, W, cellp, cnp, skipped, ovf)) W.empty = true;
-            if (ovf) break;
+            if (ovf) continue;
             poly_box(c, W, box);
             hit = true;
         } else {
             ++tests;
             const double* X = Vd + 3 * (int64_t)w;
             const double Wv[3] = {X[0], X[1], X[2]};
-            auto far_enough = [&](const double* x) {
-                double d[3] = {x[0] - Wv[0], x[1] - Wv[1], x[2] - Wv[2]};
-                return dot3(d, d) + c.slack <= dist2(p, x);
-            };
             // |x-w| - Dist(x,p) is convex: the whole cell keeping w out settles it
             const int64_t t0 = (int64_t)ctoff[w], t1 = (int64_t)ctoff[w + 1];
             bool all_far = true;
-            for (int64_t t = t0; t < t1 && all_far; ++t) all_far = far_enough(cpos + 3 * t);
+            for (int64_t t = t0; t < t1 && all_far; ++t) all_far = far_enough(p, Wv, cpos + 3 * t, c.slack);
             hit = false;
             if (all_far) {
                 ++quick;
             } else if (!base_empty && clip_to_cell(c, B, W, cellp, cnp, skipped, ovf)) {
                 for (int t = 0; t < W.nt; ++t)
-                    if (!far_enough(W.pos[t])) {
+                    if (!far_enough(p, Wv, W.pos[t], c.slack)) {
                         poly_box(c, W, box);
                         hit = true;
                         break;
                     }
             }
-            if (ovf) break;
+            if (ovf) continue;
         }
         if (!hit) continue;
         ++hits;
@@ -430,7 +491,7 @@ __global__ __launch_bounds__(64) void k_flood(int64_t nprim, const FloodPrim* __
         }
         for (int64_t k = nb_off[w]; k < nb_off[w + 1]; ++k) {
             const int32_t u = nb[k];
-            if (!visit(u)) continue;
+            if (!hash_visit(hset, u)) continue;
             if (qn >= visit_cap) {
                 ovf = true;
                 break;
@@ -438,15 +499,10 @@ __global__ __launch_bounds__(64) void k_flood(int64_t nprim, const FloodPrim* __
             queue[qn++] = u;
         }
     }
-    if (ovf) {
-        const unsigned long long slot = atomicAdd(&cnt->redo, 1ull);
-        redo[slot] = i;
-        return;
-    }
-    atomicAdd(&cnt->tests, (unsigned long long)tests);
-    atomicAdd(&cnt->hits, (unsigned long long)hits);
-    atomicAdd(&cnt->quick, (unsigned long long)quick);
-    atomicAdd(&cnt->skipped, (unsigned long long)skipped);
+    atomicAdd(&cnt->tests, t_tests);
+    atomicAdd(&cnt->hits, t_hits);
+    atomicAdd(&cnt->quick, t_quick);
+    atomicAdd(&cnt->skipped, t_skipped);
 }
 
 using Clock = std::chrono::steady_clock;
@@ -522,8 +578,13 @@ bool device_flood(const FloodInput& in, FloodResult& out, std::string& err) {
     if (!hip_ok(hipDeviceSynchronize(), "upload")) return false;
     out.t_upload = since(t0);
     t0 = Clock::now();
+    // enough wavefronts to fill the chip; each lane loops over primitives
     const int block = 64;
-    const int64_t grid = (in.nprim + block - 1) / block;
+    int dev = 0, cus = 256, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_flood, block, 0) != hipSuccess || per_cu < 1) per_cu = 8;
+    const int64_t grid = std::min<int64_t>((in.nprim + block - 1) / block, (int64_t)cus * per_cu);
     k_flood<<<(unsigned)grid, block, 0, 0>>>(
         in.nprim, (const FloodPrim*)(d + off[0]), (const double*)(d + off[1]), (const double*)(d + off[2]),
         (const int64_t*)(d + off[3]), (const int32_t*)(d + off[4]), (const uint64_t*)(d + off[5]),
