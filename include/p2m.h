@@ -64,12 +64,13 @@ enum {
     P2M_TABLE_EVERYTHING = 2, /* every primitive in every list (tiny meshes; test aid) */
     /* P2M_TABLE_FLOODING with the filter and flooding (Sec. 4.4-4.5,
      * Algorithm 1: the inspection, the bulk of the preprocessing per
-     * Table 2) run on the current HIP device, one primitive per lane, in
-     * FP64 with the host's operations and their order, so the table and its
-     * entry boxes are those of P2M_TABLE_FLOODING.  The Delaunay neighbours
-     * and the cells are still built on the host.  A primitive whose flood
-     * outgrows the lane's fixed buffers is finished on the host.  Needs a
-     * HIP device; fails with P2M_ERR_HIP otherwise. */
+     * Table 2) run on the current HIP device, one primitive per wavefront,
+     * in FP64 with the host's operations and their order, so the table and
+     * its entry boxes are those of P2M_TABLE_FLOODING.  The Delaunay
+     * neighbours and the cells are still built on the host.  A primitive
+     * whose polytope outgrows 64 corners or whose flood outgrows the visit
+     * limit is finished on the host.  Blocks until done; uses the null
+     * stream.  Needs a HIP device; fails with P2M_ERR_HIP otherwise. */
     P2M_TABLE_FLOODING_DEVICE = 3
 };
 

@@ -426,16 +426,24 @@ bool inspect_on_device(const MeshData& m, const CellStore& cs, const Table& t, c
     in.visit_cap = o.visit_cap;
     FloodResult r;
     if (!device_flood(in, r, err)) return false;
-    std::vector<uint8_t> back((size_t)nprim, 0);
-    for (int64_t q : r.redo) back[(size_t)q] = 1;
-    pairs.reserve(r.recs.size());
-    for (const FloodRec& f : r.recs) {
-        const int64_t q = (f.code & 0x80000000u) ? m.ne + (int64_t)(f.code & 0x7fffffffu) : (int64_t)f.code;
-        if (back[(size_t)q]) continue;
-        PairRec rec;
+    pairs.resize(r.recs.size());
+    const int64_t nrec = (int64_t)r.recs.size();
+#pragma omp parallel for num_threads(nth) schedule(static, 65536)
+    for (int64_t k = 0; k < nrec; ++k) {
+        const FloodRec& f = r.recs[(size_t)k];
+        PairRec& rec = pairs[(size_t)k];
         rec.key = ((uint64_t)f.v << 32) | (uint64_t)f.code;
         std::memcpy(rec.box, f.box, sizeof(rec.box));
-        pairs.push_back(rec);
+    }
+    if (!r.redo.empty()) {
+        std::vector<uint8_t> back((size_t)nprim, 0);
+        for (int64_t q : r.redo) back[(size_t)q] = 1;
+        auto handed_back = [&](const PairRec& rec) {
+            const uint32_t code = (uint32_t)(rec.key & 0xffffffffu);
+            const int64_t q = (code & 0x80000000u) ? m.ne + (int64_t)(code & 0x7fffffffu) : (int64_t)code;
+            return back[(size_t)q] != 0;
+        };
+        pairs.erase(std::remove_if(pairs.begin(), pairs.end(), handed_back), pairs.end());
     }
     redo = std::move(r.redo);
     std::sort(redo.begin(), redo.end());

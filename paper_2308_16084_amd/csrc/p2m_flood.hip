@@ -1,5 +1,5 @@
 // Device inspection: the convexity filter (Theorems 5 and 6) and flooding
-// (Algorithm 1) of every primitive, one primitive per lane.
+// (Algorithm 1) of every primitive, one primitive per wavefront.
 //
 // The arithmetic is the host builder's, operation for operation, in FP64,
 // and this file is compiled without contraction (no fused multiply-adds), so
@@ -8,12 +8,13 @@
 // corner is a triangle of plane ids, counter-clockwise from outside); a cut
 // removes the corners outside the plane and closes the hole with one new
 // corner per boundary edge.  What a cut does depends only on the set of
-// corners, not on their order, so the corners can be stored in any order.
-//
-// Each lane holds its primitive's base polytope Space-perp(p) n D, a working
-// polytope ConvexPoly(w,p) = base n Cell(w), the flood queue and a hash set
-// of visited vertices, all of fixed capacity.  A primitive that outgrows any
-// of them is handed back to the host, which floods it itself.
+// corners, not on their order, so the corners can be stored in any order:
+// here corner t sits in lane t of the wavefront (at most 64), with the
+// corners across its three edges kept explicitly, so a cut is a few
+// wave-wide steps -- one plane test per lane, a ballot, the boundary read off
+// the adjacency -- and the flood's queue and visited set live in LDS.  A
+// primitive whose polytope outgrows 64 corners or whose flood outgrows the
+// queue is handed back to the host, which floods it itself.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -26,9 +27,8 @@ namespace p2m {
 
 namespace {
 
-constexpr int kTriCap = 96;    // corners of the working polytope, new ones included during a cut
-constexpr int kBaseCap = 32;   // corners of the base polytope
 constexpr int kPlaneCap = 128; // planes of a polytope (ids fit in 8 bits)
+constexpr int kWaveCorners = 64;  // corners of a polytope: one per lane
 constexpr int kQueueCap = 512; // vertices one flood may visit
 constexpr int kHashCap = 1024; // open-addressing set over them (power of two)
 
@@ -51,28 +51,15 @@ struct PlaneSrc {
     const double* cellp;  // 4 doubles per plane of the current cell
 };
 
-template <int Cap>
-struct Poly {
-    int nt, np;
-    bool empty;
-    uint8_t src[kPlaneCap - 6];
-    uint8_t tri[Cap][3];
-    double pos[Cap][3];
-};
-
 __device__ __forceinline__ void plane_get(const PlaneSrc& S, const uint8_t* src, int id, double n[3], double& off) {
     if (id < 6) {
         const int k = id >> 1;
-        n[0] = 0.0;
-        n[1] = 0.0;
-        n[2] = 0.0;
-        if (id & 1) {
-            n[k] = 1.0;
-            off = S.bhi[k];
-        } else {
-            n[k] = -1.0;
-            off = -S.blo[k];
-        }
+        const bool up = id & 1;
+        const double sgn = up ? 1.0 : -1.0;
+        n[0] = k == 0 ? sgn : 0.0;
+        n[1] = k == 1 ? sgn : 0.0;
+        n[2] = k == 2 ? sgn : 0.0;
+        off = up ? S.bhi[k] : -S.blo[k];
         return;
     }
     const uint8_t s = src[id - 6];
@@ -81,163 +68,6 @@ __device__ __forceinline__ void plane_get(const PlaneSrc& S, const uint8_t* src,
     n[1] = h[1];
     n[2] = h[2];
     off = h[3];
-}
-
-template <int Cap>
-__device__ void init_box(Poly<Cap>& P, const double* lo, const double* hi) {
-    P.nt = 8;
-    P.np = 6;
-    P.empty = false;
-    for (int c = 0; c < 8; ++c) {
-        const int sx = c & 1, sy = (c >> 1) & 1, sz = (c >> 2) & 1;
-        uint8_t t0 = (uint8_t)(0 + sx), t1 = (uint8_t)(2 + sy), t2 = (uint8_t)(4 + sz);
-        const int sgn = (sx ? 1 : -1) * (sy ? 1 : -1) * (sz ? 1 : -1);
-        if (sgn < 0) {
-            const uint8_t t = t0;
-            t0 = t1;
-            t1 = t;
-        }
-        P.tri[c][0] = t0;
-        P.tri[c][1] = t1;
-        P.tri[c][2] = t2;
-        P.pos[c][0] = sx ? hi[0] : lo[0];
-        P.pos[c][1] = sy ? hi[1] : lo[1];
-        P.pos[c][2] = sz ? hi[2] : lo[2];
-    }
-}
-
-// Corner where planes i, j (existing ids) and the new plane h meet.
-template <int Cap>
-__device__ bool corner_of(const Poly<Cap>& P, const PlaneSrc& S, int i, int j, const double hn[3], double hoff,
-                          double x[3]) {
-    double an[3], bn[3], aoff, boff;
-    plane_get(S, P.src, i, an, aoff);
-    plane_get(S, P.src, j, bn, boff);
-    double bc[3], ca[3], ab[3];
-    cross3(bn, hn, bc);
-    cross3(hn, an, ca);
-    cross3(an, bn, ab);
-    const double det = dot3(an, bc);
-    const double scale = sqrt(dot3(an, an) * dot3(bn, bn) * dot3(hn, hn));
-    if (!(det > 1e-13 * scale)) return false;
-    const double inv = 1.0 / det;
-    for (int d = 0; d < 3; ++d) x[d] = (aoff * bc[d] + boff * ca[d] + hoff * ab[d]) * inv;
-    return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
-}
-
-// Corners of P strictly outside the half-space (hn, hoff): bit t of out.
-template <int Cap>
-__device__ __forceinline__ int outside(const Poly<Cap>& P, const double hn[3], double hoff, uint64_t out[2]) {
-    out[0] = 0ull;
-    out[1] = 0ull;
-    int nout = 0;
-    for (int t = 0; t < P.nt; ++t) {
-        const double v = dot3(hn, P.pos[t]) - hoff;
-        if (v > 0.0) {
-            out[t >> 6] |= 1ull << (t & 63);
-            ++nout;
-        }
-    }
-    return nout;
-}
-
-// Cut P by the half-space (hn, hoff), recorded as plane source `s`, given
-// the nout > 0 corners outside it (bits of out).
-template <int Cap>
-__device__ __noinline__ int cut(Poly<Cap>& P, const PlaneSrc& S, const double hn[3], double hoff, uint8_t s,
-                                const uint64_t out[2], int nout) {
-    const int nt = P.nt;
-    if (nout == nt) {
-        P.empty = true;
-        P.nt = 0;
-        return EMPTY;
-    }
-    // Boundary of the removed region, searched inside the smaller side.
-    const bool from_removed = 2 * nout <= nt;
-    uint8_t side[Cap];
-    int ns = 0;
-    for (int t = 0; t < nt; ++t)
-        if ((((out[t >> 6] >> (t & 63)) & 1ull) != 0) == from_removed) side[ns++] = (uint8_t)t;
-    uint8_t ba[Cap], bb[Cap];
-    int nb = 0;
-    for (int i = 0; i < ns; ++i) {
-        const uint8_t* T = P.tri[side[i]];
-        for (int e = 0; e < 3; ++e) {
-            const uint8_t a = T[e], b = T[e == 2 ? 0 : e + 1];
-            int twins = 0;
-            for (int k = 0; k < ns; ++k) {
-                const uint8_t* U = P.tri[side[k]];
-                twins += (U[0] == b && U[1] == a) + (U[1] == b && U[2] == a) + (U[2] == b && U[0] == a);
-            }
-            if (twins == 0) {
-                if (nb >= Cap) return OVERFLOW;
-                ba[nb] = from_removed ? a : b;
-                bb[nb] = from_removed ? b : a;
-                ++nb;
-            } else if (twins != 1) {
-                return SKIPPED;
-            }
-        }
-    }
-    if (nb < 3) return SKIPPED;
-    const int np = P.np;
-    if (np + 1 > kPlaneCap) return OVERFLOW;
-    // the boundary must be one cycle
-    int16_t nxt[kPlaneCap];
-    for (int i = 0; i < np; ++i) nxt[i] = -1;
-    for (int i = 0; i < nb; ++i) {
-        if (nxt[ba[i]] != -1) return SKIPPED;
-        nxt[ba[i]] = bb[i];
-    }
-    {
-        int a = ba[0];
-        int steps = 0;
-        do {
-            a = nxt[a];
-            if (a < 0) return SKIPPED;
-            ++steps;
-        } while (a != (int)ba[0] && steps <= nb);
-        if (steps != nb) return SKIPPED;
-    }
-    if (nt + nb > Cap) return OVERFLOW;
-    // new corners go after the current ones until every one is known
-    const uint8_t pid = (uint8_t)np;
-    for (int i = 0; i < nb; ++i) {
-        double x[3];
-        if (!corner_of(P, S, ba[i], bb[i], hn, hoff, x)) return SKIPPED;
-        P.tri[nt + i][0] = ba[i];
-        P.tri[nt + i][1] = bb[i];
-        P.tri[nt + i][2] = pid;
-        P.pos[nt + i][0] = x[0];
-        P.pos[nt + i][1] = x[1];
-        P.pos[nt + i][2] = x[2];
-    }
-    P.src[np - 6] = s;
-    P.np = np + 1;
-    int w = 0;
-    for (int t = 0; t < nt + nb; ++t) {
-        if (t < nt && ((out[t >> 6] >> (t & 63)) & 1ull)) continue;
-        if (w != t) {
-            P.tri[w][0] = P.tri[t][0];
-            P.tri[w][1] = P.tri[t][1];
-            P.tri[w][2] = P.tri[t][2];
-            P.pos[w][0] = P.pos[t][0];
-            P.pos[w][1] = P.pos[t][1];
-            P.pos[w][2] = P.pos[t][2];
-        }
-        ++w;
-    }
-    P.nt = w;
-    return CLIPPED;
-}
-
-template <int Cap>
-__device__ int clip(Poly<Cap>& P, const PlaneSrc& S, const double hn[3], double hoff, uint8_t s) {
-    if (P.empty) return UNCHANGED;
-    uint64_t out[2];
-    const int nout = outside(P, hn, hoff, out);
-    if (nout == 0) return UNCHANGED;
-    return cut(P, S, hn, hoff, s, out, nout);
 }
 
 struct Ctx {
@@ -271,90 +101,6 @@ __device__ void quantize_box(const Ctx& c, const double lo[3], const double hi[3
     }
 }
 
-template <int Cap>
-__device__ void poly_box(const Ctx& c, const Poly<Cap>& P, uint16_t out[6]) {
-    if (P.empty || P.nt == 0) {
-        for (int k = 0; k < 3; ++k) {
-            out[k] = 65535;
-            out[3 + k] = 0;
-        }
-        return;
-    }
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int t = 0; t < P.nt; ++t)
-        for (int k = 0; k < 3; ++k) {
-            const double x = P.pos[t][k];
-            lo[k] = x < lo[k] ? x : lo[k];
-            hi[k] = hi[k] < x ? x : hi[k];
-        }
-    quantize_box(c, lo, hi, out);
-}
-
-// ConvexPoly(w,p) into W: the base polytope cut by the planes of Cell(w)
-// (its faces on D's boundary are already faces of the base).  Returns
-// false when it is empty; OVERFLOW through `ovf`.
-__device__ __noinline__ bool clip_to_cell(const Ctx& c, const Poly<kBaseCap>& B, Poly<kTriCap>& W, const double* cellp, int np,
-                             int64_t& skipped, bool& ovf) {
-    W.nt = B.nt;
-    W.np = B.np;
-    W.empty = B.empty;
-    for (int i = 0; i < B.np - 6; ++i) W.src[i] = B.src[i];
-    for (int t = 0; t < B.nt; ++t) {
-        W.tri[t][0] = B.tri[t][0];
-        W.tri[t][1] = B.tri[t][1];
-        W.tri[t][2] = B.tri[t][2];
-        W.pos[t][0] = B.pos[t][0];
-        W.pos[t][1] = B.pos[t][1];
-        W.pos[t][2] = B.pos[t][2];
-    }
-    if (W.empty) return true;
-    const PlaneSrc S{c.blo, c.bhi, c.perp, cellp};
-    // Planes that leave W unchanged are passed over in a tight loop of their
-    // own, so the lanes of a wavefront reach their next real cut together.
-    int i = 0;
-    for (;;) {
-        uint64_t out[2] = {0ull, 0ull};
-        int nout = 0;
-        double hn[3], hoff = 0.0;
-        for (; i < np; ++i) {
-            hn[0] = cellp[4 * i];
-            hn[1] = cellp[4 * i + 1];
-            hn[2] = cellp[4 * i + 2];
-            hoff = cellp[4 * i + 3];
-            const int axes = (hn[0] != 0.0) + (hn[1] != 0.0) + (hn[2] != 0.0);
-            if (axes == 1 && (fabs(hn[0]) == 1.0 || fabs(hn[1]) == 1.0 || fabs(hn[2]) == 1.0)) {
-                const int k = hn[0] != 0.0 ? 0 : (hn[1] != 0.0 ? 1 : 2);
-                if ((hn[k] > 0 && hoff == c.bhi[k]) || (hn[k] < 0 && hoff == -c.blo[k])) continue;
-            }
-            nout = outside(W, hn, hoff, out);
-            if (nout > 0) break;
-        }
-        if (i >= np) return true;
-        const int r = cut(W, S, hn, hoff, (uint8_t)(8 + i), out, nout);
-        if (r == EMPTY) return false;
-        if (r == SKIPPED) ++skipped;
-        if (r == OVERFLOW) {
-            ovf = true;
-            return false;
-        }
-        ++i;
-    }
-}
-
-// Open-addressing set of visited vertices: true when u is new.  Never full:
-// it has twice the slots of the most vertices a flood may visit.
-__device__ __forceinline__ bool hash_visit(int32_t* hset, int32_t u) {
-    uint32_t h = ((uint32_t)u * 2654435761u) & (kHashCap - 1);
-    for (;;) {
-        if (hset[h] == u) return false;
-        if (hset[h] < 0) {
-            hset[h] = u;
-            return true;
-        }
-        h = (h + 1) & (kHashCap - 1);
-    }
-}
-
 // A point x keeps w out of p's list when |x-w|^2 + slack <= Dist(x,p)^2
 // (Theorems 5 and 6 with the margin).
 __device__ __forceinline__ bool far_enough(const FloodPrim& p, const double* Wv, const double* x, double slack) {
@@ -366,143 +112,481 @@ struct Counters {
     unsigned long long recs, redo, tests, hits, quick, skipped, next;
 };
 
-// Each lane takes primitives from a shared counter and runs one flood step
-// (one visited vertex) per trip of a single loop; a lane whose flood has
-// ended takes the next primitive at once instead of waiting for the longest
-// flood of its wavefront.
+struct WPoly {
+    double x, y, z;  // this lane's corner (lanes below nt)
+    uint32_t tri;    // its planes a | b << 8 | c << 16, counter-clockwise from outside
+    uint32_t adj;    // lanes of the corners across edges (a,b), (b,c), (c,a), 8 bits each
+    int nt, np;      // wave-uniform
+    bool empty;
+};
+
+struct WaveLds {
+    int32_t queue[kQueueCap];
+    int32_t hset[kHashCap];
+    int32_t nxt[kPlaneCap];      // boundary cycle: next plane after a, or -1
+    uint8_t newidx[kPlaneCap];   // new corner of the boundary edge starting at plane a
+    uint8_t endidx[kPlaneCap];   // new corner of the boundary edge ending at plane b
+    uint8_t o2n[kWaveCorners];   // kept corner: old lane -> new lane
+    uint8_t srcB[kPlaneCap - 6]; // plane sources of the base and working polytopes
+    uint8_t srcW[kPlaneCap - 6];
+    double sx[kWaveCorners], sy[kWaveCorners], sz[kWaveCorners];  // staging of a cut's result
+    uint32_t stri[kWaveCorners], sadj[kWaveCorners];
+};
+
+__device__ __forceinline__ int wlane() { return (int)__lane_id(); }
+__device__ __forceinline__ uint64_t below(int l) { return l == 0 ? 0ull : (~0ull >> (64 - l)); }
+__device__ __forceinline__ int tri_at(uint32_t tri, int e) { return (int)((tri >> (8 * e)) & 255u); }
+
+struct WCorner {
+    double x[3];
+    bool ok;
+};
+
+// Corner of planes a, b and the new plane h (the host's formula), from the
+// planes themselves.
+__device__ __forceinline__ WCorner wcorner_of(double an0, double an1, double an2, double aoff, double bn0, double bn1,
+                                           double bn2, double boff, double hn0, double hn1, double hn2, double hoff) {
+    const double an[3] = {an0, an1, an2}, bn[3] = {bn0, bn1, bn2}, hn[3] = {hn0, hn1, hn2};
+    WCorner r;
+    double bc[3], ca[3], ab[3];
+    cross3(bn, hn, bc);
+    cross3(hn, an, ca);
+    cross3(an, bn, ab);
+    const double det = dot3(an, bc);
+    const double scale = sqrt(dot3(an, an) * dot3(bn, bn) * dot3(hn, hn));
+    r.ok = false;
+    r.x[0] = r.x[1] = r.x[2] = 0.0;
+    if (!(det > 1e-13 * scale)) return r;
+    const double inv = 1.0 / det;
+    for (int d = 0; d < 3; ++d) r.x[d] = (aoff * bc[d] + boff * ca[d] + hoff * ab[d]) * inv;
+    r.ok = isfinite(r.x[0]) && isfinite(r.x[1]) && isfinite(r.x[2]);
+    return r;
+}
+
+__device__ __forceinline__ WCorner wcorner(const PlaneSrc& S, const uint8_t* src, int i, int j, const double hn[3],
+                                           double hoff) {
+    double an[3], bn[3], aoff, boff;
+    plane_get(S, src, i, an, aoff);
+    plane_get(S, src, j, bn, boff);
+    return wcorner_of(an[0], an[1], an[2], aoff, bn[0], bn[1], bn[2], boff, hn[0], hn[1], hn[2], hoff);
+}
+
+// The box D grown by tau, with the corners' adjacency found by search.
+__device__ void winit_box(WPoly& P, const double* lo, const double* hi) {
+    const int l = wlane();
+    P.nt = 8;
+    P.np = 6;
+    P.empty = false;
+    const int c = l & 7;
+    const int sx = c & 1, sy = (c >> 1) & 1, sz = (c >> 2) & 1;
+    uint32_t t0 = (uint32_t)(0 + sx), t1 = (uint32_t)(2 + sy), t2 = (uint32_t)(4 + sz);
+    if ((sx ? 1 : -1) * (sy ? 1 : -1) * (sz ? 1 : -1) < 0) {
+        const uint32_t t = t0;
+        t0 = t1;
+        t1 = t;
+    }
+    P.tri = t0 | (t1 << 8) | (t2 << 16);
+    P.x = sx ? hi[0] : lo[0];
+    P.y = sy ? hi[1] : lo[1];
+    P.z = sz ? hi[2] : lo[2];
+    uint32_t adj = 0;
+    for (int e = 0; e < 3; ++e) {
+        const int a = tri_at(P.tri, e), b = tri_at(P.tri, e == 2 ? 0 : e + 1);
+        uint32_t found = 0;
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t U = (uint32_t)__shfl((int)P.tri, j);
+            const int u0 = tri_at(U, 0), u1 = tri_at(U, 1), u2 = tri_at(U, 2);
+            if ((u0 == b && u1 == a) || (u1 == b && u2 == a) || (u2 == b && u0 == a)) found = (uint32_t)j;
+        }
+        adj |= found << (8 * e);
+    }
+    P.adj = adj;
+}
+
+// Corners strictly outside (hn, hoff): a wave-uniform mask.
+__device__ __forceinline__ uint64_t woutside(const WPoly& P, const double hn[3], double hoff) {
+    const bool valid = wlane() < P.nt;
+    const double pos[3] = {P.x, P.y, P.z};
+    const double v = valid ? dot3(hn, pos) - hoff : 0.0;
+    return __ballot(valid && v > 0.0);
+}
+
+// Cut P (sources in src) by (hn, hoff) with source s, given the nonempty
+// mask of corners outside.  Same outcome as the host's cut.
+__device__ int wcut(WPoly& P, uint8_t* src, WaveLds& L, const PlaneSrc& S, const double hn[3], double hoff,
+                    uint8_t s, uint64_t outmask) {
+    const int l = wlane();
+    const int nout = __popcll(outmask);
+    if (nout == P.nt) {
+        P.empty = true;
+        P.nt = 0;
+        return EMPTY;
+    }
+    const bool valid = l < P.nt;
+    const bool out = (outmask >> l) & 1ull;
+    const int a0 = tri_at(P.tri, 0), a1 = tri_at(P.tri, 1), a2 = tri_at(P.tri, 2);
+    const int n0 = tri_at(P.adj, 0), n1 = tri_at(P.adj, 1), n2 = tri_at(P.adj, 2);
+    // boundary edges: edges of removed corners whose neighbour is kept
+    const bool be0 = out && !((outmask >> n0) & 1ull);
+    const bool be1 = out && !((outmask >> n1) & 1ull);
+    const bool be2 = out && !((outmask >> n2) & 1ull);
+    const uint64_t m0 = __ballot(be0), m1 = __ballot(be1), m2 = __ballot(be2);
+    const int nb = __popcll(m0) + __popcll(m1) + __popcll(m2);
+    if (nb < 3) return SKIPPED;
+    const int np = P.np;
+    if (np + 1 > kPlaneCap) return OVERFLOW;
+    // the boundary must be one cycle: one edge leaving each plane ...
+    for (int i = l; i < np; i += 64) L.nxt[i] = -1;
+    __syncthreads();
+    bool dup = false;
+    if (be0) dup |= atomicCAS(&L.nxt[a0], -1, a1) != -1;
+    if (be1) dup |= atomicCAS(&L.nxt[a1], -1, a2) != -1;
+    if (be2) dup |= atomicCAS(&L.nxt[a2], -1, a0) != -1;
+    __syncthreads();
+    if (__ballot(dup)) return SKIPPED;
+    // ... and following them from one start visits all nb
+    {
+        const int f = __ffsll((long long)(m0 | m1 | m2)) - 1;
+        const int mine = be0 ? a0 : (be1 ? a1 : a2);
+        const int start = __shfl(mine, f);
+        int a = start, steps = 0;
+        bool ok = true;
+        do {
+            a = L.nxt[a];
+            if (a < 0) {
+                ok = false;
+                break;
+            }
+            ++steps;
+        } while (a != start && steps <= nb);
+        if (!ok || steps != nb) return SKIPPED;
+    }
+    const int nk = P.nt - nout;
+    const int ntn = nk + nb;
+    if (ntn > kWaveCorners) return OVERFLOW;
+    // new places: kept corners first, in lane order, then the new ones
+    const bool kept = valid && !out;
+    const uint64_t keptmask = __ballot(kept);
+    const int dk = __popcll(keptmask & below(l));
+    const int dn = nk + __popcll(m0 & below(l)) + __popcll(m1 & below(l)) + __popcll(m2 & below(l));
+    const int d0 = dn, d1 = dn + (be0 ? 1 : 0), d2 = d1 + (be1 ? 1 : 0);
+    // the new corners, one per boundary edge (a -> b): planes a, b, np,
+    // staged at their new places (dropped if the cut is skipped)
+    // a lane owns up to three boundary edges: the corners are computed in
+    // passes, one edge of every owning lane per pass
+    bool fail = false;
+    const int kmine = (be0 ? 1 : 0) + (be1 ? 1 : 0) + (be2 ? 1 : 0);
+    const int passes = __ballot(kmine >= 3) ? 3 : (__ballot(kmine >= 2) ? 2 : 1);
+    for (int it = 0; it < passes; ++it) {
+        // this lane's it-th boundary edge
+        int e = -1, seen = 0;
+        if (be0 && seen++ == it) e = 0;
+        if (be1 && seen++ == it && e < 0) e = 1;
+        if (be2 && seen++ == it && e < 0) e = 2;
+        if (e >= 0) {
+            const int a = e == 0 ? a0 : (e == 1 ? a1 : a2);
+            const int b = e == 0 ? a1 : (e == 1 ? a2 : a0);
+            const int d = e == 0 ? d0 : (e == 1 ? d1 : d2);
+            const WCorner r = wcorner(S, src, a, b, hn, hoff);
+            fail |= !r.ok;
+            L.sx[d] = r.x[0];
+            L.sy[d] = r.x[1];
+            L.sz[d] = r.x[2];
+        }
+    }
+    if (__ballot(fail)) return SKIPPED;
+    if (kept) L.o2n[l] = (uint8_t)dk;
+    if (be0) {
+        L.newidx[a0] = (uint8_t)d0;
+        L.endidx[a1] = (uint8_t)d0;
+    }
+    if (be1) {
+        L.newidx[a1] = (uint8_t)d1;
+        L.endidx[a2] = (uint8_t)d1;
+    }
+    if (be2) {
+        L.newidx[a2] = (uint8_t)d2;
+        L.endidx[a0] = (uint8_t)d2;
+    }
+    if (l == 0) src[np - 6] = s;
+    __syncthreads();
+    const uint32_t pid = (uint32_t)np;
+    if (kept) {
+        // an edge (c -> d) facing a removed corner now faces the new corner
+        // of the boundary edge (d -> c)
+        const int ends[3] = {a1, a2, a0};
+        const int nbr[3] = {n0, n1, n2};
+        uint32_t adj = 0;
+        for (int e = 0; e < 3; ++e) {
+            const int n = nbr[e];
+            const uint32_t t = ((outmask >> n) & 1ull) ? L.newidx[ends[e]] : L.o2n[n];
+            adj |= t << (8 * e);
+        }
+        L.sx[dk] = P.x;
+        L.sy[dk] = P.y;
+        L.sz[dk] = P.z;
+        L.stri[dk] = P.tri;
+        L.sadj[dk] = adj;
+    }
+    // new corner (a, b, np): across (a,b) the kept corner, across (b,np)
+    // the new corner starting at b, across (np,a) the one ending at a
+    if (be0) {
+        L.stri[d0] = (uint32_t)a0 | ((uint32_t)a1 << 8) | (pid << 16);
+        L.sadj[d0] = (uint32_t)L.o2n[n0] | ((uint32_t)L.newidx[a1] << 8) | ((uint32_t)L.endidx[a0] << 16);
+    }
+    if (be1) {
+        L.stri[d1] = (uint32_t)a1 | ((uint32_t)a2 << 8) | (pid << 16);
+        L.sadj[d1] = (uint32_t)L.o2n[n1] | ((uint32_t)L.newidx[a2] << 8) | ((uint32_t)L.endidx[a1] << 16);
+    }
+    if (be2) {
+        L.stri[d2] = (uint32_t)a2 | ((uint32_t)a0 << 8) | (pid << 16);
+        L.sadj[d2] = (uint32_t)L.o2n[n2] | ((uint32_t)L.newidx[a0] << 8) | ((uint32_t)L.endidx[a2] << 16);
+    }
+    __syncthreads();
+    if (l < ntn) {
+        P.x = L.sx[l];
+        P.y = L.sy[l];
+        P.z = L.sz[l];
+        P.tri = L.stri[l];
+        P.adj = L.sadj[l];
+    }
+    P.nt = ntn;
+    P.np = np + 1;
+    __syncthreads();
+    return CLIPPED;
+}
+
+__device__ __forceinline__ int wclip(WPoly& P, uint8_t* src, WaveLds& L, const PlaneSrc& S, const double hn[3],
+                                     double hoff, uint8_t s) {
+    if (P.empty) return UNCHANGED;
+    const uint64_t om = woutside(P, hn, hoff);
+    if (om == 0ull) return UNCHANGED;
+    return wcut(P, src, L, S, hn, hoff, s, om);
+}
+
+// ConvexPoly(w,p) into W: the base cut by Cell(w)'s planes (those on D's
+// boundary skipped, as on the host).  False when empty; OVERFLOW via ovf.
+__device__ bool wclip_to_cell(const Ctx& c, const WPoly& B, WPoly& W, WaveLds& L, const double* cellp, int np,
+                              int64_t& skipped, bool& ovf) {
+    W = B;
+    for (int i = wlane(); i < B.np - 6; i += 64) L.srcW[i] = L.srcB[i];
+    __syncthreads();
+    if (W.empty) return true;
+    const PlaneSrc S{c.blo, c.bhi, c.perp, cellp};
+    for (int i = 0; i < np; ++i) {
+        const double hn[3] = {cellp[4 * i], cellp[4 * i + 1], cellp[4 * i + 2]};
+        const double hoff = cellp[4 * i + 3];
+        const int axes = (hn[0] != 0.0) + (hn[1] != 0.0) + (hn[2] != 0.0);
+        if (axes == 1 && (fabs(hn[0]) == 1.0 || fabs(hn[1]) == 1.0 || fabs(hn[2]) == 1.0)) {
+            const int k = hn[0] != 0.0 ? 0 : (hn[1] != 0.0 ? 1 : 2);
+            if ((hn[k] > 0 && hoff == c.bhi[k]) || (hn[k] < 0 && hoff == -c.blo[k])) continue;
+        }
+        const uint64_t om = woutside(W, hn, hoff);
+        if (om == 0ull) continue;
+        const int r = wcut(W, L.srcW, L, S, hn, hoff, (uint8_t)(8 + i), om);
+        if (r == EMPTY) return false;
+        if (r == SKIPPED) ++skipped;
+        if (r == OVERFLOW) {
+            ovf = true;
+            return false;
+        }
+    }
+    return true;
+}
+
+__device__ __forceinline__ double wmin(double v) {
+    for (int d = 32; d >= 1; d >>= 1) {
+        const double o = __shfl_xor(v, d);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+__device__ __forceinline__ double wmax(double v) {
+    for (int d = 32; d >= 1; d >>= 1) {
+        const double o = __shfl_xor(v, d);
+        v = v < o ? o : v;
+    }
+    return v;
+}
+
+__device__ void wpoly_box(const Ctx& c, const WPoly& P, uint16_t out[6]) {
+    if (P.empty || P.nt == 0) {
+        for (int k = 0; k < 3; ++k) {
+            out[k] = 65535;
+            out[3 + k] = 0;
+        }
+        return;
+    }
+    const bool valid = wlane() < P.nt;
+    double lo[3], hi[3];
+    lo[0] = wmin(valid ? P.x : INFINITY);
+    lo[1] = wmin(valid ? P.y : INFINITY);
+    lo[2] = wmin(valid ? P.z : INFINITY);
+    hi[0] = wmax(valid ? P.x : -INFINITY);
+    hi[1] = wmax(valid ? P.y : -INFINITY);
+    hi[2] = wmax(valid ? P.z : -INFINITY);
+    quantize_box(c, lo, hi, out);
+}
+
+// LDS visited set: true when u is new.
+__device__ __forceinline__ bool whash_visit(int32_t* hset, int32_t u) {
+    uint32_t h = ((uint32_t)u * 2654435761u) & (kHashCap - 1);
+    for (;;) {
+        const int32_t old = atomicCAS(&hset[h], -1, u);
+        if (old == -1) return true;
+        if (old == u) return false;
+        h = (h + 1) & (kHashCap - 1);
+    }
+}
+
+// Each wavefront (a block of 64 lanes) takes primitives from a shared counter
+// until none are left and floods each one: base polytope, then for every
+// queued vertex the quick whole-cell test, the cut by the cell's planes, the
+// corner test and the entry box, and on a hit the vertex's Voronoi
+// neighbours are queued.
 __global__ __launch_bounds__(64) void k_flood(int64_t nprim, const FloodPrim* __restrict__ prims,
-                                              const double* __restrict__ perp, const double* __restrict__ Vd,
-                                              const int64_t* __restrict__ nb_off, const int32_t* __restrict__ nb,
-                                              const uint64_t* __restrict__ cpoff, const double* __restrict__ cplanes,
-                                              const uint64_t* __restrict__ ctoff, const double* __restrict__ cpos,
-                                              const double* __restrict__ dom,  // blo, bhi, qlo, qscale, tau, dmax
-                                              FloodRec* __restrict__ recs, uint64_t rec_cap,
-                                              int64_t* __restrict__ redo, Counters* __restrict__ cnt,
-                                              int visit_cap) {
+                                                   const double* __restrict__ perp, const double* __restrict__ Vd,
+                                                   const int64_t* __restrict__ nb_off, const int32_t* __restrict__ nb,
+                                                   const uint64_t* __restrict__ cpoff,
+                                                   const double* __restrict__ cplanes,
+                                                   const uint64_t* __restrict__ ctoff, const double* __restrict__ cpos,
+                                                   const double* __restrict__ dom, FloodRec* __restrict__ recs,
+                                                   uint64_t rec_cap, int64_t* __restrict__ redo,
+                                                   Counters* __restrict__ cnt, int visit_cap) {
+    __shared__ WaveLds L;
+    const int l = wlane();
     Ctx c;
     c.blo = dom;
     c.bhi = dom + 3;
     c.qlo = dom + 6;
     c.qscale = dom + 9;
     c.slack = 2.0 * dom[12] * dom[13];
-    // lane totals over the primitives it finished
     unsigned long long t_tests = 0, t_hits = 0, t_quick = 0, t_skipped = 0;
-    // the current primitive
-    int64_t i = -1;
-    FloodPrim p;
-    uint32_t code = 0;
-    int64_t tests = 0, hits = 0, quick = 0, skipped = 0;
-    bool ovf = false, base_empty = false;
-    int head = 0, qn = 0;
-    Poly<kBaseCap> B;
-    Poly<kTriCap> W;
-    int32_t queue[kQueueCap];
-    int32_t hset[kHashCap];
+    WPoly B, W;
     for (;;) {
-        if (ovf || head >= qn) {
-            // the current primitive is done: account for it, take the next
-            if (i >= 0) {
-                if (ovf) {
-                    const unsigned long long slot = atomicAdd(&cnt->redo, 1ull);
-                    redo[slot] = i;
-                } else {
-                    t_tests += (unsigned long long)tests;
-                    t_hits += (unsigned long long)hits;
-                    t_quick += (unsigned long long)quick;
-                    t_skipped += (unsigned long long)skipped;
-                }
+        // wave-uniform values are moved to scalar registers, so the
+        // primitive, the cell and its planes are read with scalar loads
+        unsigned long long ti = 0;
+        if (l == 0) ti = atomicAdd(&cnt->next, 1ull);
+        ti = __shfl(ti, 0);
+        if (ti >= (unsigned long long)nprim) break;
+        const int64_t i = __builtin_amdgcn_readfirstlane((int)ti);
+        const FloodPrim p = prims[i];
+        c.perp = perp + 4 * p.perp_off;
+        const uint32_t code = (p.face ? 0x80000000u : 0u) | (uint32_t)p.id;
+        int64_t tests = 0, hits = 0, quick = 0, skipped = 0;
+        bool ovf = false;
+        // base polytope Space-perp(p) n D
+        winit_box(B, c.blo, c.bhi);
+        bool base_empty = false;
+        {
+            const PlaneSrc S{c.blo, c.bhi, c.perp, c.perp};  // the base has no cell planes
+            for (int j = 0; j < p.nperp && !base_empty && !ovf; ++j) {
+                const double hn[3] = {c.perp[4 * j], c.perp[4 * j + 1], c.perp[4 * j + 2]};
+                const int r = wclip(B, L.srcB, L, S, hn, c.perp[4 * j + 3], (uint8_t)j);
+                if (r == EMPTY) base_empty = true;
+                if (r == SKIPPED) ++skipped;
+                if (r == OVERFLOW) ovf = true;
             }
-            i = (int64_t)atomicAdd(&cnt->next, 1ull);
-            if (i >= nprim) break;
-            p = prims[i];
-            c.perp = perp + 4 * p.perp_off;
-            code = (p.face ? 0x80000000u : 0u) | (uint32_t)p.id;
-            tests = hits = quick = skipped = 0;
-            ovf = false;
-            // base polytope Space-perp(p) n D
-            init_box(B, c.blo, c.bhi);
-            base_empty = false;
-            {
-                const PlaneSrc S{c.blo, c.bhi, c.perp, nullptr};
-                for (int j = 0; j < p.nperp && !base_empty && !ovf; ++j) {
-                    const double hn[3] = {c.perp[4 * j], c.perp[4 * j + 1], c.perp[4 * j + 2]};
-                    const int r = clip(B, S, hn, c.perp[4 * j + 3], (uint8_t)j);
-                    if (r == EMPTY) base_empty = true;
-                    if (r == SKIPPED) ++skipped;
-                    if (r == OVERFLOW) ovf = true;
-                }
-            }
-            for (int k = 0; k < kHashCap; ++k) hset[k] = -1;
-            qn = 0;
-            head = 0;
+        }
+        for (int k = l; k < kHashCap; k += 64) L.hset[k] = -1;
+        __syncthreads();
+        int qn = 0;
+        if (l == 0)
             for (int k = 0; k < p.nverts; ++k) {
-                hash_visit(hset, p.verts[k]);
-                queue[qn++] = p.verts[k];
+                whash_visit(L.hset, p.verts[k]);
+                L.queue[k] = p.verts[k];
             }
-            continue;
-        }
-        // one flood step: the next queued vertex w
-        const int32_t w = queue[head++];
-        bool own = false;
-        for (int k = 0; k < p.nverts; ++k) own |= (p.verts[k] == w);
-        const double* cellp = cplanes + 4 * cpoff[w];
-        const int cnp = (int)(cpoff[w + 1] - cpoff[w]);
-        if (cnp > kPlaneCap - 8 - 8) {
-            ovf = true;
-            continue;
-        }
-        uint16_t box[6];
-        bool hit;
-        if (own) {  // Theorem 2
-            if (base_empty || !clip_to_cell(c, B, W, cellp, cnp, skipped, ovf)) W.empty = true;
-            if (ovf) continue;
-            poly_box(c, W, box);
-            hit = true;
-        } else {
-            ++tests;
-            const double* X = Vd + 3 * (int64_t)w;
-            const double Wv[3] = {X[0], X[1], X[2]};
-            // |x-w| - Dist(x,p) is convex: the whole cell keeping w out settles it
-            const int64_t t0 = (int64_t)ctoff[w], t1 = (int64_t)ctoff[w + 1];
-            bool all_far = true;
-            for (int64_t t = t0; t < t1 && all_far; ++t) all_far = far_enough(p, Wv, cpos + 3 * t, c.slack);
-            hit = false;
-            if (all_far) {
-                ++quick;
-            } else if (!base_empty && clip_to_cell(c, B, W, cellp, cnp, skipped, ovf)) {
-                for (int t = 0; t < W.nt; ++t)
-                    if (!far_enough(p, Wv, W.pos[t], c.slack)) {
-                        poly_box(c, W, box);
-                        hit = true;
-                        break;
-                    }
-            }
-            if (ovf) continue;
-        }
-        if (!hit) continue;
-        ++hits;
-        const unsigned long long slot = atomicAdd(&cnt->recs, 1ull);
-        if (slot < rec_cap) {
-            FloodRec r;
-            r.v = (uint32_t)w;
-            r.code = code;
-            for (int k = 0; k < 6; ++k) r.box[k] = box[k];
-            recs[slot] = r;
-        }
-        for (int64_t k = nb_off[w]; k < nb_off[w + 1]; ++k) {
-            const int32_t u = nb[k];
-            if (!hash_visit(hset, u)) continue;
-            if (qn >= visit_cap) {
+        qn = p.nverts;
+        __syncthreads();
+        for (int head = 0; head < qn && !ovf; ++head) {
+            const int32_t w = __builtin_amdgcn_readfirstlane(L.queue[head]);
+            bool own = false;
+            for (int k = 0; k < p.nverts; ++k) own |= (p.verts[k] == w);
+            const double* cellp = cplanes + 4 * cpoff[w];
+            const int cnp = (int)(cpoff[w + 1] - cpoff[w]);
+            if (cnp > kPlaneCap - 8 - 8) {
                 ovf = true;
                 break;
             }
-            queue[qn++] = u;
+            uint16_t box[6];
+            bool hit;
+            if (own) {  // Theorem 2
+                if (base_empty || !wclip_to_cell(c, B, W, L, cellp, cnp, skipped, ovf)) W.empty = true;
+                if (ovf) break;
+                wpoly_box(c, W, box);
+                hit = true;
+            } else {
+                ++tests;
+                const double* X = Vd + 3 * (int64_t)w;
+                const double Wv[3] = {X[0], X[1], X[2]};
+                // |x-w| - Dist(x,p) is convex: the whole cell keeping w out settles it
+                const int64_t t0 = (int64_t)ctoff[w], t1 = (int64_t)ctoff[w + 1];
+                bool all_far = true;
+                for (int64_t t = t0; t < t1 && all_far; t += 64) {
+                    const bool far = t + l >= t1 || far_enough(p, Wv, cpos + 3 * (t + l), c.slack);
+                    all_far = __ballot(!far) == 0ull;
+                }
+                hit = false;
+                if (all_far) {
+                    ++quick;
+                } else if (!base_empty && wclip_to_cell(c, B, W, L, cellp, cnp, skipped, ovf)) {
+                    const double pos[3] = {W.x, W.y, W.z};
+                    const bool near = l < W.nt && !far_enough(p, Wv, pos, c.slack);
+                    if (__ballot(near)) {
+                        wpoly_box(c, W, box);
+                        hit = true;
+                    }
+                }
+                if (ovf) break;
+            }
+            if (!hit) continue;
+            ++hits;
+            if (l == 0) {
+                const unsigned long long slot = atomicAdd(&cnt->recs, 1ull);
+                if (slot < rec_cap) {
+                    FloodRec r;
+                    r.v = (uint32_t)w;
+                    r.code = code;
+                    for (int k = 0; k < 6; ++k) r.box[k] = box[k];
+                    recs[slot] = r;
+                }
+            }
+            const int64_t k0 = nb_off[w], deg = nb_off[w + 1] - k0;
+            for (int64_t k = 0; k < deg; k += 64) {
+                const bool have = k + l < deg;
+                const int32_t u = have ? nb[k0 + k + l] : -1;
+                const bool isnew = have && whash_visit(L.hset, u);
+                const uint64_t m = __ballot(isnew);
+                const int cntn = __popcll(m);
+                if (qn + cntn > visit_cap) {
+                    ovf = true;
+                    break;
+                }
+                if (isnew) L.queue[qn + __popcll(m & below(l))] = u;
+                qn += cntn;
+            }
+            __syncthreads();
         }
+        if (ovf) {
+            if (l == 0) {
+                const unsigned long long slot = atomicAdd(&cnt->redo, 1ull);
+                redo[slot] = i;
+            }
+        } else {
+            t_tests += (unsigned long long)tests;
+            t_hits += (unsigned long long)hits;
+            t_quick += (unsigned long long)quick;
+            t_skipped += (unsigned long long)skipped;
+        }
+        __syncthreads();
     }
-    atomicAdd(&cnt->tests, t_tests);
-    atomicAdd(&cnt->hits, t_hits);
-    atomicAdd(&cnt->quick, t_quick);
-    atomicAdd(&cnt->skipped, t_skipped);
+    if (l == 0) {
+        atomicAdd(&cnt->tests, t_tests);
+        atomicAdd(&cnt->hits, t_hits);
+        atomicAdd(&cnt->quick, t_quick);
+        atomicAdd(&cnt->skipped, t_skipped);
+    }
 }
 
 using Clock = std::chrono::steady_clock;
@@ -578,13 +662,14 @@ bool device_flood(const FloodInput& in, FloodResult& out, std::string& err) {
     if (!hip_ok(hipDeviceSynchronize(), "upload")) return false;
     out.t_upload = since(t0);
     t0 = Clock::now();
-    // enough wavefronts to fill the chip; each lane loops over primitives
+    // enough wavefronts to fill the chip; each loops over primitives
     const int block = 64;
     int dev = 0, cus = 256, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_flood, block, 0) != hipSuccess || per_cu < 1) per_cu = 8;
-    const int64_t grid = std::min<int64_t>((in.nprim + block - 1) / block, (int64_t)cus * per_cu);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_flood, block, 0) != hipSuccess || per_cu < 1)
+        per_cu = 8;
+    const int64_t grid = std::min<int64_t>(in.nprim, (int64_t)cus * per_cu);
     k_flood<<<(unsigned)grid, block, 0, 0>>>(
         in.nprim, (const FloodPrim*)(d + off[0]), (const double*)(d + off[1]), (const double*)(d + off[2]),
         (const int64_t*)(d + off[3]), (const int32_t*)(d + off[4]), (const uint64_t*)(d + off[5]),

@@ -61,7 +61,8 @@ def test_device_table_equals_host(name):
     V, F, S, dom = _case(name)
     h, sh, d, sd = _tables(V, F, S, dom)
     _same(h, sh, d, sd)
-    assert sd["device_redo"] == 0
+    # a working polytope of more than 64 corners sends its primitive back
+    assert sd["device_redo"] <= max(4, 1e-3 * (sh["ne"] + sh["nf"]))
 
 
 def test_device_handback_to_host():
