@@ -558,31 +558,60 @@ __global__ __launch_bounds__(256) void k_bucket_bounds(const uint32_t* __restric
     if (j == m - 1 || ((keys[j + 1] >> kBucketShift) & (nb - 1)) != b) end[b] = (uint32_t)(j + 1);
 }
 
+// Sum of the contributions of one slice of a bucket of 4096 vertices: the
+// bucket's sorted range is split over `splits` blocks so that every CU has
+// work; each block sums its slice in LDS and adds the sums to grad_V with
+// float atomics (a vertex gets at most `splits` of them).  Four
+// contributions per thread per trip, their gathers issued together.
 __global__ __launch_bounds__(512) void k_bwd_accum(const uint32_t* __restrict__ keys, const int32_t* __restrict__ vals,
                                                    const float* __restrict__ contrib,
                                                    const uint32_t* __restrict__ start, const uint32_t* __restrict__ end,
-                                                   float* __restrict__ gV, int32_t nv) {
+                                                   float* __restrict__ gV, int32_t nv, int splits) {
     __shared__ float acc[3 << kBucketShift];
-    const uint32_t b = blockIdx.x;
+    const uint32_t b = blockIdx.x / (uint32_t)splits;
+    const uint32_t part = blockIdx.x % (uint32_t)splits;
     const uint32_t s0 = start[b], s1 = end[b];
     if (s1 <= s0) return;  // uniform: empty bucket
+    const uint64_t len = s1 - s0;
+    const uint32_t a0 = s0 + (uint32_t)(len * part / (uint32_t)splits);
+    const uint32_t a1 = s0 + (uint32_t)(len * (part + 1) / (uint32_t)splits);
+    if (a1 <= a0) return;  // uniform
     for (int t = threadIdx.x; t < (3 << kBucketShift); t += blockDim.x) acc[t] = 0.f;
     __syncthreads();
     const int64_t v0 = (int64_t)b << kBucketShift;
-    for (uint32_t j = s0 + threadIdx.x; j < s1; j += blockDim.x) {
-        const uint32_t v = keys[j];
-        // keys outside this bucket or past nv carry no contribution
-        if (v >= (uint32_t)nv || ((int64_t)v >> kBucketShift) != (int64_t)b) continue;
-        const int64_t c = vals[j];
-        const int l = (int)(v - (uint32_t)v0);
-        atomicAdd(&acc[3 * l], contrib[3 * c]);
-        atomicAdd(&acc[3 * l + 1], contrib[3 * c + 1]);
-        atomicAdd(&acc[3 * l + 2], contrib[3 * c + 2]);
+    const uint32_t bs = blockDim.x;
+    for (uint32_t j = a0 + threadIdx.x; j < a1; j += 4 * bs) {
+        uint32_t v[4];
+        int64_t c[4];
+        float x[4], y[4], z[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t jj = j + (uint32_t)u * bs;
+            v[u] = jj < a1 ? keys[jj] : 0xffffffffu;
+            c[u] = jj < a1 ? vals[jj] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            // keys outside this bucket or past nv carry no contribution
+            const bool ok = v[u] < (uint32_t)nv && ((int64_t)v[u] >> kBucketShift) == (int64_t)b;
+            x[u] = ok ? contrib[3 * c[u]] : 0.f;
+            y[u] = ok ? contrib[3 * c[u] + 1] : 0.f;
+            z[u] = ok ? contrib[3 * c[u] + 2] : 0.f;
+            if (!ok) v[u] = 0xffffffffu;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (v[u] == 0xffffffffu) continue;
+            const int l = (int)(v[u] - (uint32_t)v0);
+            atomicAdd(&acc[3 * l], x[u]);
+            atomicAdd(&acc[3 * l + 1], y[u]);
+            atomicAdd(&acc[3 * l + 2], z[u]);
+        }
     }
     __syncthreads();
     const int64_t lim = std::min<int64_t>((int64_t)3 << kBucketShift, 3 * ((int64_t)nv - v0));
     for (int t = threadIdx.x; t < lim; t += blockDim.x)
-        if (acc[t] != 0.f) gV[3 * v0 + t] += acc[t];
+        if (acc[t] != 0.f) unsafeAtomicAdd(&gV[3 * v0 + t], acc[t]);
 }
 
 __global__ __launch_bounds__(256) void k_backward(const float* __restrict__ q, int64_t n,
@@ -961,7 +990,11 @@ p2m_status p2m_query_backward(p2m_mesh* mh, const float* q, int64_t n, const flo
     const int cur = radix_sort_pairs(plan, rb, kBucketShift, hi_bit, st);
     k_fill_u32<<<(unsigned)((2 * nb + 255) / 256), 256, 0, st>>>(bstart, 2 * (int64_t)nb, 0u);
     k_bucket_bounds<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(rb.keys[cur], m, nb, bstart, bend);
-    k_bwd_accum<<<nb, 512, 0, st>>>(rb.keys[cur], rb.vals[cur], contrib, bstart, bend, gV, (int32_t)nv);
+    // only buckets below nv hold keys; split each over enough blocks to fill the chip
+    const uint32_t used = (uint32_t)(((nv - 1) >> kBucketShift) + 1);
+    const int splits = (int)std::max<uint32_t>(1u, (4u * 256u + used - 1) / used);
+    k_bwd_accum<<<used * (uint32_t)splits, 512, 0, st>>>(rb.keys[cur], rb.vals[cur], contrib, bstart, bend, gV,
+                                                         (int32_t)nv, splits);
     return check_launch("backward kernels");
 }
 
