@@ -76,5 +76,9 @@ RadixBuffers radix_buffers(const RadixPlan& p, void* scratch);
 // per pass; the span is a multiple of 8); returns which buffer (0/1) holds
 // the result.  All work is enqueued on `st`.
 int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit, hipStream_t st);
+// Exclusive prefix sum of a[0..n) in place; sums needs scan_sums_size(n)
+// entries of scratch.
+int64_t scan_sums_size(int64_t n);
+void scan_exclusive_u32(uint32_t* a, int64_t n, uint32_t* sums, hipStream_t st);
 
 }  // namespace p2m

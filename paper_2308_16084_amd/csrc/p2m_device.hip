@@ -497,121 +497,173 @@ hipError_t launch_seed_grid(const MeshView& m, float4* seed, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Bucketed reduction of the vertex gradient for large meshes: every
-// (query, corner) contribution is emitted with its vertex id as key, one
-// radix pass on the key bits above kBucketShift groups them into buckets of
-// 2^kBucketShift consecutive vertices, and one workgroup per bucket sums its
-// contributions in LDS and adds them to grad_V with coalesced stores -- no
-// scattered global atomics.
-constexpr int kBucketShift = 12;
-constexpr int64_t kAtomicMaxVertices = 65536;  // below this the direct atomics stay in L2
+// Bucketed reduction of the vertex gradient for large meshes: every valid
+// (query, corner) contribution goes, as a 16-byte record (its three
+// components and the vertex), into the run of its bucket of 2^kBucketShift
+// consecutive vertices; each bucket is then summed in LDS by one workgroup
+// (several, merged with float atomics, when there are too few buckets to
+// fill the chip) and added to grad_V -- no scattered global atomics and no
+// sort.
+constexpr int kBucketShift = 10;
+constexpr int kMaxBuckets = 4096;                // per-block LDS counters; beyond, direct atomics
+constexpr int64_t kAtomicMaxVertices = 65536;    // below this the direct atomics stay in L2
+constexpr int kBwdQueriesPerThread = 4;
 
-__global__ __launch_bounds__(256) void k_bwd_emit(const float* __restrict__ q, int64_t n,
-                                                   const float* __restrict__ closest, const float* __restrict__ dist,
-                                                   const float* __restrict__ bary, const int32_t* __restrict__ pvid,
-                                                   const float* __restrict__ gd, float* __restrict__ gq, int32_t nv,
-                                                   uint32_t* __restrict__ keys, int32_t* __restrict__ vals,
-                                                   float* __restrict__ contrib) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float d = dist[i];
-    const float g = gd[i];
-    float ux = 0.f, uy = 0.f, uz = 0.f;
+// Unit direction (q - c) / d of query i, zero when d is 0 or not finite.
+__device__ __forceinline__ void bwd_dir(const float* __restrict__ q, const float* __restrict__ closest, float d,
+                                        int64_t i, float& ux, float& uy, float& uz) {
+    ux = uy = uz = 0.f;
     if (d > 0.f && isfinite(d)) {
         const float inv = 1.f / d;
         ux = (q[3 * i] - closest[3 * i]) * inv;
         uy = (q[3 * i + 1] - closest[3 * i + 1]) * inv;
         uz = (q[3 * i + 2] - closest[3 * i + 2]) * inv;
     }
-    if (gq) {
-        gq[3 * i] = g * ux;
-        gq[3 * i + 1] = g * uy;
-        gq[3 * i + 2] = g * uz;
+}
+
+// Counts of each block's contributions per bucket (in LDS), written to a
+// bucket-major matrix mat[b * blocks + block] whose exclusive scan gives
+// every (bucket, block) its first place; and grad_q.
+__global__ __launch_bounds__(256) void k_bwd_count(const float* __restrict__ q, int64_t n,
+                                                   const float* __restrict__ closest, const float* __restrict__ dist,
+                                                   const float* __restrict__ bary, const int32_t* __restrict__ pvid,
+                                                   const float* __restrict__ gd, float* __restrict__ gq, int32_t nv,
+                                                   int nbk, uint32_t* __restrict__ mat) {
+    __shared__ uint32_t h[kMaxBuckets];
+    for (int b = threadIdx.x; b < nbk; b += blockDim.x) h[b] = 0u;
+    __syncthreads();
+    // a block takes kBwdQueriesPerThread * 256 consecutive queries, lanes
+    // adjacent in each round (coalesced)
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x * kBwdQueriesPerThread + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kBwdQueriesPerThread; ++u) {
+        const int64_t i = i0 + (int64_t)u * blockDim.x;
+        float ux = 0.f, uy = 0.f, uz = 0.f, g = 0.f;
+        if (i < n) {
+            g = gd[i];
+            bwd_dir(q, closest, dist[i], i, ux, uy, uz);
+            if (gq) {
+                gq[3 * i] = g * ux;
+                gq[3 * i + 1] = g * uy;
+                gq[3 * i + 2] = g * uz;
+            }
+        }
+        const bool any = i < n && (ux != 0.f || uy != 0.f || uz != 0.f) && g != 0.f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int32_t v = any ? pvid[3 * i + k] : -1;
+            const float w = any ? bary[3 * i + k] : 0.f;
+            if (v >= 0 && v < nv && w != 0.f) atomicAdd(&h[(uint32_t)v >> kBucketShift], 1u);
+        }
     }
-    const bool any = (ux != 0.f || uy != 0.f || uz != 0.f) && g != 0.f;
-    for (int k = 0; k < 3; ++k) {
-        const int64_t c = 3 * i + k;
-        const int32_t v = pvid[c];
-        const float w = bary[c];
-        const bool ok = any && v >= 0 && v < nv && w != 0.f;
-        const float s = -g * w;
-        keys[c] = ok ? (uint32_t)v : 0xffffffffu;
-        vals[c] = (int32_t)c;
-        contrib[3 * c] = ok ? s * ux : 0.f;
-        contrib[3 * c + 1] = ok ? s * uy : 0.f;
-        contrib[3 * c + 2] = ok ? s * uz : 0.f;
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbk; b += blockDim.x) mat[(int64_t)b * gridDim.x + blockIdx.x] = h[b];
+    if (blockIdx.x == 0 && threadIdx.x == 0) mat[(int64_t)nbk * gridDim.x] = 0u;  // becomes the total
+}
+
+// Writes every valid contribution as (x, y, z, vertex) into its bucket's
+// run: a block ranks its contributions per bucket in LDS and places them
+// after the scanned offset of (bucket, block).
+__global__ __launch_bounds__(256) void k_bwd_scatter(const float* __restrict__ q, int64_t n,
+                                                     const float* __restrict__ closest, const float* __restrict__ dist,
+                                                     const float* __restrict__ bary, const int32_t* __restrict__ pvid,
+                                                     const float* __restrict__ gd, int32_t nv, int nbk,
+                                                     const uint32_t* __restrict__ mat, float4* __restrict__ recs) {
+    __shared__ uint32_t h[kMaxBuckets];
+    for (int b = threadIdx.x; b < nbk; b += blockDim.x) h[b] = 0u;
+    __syncthreads();
+    constexpr int kC = 3 * kBwdQueriesPerThread;
+    uint32_t vb[kC], rank[kC];
+    float cx[kC], cy[kC], cz[kC];
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x * kBwdQueriesPerThread + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kBwdQueriesPerThread; ++u) {
+        const int64_t i = i0 + (int64_t)u * blockDim.x;
+        float ux = 0.f, uy = 0.f, uz = 0.f, g = 0.f;
+        if (i < n) {
+            g = gd[i];
+            bwd_dir(q, closest, dist[i], i, ux, uy, uz);
+        }
+        const bool any = i < n && (ux != 0.f || uy != 0.f || uz != 0.f) && g != 0.f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int c = 3 * u + k;
+            const int32_t v = any ? pvid[3 * i + k] : -1;
+            const float w = any ? bary[3 * i + k] : 0.f;
+            const bool ok = v >= 0 && v < nv && w != 0.f;
+            const float s = -g * w;
+            vb[c] = ok ? (uint32_t)v : 0xffffffffu;
+            cx[c] = s * ux;
+            cy[c] = s * uy;
+            cz[c] = s * uz;
+            rank[c] = ok ? atomicAdd(&h[(uint32_t)v >> kBucketShift], 1u) : 0u;
+        }
     }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbk; b += blockDim.x)
+        if (h[b]) h[b] = mat[(int64_t)b * gridDim.x + blockIdx.x];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kC; ++c)
+        if (vb[c] != 0xffffffffu)
+            recs[h[vb[c] >> kBucketShift] + rank[c]] = make_float4(cx[c], cy[c], cz[c], __uint_as_float(vb[c]));
 }
 
-__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ a, int64_t n, uint32_t x) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = x;
-}
-
-// First and one-past-last sorted position of every bucket present.
-__global__ __launch_bounds__(256) void k_bucket_bounds(const uint32_t* __restrict__ keys, int64_t m, uint32_t nb,
-                                                       uint32_t* __restrict__ start, uint32_t* __restrict__ end) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
-    const uint32_t b = (keys[j] >> kBucketShift) & (nb - 1);
-    if (j == 0 || ((keys[j - 1] >> kBucketShift) & (nb - 1)) != b) start[b] = (uint32_t)j;
-    if (j == m - 1 || ((keys[j + 1] >> kBucketShift) & (nb - 1)) != b) end[b] = (uint32_t)(j + 1);
-}
-
-// Sum of the contributions of one slice of a bucket of 4096 vertices: the
-// bucket's sorted range is split over `splits` blocks so that every CU has
-// work; each block sums its slice in LDS and adds the sums to grad_V with
-// float atomics (a vertex gets at most `splits` of them).  Four
-// contributions per thread per trip, their gathers issued together.
-__global__ __launch_bounds__(512) void k_bwd_accum(const uint32_t* __restrict__ keys, const int32_t* __restrict__ vals,
-                                                   const float* __restrict__ contrib,
-                                                   const uint32_t* __restrict__ start, const uint32_t* __restrict__ end,
+// Sum of one slice of a bucket's run in LDS, added to grad_V (with float
+// atomics when the bucket's run is split over several blocks).
+__global__ __launch_bounds__(512) void k_bwd_accum(const float4* __restrict__ recs,
+                                                   const uint32_t* __restrict__ mat, int64_t stride,
                                                    float* __restrict__ gV, int32_t nv, int splits) {
-    __shared__ float acc[3 << kBucketShift];
+    __shared__ __align__(16) float acc[3 << kBucketShift];
     const uint32_t b = blockIdx.x / (uint32_t)splits;
     const uint32_t part = blockIdx.x % (uint32_t)splits;
-    const uint32_t s0 = start[b], s1 = end[b];
+    // bucket b's run: from its first block's offset to the next bucket's
+    const uint32_t s0 = mat[(int64_t)b * stride], s1 = mat[(int64_t)(b + 1) * stride];
     if (s1 <= s0) return;  // uniform: empty bucket
     const uint64_t len = s1 - s0;
     const uint32_t a0 = s0 + (uint32_t)(len * part / (uint32_t)splits);
     const uint32_t a1 = s0 + (uint32_t)(len * (part + 1) / (uint32_t)splits);
     if (a1 <= a0) return;  // uniform
-    for (int t = threadIdx.x; t < (3 << kBucketShift); t += blockDim.x) acc[t] = 0.f;
+    for (int t = threadIdx.x; t < (3 << kBucketShift) / 4; t += blockDim.x)
+        reinterpret_cast<float4*>(acc)[t] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
     const int64_t v0 = (int64_t)b << kBucketShift;
     const uint32_t bs = blockDim.x;
     for (uint32_t j = a0 + threadIdx.x; j < a1; j += 4 * bs) {
-        uint32_t v[4];
-        int64_t c[4];
-        float x[4], y[4], z[4];
+        float4 r[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint32_t jj = j + (uint32_t)u * bs;
-            v[u] = jj < a1 ? keys[jj] : 0xffffffffu;
-            c[u] = jj < a1 ? vals[jj] : 0;
+            r[u] = jj < a1 ? recs[jj] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            // keys outside this bucket or past nv carry no contribution
-            const bool ok = v[u] < (uint32_t)nv && ((int64_t)v[u] >> kBucketShift) == (int64_t)b;
-            x[u] = ok ? contrib[3 * c[u]] : 0.f;
-            y[u] = ok ? contrib[3 * c[u] + 1] : 0.f;
-            z[u] = ok ? contrib[3 * c[u] + 2] : 0.f;
-            if (!ok) v[u] = 0xffffffffu;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (v[u] == 0xffffffffu) continue;
-            const int l = (int)(v[u] - (uint32_t)v0);
-            atomicAdd(&acc[3 * l], x[u]);
-            atomicAdd(&acc[3 * l + 1], y[u]);
-            atomicAdd(&acc[3 * l + 2], z[u]);
+            if (j + (uint32_t)u * bs >= a1) break;
+            const int l = (int)(__float_as_uint(r[u].w) - (uint32_t)v0);
+            atomicAdd(&acc[3 * l], r[u].x);
+            atomicAdd(&acc[3 * l + 1], r[u].y);
+            atomicAdd(&acc[3 * l + 2], r[u].z);
         }
     }
     __syncthreads();
     const int64_t lim = std::min<int64_t>((int64_t)3 << kBucketShift, 3 * ((int64_t)nv - v0));
-    for (int t = threadIdx.x; t < lim; t += blockDim.x)
-        if (acc[t] != 0.f) unsafeAtomicAdd(&gV[3 * v0 + t], acc[t]);
+    if (splits == 1) {  // the block alone holds these vertices: float4 read-modify-write
+        float4* g4 = reinterpret_cast<float4*>(gV + 3 * v0);  // 3 * v0 floats: a multiple of 4
+        const float4* a4 = reinterpret_cast<const float4*>(acc);
+        for (int t = threadIdx.x; t < lim / 4; t += blockDim.x) {
+            float4 x = g4[t];
+            const float4 y = a4[t];
+            x.x += y.x;
+            x.y += y.y;
+            x.z += y.z;
+            x.w += y.w;
+            g4[t] = x;
+        }
+        for (int64_t t = (lim / 4) * 4 + threadIdx.x; t < lim; t += blockDim.x) gV[3 * v0 + t] += acc[t];
+    } else {
+        for (int t = threadIdx.x; t < lim; t += blockDim.x)
+            if (acc[t] != 0.f) unsafeAtomicAdd(&gV[3 * v0 + t], acc[t]);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_backward(const float* __restrict__ q, int64_t n,
@@ -964,37 +1016,32 @@ p2m_status p2m_query_backward(p2m_mesh* mh, const float* q, int64_t n, const flo
     DeviceGuard g(s.dev.device);
     hipStream_t st = (hipStream_t)stream;
     const int64_t nv = s.m.nv;
-    if (!gV || nv <= kAtomicMaxVertices || 3 * n > (int64_t)INT32_MAX) {
+    if (!gV || nv <= kAtomicMaxVertices || ((nv - 1) >> kBucketShift) + 1 > kMaxBuckets ||
+        3 * n > (int64_t)INT32_MAX) {
         k_backward<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(q, n, closest, dist, bary, pvid, gd, gq, gV,
                                                                 (int32_t)nv);
         return check_launch("backward kernel");
     }
-    // bucketed reduction: key bits [kBucketShift, kBucketShift + 8 * passes)
-    int bits = 0;
-    while (((int64_t)1 << bits) < nv) ++bits;
-    const int passes = (bits - kBucketShift + 7) / 8;
-    const int hi_bit = kBucketShift + 8 * passes;
-    const uint32_t nb = 1u << (8 * passes);
+    // bucketed reduction: per-block counts per bucket, their scan, the
+    // records, the sums
+    const int nbk = (int)((nv - 1) >> kBucketShift) + 1;
     const int64_t m = 3 * n;
-    const RadixPlan plan = radix_plan(m);
-    const int64_t a = (plan.bytes + 255) / 256 * 256;
-    const int64_t b_contrib = (12 * m + 255) / 256 * 256;
-    p2m_status r = ensure_scratch(s, a + b_contrib + 8 * (int64_t)nb);
+    const int64_t threads = (n + kBwdQueriesPerThread - 1) / kBwdQueriesPerThread;
+    const int64_t blocks = (threads + 255) / 256;
+    const int64_t cells = (int64_t)nbk * blocks + 1;
+    const int64_t b_mat = (4 * cells + 255) / 256 * 256;
+    const int64_t b_sums = (4 * scan_sums_size(cells) + 255) / 256 * 256;
+    p2m_status r = ensure_scratch(s, b_mat + b_sums + 16 * m);
     if (r != P2M_OK) return r;
-    RadixBuffers rb = radix_buffers(plan, s.dev.scratch);
-    float* contrib = (float*)((char*)s.dev.scratch + a);
-    uint32_t* bstart = (uint32_t*)((char*)s.dev.scratch + a + b_contrib);
-    uint32_t* bend = bstart + nb;
-    k_bwd_emit<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(q, n, closest, dist, bary, pvid, gd, gq, (int32_t)nv,
-                                                            rb.keys[0], rb.vals[0], contrib);
-    const int cur = radix_sort_pairs(plan, rb, kBucketShift, hi_bit, st);
-    k_fill_u32<<<(unsigned)((2 * nb + 255) / 256), 256, 0, st>>>(bstart, 2 * (int64_t)nb, 0u);
-    k_bucket_bounds<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(rb.keys[cur], m, nb, bstart, bend);
-    // only buckets below nv hold keys; split each over enough blocks to fill the chip
-    const uint32_t used = (uint32_t)(((nv - 1) >> kBucketShift) + 1);
-    const int splits = (int)std::max<uint32_t>(1u, (4u * 256u + used - 1) / used);
-    k_bwd_accum<<<used * (uint32_t)splits, 512, 0, st>>>(rb.keys[cur], rb.vals[cur], contrib, bstart, bend, gV,
-                                                         (int32_t)nv, splits);
+    uint32_t* mat = (uint32_t*)s.dev.scratch;
+    uint32_t* sums = (uint32_t*)((char*)s.dev.scratch + b_mat);
+    float4* recs = (float4*)((char*)s.dev.scratch + b_mat + b_sums);
+    k_bwd_count<<<(unsigned)blocks, 256, 0, st>>>(q, n, closest, dist, bary, pvid, gd, gq, (int32_t)nv, nbk, mat);
+    scan_exclusive_u32(mat, cells, sums, st);
+    k_bwd_scatter<<<(unsigned)blocks, 256, 0, st>>>(q, n, closest, dist, bary, pvid, gd, (int32_t)nv, nbk, mat, recs);
+    // small meshes: each bucket split over enough blocks to fill the chip
+    const int splits = nbk >= 256 ? 1 : (4 * 256 + nbk - 1) / nbk;
+    k_bwd_accum<<<(unsigned)(nbk * splits), 512, 0, st>>>(recs, mat, blocks, gV, (int32_t)nv, splits);
     return check_launch("backward kernels");
 }
 

@@ -230,6 +230,16 @@ RadixBuffers radix_buffers(const RadixPlan& p, void* scratch) {
     return b;
 }
 
+int64_t scan_sums_size(int64_t n) { return std::max<int64_t>(1, (n + kRadixTile - 1) / kRadixTile); }
+
+void scan_exclusive_u32(uint32_t* a, int64_t n, uint32_t* sums, hipStream_t st) {
+    if (n <= 0) return;
+    const int64_t blocks = scan_sums_size(n);
+    k_scan_local<<<(unsigned)blocks, kT, 0, st>>>(a, n, sums);
+    k_scan_sums<<<1, kT, 0, st>>>(sums, blocks);
+    k_scan_add<<<(unsigned)blocks, kT, 0, st>>>(a, n, sums);
+}
+
 int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit, hipStream_t st) {
     int cur = 0;
     if (p.n <= 1) return cur;
