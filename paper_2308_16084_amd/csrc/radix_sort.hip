@@ -105,14 +105,17 @@ __global__ __launch_bounds__(kT) void k_scan_add(uint32_t* __restrict__ a, int64
 // digit order (stable: by digit, then by position in the tile), then written
 // out so that consecutive threads write consecutive places of each digit's
 // run -- coalesced runs of ~16 keys instead of one cache line per key.
+// Each wavefront ranks its own contiguous quarter of the tile, 64 keys per
+// round, against a running per-digit count of its earlier rounds (ballots
+// on the 8 digit bits find the lanes of equal digit), so the block meets at
+// a barrier only a few times per tile.
 __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
                                                       int64_t n, int shift, const uint32_t* __restrict__ offs,
                                                       int64_t tiles, uint32_t* __restrict__ kout,
                                                       int32_t* __restrict__ vout) {
-    __shared__ uint32_t gbase[256];  // global start of each digit's run of this tile
-    __shared__ uint32_t lstart[256];  // start of each digit in the tile's LDS order
-    __shared__ uint32_t run[256];     // pairs of each digit placed so far
-    __shared__ uint32_t wc[kWaves][256];
+    __shared__ uint32_t gbase[256];        // global start of each digit's run of this tile
+    __shared__ uint32_t lstart[256];       // start of each digit in the tile's LDS order
+    __shared__ uint32_t wc[kWaves][256];   // per wave: running count, then its base per digit
     __shared__ uint32_t lk[kRadixTile];
     __shared__ int32_t lv[kRadixTile];
     const int t = threadIdx.x;
@@ -121,49 +124,22 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
     const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
     const int cnt = (int)std::min<int64_t>(kRadixTile, n - tile0);
     gbase[t] = offs[(int64_t)t * tiles + blockIdx.x];
-    run[t] = 0;
-    // digit histogram of the tile and its exclusive scan
-    lstart[t] = 0;
-    __syncthreads();
-    uint32_t key[kI];
-    int32_t val[kI];
-#pragma unroll
-    for (int it = 0; it < kI; ++it) {
-        const int i = it * kT + t;
-        key[it] = i < cnt ? kin[tile0 + i] : 0u;
-        val[it] = i < cnt ? vin[tile0 + i] : 0;
-        if (i < cnt) atomicAdd(&lstart[(key[it] >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    {
-        // exclusive scan of 256 counts by the first wave (4 per lane)
-        uint32_t c[4], s = 0;
-        if (w == 0) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                c[k] = lstart[4 * lane + k];
-                s += c[k];
-            }
-            uint32_t incl = s;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint32_t x = __shfl_up(incl, d);
-                if (lane >= d) incl += x;
-            }
-            uint32_t e = incl - s;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                lstart[4 * lane + k] = e;
-                e += c[k];
-            }
-        }
-    }
 #pragma unroll
     for (int k = 0; k < kWaves; ++k) wc[k][t] = 0;
     __syncthreads();
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int wbase = w * (kI * 64);
+    uint32_t key[kI], rank[kI];
+    int32_t val[kI];
+#pragma unroll
     for (int it = 0; it < kI; ++it) {
-        const bool valid = it * kT + t < cnt;
+        const int i = wbase + it * 64 + lane;
+        const bool valid = i < cnt;
+        key[it] = valid ? kin[tile0 + i] : 0u;
+        val[it] = valid ? vin[tile0 + i] : 0;
+    }
+    for (int it = 0; it < kI; ++it) {
+        const bool valid = wbase + it * 64 + lane < cnt;
         const uint32_t d = (key[it] >> shift) & 255u;
         unsigned long long mask = __ballot(valid);
 #pragma unroll
@@ -172,25 +148,64 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
             const unsigned long long bm = __ballot(bit);
             mask &= bit ? bm : ~bm;
         }
-        const uint32_t rank = (uint32_t)__popcll(mask & lt);
-        if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(mask);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = lstart[d] + run[d] + rank;
-            for (int k = 0; k < w; ++k) pos += wc[k][d];
+        const uint32_t r = (uint32_t)__popcll(mask & lt);
+        const uint32_t prior = valid ? wc[w][d] : 0u;
+        rank[it] = prior + r;
+        // the lowest lane of each digit advances the wave's count; this
+        // wave's LDS accesses stay in program order
+        if (valid && r == 0) wc[w][d] = prior + (uint32_t)__popcll(mask);
+    }
+    __syncthreads();
+    // digit totals, their exclusive scan (the tile's LDS order), and each
+    // wave's base within each digit
+    uint32_t c[kWaves], tot = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+        c[k] = wc[k][t];
+        tot += c[k];
+    }
+    lstart[t] = tot;
+    __syncthreads();
+    if (w == 0) {
+        uint32_t v[4], sum = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = lstart[4 * lane + k];
+            sum += v[k];
+        }
+        uint32_t incl = sum;
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const uint32_t x = __shfl_up(incl, dd);
+            if (lane >= dd) incl += x;
+        }
+        uint32_t e = incl - sum;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            lstart[4 * lane + k] = e;
+            e += v[k];
+        }
+    }
+    __syncthreads();
+    {
+        uint32_t base = lstart[t];
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) {
+            wc[k][t] = base;
+            base += c[k];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kI; ++it) {
+        if (wbase + it * 64 + lane < cnt) {
+            const uint32_t d = (key[it] >> shift) & 255u;
+            const uint32_t pos = wc[w][d] + rank[it];
             lk[pos] = key[it];
             lv[pos] = val[it];
         }
-        __syncthreads();
-        uint32_t tot = 0;
-#pragma unroll
-        for (int k = 0; k < kWaves; ++k) {
-            tot += wc[k][t];
-            wc[k][t] = 0;
-        }
-        run[t] += tot;
-        __syncthreads();
     }
+    __syncthreads();
     // coalesced write-out: LDS place p of digit d goes to gbase[d] + p - lstart[d]
     for (int p = t; p < cnt; p += kT) {
         const uint32_t k = lk[p];
