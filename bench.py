@@ -88,8 +88,8 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="also run the near/far sweep: the C2 mesh precomputed for D = 10x AABB, 1e6 uniform "
                          "queries in boxes of 1x..10x AABB (not part of the default run)")
-    ap.add_argument("--batched-full", action="store_true",
-                    help="batched leg on all 256 meshes (default: the first 64 of the same seeded plan)")
+    ap.add_argument("--batched-meshes", type=int, default=256,
+                    help="batched leg on the first N meshes of the seeded 256-mesh plan (default: all 256)")
     ap.add_argument("--breakdown", action="store_true",
                     help="also time the nearest-vertex step alone and the query kernel on pre-sorted queries "
                          "(extra launches of the same kernel; off by default so profiles average the step only)")
@@ -344,13 +344,17 @@ def main():
         del m10
 
     if not args.no_batched:
-        count = 256 if args.batched_full else 64
+        from concurrent.futures import ThreadPoolExecutor
+        count = max(1, min(256, args.batched_meshes))
         t0 = time.time()
         plan = C.c4_plan()[:count]
-        works = [C.c4_mesh(e) for e in plan]
+        with ThreadPoolExecutor(max_workers=max(1, len(os.sched_getaffinity(0)))) as ex:
+            works = list(ex.map(C.c4_mesh, plan))
         t_gen = time.time() - t0
         t0 = time.time()
-        meshes = P.precompute_many([(x.V, x.F, (x.domain_lo, x.domain_hi)) for x in works], args.cache or None)
+        # inspection on the device (the table is the host build's)
+        meshes = P.precompute_many([(x.V, x.F, (x.domain_lo, x.domain_hi)) for x in works], args.cache or None,
+                                   table_mode=P.TABLE_FLOODING_DEVICE)
         t_pre4 = time.time() - t0
         Qb = np.concatenate([x.Q for x in works])
         offb = np.concatenate([[0], np.cumsum([len(x.Q) for x in works])]).astype(np.int64)
@@ -397,10 +401,11 @@ def main():
                              "speedup_vs_plain": round(ms_p / ms_b, 3),
                              "shape": {"block": shape[0], "queries_per_lane": shape[1],
                                        "traversal": {1: "kd per-lane", 2: "kd wavefront", 3: "voronoi walk"}[shape[2]]},
-                             "workload": (f"{'all' if args.batched_full else 'first'} {count} meshes of the seeded 256-mesh plan "
+                             "workload": (f"{'all' if count == 256 else 'first'} {count} meshes of the seeded 256-mesh plan "
                                           f"(displaced geodesic spheres / heightfields, log-uniform sizes): {ntri} triangles, "
                                           f"{nb} queries (log-uniform per mesh, mixed uniform/near-surface); one graph launch"),
-                             "host_precompute_s": round(t_pre4, 1), "generate_s": round(t_gen, 1)}
+                             "precompute_s": round(t_pre4, 1), "precompute": "host Delaunay + cells, inspection on the GPU",
+                             "generate_s": round(t_gen, 1)}
         log(f"[bench] batched ({count} meshes, {ntri} tris, {nb} queries): {ms_b:.3f} ms graph vs {ms_p:.3f} ms "
             f"for {count} plain launches; shape {shape}; precompute {t_pre4:.1f}s")
         del batch, meshes, qb, outb, outs, qsl
