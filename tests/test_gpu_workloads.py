@@ -1,5 +1,5 @@
 """Full-size workloads on the GPU: C3 (needle heightfield, 10^7 queries) and
-the batched C4 plan (first 64 meshes, as benchmarked), sampled against the
+the batched C4 plan (all 256 meshes, as benchmarked), sampled against the
 FP64 oracle; C5 (10^6 near-surface queries on the C2 mesh) forward and
 backward against the oracle's closest points and gradients."""
 from __future__ import annotations
@@ -24,14 +24,15 @@ def _np(out):
 
 
 def test_c3_full_size_sampled():
-    """Heightfield 1024 x 1024 with compressed rows (needles), 10^7 queries in
-    one sorted launch; 1,200 sampled rows against the oracle."""
+    """Heightfield 1024 x 1024 with compressed rows (needles; table built with
+    the inspection on the device), 10^7 queries in one sorted launch; 1,200
+    sampled rows against the oracle."""
     import torch
 
     import paper_2308_16084_amd as P
     print("case: c3 build", flush=True)
     w = C.c3()
-    m, _ = P.Mesh.cached(w.V, w.F, (w.domain_lo, w.domain_hi), CACHE)
+    m, _ = P.Mesh.cached(w.V, w.F, (w.domain_lo, w.domain_hi), CACHE, table_mode=P.TABLE_FLOODING_DEVICE)
     m.upload(0)
     q = torch.from_numpy(w.Q).cuda()
     out = _np(m.query(q))
@@ -45,15 +46,20 @@ def test_c3_full_size_sampled():
     assert check_answers(om, w.Q[idx], ans, out["prim"][idx], out["closest"][idx], out["dist"][idx], idx=idx) == []
 
 
-def test_c4_subset_batched_sampled():
-    """First 64 meshes of the seeded C4 plan in one graph launch; 48 sampled
-    queries per mesh against the oracle."""
+def test_c4_batched_sampled():
+    """All 256 meshes of the seeded C4 plan (tables built with the inspection
+    on the device) in one graph launch; 64 sampled queries per mesh against
+    the oracle."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import torch
 
     import paper_2308_16084_amd as P
     print("case: c4 build", flush=True)
-    works = [C.c4_mesh(e) for e in C.c4_plan()[:64]]
-    meshes = P.precompute_many([(x.V, x.F, (x.domain_lo, x.domain_hi)) for x in works], CACHE)
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        works = list(ex.map(C.c4_mesh, C.c4_plan()))
+    meshes = P.precompute_many([(x.V, x.F, (x.domain_lo, x.domain_hi)) for x in works], CACHE,
+                               table_mode=P.TABLE_FLOODING_DEVICE)
     b = P.Batch(meshes, 0)
     Q = np.concatenate([x.Q for x in works])
     off = np.concatenate([[0], np.cumsum([len(x.Q) for x in works])]).astype(np.int64)
@@ -61,7 +67,7 @@ def test_c4_subset_batched_sampled():
     torch.cuda.synchronize()
     rng = np.random.default_rng(44)
     for k, x in enumerate(works):
-        idx = np.sort(rng.choice(len(x.Q), size=min(48, len(x.Q)), replace=False))
+        idx = np.sort(rng.choice(len(x.Q), size=min(64, len(x.Q)), replace=False))
         rows = off[k] + idx
         om = oracle.OracleMesh(x.V, x.F)
         fails = check_answers(om, x.Q[idx], om.query(x.Q[idx]), out["prim"][rows], out["closest"][rows],
