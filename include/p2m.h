@@ -66,10 +66,12 @@ enum {
      * Algorithm 1: the inspection, the bulk of the preprocessing per
      * Table 2) run on the current HIP device, one primitive per wavefront,
      * in FP64 with the host's operations and their order, so the table and
-     * its entry boxes are those of P2M_TABLE_FLOODING.  The Delaunay
-     * neighbours and the cells are still built on the host.  A primitive
-     * whose polytope outgrows 64 corners or whose flood outgrows the visit
-     * limit is finished on the host.  Blocks until done; uses the null
+     * its entry boxes are those of P2M_TABLE_FLOODING.  The Voronoi cells
+     * are built on the device too, from the Delaunay neighbours (still
+     * computed on the host, with exact predicates), with the host's
+     * arithmetic.  A primitive whose polytope outgrows 64 corners or whose
+     * flood outgrows the visit limit, and a cell of more than 64 corners or
+     * neighbours, are finished on the host.  Blocks until done; uses the null
      * stream.  Needs a HIP device; fails with P2M_ERR_HIP otherwise. */
     P2M_TABLE_FLOODING_DEVICE = 3
 };
@@ -98,10 +100,11 @@ typedef struct {
     int64_t flood_tests, flood_hits, quick_rejects, skipped_clips;
     int64_t nnz_edges, nnz_faces, max_list;
     double avg_list; /* (nnz_edges + nnz_faces) / nv */
-    /* P2M_TABLE_FLOODING_DEVICE: seconds spent uploading, in the kernel and
-     * downloading; primitives the host finished */
+    /* P2M_TABLE_FLOODING_DEVICE: seconds spent uploading, in the inspection
+     * kernel and downloading (t_cells: the cells, built on the device);
+     * primitives and cells the host finished */
     double t_dev_upload, t_dev_kernel, t_dev_download;
-    int64_t device_redo;
+    int64_t device_redo, device_cells_back;
 } p2m_build_stats;
 
 typedef struct {

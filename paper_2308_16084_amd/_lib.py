@@ -32,7 +32,7 @@ class BuildStats(ctypes.Structure):
                                    "nnz_edges", "nnz_faces", "max_list")] + \
                [("avg_list", ctypes.c_double)] + \
                [(n, ctypes.c_double) for n in ("t_dev_upload", "t_dev_kernel", "t_dev_download")] + \
-               [("device_redo", I64)]
+               [("device_redo", I64), ("device_cells_back", I64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -23,21 +24,17 @@ struct FloodPrim {
     int64_t id;      // edge or face id
 };
 
-// Voronoi cells (clipped to D grown by tau) in flat arrays, vertex order:
-// planes (n, off) at planes[4*poff[v] ...], poff[nv] = total; corners as
-// plane-index triples tris[3*toff[v] ...] and positions pos[3*toff[v] ...].
-struct FlatCells {
-    std::vector<uint64_t> poff, toff;
-    std::vector<double> planes, pos;
-    std::vector<uint16_t> tris;
-};
+// Builds the Voronoi cell of vertex v on the host (the planes (n, off) that
+// bound a corner, 4 doubles each, and the corners, 3 doubles each); returns
+// the number of cuts it had to skip.
+using HostCellFn = std::function<int64_t(int64_t v, std::vector<double>& planes, std::vector<double>& pos)>;
 
 struct FloodInput {
     int64_t nv = 0, nprim = 0;
     const double* Vd = nullptr;  // [3*nv]
     const int64_t* nb_off = nullptr;  // [nv+1] Voronoi neighbours
     const int32_t* nb = nullptr;
-    const FlatCells* cells = nullptr;
+    HostCellFn host_cell;             // cells the device hands back
     const FloodPrim* prims = nullptr;  // [nprim]
     const double* perp = nullptr;      // [4 * total half-spaces]
     int64_t nperp_total = 0;
@@ -60,11 +57,13 @@ struct FloodResult {
                                      // set beyond its fixed capacity): the
                                      // host floods these itself
     int64_t tests = 0, hits = 0, quick = 0, skipped = 0;
-    double t_upload = 0, t_kernel = 0, t_download = 0;
+    int64_t cells_skipped = 0, cells_back = 0;  // cell construction: skipped cuts, cells built on the host
+    double t_upload = 0, t_cells = 0, t_kernel = 0, t_download = 0;
 };
 
-// Runs the inspection of every primitive on the current HIP device.
-// False (with err) on a HIP error.
+// Builds every vertex's Voronoi cell and then runs the inspection of every
+// primitive on the current HIP device.  False (with err) on a HIP error or a
+// host-built cell too large for its slot.
 bool device_flood(const FloodInput& in, FloodResult& out, std::string& err);
 
 }  // namespace p2m

@@ -4,7 +4,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
+#include <unordered_map>
 
 #include "convex_cell.hpp"
 #include "delaunay.hpp"
@@ -44,8 +46,64 @@ int num_threads(int requested) {
 #endif
 }
 
-// Voronoi cells of all vertices, clipped to D, in per-thread flat buffers.
+// Voronoi cell of vertex v clipped to the box blo..bhi (D grown by tau): the
+// box cut by the bisector of v and each Voronoi (Delaunay) neighbour, nearest
+// first (ties by id), each moved outward by tau; planes that bound no corner
+// dropped.  Returns the number of cuts skipped.
+int64_t build_cell(const MeshData& m, const Table& t, int64_t v, const double blo[3], const double bhi[3],
+                   double tau, ConvexCell& cell, std::vector<std::pair<double, int32_t>>& order) {
+    int64_t skipped = 0;
+    const double* pv = &m.Vd[3 * (size_t)v];
+    cell.init_box(blo, bhi);
+    order.clear();
+    for (int64_t k = t.nb_off[(size_t)v]; k < t.nb_off[(size_t)v + 1]; ++k) {
+        int32_t w = t.nb[(size_t)k];
+        const double* pw = &m.Vd[3 * (size_t)w];
+        double d[3] = {pw[0] - pv[0], pw[1] - pv[1], pw[2] - pv[2]};
+        order.push_back({dot3(d, d), w});
+    }
+    std::sort(order.begin(), order.end());
+    for (const auto& e : order) {
+        const double* pw = &m.Vd[3 * (size_t)e.second];
+        HalfSpace h;
+        for (int k = 0; k < 3; ++k) h.n[k] = pw[k] - pv[k];
+        double nl = std::sqrt(dot3(h.n, h.n));
+        // bisector of v and w, on v's side, moved outward by tau
+        h.off = 0.5 * (dot3(pw, pw) - dot3(pv, pv)) + tau * nl;
+        if (cell.clip(h) == ConvexCell::SKIPPED) ++skipped;
+    }
+    cell.compact();
+    return skipped;
+}
+
+// Voronoi cells of all vertices, clipped to D, in per-thread flat buffers;
+// or, when `lazy`, each built on first use (the inspection on the device
+// builds its own and the host needs only those of the primitives it takes
+// back).  The inspection reads a cell's planes and corners.
 struct CellStore {
+    bool lazy = false;
+    const MeshData* m = nullptr;
+    const Table* t = nullptr;
+    double blo[3], bhi[3], tau = 0;
+    struct Built {
+        std::vector<double> planes, pos;
+    };
+    mutable std::mutex mu;
+    mutable std::unordered_map<int64_t, Built> built;
+
+    const Built& get(int64_t v) const {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = built.find(v);
+        if (it != built.end()) return it->second;
+        ConvexCell cell;
+        std::vector<std::pair<double, int32_t>> order;
+        build_cell(*m, *t, v, blo, bhi, tau, cell, order);
+        Built b;
+        std::vector<uint16_t> tris;
+        cell.save(b.planes, tris, b.pos);
+        return built.emplace(v, std::move(b)).first->second;
+    }
+
     struct Ref {
         int32_t thread;
         uint32_t np, nt;
@@ -61,11 +119,21 @@ struct CellStore {
                pos[(size_t)r.thread].data() + 3 * r.toff, r.nt);
     }
     const double* corners(int64_t v, uint32_t& n) const {
+        if (lazy) {
+            const Built& b = get(v);
+            n = (uint32_t)(b.pos.size() / 3);
+            return b.pos.data();
+        }
         const Ref& r = ref[(size_t)v];
         n = r.nt;
         return pos[(size_t)r.thread].data() + 3 * r.toff;
     }
     const double* plane_data(int64_t v, uint32_t& n) const {
+        if (lazy) {
+            const Built& b = get(v);
+            n = (uint32_t)(b.planes.size() / 4);
+            return b.planes.data();
+        }
         const Ref& r = ref[(size_t)v];
         n = r.np;
         return planes[(size_t)r.thread].data() + 4 * r.poff;
@@ -344,31 +412,15 @@ void flood(const MeshData& m, const CellStore& cs, const Table& t, const Primiti
     }
 }
 
-// Flat copies of the cells and the primitives' Space-perp half-spaces for
-// the device inspection, which returns every entry of the primitives it
-// finished and the list of those it hands back (their entries, if any, are
-// dropped here; the host floods them afterwards).
+// The device inspection: the cells and then the filter and flooding of
+// every primitive on the device, from the primitives' Space-perp
+// half-spaces; it returns every entry of the primitives it finished and the
+// list of those it hands back (their entries, if any, are dropped here; the
+// host floods them afterwards, with cells it builds on demand).
 bool inspect_on_device(const MeshData& m, const CellStore& cs, const Table& t, const TableOptions& o,
                        const double blo[3], const double bhi[3], double dmax, int nth, std::vector<PairRec>& pairs,
                        std::vector<int64_t>& redo, TableStats& st, std::string& err) {
     const int64_t nv = m.nv, nprim = m.ne + m.nf;
-    FlatCells fc;
-    fc.poff.assign((size_t)nv + 1, 0);
-    fc.toff.assign((size_t)nv + 1, 0);
-    for (int64_t v = 0; v < nv; ++v) {
-        fc.poff[(size_t)v + 1] = fc.poff[(size_t)v] + cs.ref[(size_t)v].np;
-        fc.toff[(size_t)v + 1] = fc.toff[(size_t)v] + cs.ref[(size_t)v].nt;
-    }
-    fc.planes.resize(4 * (size_t)fc.poff[(size_t)nv]);
-    fc.pos.resize(3 * (size_t)fc.toff[(size_t)nv]);
-#pragma omp parallel for num_threads(nth) schedule(static, 4096)
-    for (int64_t v = 0; v < nv; ++v) {
-        uint32_t np = 0, nt = 0;
-        const double* P = cs.plane_data(v, np);
-        const double* X = cs.corners(v, nt);
-        std::memcpy(&fc.planes[4 * (size_t)fc.poff[(size_t)v]], P, sizeof(double) * 4 * np);
-        std::memcpy(&fc.pos[3 * (size_t)fc.toff[(size_t)v]], X, sizeof(double) * 3 * nt);
-    }
     // half-spaces per primitive: a face has 3, an edge its 2 end planes and
     // one per incident face, 8 at most (as make_edge keeps them)
     std::vector<FloodPrim> prims((size_t)nprim);
@@ -411,7 +463,14 @@ bool inspect_on_device(const MeshData& m, const CellStore& cs, const Table& t, c
     in.Vd = m.Vd.data();
     in.nb_off = t.nb_off.data();
     in.nb = t.nb.data();
-    in.cells = &fc;
+    in.host_cell = [&](int64_t v, std::vector<double>& P, std::vector<double>& X) -> int64_t {
+        ConvexCell cell;
+        std::vector<std::pair<double, int32_t>> order;
+        const int64_t sk = build_cell(m, t, v, blo, bhi, o.tau, cell, order);
+        std::vector<uint16_t> tris;
+        cell.save(P, tris, X);
+        return sk;
+    };
     in.prims = prims.data();
     in.perp = perp.data();
     in.nperp_total = poff[(size_t)nprim];
@@ -450,7 +509,9 @@ bool inspect_on_device(const MeshData& m, const CellStore& cs, const Table& t, c
     st.flood_tests += r.tests;
     st.flood_hits += r.hits;
     st.quick_rejects += r.quick;
-    st.skipped_clips += r.skipped;
+    st.skipped_clips += r.skipped + r.cells_skipped;
+    st.t_cells = r.t_cells;
+    st.device_cells_back = r.cells_back;
     st.t_dev_upload = r.t_upload;
     st.t_dev_kernel = r.t_kernel;
     st.t_dev_download = r.t_download;
@@ -490,7 +551,18 @@ bool build_table(const MeshData& m, const TableOptions& o, Table& t, TableStats&
         blo[k] = o.lo[k] - o.tau;
         bhi[k] = o.hi[k] + o.tau;
     }
-#pragma omp parallel num_threads(nth) reduction(+ : skipped_cells)
+    if (o.mode == TABLE_FLOODING_DEVICE) {
+        // the device builds the cells; the host builds on demand those it needs
+        cs.lazy = true;
+        cs.m = &m;
+        cs.t = &t;
+        cs.tau = o.tau;
+        for (int k = 0; k < 3; ++k) {
+            cs.blo[k] = blo[k];
+            cs.bhi[k] = bhi[k];
+        }
+    }
+#pragma omp parallel num_threads(nth) reduction(+ : skipped_cells) if (!cs.lazy)
     {
         int tid = 0;
 #ifdef _OPENMP
@@ -501,28 +573,10 @@ bool build_table(const MeshData& m, const TableOptions& o, Table& t, TableStats&
         auto& P = cs.planes[(size_t)tid];
         auto& X = cs.pos[(size_t)tid];
         auto& T = cs.tris[(size_t)tid];
+        const int64_t ncell = cs.lazy ? 0 : nv;
 #pragma omp for schedule(dynamic, 256)
-        for (int64_t v = 0; v < nv; ++v) {
-            const double* pv = &m.Vd[3 * (size_t)v];
-            cell.init_box(blo, bhi);
-            order.clear();
-            for (int64_t k = t.nb_off[(size_t)v]; k < t.nb_off[(size_t)v + 1]; ++k) {
-                int32_t w = t.nb[(size_t)k];
-                const double* pw = &m.Vd[3 * (size_t)w];
-                double d[3] = {pw[0] - pv[0], pw[1] - pv[1], pw[2] - pv[2]};
-                order.push_back({dot3(d, d), w});
-            }
-            std::sort(order.begin(), order.end());
-            for (const auto& e : order) {
-                const double* pw = &m.Vd[3 * (size_t)e.second];
-                HalfSpace h;
-                for (int k = 0; k < 3; ++k) h.n[k] = pw[k] - pv[k];
-                double nl = std::sqrt(dot3(h.n, h.n));
-                // bisector of v and w, on v's side, moved outward by tau
-                h.off = 0.5 * (dot3(pw, pw) - dot3(pv, pv)) + o.tau * nl;
-                if (cell.clip(h) == ConvexCell::SKIPPED) ++skipped_cells;
-            }
-            cell.compact();
+        for (int64_t v = 0; v < ncell; ++v) {
+            skipped_cells += build_cell(m, t, v, blo, bhi, o.tau, cell, order);
             CellStore::Ref r;
             r.thread = tid;
             r.poff = P.size() / 4;

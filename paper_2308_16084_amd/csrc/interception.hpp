@@ -41,7 +41,7 @@ struct TableStats {
     double t_delaunay = 0, t_cells = 0, t_flood = 0, t_pack = 0;
     // device inspection: upload, kernel, download; primitives left to the host
     double t_dev_upload = 0, t_dev_kernel = 0, t_dev_download = 0;
-    int64_t device_redo = 0;
+    int64_t device_redo = 0, device_cells_back = 0;
     int64_t delaunay_edges = 0, tets = 0;
     long long exact_predicates = 0;
     int64_t flood_tests = 0, flood_hits = 0, quick_rejects = 0, skipped_clips = 0;

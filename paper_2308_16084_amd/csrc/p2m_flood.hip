@@ -31,6 +31,10 @@ constexpr int kPlaneCap = 128; // planes of a polytope (ids fit in 8 bits)
 constexpr int kWaveCorners = 64;  // corners of a polytope: one per lane
 constexpr int kQueueCap = 512; // vertices one flood may visit
 constexpr int kHashCap = 1024; // open-addressing set over them (power of two)
+// Each vertex's cell in a fixed slot: at most kSlotPlanes planes (n, off)
+// and kSlotCorners corners.
+constexpr int kSlotPlanes = 128;
+constexpr int kSlotCorners = 128;
 
 enum { UNCHANGED = 0, CLIPPED = 1, EMPTY = 2, SKIPPED = 3, OVERFLOW = 4 };
 
@@ -49,6 +53,7 @@ struct PlaneSrc {
     const double* bhi;
     const double* perp;   // 4 doubles per half-space of p
     const double* cellp;  // 4 doubles per plane of the current cell
+    bool lds = false;     // the cell's planes are in LDS instead (cell construction)
 };
 
 __device__ __forceinline__ void plane_get(const PlaneSrc& S, const uint8_t* src, int id, double n[3], double& off) {
@@ -131,6 +136,7 @@ struct WaveLds {
     uint8_t srcW[kPlaneCap - 6];
     double sx[kWaveCorners], sy[kWaveCorners], sz[kWaveCorners];  // staging of a cut's result
     uint32_t stri[kWaveCorners], sadj[kWaveCorners];
+    double cpl[kWaveCorners][4];  // cell construction: the bisector planes so far
 };
 
 __device__ __forceinline__ int wlane() { return (int)__lane_id(); }
@@ -163,11 +169,24 @@ __device__ __forceinline__ WCorner wcorner_of(double an0, double an1, double an2
     return r;
 }
 
-__device__ __forceinline__ WCorner wcorner(const PlaneSrc& S, const uint8_t* src, int i, int j, const double hn[3],
-                                           double hoff) {
+__device__ __forceinline__ void wplane_get(const PlaneSrc& S, const WaveLds& L, const uint8_t* src, int id,
+                                           double n[3], double& off) {
+    if (S.lds && id >= 6) {
+        const int r = src[id - 6] - 8;
+        n[0] = L.cpl[r][0];
+        n[1] = L.cpl[r][1];
+        n[2] = L.cpl[r][2];
+        off = L.cpl[r][3];
+        return;
+    }
+    plane_get(S, src, id, n, off);
+}
+
+__device__ __forceinline__ WCorner wcorner(const PlaneSrc& S, const WaveLds& L, const uint8_t* src, int i, int j,
+                                           const double hn[3], double hoff) {
     double an[3], bn[3], aoff, boff;
-    plane_get(S, src, i, an, aoff);
-    plane_get(S, src, j, bn, boff);
+    wplane_get(S, L, src, i, an, aoff);
+    wplane_get(S, L, src, j, bn, boff);
     return wcorner_of(an[0], an[1], an[2], aoff, bn[0], bn[1], bn[2], boff, hn[0], hn[1], hn[2], hoff);
 }
 
@@ -287,7 +306,7 @@ __device__ int wcut(WPoly& P, uint8_t* src, WaveLds& L, const PlaneSrc& S, const
             const int a = e == 0 ? a0 : (e == 1 ? a1 : a2);
             const int b = e == 0 ? a1 : (e == 1 ? a2 : a0);
             const int d = e == 0 ? d0 : (e == 1 ? d1 : d2);
-            const WCorner r = wcorner(S, src, a, b, hn, hoff);
+            const WCorner r = wcorner(S, L, src, a, b, hn, hoff);
             fail |= !r.ok;
             L.sx[d] = r.x[0];
             L.sy[d] = r.x[1];
@@ -439,6 +458,131 @@ __device__ __forceinline__ bool whash_visit(int32_t* hset, int32_t u) {
     }
 }
 
+struct CellCounters {
+    unsigned long long next, back, skipped;
+};
+
+// The Voronoi cell of every vertex, one vertex per wavefront, as on the
+// host: the box D grown by tau cut by the bisector of v and each Voronoi
+// (Delaunay) neighbour w, nearest first (ties by id), each moved outward by
+// tau; then the planes that bound a corner, in the order they were added,
+// and the corners go to the vertex's slot.  A vertex with more than 64
+// neighbours or a cell of more than 64 corners is handed back to the host.
+__global__ __launch_bounds__(64) void k_cells(int64_t nv, const double* __restrict__ Vd,
+                                              const int64_t* __restrict__ nb_off, const int32_t* __restrict__ nb,
+                                              const double* __restrict__ dom, double* __restrict__ slot_planes,
+                                              double* __restrict__ slot_pos, int32_t* __restrict__ cnp_of,
+                                              int32_t* __restrict__ cnt_of, int64_t* __restrict__ back,
+                                              CellCounters* __restrict__ cc) {
+    __shared__ WaveLds L;
+    const int l = wlane();
+    const double* blo = dom;
+    const double* bhi = dom + 3;
+    const double tau = dom[12];
+    unsigned long long skipped_all = 0;
+    WPoly W;
+    for (;;) {
+        unsigned long long tv = 0;
+        if (l == 0) tv = atomicAdd(&cc->next, 1ull);
+        tv = __shfl(tv, 0);
+        if (tv >= (unsigned long long)nv) break;
+        const int64_t v = __builtin_amdgcn_readfirstlane((int)tv);
+        const int64_t k0 = nb_off[v];
+        const int deg = (int)(nb_off[v + 1] - k0);
+        if (deg > 64) {
+            if (l == 0) back[atomicAdd(&cc->back, 1ull)] = v;
+            continue;
+        }
+        const double pv[3] = {Vd[3 * v], Vd[3 * v + 1], Vd[3 * v + 2]};
+        // neighbour l and its squared distance; its rank in (distance, id) order
+        const bool have = l < deg;
+        const int32_t wl = have ? nb[k0 + l] : 0x7fffffff;
+        double pw[3] = {0.0, 0.0, 0.0};
+        double d2 = INFINITY;
+        if (have) {
+            pw[0] = Vd[3 * (int64_t)wl];
+            pw[1] = Vd[3 * (int64_t)wl + 1];
+            pw[2] = Vd[3 * (int64_t)wl + 2];
+            const double d[3] = {pw[0] - pv[0], pw[1] - pv[1], pw[2] - pv[2]};
+            d2 = dot3(d, d);
+        }
+        int rank = 0;
+        for (int i = 0; i < deg; ++i) {
+            const double di = __shfl(d2, i);
+            const int32_t wi = __shfl(wl, i);
+            rank += (di < d2 || (di == d2 && wi < wl)) ? 1 : 0;
+        }
+        winit_box(W, blo, bhi);
+        const PlaneSrc S{blo, bhi, blo, blo, true};
+        int64_t skipped = 0;
+        bool ovf = false;
+        for (int r = 0; r < deg && !ovf; ++r) {
+            const int o = __ffsll((long long)__ballot(have && rank == r)) - 1;
+            // bisector of v and w, on v's side, moved outward by tau
+            double n[3] = {pw[0] - pv[0], pw[1] - pv[1], pw[2] - pv[2]};
+            const double nl = sqrt(dot3(n, n));
+            const double off = 0.5 * (dot3(pw, pw) - dot3(pv, pv)) + tau * nl;
+            const double hn[3] = {__shfl(n[0], o), __shfl(n[1], o), __shfl(n[2], o)};
+            const double hoff = __shfl(off, o);
+            if (l == 0) {
+                L.cpl[r][0] = hn[0];
+                L.cpl[r][1] = hn[1];
+                L.cpl[r][2] = hn[2];
+                L.cpl[r][3] = hoff;
+            }
+            __syncthreads();
+            const int res = wclip(W, L.srcW, L, S, hn, hoff, (uint8_t)(8 + r));
+            if (res == SKIPPED) ++skipped;
+            if (res == OVERFLOW) ovf = true;
+        }
+        if (ovf) {
+            if (l == 0) back[atomicAdd(&cc->back, 1ull)] = v;
+            __syncthreads();
+            continue;
+        }
+        // the planes that bound a corner, renumbered in their order
+        const bool valid = l < W.nt;
+        uint64_t u0 = 0, u1 = 0;
+        if (valid)
+            for (int e = 0; e < 3; ++e) {
+                const int id = tri_at(W.tri, e);
+                if (id < 64) u0 |= 1ull << id;
+                else u1 |= 1ull << (id - 64);
+            }
+        for (int d = 32; d >= 1; d >>= 1) {
+            u0 |= __shfl_xor(u0, d);
+            u1 |= __shfl_xor(u1, d);
+        }
+        u0 = __shfl(u0, 0);
+        u1 = __shfl(u1, 0);
+        double* sp = slot_planes + v * (4 * kSlotPlanes);
+        for (int id = l; id < W.np; id += 64) {
+            const bool used = id < 64 ? ((u0 >> id) & 1ull) : ((u1 >> (id - 64)) & 1ull);
+            if (!used) continue;
+            const int k = id < 64 ? __popcll(u0 & below(id)) : __popcll(u0) + __popcll(u1 & below(id - 64));
+            double hn[3], hoff;
+            wplane_get(S, L, L.srcW, id, hn, hoff);
+            sp[4 * k] = hn[0];
+            sp[4 * k + 1] = hn[1];
+            sp[4 * k + 2] = hn[2];
+            sp[4 * k + 3] = hoff;
+        }
+        if (valid) {
+            double* xp = slot_pos + (v * kSlotCorners + l) * 3;
+            xp[0] = W.x;
+            xp[1] = W.y;
+            xp[2] = W.z;
+        }
+        if (l == 0) {
+            cnp_of[v] = W.empty ? 0 : __popcll(u0) + __popcll(u1);
+            cnt_of[v] = W.empty ? 0 : W.nt;
+        }
+        skipped_all += (unsigned long long)skipped;
+        __syncthreads();
+    }
+    if (l == 0) atomicAdd(&cc->skipped, skipped_all);
+}
+
 // Each wavefront (a block of 64 lanes) takes primitives from a shared counter
 // until none are left and floods each one: base polytope, then for every
 // queued vertex the quick whole-cell test, the cut by the cell's planes, the
@@ -447,9 +591,9 @@ __device__ __forceinline__ bool whash_visit(int32_t* hset, int32_t u) {
 __global__ __launch_bounds__(64) void k_flood(int64_t nprim, const FloodPrim* __restrict__ prims,
                                                    const double* __restrict__ perp, const double* __restrict__ Vd,
                                                    const int64_t* __restrict__ nb_off, const int32_t* __restrict__ nb,
-                                                   const uint64_t* __restrict__ cpoff,
+                                                   const int32_t* __restrict__ cnp_of,
                                                    const double* __restrict__ cplanes,
-                                                   const uint64_t* __restrict__ ctoff, const double* __restrict__ cpos,
+                                                   const int32_t* __restrict__ cnt_of, const double* __restrict__ cpos,
                                                    const double* __restrict__ dom, FloodRec* __restrict__ recs,
                                                    uint64_t rec_cap, int64_t* __restrict__ redo,
                                                    Counters* __restrict__ cnt, int visit_cap) {
@@ -503,8 +647,8 @@ __global__ __launch_bounds__(64) void k_flood(int64_t nprim, const FloodPrim* __
             const int32_t w = __builtin_amdgcn_readfirstlane(L.queue[head]);
             bool own = false;
             for (int k = 0; k < p.nverts; ++k) own |= (p.verts[k] == w);
-            const double* cellp = cplanes + 4 * cpoff[w];
-            const int cnp = (int)(cpoff[w + 1] - cpoff[w]);
+            const double* cellp = cplanes + (int64_t)w * (4 * kSlotPlanes);
+            const int cnp = cnp_of[w];
             if (cnp > kPlaneCap - 8 - 8) {
                 ovf = true;
                 break;
@@ -521,7 +665,7 @@ __global__ __launch_bounds__(64) void k_flood(int64_t nprim, const FloodPrim* __
                 const double* X = Vd + 3 * (int64_t)w;
                 const double Wv[3] = {X[0], X[1], X[2]};
                 // |x-w| - Dist(x,p) is convex: the whole cell keeping w out settles it
-                const int64_t t0 = (int64_t)ctoff[w], t1 = (int64_t)ctoff[w + 1];
+                const int64_t t0 = (int64_t)w * kSlotCorners, t1 = t0 + cnt_of[w];
                 bool all_far = true;
                 for (int64_t t = t0; t < t1 && all_far; t += 64) {
                     const bool far = t + l >= t1 || far_enough(p, Wv, cpos + 3 * (t + l), c.slack);
@@ -609,7 +753,6 @@ bool device_flood(const FloodInput& in, FloodResult& out, std::string& err) {
     };
     out = FloodResult();
     if (in.nprim == 0) return true;
-    const FlatCells& cs = *in.cells;
     auto t0 = Clock::now();
     const size_t nv = (size_t)in.nv;
     const uint64_t rec_cap = std::max<uint64_t>(1u << 20, 64ull * nv + 16ull * (uint64_t)in.nprim);
@@ -626,31 +769,30 @@ bool device_flood(const FloodInput& in, FloodResult& out, std::string& err) {
     }
     dom[12] = in.tau;
     dom[13] = in.dmax;
+    // uploaded parts, then the parts the device fills
     const Part parts[] = {
         {in.prims, sizeof(FloodPrim) * (size_t)in.nprim},
         {in.perp, sizeof(double) * 4 * (size_t)std::max<int64_t>(1, in.nperp_total)},
         {in.Vd, sizeof(double) * 3 * nv},
         {in.nb_off, sizeof(int64_t) * (nv + 1)},
         {in.nb, sizeof(int32_t) * std::max<size_t>(1, (size_t)in.nb_off[nv])},
-        {cs.poff.data(), sizeof(uint64_t) * (nv + 1)},
-        {cs.planes.data(), sizeof(double) * std::max<size_t>(4, cs.planes.size())},
-        {cs.toff.data(), sizeof(uint64_t) * (nv + 1)},
-        {cs.pos.data(), sizeof(double) * std::max<size_t>(3, cs.pos.size())},
         {dom, sizeof(dom)},
+        {nullptr, sizeof(double) * 4 * kSlotPlanes * nv},   // 6: cell planes
+        {nullptr, sizeof(double) * 3 * kSlotCorners * nv},  // 7: cell corners
+        {nullptr, sizeof(int32_t) * nv},                    // 8: planes per cell
+        {nullptr, sizeof(int32_t) * nv},                    // 9: corners per cell
+        {nullptr, sizeof(int64_t) * nv},                    // 10: cells handed back
+        {nullptr, sizeof(FloodRec) * rec_cap},              // 11: table entries
+        {nullptr, sizeof(int64_t) * (size_t)in.nprim},      // 12: primitives handed back
+        {nullptr, 256},                                     // 13: counters
     };
     constexpr int kParts = sizeof(parts) / sizeof(parts[0]);
-    size_t off[kParts + 3];
+    size_t off[kParts];
     size_t total = 0;
     for (int k = 0; k < kParts; ++k) {
         off[k] = total;
         total += (parts[k].bytes + 255) / 256 * 256;
     }
-    off[kParts] = total;  // records
-    total += (sizeof(FloodRec) * rec_cap + 255) / 256 * 256;
-    off[kParts + 1] = total;  // redo list
-    total += (sizeof(int64_t) * (size_t)in.nprim + 255) / 256 * 256;
-    off[kParts + 2] = total;  // counters
-    total += 256;
     DevBuf buf;
     if (!hip_ok(hipMalloc(&buf.p, total), "hipMalloc")) return false;
     char* d = (char*)buf.p;
@@ -658,40 +800,93 @@ bool device_flood(const FloodInput& in, FloodResult& out, std::string& err) {
         if (parts[k].src && parts[k].bytes &&
             !hip_ok(hipMemcpy(d + off[k], parts[k].src, parts[k].bytes, hipMemcpyHostToDevice), "upload"))
             return false;
-    if (!hip_ok(hipMemset(d + off[kParts + 2], 0, sizeof(Counters)), "hipMemset")) return false;
+    if (!hip_ok(hipMemset(d + off[13], 0, 256), "hipMemset")) return false;
     if (!hip_ok(hipDeviceSynchronize(), "upload")) return false;
     out.t_upload = since(t0);
-    t0 = Clock::now();
-    // enough wavefronts to fill the chip; each loops over primitives
-    const int block = 64;
-    int dev = 0, cus = 256, per_cu = 0;
+    const double* dVd = (const double*)(d + off[2]);
+    const int64_t* dnb_off = (const int64_t*)(d + off[3]);
+    const int32_t* dnb = (const int32_t*)(d + off[4]);
+    const double* ddom = (const double*)(d + off[5]);
+    double* cplanes = (double*)(d + off[6]);
+    double* cpos = (double*)(d + off[7]);
+    int32_t* cnp = (int32_t*)(d + off[8]);
+    int32_t* cnt = (int32_t*)(d + off[9]);
+    int64_t* cback = (int64_t*)(d + off[10]);
+    Counters* counters = (Counters*)(d + off[13]);
+    CellCounters* ccount = (CellCounters*)(d + off[13] + 128);
+    int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_flood, block, 0) != hipSuccess || per_cu < 1)
-        per_cu = 8;
-    const int64_t grid = std::min<int64_t>(in.nprim, (int64_t)cus * per_cu);
-    k_flood<<<(unsigned)grid, block, 0, 0>>>(
-        in.nprim, (const FloodPrim*)(d + off[0]), (const double*)(d + off[1]), (const double*)(d + off[2]),
-        (const int64_t*)(d + off[3]), (const int32_t*)(d + off[4]), (const uint64_t*)(d + off[5]),
-        (const double*)(d + off[6]), (const uint64_t*)(d + off[7]), (const double*)(d + off[8]),
-        (const double*)(d + off[9]), (FloodRec*)(d + off[kParts]), rec_cap, (int64_t*)(d + off[kParts + 1]),
-        (Counters*)(d + off[kParts + 2]), in.visit_cap > 0 && in.visit_cap < kQueueCap ? in.visit_cap : kQueueCap);
-    if (!hip_ok(hipGetLastError(), "launch")) return false;
-    if (!hip_ok(hipDeviceSynchronize(), "kernel")) return false;
+    const int block = 64;
+
+    // 1. cells: on the device, those it hands back on the host
+    t0 = Clock::now();
+    {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cells, block, 0) != hipSuccess || per_cu < 1)
+            per_cu = 8;
+        const int64_t grid = std::min<int64_t>(in.nv, (int64_t)cus * per_cu);
+        k_cells<<<(unsigned)grid, block, 0, 0>>>(in.nv, dVd, dnb_off, dnb, ddom, cplanes, cpos, cnp, cnt, cback,
+                                                 ccount);
+        if (!hip_ok(hipGetLastError(), "launch")) return false;
+        if (!hip_ok(hipDeviceSynchronize(), "cell kernel")) return false;
+        CellCounters cc;
+        if (!hip_ok(hipMemcpy(&cc, ccount, sizeof(cc), hipMemcpyDeviceToHost), "download")) return false;
+        out.cells_skipped = (int64_t)cc.skipped;
+        out.cells_back = (int64_t)cc.back;
+        std::vector<int64_t> back((size_t)cc.back);
+        if (cc.back && !hip_ok(hipMemcpy(back.data(), cback, sizeof(int64_t) * cc.back, hipMemcpyDeviceToHost),
+                               "download"))
+            return false;
+        std::vector<double> P, X;
+        for (int64_t v : back) {
+            P.clear();
+            X.clear();
+            out.cells_skipped += in.host_cell(v, P, X);
+            const int32_t np = (int32_t)(P.size() / 4), nt = (int32_t)(X.size() / 3);
+            if (np > kSlotPlanes || nt > kSlotCorners) {
+                err = "device inspection: a Voronoi cell has more planes or corners than its slot holds";
+                return false;
+            }
+            if ((np && !hip_ok(hipMemcpy(cplanes + (size_t)v * 4 * kSlotPlanes, P.data(), sizeof(double) * P.size(),
+                                         hipMemcpyHostToDevice), "upload")) ||
+                (nt && !hip_ok(hipMemcpy(cpos + (size_t)v * 3 * kSlotCorners, X.data(), sizeof(double) * X.size(),
+                                         hipMemcpyHostToDevice), "upload")) ||
+                !hip_ok(hipMemcpy(cnp + v, &np, sizeof(np), hipMemcpyHostToDevice), "upload") ||
+                !hip_ok(hipMemcpy(cnt + v, &nt, sizeof(nt), hipMemcpyHostToDevice), "upload"))
+                return false;
+        }
+    }
+    out.t_cells = since(t0);
+
+    // 2. filter + flooding of every primitive
+    t0 = Clock::now();
+    {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_flood, block, 0) != hipSuccess || per_cu < 1)
+            per_cu = 8;
+        const int64_t grid = std::min<int64_t>(in.nprim, (int64_t)cus * per_cu);
+        k_flood<<<(unsigned)grid, block, 0, 0>>>(
+            in.nprim, (const FloodPrim*)(d + off[0]), (const double*)(d + off[1]), dVd, dnb_off, dnb, cnp, cplanes,
+            cnt, cpos, ddom, (FloodRec*)(d + off[11]), rec_cap, (int64_t*)(d + off[12]), counters,
+            in.visit_cap > 0 && in.visit_cap < kQueueCap ? in.visit_cap : kQueueCap);
+        if (!hip_ok(hipGetLastError(), "launch")) return false;
+        if (!hip_ok(hipDeviceSynchronize(), "kernel")) return false;
+    }
     out.t_kernel = since(t0);
     t0 = Clock::now();
     Counters c;
-    if (!hip_ok(hipMemcpy(&c, d + off[kParts + 2], sizeof(c), hipMemcpyDeviceToHost), "download")) return false;
+    if (!hip_ok(hipMemcpy(&c, counters, sizeof(c), hipMemcpyDeviceToHost), "download")) return false;
     if (c.recs > rec_cap) {
         err = "device inspection: more table entries than the record buffer holds";
         return false;
     }
     out.recs.resize((size_t)c.recs);
     out.redo.resize((size_t)c.redo);
-    if (c.recs && !hip_ok(hipMemcpy(out.recs.data(), d + off[kParts], sizeof(FloodRec) * c.recs,
+    if (c.recs && !hip_ok(hipMemcpy(out.recs.data(), d + off[11], sizeof(FloodRec) * c.recs,
                                     hipMemcpyDeviceToHost), "download"))
         return false;
-    if (c.redo && !hip_ok(hipMemcpy(out.redo.data(), d + off[kParts + 1], sizeof(int64_t) * c.redo,
+    if (c.redo && !hip_ok(hipMemcpy(out.redo.data(), d + off[12], sizeof(int64_t) * c.redo,
                                     hipMemcpyDeviceToHost), "download"))
         return false;
     out.tests = (int64_t)c.tests;

@@ -173,6 +173,7 @@ p2m_status p2m_precompute(p2m_mesh* m, const p2m_build_opts* opts, p2m_build_sta
         st.t_dev_kernel = s.ts.t_dev_kernel;
         st.t_dev_download = s.ts.t_dev_download;
         st.device_redo = s.ts.device_redo;
+        st.device_cells_back = s.ts.device_cells_back;
     }
     return P2M_OK;
 }
