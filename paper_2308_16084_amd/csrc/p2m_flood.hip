@@ -1,5 +1,6 @@
-// Device inspection: the convexity filter (Theorems 5 and 6) and flooding
-// (Algorithm 1) of every primitive, one primitive per wavefront.
+// Device preprocessing: the Voronoi cell of every vertex (from its Delaunay
+// neighbours), then the convexity filter (Theorems 5 and 6) and flooding
+// (Algorithm 1) of every primitive, one vertex or primitive per wavefront.
 //
 // The arithmetic is the host builder's, operation for operation, in FP64,
 // and this file is compiled without contraction (no fused multiply-adds), so
