@@ -24,10 +24,11 @@ struct FloodPrim {
     int64_t id;      // edge or face id
 };
 
-// Builds the Voronoi cell of vertex v on the host (the planes (n, off) that
-// bound a corner, 4 doubles each, and the corners, 3 doubles each); returns
-// the number of cuts it had to skip.
-using HostCellFn = std::function<int64_t(int64_t v, std::vector<double>& planes, std::vector<double>& pos)>;
+// Builds the Voronoi cells of vertices vs on the host (for each, the planes
+// (n, off) that bound a corner, 4 doubles each, and the corners, 3 doubles
+// each); returns the number of cuts it had to skip.
+using HostCellFn = std::function<int64_t(const std::vector<int64_t>& vs, std::vector<std::vector<double>>& planes,
+                                         std::vector<std::vector<double>>& pos)>;
 
 struct FloodInput {
     int64_t nv = 0, nprim = 0;
@@ -62,8 +63,7 @@ struct FloodResult {
 };
 
 // Builds every vertex's Voronoi cell and then runs the inspection of every
-// primitive on the current HIP device.  False (with err) on a HIP error or a
-// host-built cell too large for its slot.
+// primitive on the current HIP device.  False (with err) on a HIP error.
 bool device_flood(const FloodInput& in, FloodResult& out, std::string& err);
 
 }  // namespace p2m

@@ -463,12 +463,24 @@ bool inspect_on_device(const MeshData& m, const CellStore& cs, const Table& t, c
     in.Vd = m.Vd.data();
     in.nb_off = t.nb_off.data();
     in.nb = t.nb.data();
-    in.host_cell = [&](int64_t v, std::vector<double>& P, std::vector<double>& X) -> int64_t {
-        ConvexCell cell;
-        std::vector<std::pair<double, int32_t>> order;
-        const int64_t sk = build_cell(m, t, v, blo, bhi, o.tau, cell, order);
-        std::vector<uint16_t> tris;
-        cell.save(P, tris, X);
+    in.host_cell = [&](const std::vector<int64_t>& vs, std::vector<std::vector<double>>& P,
+                       std::vector<std::vector<double>>& X) -> int64_t {
+        const int64_t n = (int64_t)vs.size();
+        P.assign((size_t)n, {});
+        X.assign((size_t)n, {});
+        int64_t sk = 0;
+#pragma omp parallel num_threads(nth) reduction(+ : sk)
+        {
+            ConvexCell cell;
+            std::vector<std::pair<double, int32_t>> order;
+            std::vector<uint16_t> tris;
+#pragma omp for schedule(dynamic, 16)
+            for (int64_t k = 0; k < n; ++k) {
+                sk += build_cell(m, t, vs[(size_t)k], blo, bhi, o.tau, cell, order);
+                tris.clear();
+                cell.save(P[(size_t)k], tris, X[(size_t)k]);
+            }
+        }
         return sk;
     };
     in.prims = prims.data();

@@ -32,10 +32,13 @@ constexpr int kPlaneCap = 128; // planes of a polytope (ids fit in 8 bits)
 constexpr int kWaveCorners = 64;  // corners of a polytope: one per lane
 constexpr int kQueueCap = 512; // vertices one flood may visit
 constexpr int kHashCap = 1024; // open-addressing set over them (power of two)
-// Each vertex's cell in a fixed slot: at most kSlotPlanes planes (n, off)
-// and kSlotCorners corners.
-constexpr int kSlotPlanes = 128;
-constexpr int kSlotCorners = 128;
+// A cell built on the device sits in its vertex's fixed slot: at most
+// kSlotPlanes planes (n, off; the 6 box planes and one per neighbour) and
+// kSlotCorners corners.  Cells built on the host, of any size, sit in a
+// second allocation; a vertex's plane and corner offsets (in planes and in
+// corners) are negative there: -(offset + 1).
+constexpr int kSlotPlanes = 72;
+constexpr int kSlotCorners = 64;
 
 enum { UNCHANGED = 0, CLIPPED = 1, EMPTY = 2, SKIPPED = 3, OVERFLOW = 4 };
 
@@ -473,7 +476,8 @@ __global__ __launch_bounds__(64) void k_cells(int64_t nv, const double* __restri
                                               const int64_t* __restrict__ nb_off, const int32_t* __restrict__ nb,
                                               const double* __restrict__ dom, double* __restrict__ slot_planes,
                                               double* __restrict__ slot_pos, int32_t* __restrict__ cnp_of,
-                                              int32_t* __restrict__ cnt_of, int64_t* __restrict__ back,
+                                              int32_t* __restrict__ cnt_of, int64_t* __restrict__ pl_at,
+                                              int64_t* __restrict__ co_at, int64_t* __restrict__ back,
                                               CellCounters* __restrict__ cc) {
     __shared__ WaveLds L;
     const int l = wlane();
@@ -577,11 +581,27 @@ __global__ __launch_bounds__(64) void k_cells(int64_t nv, const double* __restri
         if (l == 0) {
             cnp_of[v] = W.empty ? 0 : __popcll(u0) + __popcll(u1);
             cnt_of[v] = W.empty ? 0 : W.nt;
+            pl_at[v] = v * kSlotPlanes;
+            co_at[v] = v * kSlotCorners;
         }
         skipped_all += (unsigned long long)skipped;
         __syncthreads();
     }
     if (l == 0) atomicAdd(&cc->skipped, skipped_all);
+}
+
+// Places of the cells built on the host: vertex, plane and corner offsets
+// (already negative) and counts.
+__global__ __launch_bounds__(256) void k_set_cells(int64_t n, const int64_t* __restrict__ meta,
+                                                   int64_t* __restrict__ pl_at, int64_t* __restrict__ co_at,
+                                                   int32_t* __restrict__ cnp_of, int32_t* __restrict__ cnt_of) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t v = meta[5 * i];
+    pl_at[v] = meta[5 * i + 1];
+    co_at[v] = meta[5 * i + 2];
+    cnp_of[v] = (int32_t)meta[5 * i + 3];
+    cnt_of[v] = (int32_t)meta[5 * i + 4];
 }
 
 // Each wavefront (a block of 64 lanes) takes primitives from a shared counter
@@ -595,6 +615,9 @@ __global__ __launch_bounds__(64) void k_flood(int64_t nprim, const FloodPrim* __
                                                    const int32_t* __restrict__ cnp_of,
                                                    const double* __restrict__ cplanes,
                                                    const int32_t* __restrict__ cnt_of, const double* __restrict__ cpos,
+                                                   const int64_t* __restrict__ pl_at, const int64_t* __restrict__ co_at,
+                                                   const double* __restrict__ xplanes,
+                                                   const double* __restrict__ xpos,
                                                    const double* __restrict__ dom, FloodRec* __restrict__ recs,
                                                    uint64_t rec_cap, int64_t* __restrict__ redo,
                                                    Counters* __restrict__ cnt, int visit_cap) {
@@ -648,7 +671,8 @@ __global__ __launch_bounds__(64) void k_flood(int64_t nprim, const FloodPrim* __
             const int32_t w = __builtin_amdgcn_readfirstlane(L.queue[head]);
             bool own = false;
             for (int k = 0; k < p.nverts; ++k) own |= (p.verts[k] == w);
-            const double* cellp = cplanes + (int64_t)w * (4 * kSlotPlanes);
+            const int64_t pa = pl_at[w];
+            const double* cellp = pa >= 0 ? cplanes + 4 * pa : xplanes + 4 * (-pa - 1);
             const int cnp = cnp_of[w];
             if (cnp > kPlaneCap - 8 - 8) {
                 ovf = true;
@@ -666,10 +690,12 @@ __global__ __launch_bounds__(64) void k_flood(int64_t nprim, const FloodPrim* __
                 const double* X = Vd + 3 * (int64_t)w;
                 const double Wv[3] = {X[0], X[1], X[2]};
                 // |x-w| - Dist(x,p) is convex: the whole cell keeping w out settles it
-                const int64_t t0 = (int64_t)w * kSlotCorners, t1 = t0 + cnt_of[w];
+                const int64_t ca = co_at[w];
+                const double* cposw = ca >= 0 ? cpos + 3 * ca : xpos + 3 * (-ca - 1);
+                const int64_t t0 = 0, t1 = cnt_of[w];
                 bool all_far = true;
                 for (int64_t t = t0; t < t1 && all_far; t += 64) {
-                    const bool far = t + l >= t1 || far_enough(p, Wv, cpos + 3 * (t + l), c.slack);
+                    const bool far = t + l >= t1 || far_enough(p, Wv, cposw + 3 * (t + l), c.slack);
                     all_far = __ballot(!far) == 0ull;
                 }
                 hit = false;
@@ -786,6 +812,8 @@ bool device_flood(const FloodInput& in, FloodResult& out, std::string& err) {
         {nullptr, sizeof(FloodRec) * rec_cap},              // 11: table entries
         {nullptr, sizeof(int64_t) * (size_t)in.nprim},      // 12: primitives handed back
         {nullptr, 256},                                     // 13: counters
+        {nullptr, sizeof(int64_t) * nv},                    // 14: plane offset of each cell
+        {nullptr, sizeof(int64_t) * nv},                    // 15: corner offset of each cell
     };
     constexpr int kParts = sizeof(parts) / sizeof(parts[0]);
     size_t off[kParts];
@@ -813,6 +841,11 @@ bool device_flood(const FloodInput& in, FloodResult& out, std::string& err) {
     int32_t* cnp = (int32_t*)(d + off[8]);
     int32_t* cnt = (int32_t*)(d + off[9]);
     int64_t* cback = (int64_t*)(d + off[10]);
+    int64_t* pl_at = (int64_t*)(d + off[14]);
+    int64_t* co_at = (int64_t*)(d + off[15]);
+    DevBuf xbuf;  // cells built on the host
+    const double* xplanes = cplanes;
+    const double* xpos = cpos;
     Counters* counters = (Counters*)(d + off[13]);
     CellCounters* ccount = (CellCounters*)(d + off[13] + 128);
     int dev = 0, cus = 256;
@@ -827,8 +860,8 @@ bool device_flood(const FloodInput& in, FloodResult& out, std::string& err) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cells, block, 0) != hipSuccess || per_cu < 1)
             per_cu = 8;
         const int64_t grid = std::min<int64_t>(in.nv, (int64_t)cus * per_cu);
-        k_cells<<<(unsigned)grid, block, 0, 0>>>(in.nv, dVd, dnb_off, dnb, ddom, cplanes, cpos, cnp, cnt, cback,
-                                                 ccount);
+        k_cells<<<(unsigned)grid, block, 0, 0>>>(in.nv, dVd, dnb_off, dnb, ddom, cplanes, cpos, cnp, cnt, pl_at,
+                                                 co_at, cback, ccount);
         if (!hip_ok(hipGetLastError(), "launch")) return false;
         if (!hip_ok(hipDeviceSynchronize(), "cell kernel")) return false;
         CellCounters cc;
@@ -839,23 +872,44 @@ bool device_flood(const FloodInput& in, FloodResult& out, std::string& err) {
         if (cc.back && !hip_ok(hipMemcpy(back.data(), cback, sizeof(int64_t) * cc.back, hipMemcpyDeviceToHost),
                                "download"))
             return false;
-        std::vector<double> P, X;
-        for (int64_t v : back) {
-            P.clear();
-            X.clear();
-            out.cells_skipped += in.host_cell(v, P, X);
-            const int32_t np = (int32_t)(P.size() / 4), nt = (int32_t)(X.size() / 3);
-            if (np > kSlotPlanes || nt > kSlotCorners) {
-                err = "device inspection: a Voronoi cell has more planes or corners than its slot holds";
-                return false;
+        if (!back.empty()) {
+            // the cells handed back, built on the host, packed into a second
+            // allocation; their places and counts scattered by k_set_cells
+            std::vector<double> XP, XX;
+            std::vector<std::vector<double>> PS, XS;
+            out.cells_skipped += in.host_cell(back, PS, XS);
+            std::vector<int64_t> meta;
+            meta.reserve(5 * back.size());
+            for (size_t k = 0; k < back.size(); ++k) {
+                const int64_t v = back[k];
+                const std::vector<double>& P = PS[k];
+                const std::vector<double>& X = XS[k];
+                meta.push_back(v);
+                meta.push_back(-(int64_t)(XP.size() / 4) - 1);
+                meta.push_back(-(int64_t)(XX.size() / 3) - 1);
+                meta.push_back((int64_t)(P.size() / 4));
+                meta.push_back((int64_t)(X.size() / 3));
+                XP.insert(XP.end(), P.begin(), P.end());
+                XX.insert(XX.end(), X.begin(), X.end());
             }
-            if ((np && !hip_ok(hipMemcpy(cplanes + (size_t)v * 4 * kSlotPlanes, P.data(), sizeof(double) * P.size(),
-                                         hipMemcpyHostToDevice), "upload")) ||
-                (nt && !hip_ok(hipMemcpy(cpos + (size_t)v * 3 * kSlotCorners, X.data(), sizeof(double) * X.size(),
-                                         hipMemcpyHostToDevice), "upload")) ||
-                !hip_ok(hipMemcpy(cnp + v, &np, sizeof(np), hipMemcpyHostToDevice), "upload") ||
-                !hip_ok(hipMemcpy(cnt + v, &nt, sizeof(nt), hipMemcpyHostToDevice), "upload"))
+            const size_t bp = (sizeof(double) * std::max<size_t>(4, XP.size()) + 255) / 256 * 256;
+            const size_t bx = (sizeof(double) * std::max<size_t>(3, XX.size()) + 255) / 256 * 256;
+            const size_t bm = sizeof(int64_t) * meta.size();
+            if (!hip_ok(hipMalloc(&xbuf.p, bp + bx + bm), "hipMalloc")) return false;
+            char* x = (char*)xbuf.p;
+            if ((!XP.empty() && !hip_ok(hipMemcpy(x, XP.data(), sizeof(double) * XP.size(), hipMemcpyHostToDevice),
+                                        "upload")) ||
+                (!XX.empty() && !hip_ok(hipMemcpy(x + bp, XX.data(), sizeof(double) * XX.size(),
+                                                  hipMemcpyHostToDevice), "upload")) ||
+                !hip_ok(hipMemcpy(x + bp + bx, meta.data(), bm, hipMemcpyHostToDevice), "upload"))
                 return false;
+            xplanes = (const double*)x;
+            xpos = (const double*)(x + bp);
+            const int64_t nb_back = (int64_t)back.size();
+            k_set_cells<<<(unsigned)((nb_back + 255) / 256), 256, 0, 0>>>(nb_back, (const int64_t*)(x + bp + bx),
+                                                                        pl_at, co_at, cnp, cnt);
+            if (!hip_ok(hipGetLastError(), "launch")) return false;
+            if (!hip_ok(hipDeviceSynchronize(), "cell placement")) return false;
         }
     }
     out.t_cells = since(t0);
@@ -869,7 +923,8 @@ bool device_flood(const FloodInput& in, FloodResult& out, std::string& err) {
         const int64_t grid = std::min<int64_t>(in.nprim, (int64_t)cus * per_cu);
         k_flood<<<(unsigned)grid, block, 0, 0>>>(
             in.nprim, (const FloodPrim*)(d + off[0]), (const double*)(d + off[1]), dVd, dnb_off, dnb, cnp, cplanes,
-            cnt, cpos, ddom, (FloodRec*)(d + off[11]), rec_cap, (int64_t*)(d + off[12]), counters,
+            cnt, cpos, pl_at, co_at, xplanes, xpos, ddom, (FloodRec*)(d + off[11]), rec_cap,
+            (int64_t*)(d + off[12]), counters,
             in.visit_cap > 0 && in.visit_cap < kQueueCap ? in.visit_cap : kQueueCap);
         if (!hip_ok(hipGetLastError(), "launch")) return false;
         if (!hip_ok(hipDeviceSynchronize(), "kernel")) return false;

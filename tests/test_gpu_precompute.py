@@ -89,3 +89,15 @@ def test_device_built_mesh_queries():
     om = oracle.OracleMesh(w.V, w.F)
     ans = om.query(w.Q)
     assert check_answers(om, w.Q, ans, out["prim"], out["closest"], out["dist"]) == []
+
+
+def test_device_table_equals_host_with_host_built_cells():
+    """A level-6 C2-style sphere (40,962 vertices): some Voronoi cells have
+    more than 64 corners and are built on the host into the second cell
+    allocation; the table must still equal the host build's."""
+    print("case: device inspection, host-built cells", flush=True)
+    w = C.c2(1000, level=6)
+    h, sh, d, sd = _tables(w.V, w.F, None, (w.domain_lo, w.domain_hi))
+    print("cells built on the host:", sd["device_cells_back"], flush=True)
+    assert sd["device_cells_back"] > 0
+    _same(h, sh, d, sd)
