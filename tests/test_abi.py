@@ -62,3 +62,39 @@ def test_errors_without_device():
     assert lib().p2m_mesh_create(None, 3, None, 1, ctypes.byref(ctypes.c_void_p())) == -1
     with pytest.raises(P.P2MError):
         P.Mesh(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32))
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures have the size and field offsets the C
+    compiler gives the header's structs."""
+    import ctypes
+
+    from paper_2308_16084_amd import _lib
+    pairs = {"p2m_build_opts": _lib.BuildOpts, "p2m_build_stats": _lib.BuildStats, "p2m_query_opts": _lib.QueryOpts}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "p2m.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'    printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU; --gpus above 1 exits with a message."""
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
