@@ -58,6 +58,9 @@ __host__ __device__ inline MeshView arena_view(const BatchMesh& d, const KdNode*
     v.nboff = nboff + d.nboff;
     v.nbrec = nbrec + d.nbrec;
     v.seed = seed + d.seed;
+    v.seed2 = nullptr;  // one grid per mesh in the batch arena
+    v.grid2 = 0;
+    for (int k = 0; k < 3; ++k) v.glo2[k] = v.gscale2[k] = v.ghi2[k] = 0.f;
     v.frec = frec + d.frec;
     v.erec = erec + d.erec;
     v.mu = d.mu;

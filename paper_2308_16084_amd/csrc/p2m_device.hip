@@ -253,6 +253,7 @@ void pack_mesh(MeshState& s) {
         d[3] = bits_as_float(w);
     }
     s.pk_seed.clear();
+    s.pk_seed2.clear();
     s.packed = true;
 }
 
@@ -285,6 +286,34 @@ MeshView host_view(const MeshState& s) {
         v.glo[k] = v.dlo[k];
         v.gscale[k] = (float)((double)v.grid / ((double)v.dhi[k] - (double)v.dlo[k]));
     }
+    // the finer grid: the mesh's box grown by 5 % of its diagonal, when D
+    // is more than twice as long on some axis (for a D just around the mesh
+    // the second grid costs more in cache than it saves in walk steps)
+    v.seed2 = s.pk_seed2.empty() ? nullptr : (const float4*)s.pk_seed2.data();
+    v.grid2 = 0;
+    {
+        double diag = 0.0;
+        for (int k = 0; k < 3; ++k) diag += (s.m.hi[k] - s.m.lo[k]) * (s.m.hi[k] - s.m.lo[k]);
+        const double grow = 0.05 * std::sqrt(diag);
+        bool wide = false;
+        double flo[3], fhi[3];
+        for (int k = 0; k < 3; ++k) {
+            flo[k] = s.m.lo[k] - grow;
+            fhi[k] = s.m.hi[k] + grow;
+            if (!(fhi[k] > flo[k])) fhi[k] = flo[k] + 1.0;
+            wide |= (s.dhi[k] - s.dlo[k]) > 2.0 * (fhi[k] - flo[k]);
+        }
+        if (wide) {
+            v.grid2 = walk_grid_side(s.m.nv);
+            for (int k = 0; k < 3; ++k) {
+                v.glo2[k] = (float)flo[k];
+                v.gscale2[k] = (float)((double)v.grid2 / (fhi[k] - flo[k]));
+                v.ghi2[k] = (float)fhi[k];
+            }
+        } else {
+            for (int k = 0; k < 3; ++k) v.glo2[k] = v.gscale2[k] = v.ghi2[k] = 0.f;
+        }
+    }
     v.nboff = s.pk_nboff.data();
     v.nbrec = (const float4*)s.pk_nbrec.data();
     return v;
@@ -308,6 +337,7 @@ MeshView device_view(const MeshState& s) {
     v.nboff = (const uint32_t*)s.dev.nboff;
     v.nbrec = (const float4*)s.dev.nbrec;
     v.seed = (const float4*)s.dev.seed;
+    v.seed2 = (const float4*)s.dev.seed2;
     return v;
 }
 
@@ -461,10 +491,25 @@ __global__ __launch_bounds__(256) void k_seed_grid(MeshView m, float4* __restric
 
 // Host copy of the seed grid for the host query, same definition as the
 // device kernel above.
+static void host_seed_grid_one(MeshState& s, int nt, const MeshView& v, std::vector<float>& out);
+
 static void host_seed_grid(MeshState& s, int nt) {
-    const MeshView v = host_view(s);
+    MeshView v = host_view(s);
+    host_seed_grid_one(s, nt, v, s.pk_seed);
+    if (v.grid2 > 0) {
+        v.grid = v.grid2;
+        for (int k = 0; k < 3; ++k) {
+            v.glo[k] = v.glo2[k];
+            v.gscale[k] = v.gscale2[k];
+        }
+        host_seed_grid_one(s, nt, v, s.pk_seed2);
+    }
+}
+
+static void host_seed_grid_one(MeshState& s, int nt, const MeshView& v, std::vector<float>& out) {
+    (void)s;
     const int64_t G = v.grid, cells = G * G * G;
-    s.pk_seed.assign((size_t)(4 * cells), 0.f);
+    out.assign((size_t)(4 * cells), 0.f);
     std::atomic<int64_t> cursor{0};
     auto work = [&]() {
         for (;;) {
@@ -477,7 +522,7 @@ static void host_seed_grid(MeshState& s, int nt) {
                 const float cz = v.glo[2] + ((float)iz + 0.5f) / v.gscale[2];
                 uint64_t visits = 0;
                 const Nearest b = kdt_nearest(v.node, v.nv, cx, cy, cz, visits);
-                float* d = &s.pk_seed[(size_t)(4 * i)];
+                float* d = &out[(size_t)(4 * i)];
                 d[0] = b.px;
                 d[1] = b.py;
                 d[2] = b.pz;
@@ -812,10 +857,12 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
     const size_t b_nboff = sizeof(uint32_t) * s.pk_nboff.size();
     const size_t b_nb = sizeof(float) * std::max<size_t>(4, s.pk_nbrec.size());
     const size_t b_seed = sizeof(float4) * (size_t)G * (size_t)G * (size_t)G;
+    const MeshView hv = host_view(s);
+    const size_t b_seed2 = sizeof(float4) * (size_t)hv.grid2 * (size_t)hv.grid2 * (size_t)hv.grid2;
     const size_t b_frec = sizeof(float) * s.pk_frec.size();
     const size_t b_erec = sizeof(float) * std::max<size_t>(1, s.pk_erec.size());
     const size_t total = up(b_node) + up(b_off) + up(b_ent) + up(b_seg) + up(b_tri) + up(b_fe) + up(b_nboff) +
-                         up(b_nb) + up(b_seed) + up(b_frec) + up(b_erec);
+                         up(b_nb) + up(b_seed) + up(b_seed2) + up(b_frec) + up(b_erec);
     void* base = nullptr;
     hipError_t e = hipMalloc(&base, total);
     if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? P2M_ERR_OOM : P2M_ERR_HIP, "device arena allocation");
@@ -841,6 +888,8 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
     p += up(b_nb);
     s.dev.seed = p;
     p += up(b_seed);
+    s.dev.seed2 = b_seed2 ? p : nullptr;
+    p += up(b_seed2);
     s.dev.frec = p;
     p += up(b_frec);
     s.dev.erec = p;
@@ -865,6 +914,16 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
         }
     }
     e = launch_seed_grid(device_view(s), (float4*)s.dev.seed, st);
+    if (e == hipSuccess && hv.grid2 > 0) {
+        // the finer grid: the same kernel on a view with that grid's frame
+        MeshView fv = device_view(s);
+        fv.grid = fv.grid2;
+        for (int k = 0; k < 3; ++k) {
+            fv.glo[k] = fv.glo2[k];
+            fv.gscale[k] = fv.gscale2[k];
+        }
+        e = launch_seed_grid(fv, (float4*)s.dev.seed2, st);
+    }
     if (e != hipSuccess) {
         device_release(s);
         return fail(P2M_ERR_HIP, std::string("seed grid kernel: ") + hipGetErrorString(e));

@@ -37,6 +37,7 @@ struct DeviceMesh {
     void* nboff = nullptr;
     void* nbrec = nullptr;
     void* seed = nullptr;
+    void* seed2 = nullptr;  // finer grid over the mesh's box (may be absent)
     // list-scan forms: frec float4[3nf], erec float4[2ne]
     void* frec = nullptr;
     void* erec = nullptr;
@@ -67,6 +68,7 @@ struct MeshState {
     std::vector<uint32_t> pk_nboff;              // 32-bit neighbour offsets
     std::vector<float> pk_nbrec;                 // 4 floats per neighbour entry (position, id)
     std::vector<float> pk_seed;                  // host copy of the seed grid, 4 floats per cell (host query only)
+    std::vector<float> pk_seed2;                 // and of the finer grid
     std::vector<float> pk_frec, pk_erec;         // list-scan forms: 12 floats per face, 8 per edge
     std::vector<uint32_t> pk_vhead;              // list heads: 8 words per vertex
     std::vector<uint32_t> pk_lent;               // list entries: id + 5-bit box, 2 words each, runs padded

@@ -69,6 +69,11 @@ struct MeshView {
     const float4* seed;     // [grid^3] nearest vertex of each grid-cell centre (position, id bits)
     int32_t grid;
     float glo[3], gscale[3];  // cell = floor((q - glo) * gscale), clamped
+    // finer seed grid over the mesh's box, grown (grid2 = 0: none), for the
+    // queries inside it when D is much larger than the mesh
+    const float4* seed2;
+    int32_t grid2;
+    float glo2[3], gscale2[3], ghi2[3];
 };
 
 P2M_HD int depth_of(int32_t node) { return 31 - __builtin_clz((unsigned)(node + 1)); }
@@ -192,18 +197,22 @@ P2M_HD Nearest kdt_nearest(const KdNode* __restrict__ node, int32_t n, float qx,
 // neighbour of v, which is then closer.  The order is strict, so the walk
 // cannot cycle; `cap` bounds it regardless.
 P2M_HD Nearest voronoi_walk(const MeshView& m, float qx, float qy, float qz, uint64_t& visits, uint64_t& steps) {
-    const int32_t G = m.grid;
+    // the finer grid when q is inside its box (the walk is exact from any seed)
+    const bool fine = m.grid2 > 0 && qx >= m.glo2[0] && qx < m.ghi2[0] && qy >= m.glo2[1] && qy < m.ghi2[1] &&
+                      qz >= m.glo2[2] && qz < m.ghi2[2];
+    const int32_t G = fine ? m.grid2 : m.grid;
     auto cell = [&](float x, float lo, float s) {
         const float t = (x - lo) * s;
         return t >= 0.f ? (t < (float)G ? (int32_t)t : G - 1) : 0;
     };
-    const int32_t c = (cell(qz, m.glo[2], m.gscale[2]) * G + cell(qy, m.glo[1], m.gscale[1])) * G +
-                      cell(qx, m.glo[0], m.gscale[0]);
+    const int32_t c = (cell(qz, fine ? m.glo2[2] : m.glo[2], fine ? m.gscale2[2] : m.gscale[2]) * G +
+                       cell(qy, fine ? m.glo2[1] : m.glo[1], fine ? m.gscale2[1] : m.gscale[1])) * G +
+                      cell(qx, fine ? m.glo2[0] : m.glo[0], fine ? m.gscale2[0] : m.gscale[0]);
     Nearest b;
     b.d2 = INFINITY;
     b.px = b.py = b.pz = 0.f;
     b.vid = -1;
-    float4 p = m.seed[c];
+    float4 p = (fine ? m.seed2 : m.seed)[c];
     {
         const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
         consider(b, qx, qy, qz, dx * dx + dy * dy + dz * dz, p);
