@@ -370,6 +370,21 @@ __global__ void k_morton(const float* __restrict__ q, int64_t n, float lox, floa
     vals[i] = (int32_t)i;
 }
 
+// Steps of a vertex's two list loops (edge then face entries, four a step).
+__device__ __forceinline__ int list_steps(const MeshView& m, int32_t vid) {
+    const uint4 h = m.vhead[2 * vid];
+    return (int)(((h.y - h.x + 3u) >> 2) + ((h.z - h.y + 3u) >> 2));
+}
+
+// Regrouping after the nearest-vertex step: a wavefront runs each list loop
+// as long as its longest lane, and lanes of one wavefront hold lists of
+// quite different lengths.  The block sorts its queries by the steps their
+// lists take (a counting sort over kRegroupBins bins in LDS) and each lane
+// takes the query of its sorted place, so a wavefront holds lists of nearly
+// one length.  Only which lane answers a query changes.
+constexpr int kRegroupBins = 64;
+constexpr size_t regroup_lds_bytes(int block) { return sizeof(uint32_t) * (kRegroupBins + 9 * (size_t)block); }
+
 // stage (ordered batches): query i's answer goes to stage[S*i .. S*i+S-1]
 // (S = 2, or 3 with the backward extras) as (prim, closest), (dist, status,
 // w0, w1), (w2, pv0, pv1, pv2) -- one aligned record per query instead of
@@ -383,8 +398,10 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const floa
                                                 float* __restrict__ dist, uint8_t* __restrict__ status,
                                                 float* __restrict__ bary, int32_t* __restrict__ pvid,
                                                 float4* __restrict__ stage) {
+    extern __shared__ uint32_t lds[];
     const int64_t tile = xcd_tile(blockIdx.x, chunk);
-    const int64_t j = tile * blockDim.x + threadIdx.x;
+    const int t = threadIdx.x, B = blockDim.x;
+    const int64_t j = tile * B + t;
     int64_t i = j < n ? (perm ? (int64_t)perm[j] : j) : -1;
     if (i >= n) i = -1;
     float qx = 0.f, qy = 0.f, qz = 0.f;
@@ -393,11 +410,52 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const floa
         qy = q[3 * i + 1];
         qz = q[3 * i + 2];
     }
-    const bool fin = finite3(qx, qy, qz);
+    bool fin = finite3(qx, qy, qz);
     ScanCounters c;
     // with WALK_WAVE every lane of the wavefront takes part in the shared walk
-    const Nearest nv = nearest_vertex<kWalk>(m, qx, qy, qz, i >= 0 && fin, c.nodes, c.steps);
+    Nearest nv = nearest_vertex<kWalk>(m, qx, qy, qz, i >= 0 && fin, c.nodes, c.steps);
+
+    // regroup the block's queries by list length (see list_steps)
+    uint32_t* hist = lds;
+    float* col = (float*)(lds + kRegroupBins);  // qx qy qz d2 px py pz, B each
+    int32_t* icol = (int32_t*)(col + 7 * B);    // query index, vertex
+    const int bin = (i >= 0 && fin) ? min(list_steps(m, nv.vid), kRegroupBins - 1) : 0;
+    if (t < kRegroupBins) hist[t] = 0;
+    __syncthreads();
+    const uint32_t rank = atomicAdd(&hist[bin], 1u);
+    __syncthreads();
+    if (t < kRegroupBins) {  // the first wavefront: inclusive scan of the bins
+        uint32_t x = hist[t];
+#pragma unroll
+        for (int d = 1; d < kRegroupBins; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d);
+            if (t >= d) x += y;
+        }
+        hist[t] = x;
+    }
+    __syncthreads();
+    const uint32_t pos = (bin ? hist[bin - 1] : 0u) + rank;
+    col[pos] = qx;
+    col[B + pos] = qy;
+    col[2 * B + pos] = qz;
+    col[3 * B + pos] = nv.d2;
+    col[4 * B + pos] = nv.px;
+    col[5 * B + pos] = nv.py;
+    col[6 * B + pos] = nv.pz;
+    icol[pos] = (int32_t)i;
+    icol[B + pos] = nv.vid;
+    __syncthreads();
+    i = icol[t];
     if (i < 0) return;
+    qx = col[t];
+    qy = col[B + t];
+    qz = col[2 * B + t];
+    nv.d2 = col[3 * B + t];
+    nv.px = col[4 * B + t];
+    nv.py = col[5 * B + t];
+    nv.pz = col[6 * B + t];
+    nv.vid = icol[B + t];
+    fin = finite3(qx, qy, qz);
     uint8_t st = fin ? domain_status(m, qx, qy, qz) : (uint8_t)2;
     const Answer a = fin ? p2m_answer(m, qx, qy, qz, nv, c) : nonfinite_answer();
     if (stage) {
@@ -978,7 +1036,8 @@ p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, flo
     const unsigned grid = (unsigned)(chunk * kXcds);
     const int walk = pick_walk(traversal);
 #define P2M_LAUNCH_QUERY(X, W) \
-    k_query<X, W><<<grid, block, 0, st>>>(v, q, perm, n, chunk, prim, closest, dist, status, bary, pvid, stage)
+    k_query<X, W><<<grid, block, regroup_lds_bytes(block), st>>>(v, q, perm, n, chunk, prim, closest, dist, status, \
+                                                                 bary, pvid, stage)
     if (bary) {
         if (walk == WALK_WAVE) P2M_LAUNCH_QUERY(true, WALK_WAVE);
         else if (walk == WALK_VORONOI) P2M_LAUNCH_QUERY(true, WALK_VORONOI);
