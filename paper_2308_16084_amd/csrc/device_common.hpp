@@ -72,10 +72,12 @@ constexpr int64_t kRadixTile = kRadixThreads * kRadixItems;
 
 RadixPlan radix_plan(int64_t n);
 RadixBuffers radix_buffers(const RadixPlan& p, void* scratch);
-// Stable sort of keys[0]/vals[0] by bits [lo_bit, hi_bit) of the key (8 bits
-// per pass; the span is a multiple of 8); returns which buffer (0/1) holds
-// the result.  All work is enqueued on `st`.
-int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit, hipStream_t st);
+// Stable sort of the positions 0..n-1 by bits [lo_bit, hi_bit) of keys[0]
+// (8 bits per pass; the span is a multiple of 8): vals[r] receives the
+// permutation (the input position of each sorted place) and, with
+// keep_keys, keys[r] the sorted keys, where r (0/1) is returned; vals[0] is
+// not read.  All work is enqueued on `st`.
+int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit, bool keep_keys, hipStream_t st);
 // Exclusive prefix sum of a[0..n) in place; sums needs scan_sums_size(n)
 // entries of scratch.
 int64_t scan_sums_size(int64_t n);

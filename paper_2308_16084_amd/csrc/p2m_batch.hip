@@ -22,6 +22,7 @@
 #include "p2m_internal.hpp"
 #include "nearest.hpp"
 #include "query_core.hpp"
+#include "regroup.hpp"
 
 namespace p2m {
 
@@ -131,24 +132,34 @@ namespace {
 
 int64_t up256(int64_t x) { return (x + 255) / 256 * 256; }
 
-__global__ void k_batch_keys(const float* __restrict__ q, int64_t n, const int64_t* __restrict__ qoff, int32_t count,
-                             const BatchMesh* __restrict__ desc, int bits, uint32_t* __restrict__ keys,
-                             int32_t* __restrict__ vals) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    // mesh k with qoff[k] <= i < qoff[k+1]
-    int32_t lo = 0, hi = count;
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (qoff[mid] <= i) lo = mid;
-        else hi = mid;
+__global__ __launch_bounds__(256) void k_batch_keys(const float* __restrict__ q, int64_t n,
+                                                    const int64_t* __restrict__ qoff, int32_t count,
+                                                    const BatchMesh* __restrict__ desc, int bits,
+                                                    uint32_t* __restrict__ keys) {
+    __shared__ int32_t s_mesh;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t i = i0 + threadIdx.x;
+    // mesh k with qoff[k] <= i < qoff[k+1]: a binary search for the block's
+    // first query, then each lane steps over the (few) meshes that begin
+    // before its own query
+    if (threadIdx.x == 0) {
+        int32_t lo = 0, hi = count;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (qoff[mid] <= i0) lo = mid;
+            else hi = mid;
+        }
+        s_mesh = lo;
     }
+    __syncthreads();
+    if (i >= n) return;
+    int32_t lo = s_mesh;
+    while (lo + 1 < count && qoff[lo + 1] <= i) ++lo;
     const BatchMesh& d = desc[lo];
     const float qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
     const uint32_t full = morton30(qx, qy, qz, d.mlo[0], d.mlo[1], d.mlo[2], d.msc[0], d.msc[1], d.msc[2]);
     const uint32_t code = full >> (30 - 3 * bits);  // keep the top `bits` bits per axis
     keys[i] = ((uint32_t)lo << (3 * bits)) | code;
-    vals[i] = (int32_t)i;
 }
 
 __global__ void k_reset(uint32_t* counter) {
@@ -171,41 +182,99 @@ struct Arena {
     const BatchMesh* desc;
 };
 
+// Queries regrouped by list length together (regroup.hpp): `group` rounds
+// of a tile, at most kRegroupSlots queries.
+constexpr int kRegroupSlots = 256;
+int regroup_rounds(int block, int qpl) { return std::max(1, std::min(qpl, kRegroupSlots / block)); }
+// Dynamic LDS: the bins, then per slot 7 floats (q, the nearest vertex's d2
+// and position) and 4 ints (query index, vertex, bin and rank, source slot).
+size_t batch_lds_bytes(int block, int qpl) {
+    return sizeof(uint32_t) * (kRegroupBins + 11 * (size_t)block * (size_t)regroup_rounds(block, qpl));
+}
+
 template <int kWalk>
 __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
-    Arena A, const Tile* __restrict__ tiles, int64_t ntiles, uint32_t* counter, int qpl,
+    Arena A, const Tile* __restrict__ tiles, int64_t ntiles, uint32_t* counter, int qpl, int group,
     const float* __restrict__ q, const int32_t* __restrict__ perm, int64_t n, float4* __restrict__ stage) {
+    extern __shared__ uint32_t lds[];
     __shared__ int64_t s_tile;
+    const int t = threadIdx.x, B = blockDim.x;
+    const int S = B * group;
+    uint32_t* hist = lds;
+    float* col = (float*)(lds + kRegroupBins);  // qx qy qz d2 px py pz, S each
+    int32_t* icol = (int32_t*)(col + 7 * S);    // query index, vertex, bin << 24 | rank, source slot
     for (;;) {
-        if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1u);
+        if (t == 0) s_tile = (int64_t)atomicAdd(counter, 1u);
         __syncthreads();
-        const int64_t t = s_tile;
+        const int64_t tt = s_tile;
         __syncthreads();
-        if (t >= ntiles) break;  // uniform across the workgroup
-        const Tile T = tiles[t];
+        if (tt >= ntiles) break;  // uniform across the workgroup
+        const Tile T = tiles[tt];
         const MeshView v = arena_view(A.desc[T.mesh], A.node, A.vhead, A.lent, A.seg, A.tri, A.fedge, A.nboff, A.nbrec,
                                       A.seed, A.frec, A.erec);
-        for (int r = 0; r < qpl; ++r) {
-            const int64_t local = (int64_t)r * blockDim.x + threadIdx.x;
-            const int64_t j = (int64_t)T.start + local;
-            int64_t i = (local < T.count && j < n) ? (int64_t)perm[j] : -1;
-            if (i >= n) i = -1;
-            float qx = 0.f, qy = 0.f, qz = 0.f;
-            if (i >= 0) {
-                qx = q[3 * i];
-                qy = q[3 * i + 1];
-                qz = q[3 * i + 2];
+        for (int r0 = 0; r0 < qpl; r0 += group) {
+            const int rounds = min(group, qpl - r0);
+            if (t < kRegroupBins) hist[t] = 0;
+            __syncthreads();
+            // nearest vertex of each query of these rounds, kept in LDS
+            for (int r = 0; r < rounds; ++r) {
+                const int64_t local = (int64_t)(r0 + r) * B + t;
+                const int64_t j = (int64_t)T.start + local;
+                int64_t i = (local < T.count && j < n) ? (int64_t)perm[j] : -1;
+                if (i >= n) i = -1;
+                float qx = 0.f, qy = 0.f, qz = 0.f;
+                if (i >= 0) {
+                    qx = q[3 * i];
+                    qy = q[3 * i + 1];
+                    qz = q[3 * i + 2];
+                }
+                const bool fin = finite3(qx, qy, qz);
+                ScanCounters c;
+                // every lane of the wavefront calls this (see nearest_vertex)
+                const Nearest nv = nearest_vertex<kWalk>(v, qx, qy, qz, i >= 0 && fin, c.nodes, c.steps);
+                const int bin = (i >= 0 && fin) ? regroup_bin(v, nv.vid) : 0;
+                const uint32_t rank = atomicAdd(&hist[bin], 1u);
+                const int u = r * B + t;
+                col[u] = qx;
+                col[S + u] = qy;
+                col[2 * S + u] = qz;
+                col[3 * S + u] = nv.d2;
+                col[4 * S + u] = nv.px;
+                col[5 * S + u] = nv.py;
+                col[6 * S + u] = nv.pz;
+                icol[u] = (int32_t)i;
+                icol[S + u] = nv.vid;
+                icol[2 * S + u] = (int32_t)(((uint32_t)bin << 24) | rank);
             }
-            const bool fin = finite3(qx, qy, qz);
-            ScanCounters c;
-            // every lane of the wavefront calls this (see nearest_vertex)
-            const Nearest nv = nearest_vertex<kWalk>(v, qx, qy, qz, i >= 0 && fin, c.nodes, c.steps);
-            if (i >= 0) {
-                const Answer a = fin ? p2m_answer(v, qx, qy, qz, nv, c) : nonfinite_answer();
+            __syncthreads();
+            regroup_scan(hist);
+            __syncthreads();
+            for (int r = 0; r < rounds; ++r) {
+                const int u = r * B + t;
+                const uint32_t br = (uint32_t)icol[2 * S + u];
+                const uint32_t bin = br >> 24;
+                icol[3 * S + (bin ? hist[bin - 1] : 0u) + (br & 0xffffffu)] = u;
+            }
+            __syncthreads();
+            // the list scan, lanes taking the queries in list-length order
+            for (int r = 0; r < rounds; ++r) {
+                const int u = icol[3 * S + r * B + t];
+                const int64_t i = icol[u];
+                if (i < 0) continue;
+                const float qx = col[u], qy = col[S + u], qz = col[2 * S + u];
+                Nearest nv;
+                nv.d2 = col[3 * S + u];
+                nv.px = col[4 * S + u];
+                nv.py = col[5 * S + u];
+                nv.pz = col[6 * S + u];
+                nv.vid = icol[S + u];
+                ScanCounters c;
+                const Answer a = finite3(qx, qy, qz) ? p2m_answer(v, qx, qy, qz, nv, c) : nonfinite_answer();
                 // one 32-byte record per query; split into the outputs afterwards
                 stage[2 * i] = make_float4(__int_as_float(a.prim), a.cx, a.cy, a.cz);
                 stage[2 * i + 1] = make_float4(a.dist, 0.f, 0.f, 0.f);
             }
+            __syncthreads();  // the slots are refilled by the next rounds or tile
         }
     }
 }
@@ -287,15 +356,15 @@ p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, 
     RadixPlan plan = radix_plan(n);
     RadixBuffers rb = radix_buffers(plan, b->scratch);
     k_batch_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(q, n, b->qoff, b->count, b->desc, b->key_bits,
-                                                              rb.keys[0], rb.vals[0]);
-    const int cur = radix_sort_pairs(plan, rb, 0, 32, st);
+                                                              rb.keys[0]);
+    const int cur = radix_sort_pairs(plan, rb, 0, 32, false, st);
     k_reset<<<1, 64, 0, st>>>(b->counter);
     const int grid = b->grid;
     const Arena A{b->node,  b->vhead, b->lent, b->seg,  b->tri,  b->fedge,
                   b->nboff, b->nbrec, b->seed, b->frec, b->erec, b->desc};
 #define P2M_LAUNCH_BATCH(W)                                                                                  \
-    k_batch_query<W><<<grid, b->block, 0, st>>>(A, b->tiles, b->ntiles, b->counter, b->qpl, q, rb.vals[cur], n, \
-                                                b->stage)
+    k_batch_query<W><<<grid, b->block, batch_lds_bytes(b->block, b->qpl), st>>>(                           \
+        A, b->tiles, b->ntiles, b->counter, b->qpl, regroup_rounds(b->block, b->qpl), q, rb.vals[cur], n, b->stage)
     if (b->traversal == 1) P2M_LAUNCH_BATCH(WALK_LANE);
     else if (b->traversal == 2) P2M_LAUNCH_BATCH(WALK_WAVE);
     else P2M_LAUNCH_BATCH(WALK_VORONOI);
@@ -314,7 +383,7 @@ p2m_status set_grid(p2m_batch* b) {
     const void* k = b->traversal == 1   ? (const void*)k_batch_query<WALK_LANE>
                     : b->traversal == 2 ? (const void*)k_batch_query<WALK_WAVE>
                                         : (const void*)k_batch_query<WALK_VORONOI>;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, b->block, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, b->block, batch_lds_bytes(b->block, b->qpl));
     if (e != hipSuccess) return hip_fail(e, "occupancy query");
     b->grid = std::max(1, cus * std::max(1, per));
     return P2M_OK;

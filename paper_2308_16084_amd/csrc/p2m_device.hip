@@ -16,6 +16,7 @@
 #include "p2m_internal.hpp"
 #include "nearest.hpp"
 #include "query_core.hpp"
+#include "regroup.hpp"
 
 namespace p2m {
 
@@ -363,26 +364,14 @@ void device_release(MeshState& s) {
 __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t chunk) { return (b % kXcds) * chunk + b / kXcds; }
 
 __global__ void k_morton(const float* __restrict__ q, int64_t n, float lox, float loy, float loz, float sx, float sy,
-                         float sz, uint32_t* __restrict__ keys, int32_t* __restrict__ vals) {
+                         float sz, uint32_t* __restrict__ keys) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     keys[i] = morton30(q[3 * i], q[3 * i + 1], q[3 * i + 2], lox, loy, loz, sx, sy, sz);
-    vals[i] = (int32_t)i;
 }
 
-// Steps of a vertex's two list loops (edge then face entries, four a step).
-__device__ __forceinline__ int list_steps(const MeshView& m, int32_t vid) {
-    const uint4 h = m.vhead[2 * vid];
-    return (int)(((h.y - h.x + 3u) >> 2) + ((h.z - h.y + 3u) >> 2));
-}
-
-// Regrouping after the nearest-vertex step: a wavefront runs each list loop
-// as long as its longest lane, and lanes of one wavefront hold lists of
-// quite different lengths.  The block sorts its queries by the steps their
-// lists take (a counting sort over kRegroupBins bins in LDS) and each lane
-// takes the query of its sorted place, so a wavefront holds lists of nearly
-// one length.  Only which lane answers a query changes.
-constexpr int kRegroupBins = 64;
+// Dynamic LDS of k_query: the regroup bins, then per slot 7 floats (q, the
+// nearest vertex's d2 and position) and 2 ints (query index, vertex).
 constexpr size_t regroup_lds_bytes(int block) { return sizeof(uint32_t) * (kRegroupBins + 9 * (size_t)block); }
 
 // stage (ordered batches): query i's answer goes to stage[S*i .. S*i+S-1]
@@ -415,24 +404,16 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const floa
     // with WALK_WAVE every lane of the wavefront takes part in the shared walk
     Nearest nv = nearest_vertex<kWalk>(m, qx, qy, qz, i >= 0 && fin, c.nodes, c.steps);
 
-    // regroup the block's queries by list length (see list_steps)
+    // regroup the block's queries by list length (regroup.hpp)
     uint32_t* hist = lds;
     float* col = (float*)(lds + kRegroupBins);  // qx qy qz d2 px py pz, B each
     int32_t* icol = (int32_t*)(col + 7 * B);    // query index, vertex
-    const int bin = (i >= 0 && fin) ? min(list_steps(m, nv.vid), kRegroupBins - 1) : 0;
+    const int bin = (i >= 0 && fin) ? regroup_bin(m, nv.vid) : 0;
     if (t < kRegroupBins) hist[t] = 0;
     __syncthreads();
     const uint32_t rank = atomicAdd(&hist[bin], 1u);
     __syncthreads();
-    if (t < kRegroupBins) {  // the first wavefront: inclusive scan of the bins
-        uint32_t x = hist[t];
-#pragma unroll
-        for (int d = 1; d < kRegroupBins; d <<= 1) {
-            const uint32_t y = __shfl_up(x, d);
-            if (t >= d) x += y;
-        }
-        hist[t] = x;
-    }
+    regroup_scan(hist);
     __syncthreads();
     const uint32_t pos = (bin ? hist[bin - 1] : 0u) + rank;
     col[pos] = qx;
@@ -858,7 +839,7 @@ static p2m_status ensure_scratch(MeshState& s, int64_t bytes) {
 }
 
 // Morton keys + stable sort by key bits [lo_bit, 30) into scratch; returns
-// the permutation pointer.  `extra` bytes of scratch after the sort's own
+// the permutation pointer, and the sorted keys when keys_out is not NULL.  `extra` bytes of scratch after the sort's own
 // (256-byte aligned) are returned in *extra_out.
 static p2m_status order_into_scratch(MeshState& s, const float* q, int64_t n, int lo_bit, hipStream_t st,
                                      uint32_t** keys_out, int32_t** perm_out, int64_t extra = 0,
@@ -871,13 +852,13 @@ static p2m_status order_into_scratch(MeshState& s, const float* q, int64_t n, in
     float lo[3], sc[3];
     morton_params(s.dlo, s.dhi, lo, sc);
     const int64_t blocks = (n + 255) / 256;
-    k_morton<<<(unsigned)blocks, 256, 0, st>>>(q, n, lo[0], lo[1], lo[2], sc[0], sc[1], sc[2], b.keys[0], b.vals[0]);
+    k_morton<<<(unsigned)blocks, 256, 0, st>>>(q, n, lo[0], lo[1], lo[2], sc[0], sc[1], sc[2], b.keys[0]);
     r = check_launch("morton keys");
     if (r != P2M_OK) return r;
-    int cur = radix_sort_pairs(plan, b, lo_bit, 30, st);
+    int cur = radix_sort_pairs(plan, b, lo_bit, 30, keys_out != nullptr, st);
     r = check_launch("radix sort");
     if (r != P2M_OK) return r;
-    *keys_out = b.keys[cur];
+    if (keys_out) *keys_out = b.keys[cur];
     *perm_out = b.vals[cur];
     if (extra_out) *extra_out = (char*)s.dev.scratch + sort_bytes;
     return P2M_OK;
@@ -1023,9 +1004,8 @@ p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, flo
     int32_t* perm = nullptr;
     float4* stage = nullptr;
     if (sort) {
-        uint32_t* keys = nullptr;
         void* x = nullptr;
-        p2m_status r = order_into_scratch(s, q, n, kQuerySortLoBit, st, &keys, &perm, (bary ? 48 : 32) * n, &x);
+        p2m_status r = order_into_scratch(s, q, n, kQuerySortLoBit, st, nullptr, &perm, (bary ? 48 : 32) * n, &x);
         if (r != P2M_OK) return r;
         stage = (float4*)x;
     }

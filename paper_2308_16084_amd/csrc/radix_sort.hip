@@ -21,6 +21,10 @@ constexpr int kT = kRadixThreads;
 constexpr int kI = kRadixItems;
 constexpr int kWaves = kT / 64;
 
+// Digit counts of one tile in LDS.  When every valid lane of a wavefront
+// holds the same digit (runs of equal high digits in partly sorted keys,
+// e.g. the mesh index of a batch), the first lane adds the wavefront's count
+// with one atomic instead of 64 serialized ones on one counter.
 __global__ __launch_bounds__(kT) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                    uint32_t* __restrict__ counts, int64_t tiles) {
     __shared__ uint32_t h[256];
@@ -28,10 +32,24 @@ __global__ __launch_bounds__(kT) void k_radix_hist(const uint32_t* __restrict__ 
     h[t] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    uint32_t key[kI];
 #pragma unroll
     for (int it = 0; it < kI; ++it) {
         const int64_t i = base + (int64_t)it * kT + t;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        key[it] = i < n ? keys[i] : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kI; ++it) {
+        const bool valid = base + (int64_t)it * kT + t < n;
+        const uint32_t d = (key[it] >> shift) & 255u;
+        const unsigned long long vm = __ballot(valid);
+        if (vm == 0ull) continue;
+        const uint32_t d0 = (uint32_t)__shfl(d, __ffsll((long long)vm) - 1);
+        if (__ballot(valid && d == d0) == vm) {
+            if (valid && __popcll(vm & ((1ull << (t & 63)) - 1ull)) == 0) atomicAdd(&h[d], (uint32_t)__popcll(vm));
+        } else if (valid) {
+            atomicAdd(&h[d], 1u);
+        }
     }
     __syncthreads();
     counts[(int64_t)t * tiles + blockIdx.x] = h[t];
@@ -101,7 +119,10 @@ __global__ __launch_bounds__(kT) void k_scan_add(uint32_t* __restrict__ a, int64
         if (base + k < n) a[base + k] += add;
 }
 
-// Scatter of one tile: the tile's 4096 pairs are first placed in LDS in
+// Scatter of one tile (kPositions: the values are the keys' positions, as in
+// the first pass, and vin is not read; !kKeysOut: the keys are not written,
+// as in a last pass whose caller needs only the permutation): the tile's
+// 4096 pairs are first placed in LDS in
 // digit order (stable: by digit, then by position in the tile), then written
 // out so that consecutive threads write consecutive places of each digit's
 // run -- coalesced runs of ~16 keys instead of one cache line per key.
@@ -109,6 +130,7 @@ __global__ __launch_bounds__(kT) void k_scan_add(uint32_t* __restrict__ a, int64
 // round, against a running per-digit count of its earlier rounds (ballots
 // on the 8 digit bits find the lanes of equal digit), so the block meets at
 // a barrier only a few times per tile.
+template <bool kPositions, bool kKeysOut>
 __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
                                                       int64_t n, int shift, const uint32_t* __restrict__ offs,
                                                       int64_t tiles, uint32_t* __restrict__ kout,
@@ -136,7 +158,7 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
         const int i = wbase + it * 64 + lane;
         const bool valid = i < cnt;
         key[it] = valid ? kin[tile0 + i] : 0u;
-        val[it] = valid ? vin[tile0 + i] : 0;
+        val[it] = valid ? (kPositions ? (int32_t)(tile0 + i) : vin[tile0 + i]) : 0;
     }
     for (int it = 0; it < kI; ++it) {
         const bool valid = wbase + it * 64 + lane < cnt;
@@ -212,7 +234,7 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
         const uint32_t d = (k >> shift) & 255u;
         const uint32_t pos = gbase[d] + (uint32_t)p - lstart[d];
         if (pos < (uint64_t)n) {
-            kout[pos] = k;
+            if (kKeysOut) kout[pos] = k;
             vout[pos] = lv[p];
         }
     }
@@ -255,16 +277,36 @@ void scan_exclusive_u32(uint32_t* a, int64_t n, uint32_t* sums, hipStream_t st) 
     k_scan_add<<<(unsigned)blocks, kT, 0, st>>>(a, n, sums);
 }
 
-int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit, hipStream_t st) {
+__global__ void k_iota(int32_t* __restrict__ v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = (int32_t)i;
+}
+
+int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit, bool keep_keys, hipStream_t st) {
     int cur = 0;
-    if (p.n <= 1) return cur;
+    if (p.n <= 0) return cur;
+    if (p.n == 1 || lo_bit >= hi_bit) {  // nothing to sort: the identity permutation
+        k_iota<<<(unsigned)((p.n + 255) / 256), 256, 0, st>>>(b.vals[0], p.n);
+        return cur;
+    }
     for (int shift = lo_bit; shift < hi_bit; shift += 8) {
+        const bool first = shift == lo_bit, last = shift + 8 >= hi_bit;
         k_radix_hist<<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], p.n, shift, b.counts, p.tiles);
         k_scan_local<<<(unsigned)p.scan_blocks, kT, 0, st>>>(b.counts, p.counts, b.sums);
         k_scan_sums<<<1, kT, 0, st>>>(b.sums, p.scan_blocks);
         k_scan_add<<<(unsigned)p.scan_blocks, kT, 0, st>>>(b.counts, p.counts, b.sums);
-        k_radix_scatter<<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], b.vals[cur], p.n, shift, b.counts, p.tiles,
-                                                          b.keys[cur ^ 1], b.vals[cur ^ 1]);
+#define P2M_SCATTER(P, K)                                                                                   \
+    k_radix_scatter<P, K><<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], b.vals[cur], p.n, shift, b.counts, p.tiles, \
+                                                            b.keys[cur ^ 1], b.vals[cur ^ 1])
+        const bool keys_out = !last || keep_keys;
+        if (first) {
+            if (keys_out) P2M_SCATTER(true, true);
+            else P2M_SCATTER(true, false);
+        } else {
+            if (keys_out) P2M_SCATTER(false, true);
+            else P2M_SCATTER(false, false);
+        }
+#undef P2M_SCATTER
         cur ^= 1;
     }
     return cur;

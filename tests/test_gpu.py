@@ -127,6 +127,15 @@ def test_order_bit_exact(c1, n):
     rk, rp = OM.order(Q, lo, hi)
     assert np.array_equal(keys.cpu().numpy().view(np.uint32), rk)
     assert np.array_equal(perm.cpu().numpy(), rp)
+    if n > 100:
+        # already in key order: whole wavefronts share their high digits
+        Qs = np.ascontiguousarray(Q[rp])
+        keys, perm = m.order_queries(torch.from_numpy(Qs).cuda())
+        torch.cuda.synchronize()
+        rk2, rp2 = OM.order(Qs, lo, hi)
+        assert np.array_equal(rp2, np.arange(n))
+        assert np.array_equal(keys.cpu().numpy().view(np.uint32), rk2)
+        assert np.array_equal(perm.cpu().numpy(), rp2)
 
 
 @pytest.mark.parametrize("traversal", [1, 2, 3])
