@@ -358,10 +358,20 @@ void device_release(MeshState& s) {
 // ------------------------------------------------------------- kernels
 
 // XCD-aware tile order: consecutive hardware blocks go round-robin to the 8
-// XCDs, each with its own L2.  Give XCD x the contiguous tile range
-// [x*chunk, (x+1)*chunk) so spatially adjacent (Morton-ordered) tiles share
-// an L2.  The grid is 8*chunk blocks; tiles >= ntiles are skipped.
-__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t chunk) { return (b % kXcds) * chunk + b / kXcds; }
+// XCDs, each with its own L2.  Tiles are dealt to the XCDs in runs of G
+// consecutive (Morton-ordered, so spatially adjacent) tiles: blocks b of
+// one super-group of 8G hold tiles sg*8G + x*G + k, XCD x = b mod 8 taking
+// the run x*G .. x*G+G-1.  A run shares its L2, and the blocks resident at
+// one time cover a compact stretch of the batch, which the shared Infinity
+// Cache holds.  Measured on 10^7 and 10^6 queries of one mesh: one
+// contiguous eighth of the batch per XCD was 4 % slower on the larger batch,
+// G = 1 8 % slower on the smaller.  The grid is a multiple of 8G; tiles >=
+// ntiles are skipped.
+constexpr int64_t kXcdRun = 16;
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
+    const int64_t sg = b / (kXcds * G), r = b % (kXcds * G);
+    return sg * kXcds * G + (r % kXcds) * G + r / kXcds;
+}
 
 __global__ void k_morton(const float* __restrict__ q, int64_t n, float lox, float loy, float loz, float sx, float sy,
                          float sz, uint32_t* __restrict__ keys) {
@@ -382,13 +392,13 @@ constexpr size_t regroup_lds_bytes(int block) { return sizeof(uint32_t) * (kRegr
 // output arrays directly.
 template <bool kWriteExtras, int kWalk>
 __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const float* __restrict__ q,
-                                                const int32_t* __restrict__ perm, int64_t n, int64_t chunk,
+                                                const int32_t* __restrict__ perm, int64_t n, int64_t run,
                                                 int32_t* __restrict__ prim, float* __restrict__ closest,
                                                 float* __restrict__ dist, uint8_t* __restrict__ status,
                                                 float* __restrict__ bary, int32_t* __restrict__ pvid,
                                                 float4* __restrict__ stage) {
     extern __shared__ uint32_t lds[];
-    const int64_t tile = xcd_tile(blockIdx.x, chunk);
+    const int64_t tile = xcd_tile(blockIdx.x, run);
     const int t = threadIdx.x, B = blockDim.x;
     const int64_t j = tile * B + t;
     int64_t i = j < n ? (perm ? (int64_t)perm[j] : j) : -1;
@@ -1012,11 +1022,11 @@ p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, flo
     if (profile) (void)hipEventRecord((hipEvent_t)s.dev.ev[1], st);
     const MeshView v = device_view(s);
     const int64_t tiles = (n + block - 1) / block;
-    const int64_t chunk = (tiles + kXcds - 1) / kXcds;
-    const unsigned grid = (unsigned)(chunk * kXcds);
+    const int64_t run = std::min<int64_t>(kXcdRun, (tiles + kXcds - 1) / kXcds);
+    const unsigned grid = (unsigned)((tiles + kXcds * run - 1) / (kXcds * run) * (kXcds * run));
     const int walk = pick_walk(traversal);
 #define P2M_LAUNCH_QUERY(X, W) \
-    k_query<X, W><<<grid, block, regroup_lds_bytes(block), st>>>(v, q, perm, n, chunk, prim, closest, dist, status, \
+    k_query<X, W><<<grid, block, regroup_lds_bytes(block), st>>>(v, q, perm, n, run, prim, closest, dist, status, \
                                                                  bary, pvid, stage)
     if (bary) {
         if (walk == WALK_WAVE) P2M_LAUNCH_QUERY(true, WALK_WAVE);
@@ -1137,8 +1147,8 @@ p2m_status p2m_query_backward(p2m_mesh* mh, const float* q, int64_t n, const flo
     k_bwd_count<<<(unsigned)blocks, 256, 0, st>>>(q, n, closest, dist, bary, pvid, gd, gq, (int32_t)nv, nbk, mat);
     scan_exclusive_u32(mat, cells, sums, st);
     k_bwd_scatter<<<(unsigned)blocks, 256, 0, st>>>(q, n, closest, dist, bary, pvid, gd, (int32_t)nv, nbk, mat, recs);
-    // small meshes: each bucket split over enough blocks to fill the chip
-    const int splits = nbk >= 256 ? 1 : (4 * 256 + nbk - 1) / nbk;
+    // each bucket split over enough blocks to give the chip about 4 per CU
+    const int splits = (4 * 256 + nbk - 1) / nbk;
     k_bwd_accum<<<(unsigned)(nbk * splits), 512, 0, st>>>(recs, mat, blocks, gV, (int32_t)nv, splits);
     return check_launch("backward kernels");
 }
