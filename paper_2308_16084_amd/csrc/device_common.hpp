@@ -62,8 +62,8 @@ struct RadixPlan {
 struct RadixBuffers {
     uint32_t* keys[2];
     int32_t* vals[2];
-    uint32_t* counts;
-    uint32_t* sums;
+    uint32_t* counts;  // digit-major count matrix [256 * tiles]
+    uint32_t* sums;    // the 256 digit totals of a pass
 };
 
 constexpr int kRadixThreads = 256;

@@ -1,8 +1,10 @@
 // Stable LSD radix sort of (uint32 key, int32 value) pairs for gfx950.
 //
 // Per 8-bit digit pass: (1) every tile of 4096 keys counts its digits in
-// LDS; (2) an exclusive scan over the digit-major count matrix gives each
-// (digit, tile) its output offset; (3) every tile re-reads its keys, ranks
+// LDS; (2) one block per digit scans that digit's column of the digit-major
+// count matrix (the digit's offset within its run of the output) and keeps
+// the column total; (3) every tile adds the exclusive scan of the 256 digit
+// totals to its column offsets, re-reads its keys, ranks
 // each key among equal digits with wave-wide ballots (stable within a
 // wave), adds the counts of earlier waves and of earlier chunks of the
 // tile, places the pair in LDS in digit order and finally writes each
@@ -119,6 +121,47 @@ __global__ __launch_bounds__(kT) void k_scan_add(uint32_t* __restrict__ a, int64
         if (base + k < n) a[base + k] += add;
 }
 
+// Exclusive scan of one value per thread over the kT threads of a block;
+// *total receives the block's sum.  Every thread calls it (barriers inside).
+__device__ __forceinline__ uint32_t block_scan_excl(uint32_t x, uint32_t* wsum, uint32_t* total) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+        before += k < w ? wsum[k] : 0u;
+        all += wsum[k];
+    }
+    __syncthreads();  // wsum may be reused by the caller's next scan
+    *total = all;
+    return before + incl - x;
+}
+
+// Column d of the digit-major count matrix (the tiles' counts of digit d):
+// exclusive scan in place, in chunks of kT with a carry; totals[d] = sum.
+__global__ __launch_bounds__(kT) void k_radix_colscan(uint32_t* __restrict__ counts, int64_t tiles,
+                                                      uint32_t* __restrict__ totals) {
+    __shared__ uint32_t wsum[kWaves];
+    uint32_t* col = counts + (int64_t)blockIdx.x * tiles;
+    uint32_t carry = 0;
+    for (int64_t c = 0; c < tiles; c += kT) {
+        const int64_t i = c + threadIdx.x;
+        const uint32_t x = i < tiles ? col[i] : 0u;
+        uint32_t sum;
+        const uint32_t e = block_scan_excl(x, wsum, &sum);
+        if (i < tiles) col[i] = carry + e;
+        carry += sum;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
 // Scatter of one tile (kPositions: the values are the keys' positions, as in
 // the first pass, and vin is not read; !kKeysOut: the keys are not written,
 // as in a last pass whose caller needs only the permutation): the tile's
@@ -133,8 +176,8 @@ __global__ __launch_bounds__(kT) void k_scan_add(uint32_t* __restrict__ a, int64
 template <bool kPositions, bool kKeysOut>
 __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
                                                       int64_t n, int shift, const uint32_t* __restrict__ offs,
-                                                      int64_t tiles, uint32_t* __restrict__ kout,
-                                                      int32_t* __restrict__ vout) {
+                                                      const uint32_t* __restrict__ totals, int64_t tiles,
+                                                      uint32_t* __restrict__ kout, int32_t* __restrict__ vout) {
     __shared__ uint32_t gbase[256];        // global start of each digit's run of this tile
     __shared__ uint32_t lstart[256];       // start of each digit in the tile's LDS order
     __shared__ uint32_t wc[kWaves][256];   // per wave: running count, then its base per digit
@@ -145,7 +188,13 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
     const int w = t >> 6;
     const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
     const int cnt = (int)std::min<int64_t>(kRadixTile, n - tile0);
-    gbase[t] = offs[(int64_t)t * tiles + blockIdx.x];
+    __shared__ uint32_t wsum[kWaves];
+    {
+        // digit t's run starts after the runs of smaller digits
+        uint32_t all;
+        const uint32_t dpre = block_scan_excl(totals[t], wsum, &all);
+        gbase[t] = dpre + offs[(int64_t)t * tiles + blockIdx.x];
+    }
 #pragma unroll
     for (int k = 0; k < kWaves; ++k) wc[k][t] = 0;
     __syncthreads();
@@ -250,7 +299,7 @@ RadixPlan radix_plan(int64_t n) {
     p.tiles = (n + kRadixTile - 1) / kRadixTile;
     p.counts = 256 * p.tiles;
     p.scan_blocks = (p.counts + kRadixTile - 1) / kRadixTile;
-    p.bytes = 4 * up256(4 * n) + up256(4 * p.counts) + up256(4 * std::max<int64_t>(1, p.scan_blocks));
+    p.bytes = 4 * up256(4 * n) + up256(4 * p.counts) + up256(4 * std::max<int64_t>(256, p.scan_blocks));
     return p;
 }
 
@@ -292,12 +341,10 @@ int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit
     for (int shift = lo_bit; shift < hi_bit; shift += 8) {
         const bool first = shift == lo_bit, last = shift + 8 >= hi_bit;
         k_radix_hist<<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], p.n, shift, b.counts, p.tiles);
-        k_scan_local<<<(unsigned)p.scan_blocks, kT, 0, st>>>(b.counts, p.counts, b.sums);
-        k_scan_sums<<<1, kT, 0, st>>>(b.sums, p.scan_blocks);
-        k_scan_add<<<(unsigned)p.scan_blocks, kT, 0, st>>>(b.counts, p.counts, b.sums);
+        k_radix_colscan<<<256, kT, 0, st>>>(b.counts, p.tiles, b.sums);
 #define P2M_SCATTER(P, K)                                                                                   \
-    k_radix_scatter<P, K><<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], b.vals[cur], p.n, shift, b.counts, p.tiles, \
-                                                            b.keys[cur ^ 1], b.vals[cur ^ 1])
+    k_radix_scatter<P, K><<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], b.vals[cur], p.n, shift, b.counts, b.sums, \
+                                                            p.tiles, b.keys[cur ^ 1], b.vals[cur ^ 1])
         const bool keys_out = !last || keep_keys;
         if (first) {
             if (keys_out) P2M_SCATTER(true, true);
