@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace p2m {
 
@@ -53,9 +54,10 @@ hipError_t launch_split(const float4* stage, int64_t n, int32_t* prim, float* cl
 // Stable LSD radix sort of (uint32 key, int32 value) pairs, 8-bit digits.
 struct RadixPlan {
     int64_t n = 0;
-    int64_t tiles = 0;       // blocks of kRadixTile keys
+    int64_t tiles = 0;       // blocks of at most kRadixTile keys
     int64_t counts = 0;      // 256 * tiles
     int64_t scan_blocks = 0; // blocks of the count scan
+    int64_t totals = 256;    // digit totals: 256 per segment
     int64_t bytes = 0;       // scratch bytes
 };
 
@@ -70,14 +72,43 @@ constexpr int kRadixThreads = 256;
 constexpr int kRadixItems = 16;
 constexpr int64_t kRadixTile = kRadixThreads * kRadixItems;
 
+// Segmented sort: the keys form consecutive segments (the queries of one
+// mesh of a batch) and each is sorted on its own, in place, so the segment
+// index needs no digits of the key.  Tiles never straddle a segment; the
+// count matrix holds, per segment, a digit-major block of 256 x (its tiles).
+struct RadixSegTile {
+    int64_t start;          // first key of the tile
+    int32_t count, j, seg;  // keys in the tile, its index within its segment, the segment
+    int32_t pad;
+};
+struct RadixSegInfo {
+    int64_t start;  // first key of the segment
+    int64_t base;   // its block of the count matrix: 256 * (tiles of earlier segments)
+    int32_t cols;   // its tiles
+    int32_t pad;
+};
+struct RadixSegments {
+    const RadixSegTile* tiles = nullptr;  // device [ntiles]
+    const RadixSegInfo* segs = nullptr;   // device [nseg]
+    int64_t ntiles = 0;
+    int32_t nseg = 0;
+};
+
 RadixPlan radix_plan(int64_t n);
+// Plan of a segmented sort of n keys in ntiles tiles over nseg segments.
+RadixPlan radix_plan_segmented(int64_t n, int64_t ntiles, int32_t nseg);
+// The tiles and segment records of a segmented sort (host side); seg_start
+// holds nseg+1 non-decreasing key offsets.
+void radix_segment_tiles(const std::vector<int64_t>& seg_start, std::vector<RadixSegTile>& tiles,
+                         std::vector<RadixSegInfo>& segs);
 RadixBuffers radix_buffers(const RadixPlan& p, void* scratch);
 // Stable sort of the positions 0..n-1 by bits [lo_bit, hi_bit) of keys[0]
 // (8 bits per pass; the span is a multiple of 8): vals[r] receives the
 // permutation (the input position of each sorted place) and, with
 // keep_keys, keys[r] the sorted keys, where r (0/1) is returned; vals[0] is
 // not read.  All work is enqueued on `st`.
-int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit, bool keep_keys, hipStream_t st);
+int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit, bool keep_keys, hipStream_t st,
+                     const RadixSegments* seg = nullptr);
 // Exclusive prefix sum of a[0..n) in place; sums needs scan_sums_size(n)
 // entries of scratch.
 int64_t scan_sums_size(int64_t n);

@@ -2,9 +2,10 @@
 // served by one persistent launch over a packed arena, captured in a HIP
 // graph, with the launch shape chosen by a small autotuner.
 //
-// Ordering: key = mesh index in the high bits, then a Morton code of the
-// query inside that mesh's domain box; one stable radix sort groups each
-// mesh's queries (already contiguous) and orders them spatially.
+// Ordering: key = the top 24 bits of the query's Morton code in its mesh's
+// domain box; a segmented radix sort (one segment per mesh: each mesh's
+// queries are contiguous in the batch) orders each mesh's queries
+// spatially in place, in three 8-bit passes.
 // Work list: tiles (mesh, first sorted position, count) of block x qpl
 // queries, meshes with the most work first; each workgroup of the
 // persistent kernel takes the next tile from an atomic counter until the
@@ -87,7 +88,6 @@ struct Tile {
 struct p2m_batch {
     int device = -1;
     int32_t count = 0;
-    int key_bits = 0;  // Morton bits per axis
     void* base = nullptr;
     int64_t bytes = 0;
     p2m::KdNode* node = nullptr;
@@ -106,12 +106,13 @@ struct p2m_batch {
     // per query layout
     std::vector<int64_t> layout;
     int64_t n = 0;
-    void* work = nullptr;  // qoff int64 [count+1], tiles, counter, sort scratch
+    void* work = nullptr;  // qoff int64 [count+1], tiles, counter, sort tiles and segments, sort scratch
     int64_t work_bytes = 0;
     int64_t* qoff = nullptr;
     p2m::Tile* tiles = nullptr;
     int64_t ntiles = 0;
     uint32_t* counter = nullptr;
+    p2m::RadixSegments sort_seg;  // the segmented sort's tiles and segments (device)
     void* scratch = nullptr;
     float4* stage = nullptr;  // 32-byte answer record per query
     int tile_block = 0, tile_qpl = 0;
@@ -134,7 +135,7 @@ int64_t up256(int64_t x) { return (x + 255) / 256 * 256; }
 
 __global__ __launch_bounds__(256) void k_batch_keys(const float* __restrict__ q, int64_t n,
                                                     const int64_t* __restrict__ qoff, int32_t count,
-                                                    const BatchMesh* __restrict__ desc, int bits,
+                                                    const BatchMesh* __restrict__ desc,
                                                     uint32_t* __restrict__ keys) {
     __shared__ int32_t s_mesh;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
@@ -158,8 +159,7 @@ __global__ __launch_bounds__(256) void k_batch_keys(const float* __restrict__ q,
     const BatchMesh& d = desc[lo];
     const float qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
     const uint32_t full = morton30(qx, qy, qz, d.mlo[0], d.mlo[1], d.mlo[2], d.msc[0], d.msc[1], d.msc[2]);
-    const uint32_t code = full >> (30 - 3 * bits);  // keep the top `bits` bits per axis
-    keys[i] = ((uint32_t)lo << (3 * bits)) | code;
+    keys[i] = full >> 6;  // the top 8 bits per axis
 }
 
 __global__ void k_reset(uint32_t* counter) {
@@ -301,7 +301,12 @@ p2m_status prepare(p2m_batch* b, const int64_t* qoff_host, hipStream_t st) {
     const bool same_layout = layout == b->layout;
     if (same_layout && b->tile_block == b->block && b->tile_qpl == b->qpl) return P2M_OK;
     drop_graph(b);
-    RadixPlan plan = radix_plan(std::max<int64_t>(n, 1));
+    std::vector<RadixSegTile> stiles;
+    std::vector<RadixSegInfo> ssegs;
+    radix_segment_tiles(layout, stiles, ssegs);
+    RadixPlan plan = radix_plan_segmented(std::max<int64_t>(n, 1), (int64_t)stiles.size(), b->count);
+    const int64_t b_stiles = up256((int64_t)sizeof(RadixSegTile) * std::max<size_t>(1, stiles.size()));
+    const int64_t b_ssegs = up256((int64_t)sizeof(RadixSegInfo) * std::max<size_t>(1, ssegs.size()));
     const int64_t tsize = (int64_t)b->block * b->qpl;
     std::vector<int64_t> order((size_t)b->count);
     std::iota(order.begin(), order.end(), 0);
@@ -316,7 +321,7 @@ p2m_status prepare(p2m_batch* b, const int64_t* qoff_host, hipStream_t st) {
         for (int64_t s = layout[(size_t)k]; s < layout[(size_t)k + 1]; s += tsize)
             tiles.push_back(Tile{(int32_t)k, (int32_t)s, (int32_t)std::min(tsize, layout[(size_t)k + 1] - s), 0});
     const int64_t need = up256(8 * (int64_t)(b->count + 1)) + up256((int64_t)sizeof(Tile) * std::max<size_t>(1, tiles.size())) +
-                         256 + up256(plan.bytes) + 32 * std::max<int64_t>(n, 1);
+                         256 + b_stiles + b_ssegs + up256(plan.bytes) + 32 * std::max<int64_t>(n, 1);
     if (need > b->work_bytes) {
         if (b->work) (void)hipFree(b->work);
         b->work = nullptr;
@@ -332,12 +337,24 @@ p2m_status prepare(p2m_batch* b, const int64_t* qoff_host, hipStream_t st) {
     p += up256((int64_t)sizeof(Tile) * std::max<size_t>(1, tiles.size()));
     b->counter = (uint32_t*)p;
     p += 256;
+    b->sort_seg.tiles = (const RadixSegTile*)p;
+    p += b_stiles;
+    b->sort_seg.segs = (const RadixSegInfo*)p;
+    p += b_ssegs;
+    b->sort_seg.ntiles = (int64_t)stiles.size();
+    b->sort_seg.nseg = (int32_t)ssegs.size();
     b->scratch = p;
     p += up256(plan.bytes);
     b->stage = (float4*)p;
     hipError_t e = hipMemcpyAsync(b->qoff, layout.data(), 8 * layout.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !tiles.empty())
         e = hipMemcpyAsync(b->tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !stiles.empty())
+        e = hipMemcpyAsync((void*)b->sort_seg.tiles, stiles.data(), sizeof(RadixSegTile) * stiles.size(),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !ssegs.empty())
+        e = hipMemcpyAsync((void*)b->sort_seg.segs, ssegs.data(), sizeof(RadixSegInfo) * ssegs.size(),
+                           hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // host staging goes out of scope
     if (e != hipSuccess) return hip_fail(e, "batch layout upload");
     b->layout = layout;
@@ -353,11 +370,10 @@ p2m_status prepare(p2m_batch* b, const int64_t* qoff_host, hipStream_t st) {
 p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, float* dist, hipStream_t st) {
     const int64_t n = b->n;
     if (n == 0) return P2M_OK;
-    RadixPlan plan = radix_plan(n);
+    RadixPlan plan = radix_plan_segmented(n, b->sort_seg.ntiles, b->sort_seg.nseg);
     RadixBuffers rb = radix_buffers(plan, b->scratch);
-    k_batch_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(q, n, b->qoff, b->count, b->desc, b->key_bits,
-                                                              rb.keys[0]);
-    const int cur = radix_sort_pairs(plan, rb, 0, 32, false, st);
+    k_batch_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(q, n, b->qoff, b->count, b->desc, rb.keys[0]);
+    const int cur = radix_sort_pairs(plan, rb, 0, 24, false, st, &b->sort_seg);
     k_reset<<<1, 64, 0, st>>>(b->counter);
     const int grid = b->grid;
     const Arena A{b->node,  b->vhead, b->lent, b->seg,  b->tri,  b->fedge,
@@ -419,14 +435,10 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
         if (!meshes[k]) return fail(P2M_ERR_ARG, "NULL mesh in the batch");
         if (!meshes[k]->s.precomputed) return fail(P2M_ERR_STATE, "batch mesh not precomputed");
     }
-    int mesh_bits = 0;
-    while ((1 << mesh_bits) < count) ++mesh_bits;
-    if (mesh_bits > 26) return fail(P2M_ERR_ARG, "too many meshes in one batch");
     Guard g(device);
     p2m_batch* b = new p2m_batch();
     b->device = device;
     b->count = count;
-    b->key_bits = std::min(10, (32 - mesh_bits) / 3);
     // host staging of the arena
     std::vector<float> node, seg, tri, nbrec, frec, erec;
     std::vector<uint32_t> vhead, nboff;

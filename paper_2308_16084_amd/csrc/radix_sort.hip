@@ -9,6 +9,9 @@
 // wave), adds the counts of earlier waves and of earlier chunks of the
 // tile, places the pair in LDS in digit order and finally writes each
 // digit's run of the tile to its output offset with coalesced stores.
+// A segmented sort (RadixSegments) runs the same passes over tiles that
+// never straddle a segment, with one count block and one set of digit
+// totals per segment, so each segment is sorted within its own range.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,26 +26,57 @@ constexpr int kT = kRadixThreads;
 constexpr int kI = kRadixItems;
 constexpr int kWaves = kT / 64;
 
+// Where block b's tile lies: keys [start, start+count), column j of the
+// `cols` columns of its count block at `base`, and its segment.
+struct TileGeo {
+    int64_t start, base;
+    int32_t count, j, cols, seg;
+};
+
+template <bool kSeg>
+__device__ __forceinline__ TileGeo tile_geo(int64_t n, int64_t tiles, const RadixSegments& sg) {
+    TileGeo g;
+    if (kSeg) {
+        const RadixSegTile st = sg.tiles[blockIdx.x];
+        const RadixSegInfo si = sg.segs[st.seg];
+        g.start = st.start;
+        g.count = st.count;
+        g.j = st.j;
+        g.seg = st.seg;
+        g.base = si.base;
+        g.cols = si.cols;
+    } else {
+        g.start = (int64_t)blockIdx.x * kRadixTile;
+        g.count = (int32_t)std::min<int64_t>(kRadixTile, n - g.start);
+        g.j = (int32_t)blockIdx.x;
+        g.seg = 0;
+        g.base = 0;
+        g.cols = (int32_t)tiles;
+    }
+    return g;
+}
+
 // Digit counts of one tile in LDS.  When every valid lane of a wavefront
 // holds the same digit (runs of equal high digits in partly sorted keys,
 // e.g. the mesh index of a batch), the first lane adds the wavefront's count
 // with one atomic instead of 64 serialized ones on one counter.
+template <bool kSeg>
 __global__ __launch_bounds__(kT) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
-                                                   uint32_t* __restrict__ counts, int64_t tiles) {
+                                                   uint32_t* __restrict__ counts, int64_t tiles, RadixSegments sg) {
     __shared__ uint32_t h[256];
     const int t = threadIdx.x;
+    const TileGeo g = tile_geo<kSeg>(n, tiles, sg);
     h[t] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     uint32_t key[kI];
 #pragma unroll
     for (int it = 0; it < kI; ++it) {
-        const int64_t i = base + (int64_t)it * kT + t;
-        key[it] = i < n ? keys[i] : 0u;
+        const int i = it * kT + t;
+        key[it] = i < g.count ? keys[g.start + i] : 0u;
     }
 #pragma unroll
     for (int it = 0; it < kI; ++it) {
-        const bool valid = base + (int64_t)it * kT + t < n;
+        const bool valid = it * kT + t < g.count;
         const uint32_t d = (key[it] >> shift) & 255u;
         const unsigned long long vm = __ballot(valid);
         if (vm == 0ull) continue;
@@ -54,7 +88,7 @@ __global__ __launch_bounds__(kT) void k_radix_hist(const uint32_t* __restrict__ 
         }
     }
     __syncthreads();
-    counts[(int64_t)t * tiles + blockIdx.x] = h[t];
+    counts[g.base + (int64_t)t * g.cols + g.j] = h[t];
 }
 
 // Exclusive scan of 4096-element blocks in place; block totals to sums.
@@ -144,12 +178,21 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t x, uint32_t* wsum, 
     return before + incl - x;
 }
 
-// Column d of the digit-major count matrix (the tiles' counts of digit d):
-// exclusive scan in place, in chunks of kT with a carry; totals[d] = sum.
+// Column d of the digit-major count matrix (the tiles' counts of digit d;
+// in a segmented sort block 256*s+d takes segment s's column d): exclusive
+// scan in place, in chunks of kT with a carry; totals[256*s+d] = its sum.
+template <bool kSeg>
 __global__ __launch_bounds__(kT) void k_radix_colscan(uint32_t* __restrict__ counts, int64_t tiles,
-                                                      uint32_t* __restrict__ totals) {
+                                                      uint32_t* __restrict__ totals, RadixSegments sg) {
     __shared__ uint32_t wsum[kWaves];
-    uint32_t* col = counts + (int64_t)blockIdx.x * tiles;
+    const int d = (int)(blockIdx.x & 255u);
+    int64_t base = 0;
+    if (kSeg) {
+        const RadixSegInfo si = sg.segs[blockIdx.x >> 8];
+        base = si.base;
+        tiles = si.cols;
+    }
+    uint32_t* col = counts + base + (int64_t)d * tiles;
     uint32_t carry = 0;
     for (int64_t c = 0; c < tiles; c += kT) {
         const int64_t i = c + threadIdx.x;
@@ -173,11 +216,12 @@ __global__ __launch_bounds__(kT) void k_radix_colscan(uint32_t* __restrict__ cou
 // round, against a running per-digit count of its earlier rounds (ballots
 // on the 8 digit bits find the lanes of equal digit), so the block meets at
 // a barrier only a few times per tile.
-template <bool kPositions, bool kKeysOut>
+template <bool kPositions, bool kKeysOut, bool kSeg>
 __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
                                                       int64_t n, int shift, const uint32_t* __restrict__ offs,
                                                       const uint32_t* __restrict__ totals, int64_t tiles,
-                                                      uint32_t* __restrict__ kout, int32_t* __restrict__ vout) {
+                                                      uint32_t* __restrict__ kout, int32_t* __restrict__ vout,
+                                                      RadixSegments sg) {
     __shared__ uint32_t gbase[256];        // global start of each digit's run of this tile
     __shared__ uint32_t lstart[256];       // start of each digit in the tile's LDS order
     __shared__ uint32_t wc[kWaves][256];   // per wave: running count, then its base per digit
@@ -186,14 +230,17 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int w = t >> 6;
-    const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
-    const int cnt = (int)std::min<int64_t>(kRadixTile, n - tile0);
+    const TileGeo g = tile_geo<kSeg>(n, tiles, sg);
+    const int64_t tile0 = g.start;
+    const int cnt = g.count;
     __shared__ uint32_t wsum[kWaves];
     {
-        // digit t's run starts after the runs of smaller digits
+        // digit t's run starts after the runs of smaller digits (of the
+        // tile's segment, which starts at its first key)
         uint32_t all;
-        const uint32_t dpre = block_scan_excl(totals[t], wsum, &all);
-        gbase[t] = dpre + offs[(int64_t)t * tiles + blockIdx.x];
+        const uint32_t dpre = block_scan_excl(totals[256 * g.seg + t], wsum, &all);
+        const uint32_t seg0 = kSeg ? (uint32_t)sg.segs[g.seg].start : 0u;
+        gbase[t] = seg0 + dpre + offs[g.base + (int64_t)t * g.cols + g.j];
     }
 #pragma unroll
     for (int k = 0; k < kWaves; ++k) wc[k][t] = 0;
@@ -299,8 +346,35 @@ RadixPlan radix_plan(int64_t n) {
     p.tiles = (n + kRadixTile - 1) / kRadixTile;
     p.counts = 256 * p.tiles;
     p.scan_blocks = (p.counts + kRadixTile - 1) / kRadixTile;
-    p.bytes = 4 * up256(4 * n) + up256(4 * p.counts) + up256(4 * std::max<int64_t>(256, p.scan_blocks));
+    p.totals = 256;
+    p.bytes = 4 * up256(4 * n) + up256(4 * p.counts) + up256(4 * std::max(p.totals, p.scan_blocks));
     return p;
+}
+
+RadixPlan radix_plan_segmented(int64_t n, int64_t ntiles, int32_t nseg) {
+    RadixPlan p;
+    p.n = n;
+    p.tiles = ntiles;
+    p.counts = 256 * ntiles;
+    p.scan_blocks = 0;
+    p.totals = 256 * (int64_t)std::max(1, nseg);
+    p.bytes = 4 * up256(4 * n) + up256(4 * std::max<int64_t>(1, p.counts)) + up256(4 * p.totals);
+    return p;
+}
+
+void radix_segment_tiles(const std::vector<int64_t>& seg_start, std::vector<RadixSegTile>& tiles,
+                         std::vector<RadixSegInfo>& segs) {
+    tiles.clear();
+    segs.clear();
+    for (size_t k = 0; k + 1 < seg_start.size(); ++k) {
+        const int64_t a = seg_start[k], len = seg_start[k + 1] - a;
+        const int32_t cols = (int32_t)((len + kRadixTile - 1) / kRadixTile);
+        segs.push_back(RadixSegInfo{a, 256 * (int64_t)tiles.size(), cols, 0});
+        for (int32_t j = 0; j < cols; ++j)
+            tiles.push_back(RadixSegTile{a + (int64_t)j * kRadixTile,
+                                         (int32_t)std::min<int64_t>(kRadixTile, len - (int64_t)j * kRadixTile), j,
+                                         (int32_t)k, 0});
+    }
 }
 
 RadixBuffers radix_buffers(const RadixPlan& p, void* scratch) {
@@ -331,28 +405,37 @@ __global__ void k_iota(int32_t* __restrict__ v, int64_t n) {
     if (i < n) v[i] = (int32_t)i;
 }
 
-int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit, bool keep_keys, hipStream_t st) {
+int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit, bool keep_keys, hipStream_t st,
+                     const RadixSegments* seg) {
     int cur = 0;
     if (p.n <= 0) return cur;
     if (p.n == 1 || lo_bit >= hi_bit) {  // nothing to sort: the identity permutation
         k_iota<<<(unsigned)((p.n + 255) / 256), 256, 0, st>>>(b.vals[0], p.n);
         return cur;
     }
+    const RadixSegments sg = seg ? *seg : RadixSegments{};
+    const unsigned cols_blocks = seg ? 256u * (unsigned)seg->nseg : 256u;
     for (int shift = lo_bit; shift < hi_bit; shift += 8) {
         const bool first = shift == lo_bit, last = shift + 8 >= hi_bit;
-        k_radix_hist<<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], p.n, shift, b.counts, p.tiles);
-        k_radix_colscan<<<256, kT, 0, st>>>(b.counts, p.tiles, b.sums);
-#define P2M_SCATTER(P, K)                                                                                   \
-    k_radix_scatter<P, K><<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], b.vals[cur], p.n, shift, b.counts, b.sums, \
-                                                            p.tiles, b.keys[cur ^ 1], b.vals[cur ^ 1])
         const bool keys_out = !last || keep_keys;
-        if (first) {
-            if (keys_out) P2M_SCATTER(true, true);
-            else P2M_SCATTER(true, false);
-        } else {
-            if (keys_out) P2M_SCATTER(false, true);
-            else P2M_SCATTER(false, false);
-        }
+#define P2M_SCATTER(P, K, S)                                                                                       \
+    k_radix_scatter<P, K, S><<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], b.vals[cur], p.n, shift, b.counts,      \
+                                                               b.sums, p.tiles, b.keys[cur ^ 1], b.vals[cur ^ 1], sg)
+#define P2M_PASS(S)                                                                                             \
+    do {                                                                                                        \
+        k_radix_hist<S><<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], p.n, shift, b.counts, p.tiles, sg);      \
+        k_radix_colscan<S><<<cols_blocks, kT, 0, st>>>(b.counts, p.tiles, b.sums, sg);                          \
+        if (first) {                                                                                            \
+            if (keys_out) P2M_SCATTER(true, true, S);                                                           \
+            else P2M_SCATTER(true, false, S);                                                                   \
+        } else {                                                                                                \
+            if (keys_out) P2M_SCATTER(false, true, S);                                                          \
+            else P2M_SCATTER(false, false, S);                                                                  \
+        }                                                                                                       \
+    } while (0)
+        if (seg) P2M_PASS(true);
+        else P2M_PASS(false);
+#undef P2M_PASS
 #undef P2M_SCATTER
         cur ^= 1;
     }
