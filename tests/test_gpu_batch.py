@@ -87,7 +87,10 @@ def test_graph_replays_match_eager(batch_setup):
             v.fill_(-1)
 
 
-@pytest.mark.parametrize("shape", [(64, 1, 1), (128, 2, 2), (256, 4, 1), (192, 3, 2), (64, 2, 3), (256, 1, 3)])
+# (64, 8, 3) and (128, 5, 3): a tile's rounds regrouped in several groups of
+# up to 256 queries, the last one partial
+@pytest.mark.parametrize("shape", [(64, 1, 1), (128, 2, 2), (256, 4, 1), (192, 3, 2), (64, 2, 3), (256, 1, 3),
+                                   (64, 8, 3), (128, 5, 3)])
 def test_launch_shapes_give_same_answers(batch_setup, shape):
     works, meshes, b, Q, off, q = batch_setup
     b.set_shape(256, 1, 1)
