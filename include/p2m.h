@@ -253,7 +253,8 @@ p2m_status p2m_query_backward(p2m_mesh* m, const float* q_dev, int64_t n, const 
 
 /* Pack precomputed meshes (not necessarily uploaded) into one device arena
  * on `device` for a single persistent launch over all of them.  The copies
- * are complete when the call returns; the meshes may be destroyed after. */
+ * are complete when the call returns; the meshes may be destroyed after.
+ * count is 1 .. 2^20 (P2M_ERR_ARG beyond). */
 p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, void* stream, p2m_batch** out);
 void p2m_batch_destroy(p2m_batch* b);
 

@@ -428,6 +428,8 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
     if (!out) return fail(P2M_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (!meshes || count < 1) return fail(P2M_ERR_ARG, "need at least one mesh");
+    // the segmented sort scans 256 digit columns per mesh, one workgroup each
+    if (count > (1 << 20)) return fail(P2M_ERR_ARG, "more than 2^20 meshes in one batch");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(P2M_ERR_HIP, "no HIP device");
     if (device < 0 || device >= ndev) return fail(P2M_ERR_ARG, "device index out of range");
