@@ -107,8 +107,27 @@ RadixBuffers radix_buffers(const RadixPlan& p, void* scratch);
 // permutation (the input position of each sorted place) and, with
 // keep_keys, keys[r] the sorted keys, where r (0/1) is returned; vals[0] is
 // not read.  All work is enqueued on `st`.
+// first_counts: the first pass's count matrix was already written by the
+// kernel that made the keys (radix_hist_add), so that pass skips its
+// histogram kernel.
 int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit, bool keep_keys, hipStream_t st,
-                     const RadixSegments* seg = nullptr);
+                     const RadixSegments* seg = nullptr, bool first_counts = false);
+
+// Adds digit d of one key per lane (when valid) to the 256 LDS counters h
+// of a tile's histogram.  When every valid lane of the wavefront holds the
+// same digit (runs of equal high digits in partly sorted keys), the first of
+// them adds the wavefront's count with one atomic instead of 64 serialized
+// ones on one counter.  Every lane of the wavefront calls it.
+__device__ __forceinline__ void radix_hist_add(uint32_t* h, uint32_t d, bool valid) {
+    const unsigned long long vm = __ballot(valid);
+    if (vm == 0ull) return;
+    const uint32_t d0 = (uint32_t)__shfl(d, __ffsll((long long)vm) - 1);
+    if (__ballot(valid && d == d0) == vm) {
+        if (valid && __popcll(vm & ((1ull << (threadIdx.x & 63)) - 1ull)) == 0) atomicAdd(&h[d], (uint32_t)__popcll(vm));
+    } else if (valid) {
+        atomicAdd(&h[d], 1u);
+    }
+}
 // Exclusive prefix sum of a[0..n) in place; sums needs scan_sums_size(n)
 // entries of scratch.
 int64_t scan_sums_size(int64_t n);

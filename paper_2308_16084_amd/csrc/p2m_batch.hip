@@ -106,9 +106,8 @@ struct p2m_batch {
     // per query layout
     std::vector<int64_t> layout;
     int64_t n = 0;
-    void* work = nullptr;  // qoff int64 [count+1], tiles, counter, sort tiles and segments, sort scratch
+    void* work = nullptr;  // tiles, counter, sort tiles and segments, sort scratch, staged answers
     int64_t work_bytes = 0;
-    int64_t* qoff = nullptr;
     p2m::Tile* tiles = nullptr;
     int64_t ntiles = 0;
     uint32_t* counter = nullptr;
@@ -133,33 +132,36 @@ namespace {
 
 int64_t up256(int64_t x) { return (x + 255) / 256 * 256; }
 
-__global__ __launch_bounds__(256) void k_batch_keys(const float* __restrict__ q, int64_t n,
-                                                    const int64_t* __restrict__ qoff, int32_t count,
-                                                    const BatchMesh* __restrict__ desc,
-                                                    uint32_t* __restrict__ keys) {
-    __shared__ int32_t s_mesh;
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
-    const int64_t i = i0 + threadIdx.x;
-    // mesh k with qoff[k] <= i < qoff[k+1]: a binary search for the block's
-    // first query, then each lane steps over the (few) meshes that begin
-    // before its own query
-    if (threadIdx.x == 0) {
-        int32_t lo = 0, hi = count;
-        while (hi - lo > 1) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (qoff[mid] <= i0) lo = mid;
-            else hi = mid;
+// Keys of one radix tile of the batch (a tile lies in one mesh: the
+// segmented sort's tiles) -- the top 24 bits of the query's Morton code in
+// its mesh's domain box -- and the counts of their low digit, the first
+// pass's column of the count matrix.
+__global__ __launch_bounds__(kRadixThreads) void k_batch_keys(const float* __restrict__ q,
+                                                              const BatchMesh* __restrict__ desc, RadixSegments sg,
+                                                              uint32_t* __restrict__ keys,
+                                                              uint32_t* __restrict__ counts) {
+    __shared__ uint32_t h[256];
+    const int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const RadixSegTile st = sg.tiles[blockIdx.x];
+    const RadixSegInfo si = sg.segs[st.seg];
+    const BatchMesh& d = desc[st.seg];
+#pragma unroll 4
+    for (int it = 0; it < kRadixItems; ++it) {
+        const int j = it * kRadixThreads + t;
+        const bool valid = j < st.count;
+        uint32_t key = 0;
+        if (valid) {
+            const int64_t i = st.start + j;
+            key = morton30(q[3 * i], q[3 * i + 1], q[3 * i + 2], d.mlo[0], d.mlo[1], d.mlo[2], d.msc[0], d.msc[1],
+                           d.msc[2]) >> 6;
+            keys[i] = key;
         }
-        s_mesh = lo;
+        radix_hist_add(h, key & 255u, valid);
     }
     __syncthreads();
-    if (i >= n) return;
-    int32_t lo = s_mesh;
-    while (lo + 1 < count && qoff[lo + 1] <= i) ++lo;
-    const BatchMesh& d = desc[lo];
-    const float qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
-    const uint32_t full = morton30(qx, qy, qz, d.mlo[0], d.mlo[1], d.mlo[2], d.msc[0], d.msc[1], d.msc[2]);
-    keys[i] = full >> 6;  // the top 8 bits per axis
+    counts[si.base + (int64_t)t * si.cols + st.j] = h[t];
 }
 
 __global__ void k_reset(uint32_t* counter) {
@@ -320,8 +322,8 @@ p2m_status prepare(p2m_batch* b, const int64_t* qoff_host, hipStream_t st) {
     for (int64_t k : order)
         for (int64_t s = layout[(size_t)k]; s < layout[(size_t)k + 1]; s += tsize)
             tiles.push_back(Tile{(int32_t)k, (int32_t)s, (int32_t)std::min(tsize, layout[(size_t)k + 1] - s), 0});
-    const int64_t need = up256(8 * (int64_t)(b->count + 1)) + up256((int64_t)sizeof(Tile) * std::max<size_t>(1, tiles.size())) +
-                         256 + b_stiles + b_ssegs + up256(plan.bytes) + 32 * std::max<int64_t>(n, 1);
+    const int64_t need = up256((int64_t)sizeof(Tile) * std::max<size_t>(1, tiles.size())) + 256 + b_stiles + b_ssegs +
+                         up256(plan.bytes) + 32 * std::max<int64_t>(n, 1);
     if (need > b->work_bytes) {
         if (b->work) (void)hipFree(b->work);
         b->work = nullptr;
@@ -331,8 +333,6 @@ p2m_status prepare(p2m_batch* b, const int64_t* qoff_host, hipStream_t st) {
         b->work_bytes = need;
     }
     char* p = (char*)b->work;
-    b->qoff = (int64_t*)p;
-    p += up256(8 * (int64_t)(b->count + 1));
     b->tiles = (Tile*)p;
     p += up256((int64_t)sizeof(Tile) * std::max<size_t>(1, tiles.size()));
     b->counter = (uint32_t*)p;
@@ -346,8 +346,8 @@ p2m_status prepare(p2m_batch* b, const int64_t* qoff_host, hipStream_t st) {
     b->scratch = p;
     p += up256(plan.bytes);
     b->stage = (float4*)p;
-    hipError_t e = hipMemcpyAsync(b->qoff, layout.data(), 8 * layout.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && !tiles.empty())
+    hipError_t e = hipSuccess;
+    if (!tiles.empty())
         e = hipMemcpyAsync(b->tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !stiles.empty())
         e = hipMemcpyAsync((void*)b->sort_seg.tiles, stiles.data(), sizeof(RadixSegTile) * stiles.size(),
@@ -372,8 +372,9 @@ p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, 
     if (n == 0) return P2M_OK;
     RadixPlan plan = radix_plan_segmented(n, b->sort_seg.ntiles, b->sort_seg.nseg);
     RadixBuffers rb = radix_buffers(plan, b->scratch);
-    k_batch_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(q, n, b->qoff, b->count, b->desc, rb.keys[0]);
-    const int cur = radix_sort_pairs(plan, rb, 0, 24, false, st, &b->sort_seg);
+    k_batch_keys<<<(unsigned)b->sort_seg.ntiles, kRadixThreads, 0, st>>>(q, b->desc, b->sort_seg, rb.keys[0],
+                                                                          rb.counts);
+    const int cur = radix_sort_pairs(plan, rb, 0, 24, false, st, &b->sort_seg, true);
     k_reset<<<1, 64, 0, st>>>(b->counter);
     const int grid = b->grid;
     const Arena A{b->node,  b->vhead, b->lent, b->seg,  b->tri,  b->fedge,

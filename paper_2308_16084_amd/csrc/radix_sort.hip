@@ -56,10 +56,8 @@ __device__ __forceinline__ TileGeo tile_geo(int64_t n, int64_t tiles, const Radi
     return g;
 }
 
-// Digit counts of one tile in LDS.  When every valid lane of a wavefront
-// holds the same digit (runs of equal high digits in partly sorted keys,
-// e.g. the mesh index of a batch), the first lane adds the wavefront's count
-// with one atomic instead of 64 serialized ones on one counter.
+// Digit counts of one tile in LDS (radix_hist_add), written to the tile's
+// column of the count matrix.
 template <bool kSeg>
 __global__ __launch_bounds__(kT) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                    uint32_t* __restrict__ counts, int64_t tiles, RadixSegments sg) {
@@ -75,18 +73,7 @@ __global__ __launch_bounds__(kT) void k_radix_hist(const uint32_t* __restrict__ 
         key[it] = i < g.count ? keys[g.start + i] : 0u;
     }
 #pragma unroll
-    for (int it = 0; it < kI; ++it) {
-        const bool valid = it * kT + t < g.count;
-        const uint32_t d = (key[it] >> shift) & 255u;
-        const unsigned long long vm = __ballot(valid);
-        if (vm == 0ull) continue;
-        const uint32_t d0 = (uint32_t)__shfl(d, __ffsll((long long)vm) - 1);
-        if (__ballot(valid && d == d0) == vm) {
-            if (valid && __popcll(vm & ((1ull << (t & 63)) - 1ull)) == 0) atomicAdd(&h[d], (uint32_t)__popcll(vm));
-        } else if (valid) {
-            atomicAdd(&h[d], 1u);
-        }
-    }
+    for (int it = 0; it < kI; ++it) radix_hist_add(h, (key[it] >> shift) & 255u, it * kT + t < g.count);
     __syncthreads();
     counts[g.base + (int64_t)t * g.cols + g.j] = h[t];
 }
@@ -406,7 +393,7 @@ __global__ void k_iota(int32_t* __restrict__ v, int64_t n) {
 }
 
 int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit, bool keep_keys, hipStream_t st,
-                     const RadixSegments* seg) {
+                     const RadixSegments* seg, bool first_counts) {
     int cur = 0;
     if (p.n <= 0) return cur;
     if (p.n == 1 || lo_bit >= hi_bit) {  // nothing to sort: the identity permutation
@@ -423,7 +410,8 @@ int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit
                                                                b.sums, p.tiles, b.keys[cur ^ 1], b.vals[cur ^ 1], sg)
 #define P2M_PASS(S)                                                                                             \
     do {                                                                                                        \
-        k_radix_hist<S><<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], p.n, shift, b.counts, p.tiles, sg);      \
+        if (!(first && first_counts))                                                                           \
+            k_radix_hist<S><<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], p.n, shift, b.counts, p.tiles, sg);  \
         k_radix_colscan<S><<<cols_blocks, kT, 0, st>>>(b.counts, p.tiles, b.sums, sg);                          \
         if (first) {                                                                                            \
             if (keys_out) P2M_SCATTER(true, true, S);                                                           \
