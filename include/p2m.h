@@ -275,11 +275,19 @@ p2m_status p2m_batch_query(p2m_batch* b, const float* q_dev, const int64_t* q_of
 p2m_status p2m_batch_query_eager(p2m_batch* b, const float* q_dev, const int64_t* q_offsets_host, int32_t* prim_dev,
                                  float* closest_dev, float* dist_dev, void* stream);
 
-/* Launch shape of the persistent kernel: workgroup size (64, 128, 192 or
+/* Launch shape of the batched kernel: workgroup size (64, 128, 192 or
  * 256), queries per lane in a tile (1..16), nearest-vertex traversal (1, 2
  * or 3 as in p2m_query_opts; 3 when the batch is created). */
 p2m_status p2m_batch_set_shape(p2m_batch* b, int block, int queries_per_lane, int traversal);
 p2m_status p2m_batch_get_shape(const p2m_batch* b, int* block, int* queries_per_lane, int* traversal);
+
+/* Work distribution of the batched kernel: 0 (when the batch is created)
+ * launches one workgroup per tile of the largest-first tile list; 1
+ * launches as many workgroups as fit on the device, each taking tiles from
+ * an atomic counter until the list is exhausted.  Both give the same
+ * answers; P2M_ERR_ARG for another value. */
+p2m_status p2m_batch_set_schedule(p2m_batch* b, int persistent);
+p2m_status p2m_batch_get_schedule(const p2m_batch* b, int* persistent);
 
 /* Time every launch shape in {64,128,256} x {1,2,4} x {1,2,3} on these queries
  * (eager launches, two timed runs after a warm-up each) and keep the fastest;

@@ -70,6 +70,8 @@ _SIGS = {
     "p2m_batch_query_eager": (INT, [P, P, P, P, P, P, P]),
     "p2m_batch_set_shape": (INT, [P, INT, INT, INT]),
     "p2m_batch_get_shape": (INT, [P, P, P, P]),
+    "p2m_batch_set_schedule": (INT, [P, INT]),
+    "p2m_batch_get_schedule": (INT, [P, P]),
     "p2m_batch_autotune": (INT, [P, P, P, P, P, P, P, P, P, P]),
 }
 

@@ -326,6 +326,14 @@ class Batch:
         check(lib().p2m_batch_get_shape(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
 
+    def set_schedule(self, persistent: bool) -> None:
+        check(lib().p2m_batch_set_schedule(self._h, 1 if persistent else 0))
+
+    def schedule(self) -> bool:
+        x = ctypes.c_int()
+        check(lib().p2m_batch_get_schedule(self._h, ctypes.byref(x)))
+        return bool(x.value)
+
     def autotune(self, q, q_offsets, out: dict | None = None, stream=None) -> tuple[int, int, int]:
         torch = _torch()
         q = _dev_tensor(q, torch.float32, (3,), "q")

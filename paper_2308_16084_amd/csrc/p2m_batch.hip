@@ -7,9 +7,13 @@
 // queries are contiguous in the batch) orders each mesh's queries
 // spatially in place, in three 8-bit passes.
 // Work list: tiles (mesh, first sorted position, count) of block x qpl
-// queries, meshes with the most work first; each workgroup of the
-// persistent kernel takes the next tile from an atomic counter until the
-// list is exhausted, so every workgroup reaches the exit.
+// queries, meshes with the most work first.  By default the launch has one
+// workgroup per tile, in list order, and the hardware dispatcher hands the
+// workgroups to CUs as they free up (largest-first balancing for free).
+// The persistent schedule (p2m_batch_set_schedule) launches as many
+// workgroups as fit on the chip, each taking the next tile from an atomic
+// counter until the list is exhausted, so every workgroup reaches the exit;
+// on a batch of many small tiles its single counter serialises.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -117,6 +121,7 @@ struct p2m_batch {
     int tile_block = 0, tile_qpl = 0;
     // launch shape
     int block = 256, qpl = 1, traversal = 3;
+    int persistent = 0;  // 0: one workgroup per tile; 1: persistent workgroups and a tile counter
     int grid = 0;
     // captured graph
     hipStream_t cap_stream = nullptr;
@@ -194,7 +199,7 @@ size_t batch_lds_bytes(int block, int qpl) {
     return sizeof(uint32_t) * (kRegroupBins + 11 * (size_t)block * (size_t)regroup_rounds(block, qpl));
 }
 
-template <int kWalk>
+template <int kWalk, bool kPersistent>
 __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
     Arena A, const Tile* __restrict__ tiles, int64_t ntiles, uint32_t* counter, int qpl, int group,
     const float* __restrict__ q, const int32_t* __restrict__ perm, int64_t n, float4* __restrict__ stage) {
@@ -205,11 +210,16 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
     uint32_t* hist = lds;
     float* col = (float*)(lds + kRegroupBins);  // qx qy qz d2 px py pz, S each
     int32_t* icol = (int32_t*)(col + 7 * S);    // query index, vertex, bin << 24 | rank, source slot
-    for (;;) {
-        if (t == 0) s_tile = (int64_t)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int64_t tt = s_tile;
-        __syncthreads();
+    for (bool more = true; more;) {
+        int64_t tt = blockIdx.x;  // one tile per workgroup
+        more = false;
+        if (kPersistent) {
+            if (t == 0) s_tile = (int64_t)atomicAdd(counter, 1u);
+            __syncthreads();
+            tt = s_tile;
+            __syncthreads();
+            more = true;
+        }
         if (tt >= ntiles) break;  // uniform across the workgroup
         const Tile T = tiles[tt];
         const MeshView v = arena_view(A.desc[T.mesh], A.node, A.vhead, A.lent, A.seg, A.tri, A.fedge, A.nboff, A.nbrec,
@@ -376,15 +386,21 @@ p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, 
                                                                           rb.counts);
     const int cur = radix_sort_pairs(plan, rb, 0, 24, false, st, &b->sort_seg, true);
     k_reset<<<1, 64, 0, st>>>(b->counter);
-    const int grid = b->grid;
+    const int grid = b->persistent ? b->grid : (int)b->ntiles;
     const Arena A{b->node,  b->vhead, b->lent, b->seg,  b->tri,  b->fedge,
                   b->nboff, b->nbrec, b->seed, b->frec, b->erec, b->desc};
-#define P2M_LAUNCH_BATCH(W)                                                                                  \
-    k_batch_query<W><<<grid, b->block, batch_lds_bytes(b->block, b->qpl), st>>>(                           \
+#define P2M_LAUNCH_BATCH(W, P)                                                                               \
+    k_batch_query<W, P><<<grid, b->block, batch_lds_bytes(b->block, b->qpl), st>>>(                        \
         A, b->tiles, b->ntiles, b->counter, b->qpl, regroup_rounds(b->block, b->qpl), q, rb.vals[cur], n, b->stage)
-    if (b->traversal == 1) P2M_LAUNCH_BATCH(WALK_LANE);
-    else if (b->traversal == 2) P2M_LAUNCH_BATCH(WALK_WAVE);
-    else P2M_LAUNCH_BATCH(WALK_VORONOI);
+    if (b->persistent) {
+        if (b->traversal == 1) P2M_LAUNCH_BATCH(WALK_LANE, true);
+        else if (b->traversal == 2) P2M_LAUNCH_BATCH(WALK_WAVE, true);
+        else P2M_LAUNCH_BATCH(WALK_VORONOI, true);
+    } else {
+        if (b->traversal == 1) P2M_LAUNCH_BATCH(WALK_LANE, false);
+        else if (b->traversal == 2) P2M_LAUNCH_BATCH(WALK_WAVE, false);
+        else P2M_LAUNCH_BATCH(WALK_VORONOI, false);
+    }
 #undef P2M_LAUNCH_BATCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batched query launch");
@@ -397,9 +413,9 @@ p2m_status set_grid(p2m_batch* b) {
     int dev = b->device, cus = 0, per = 0;
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_fail(e, "device attribute");
-    const void* k = b->traversal == 1   ? (const void*)k_batch_query<WALK_LANE>
-                    : b->traversal == 2 ? (const void*)k_batch_query<WALK_WAVE>
-                                        : (const void*)k_batch_query<WALK_VORONOI>;
+    const void* k = b->traversal == 1   ? (const void*)k_batch_query<WALK_LANE, true>
+                    : b->traversal == 2 ? (const void*)k_batch_query<WALK_WAVE, true>
+                                        : (const void*)k_batch_query<WALK_VORONOI, true>;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, b->block, batch_lds_bytes(b->block, b->qpl));
     if (e != hipSuccess) return hip_fail(e, "occupancy query");
     b->grid = std::max(1, cus * std::max(1, per));
@@ -584,6 +600,20 @@ p2m_status p2m_batch_get_shape(const p2m_batch* b, int* block, int* qpl, int* tr
     if (block) *block = b->block;
     if (qpl) *qpl = b->qpl;
     if (traversal) *traversal = b->traversal;
+    return P2M_OK;
+}
+
+p2m_status p2m_batch_set_schedule(p2m_batch* b, int persistent) {
+    if (!b) return fail(P2M_ERR_ARG, "batch is NULL");
+    if (persistent != 0 && persistent != 1) return fail(P2M_ERR_ARG, "persistent must be 0 or 1");
+    if (b->persistent != persistent) drop_graph(b);
+    b->persistent = persistent;
+    return P2M_OK;
+}
+
+p2m_status p2m_batch_get_schedule(const p2m_batch* b, int* persistent) {
+    if (!b) return fail(P2M_ERR_ARG, "batch is NULL");
+    if (persistent) *persistent = b->persistent;
     return P2M_OK;
 }
 

@@ -101,6 +101,23 @@ def test_launch_shapes_give_same_answers(batch_setup, shape):
     assert np.max(np.abs(got["dist"] - ref["dist"])) <= 1e-5 * max(w.diag for w in works)
 
 
+def test_persistent_schedule_same_answers(batch_setup):
+    """One workgroup per tile (the default) and persistent workgroups taking
+    tiles from a counter give the same answers, bit for bit, graph and eager."""
+    works, meshes, b, Q, off, q = batch_setup
+    assert b.schedule() is False
+    ref = _np(b.query(q, off))
+    try:
+        b.set_schedule(True)
+        assert b.schedule() is True
+        for graph in (True, False):
+            got = _np(b.query(q, off, graph=graph))
+            for k in ref:
+                assert np.array_equal(got[k], ref[k]), (k, graph)
+    finally:
+        b.set_schedule(False)
+
+
 def test_autotune_and_layout_change(batch_setup):
     import torch
     works, meshes, b, Q, off, q = batch_setup
