@@ -199,6 +199,16 @@ size_t batch_lds_bytes(int block, int qpl) {
     return sizeof(uint32_t) * (kRegroupBins + 11 * (size_t)block * (size_t)regroup_rounds(block, qpl));
 }
 
+// One-workgroup-per-tile order: the tiles are dealt to the 8 XCDs
+// (workgroups go to them round-robin) in runs of kTileRun consecutive tiles,
+// so a run of one mesh's spatially adjacent tiles shares an L2; the grid is
+// a multiple of 8 * kTileRun and workgroups past the list exit at once.
+constexpr int64_t kTileRun = 16;
+__device__ __forceinline__ int64_t run_tile(int64_t b) {
+    const int64_t sg = b / (kXcds * kTileRun), r = b % (kXcds * kTileRun);
+    return sg * kXcds * kTileRun + (r % kXcds) * kTileRun + r / kXcds;
+}
+
 template <int kWalk, bool kPersistent>
 __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
     Arena A, const Tile* __restrict__ tiles, int64_t ntiles, uint32_t* counter, int qpl, int group,
@@ -211,7 +221,7 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
     float* col = (float*)(lds + kRegroupBins);  // qx qy qz d2 px py pz, S each
     int32_t* icol = (int32_t*)(col + 7 * S);    // query index, vertex, bin << 24 | rank, source slot
     for (bool more = true; more;) {
-        int64_t tt = blockIdx.x;  // one tile per workgroup
+        int64_t tt = run_tile(blockIdx.x);  // one tile per workgroup
         more = false;
         if (kPersistent) {
             if (t == 0) s_tile = (int64_t)atomicAdd(counter, 1u);
@@ -386,7 +396,8 @@ p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, 
                                                                           rb.counts);
     const int cur = radix_sort_pairs(plan, rb, 0, 24, false, st, &b->sort_seg, true);
     k_reset<<<1, 64, 0, st>>>(b->counter);
-    const int grid = b->persistent ? b->grid : (int)b->ntiles;
+    const int64_t run8 = kXcds * kTileRun;
+    const int grid = b->persistent ? b->grid : (int)((b->ntiles + run8 - 1) / run8 * run8);
     const Arena A{b->node,  b->vhead, b->lent, b->seg,  b->tri,  b->fedge,
                   b->nboff, b->nbrec, b->seed, b->frec, b->erec, b->desc};
 #define P2M_LAUNCH_BATCH(W, P)                                                                               \
