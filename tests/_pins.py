@@ -209,6 +209,116 @@ def pin_near_set_contains_best_and_ties(library=None):
     assert (2, 0) in ns
 
 
+# Exact near-optimal sets (tol 1e-6), derived by hand from the definition of
+# the set: a primitive belongs when its foot lies on it or within tol of it
+# (edge parameter in [-tol/|e|, 1+tol/|e|]; face foot within tol of the
+# closed triangle) and its line / plane distance is within tol of d*.  Every
+# other primitive is absent: farther, or its foot lies a finite distance
+# off it.  Rows: query, d*, members as (type, sorted vertex ids).
+_TETRA_NEAR = [
+    ((0.1, 0.2, 0.3), 0.1, {"F:0,2,3"}),
+    ((1, 1, 1), 2 / np.sqrt(3), {"F:1,2,3"}),
+    ((-1, -1, -1), np.sqrt(3), {"V:0"}),
+    # the edges at vertex 1 have their feet at t = 2 or t = -1/2; the faces
+    # at it have their feet 1 (or more) off them
+    ((2, 0, 0), 1.0, {"V:1"}),
+    ((0.5, -1, -1), np.sqrt(2), {"E:0,1"}),
+    ((0.25, 0.25, -1), 1.0, {"F:0,1,2"}),
+    # the z=0 face's foot (0.5,0.5,0) lies on its side (1,2): a tie at the boundary
+    ((0.5, 0.5, -1), 1.0, {"E:1,2", "F:0,1,2"}),
+    # on the edge (0,3): both faces at it have their foot on their boundary
+    ((0, 0, 0.5), 0.0, {"E:0,3", "F:0,2,3", "F:0,1,3"}),
+    ((0.2, 0.2, 0.2), 0.2, {"F:0,1,2", "F:0,1,3", "F:0,2,3"}),
+    ((0.25, 0.25, 0.25), 0.25 / np.sqrt(3), {"F:1,2,3"}),
+    # the x-axis edge (0,1) has its foot exactly at t = 0 (vertex 0), inside
+    # the relaxed gate, at the same distance sqrt(2) as vertex 0
+    ((0, -1, -1), np.sqrt(2), {"V:0", "E:0,1"}),
+]
+_CUBE_NEAR = [
+    # the face diagonals (1,7), (2,7) have their feet at t = 1, at 0.866 > d*
+    ((1.5, 1.5, 0.5), np.sqrt(0.5), {"E:3,7"}),
+    ((2, 2, 2), np.sqrt(3), {"V:7"}),
+    ((0.2, 0.3, 0.6), 0.2, {"F:0,4,6"}),
+    # the other z=0 triangle's foot is 0.05/sqrt(2) off it
+    ((0.3, 0.25, -0.5), 0.5, {"F:0,1,3"}),
+    # on the z=0 diagonal: both triangles have their foot on their boundary
+    ((0.5, 0.5, -2), 2.0, {"E:0,3", "F:0,1,3", "F:0,3,2"}),
+    ((-1, 0.5, 2), np.sqrt(2), {"E:4,6"}),
+    ((0.9, 0.6, 0.55), 0.1, {"F:1,3,7"}),
+    # the centre: all 12 triangles (feet at the square centres, on their
+    # diagonals) and the 6 diagonals at 0.5; the cube edges are at sqrt(0.5)
+    ((0.5, 0.5, 0.5), 0.5, {"F:0,2,6", "F:0,6,4", "F:1,3,7", "F:1,7,5", "F:0,1,5", "F:0,5,4", "F:2,3,7",
+                            "F:2,7,6", "F:0,1,3", "F:0,3,2", "F:4,5,7", "F:4,7,6", "E:0,6", "E:1,7",
+                            "E:0,5", "E:2,7", "E:0,3", "E:4,7"}),
+]
+
+
+def _named_set(om, ns):
+    out = set()
+    for t, i in ns:
+        vs = sorted(primitive_vertices(om.F, om.E, t, i))
+        out.add("VEF"[t] + ":" + ",".join(str(v) for v in vs))
+    return out
+
+
+def _check_near(V, F, rows, library):
+    om = oracle.OracleMesh(V, F, library)
+    for q, dstar, want in rows:
+        want = {w[:2] + ",".join(str(v) for v in sorted(int(x) for x in w[2:].split(","))) for w in want}
+        got = _named_set(om, om.near_set(np.array(q, np.float64), float(dstar), 1e-6))
+        assert got == want, (q, sorted(got), sorted(want))
+
+
+def pin_near_set_exact_tetrahedron(library=None):
+    """The near-optimal set holds exactly the hand-derived members: the best,
+    its rounding-level ties at a boundary, and nothing farther or off."""
+    _check_near(TETRA_V, TETRA_F, _TETRA_NEAR, library)
+
+
+def pin_near_set_exact_cube(library=None):
+    _check_near(CUBE_V, CUBE_F, _CUBE_NEAR, library)
+
+
+def pin_point_to_primitive_off_primitive(library=None):
+    """Distance from points off a closed primitive, against closed forms on
+    the unit cube: a vertex |x - v|; an axis-parallel cube edge along axis k
+    at fixed coordinates c_j (j != k): sqrt(sum_j (x_j - c_j)^2 + (x_k -
+    clamp(x_k, 0, 1))^2); a square face at x_a = s, split in two triangles:
+    the smaller of the two triangle distances equals sqrt((x_a - s)^2 +
+    sum_{j != a} (x_j - clamp(x_j, 0, 1))^2)."""
+    om = oracle.OracleMesh(CUBE_V, CUBE_F, library)
+    rng = np.random.default_rng(41)
+    X = rng.uniform(-1.0, 2.0, size=(400, 3))
+    Vd = CUBE_V.astype(np.float64)
+    edge_id = {tuple(e): k for k, e in enumerate(om.E.tolist())}
+    for x in X:
+        for v in range(8):
+            assert abs(om.point_to_primitive(0, v, x) - np.linalg.norm(x - Vd[v])) <= 1e-12
+        for (a, b), k in edge_id.items():
+            diff = np.abs(Vd[a] - Vd[b])
+            if diff.sum() != 1.0:
+                continue  # a face diagonal
+            ax = int(np.argmax(diff))
+            r = x - Vd[a]
+            r[ax] = x[ax] - np.clip(x[ax], 0.0, 1.0)
+            assert abs(om.point_to_primitive(1, k, x) - np.linalg.norm(r)) <= 1e-12, (a, b, x)
+        for f0 in range(0, 12, 2):
+            ax = int(np.argmin(np.ptp(Vd[CUBE_F[f0]], axis=0)))
+            s = Vd[CUBE_F[f0][0], ax]
+            r = x - np.clip(x, 0.0, 1.0)
+            r[ax] = x[ax] - s
+            d = min(om.point_to_primitive(2, f0, x), om.point_to_primitive(2, f0 + 1, x))
+            assert abs(d - np.linalg.norm(r)) <= 1e-12, (f0, x)
+    # tetrahedron: (2,0,0) is 1 from the slanted face (its closest point is
+    # the corner (1,0,0)), 2 from vertex 0, sqrt(2) from the edge (0,0,1)-(0,1,0)
+    ot = oracle.OracleMesh(TETRA_V, TETRA_F, library)
+    x = np.array([2.0, 0.0, 0.0])
+    assert abs(ot.point_to_primitive(2, 3, x) - 1.0) <= 1e-12
+    assert abs(ot.point_to_primitive(0, 0, x) - 2.0) <= 1e-12
+    e23 = [k for k, e in enumerate(ot.E.tolist()) if e == [2, 3]][0]
+    assert abs(ot.point_to_primitive(1, e23, x) - np.sqrt(4.5)) <= 1e-12
+
+
 _NOF = np.zeros((0, 3), np.int32)
 
 

@@ -27,6 +27,23 @@ MUTANTS = {
     "edge_t_wrong_denominator": ("double t = dot(sub(q, a), ab) / dot(ab, ab);\n    *t_out = t;",
                                  "double t = dot(sub(q, a), ab) / norm(ab);\n    *t_out = t;"),
     "cross_sign": ("a.z * b.x - a.x * b.z", "a.x * b.z - a.z * b.x"),
+    # the acceptance helpers: a near-optimal set that admits too much, a
+    # relaxed edge gate with the wrong sign, a point-to-primitive distance
+    # that ignores the point
+    "near_set_admits_every_face": ("if (off <= tol && norm(sub(q, p)) <= dstar + tol) {", "if (1) {"),
+    "near_set_admits_every_edge": ("if (!(t >= -r && t <= 1.0 + r)) continue;\n"
+                                   "        if (norm(sub(q, add(a, scl(ab, t)))) <= dstar + tol) {",
+                                   "if (1) {"),
+    "near_set_face_foot_ignored": ("if (off <= tol && norm(sub(q, p)) <= dstar + tol) {",
+                                   "if (norm(sub(q, p)) <= dstar + tol) {"),
+    "near_set_edge_gate_sign": ("if (!(t >= -r && t <= 1.0 + r)) continue;", "if (!(t >= r && t <= 1.0 + r)) continue;"),
+    "point_to_primitive_zero": ("d3 x = mk(x3[0], x3[1], x3[2]);\n    if (type == O_VERTEX)",
+                                "d3 x = mk(x3[0], x3[1], x3[2]);\n    return 0.0 * x.x;\n    if (type == O_VERTEX)"),
+    "point_to_primitive_face_plane_only": (
+        "d3 c = closest_on_triangle(x, at(V, F[3 * id]), at(V, F[3 * id + 1]), at(V, F[3 * id + 2]));\n"
+        "        return norm(sub(x, c));",
+        "double w[3];\n        d3 c = face_foot(x, at(V, F[3 * id]), at(V, F[3 * id + 1]), at(V, F[3 * id + 2]), w);\n"
+        "        return norm(sub(x, c));"),
 }
 
 
