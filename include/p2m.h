@@ -188,9 +188,12 @@ p2m_status p2m_load(const char* path, p2m_mesh** out);
  * queries: [0] nearest-vertex candidates evaluated (walk: neighbour
  * vertices; tree: nodes), [1] edge entries and [2] face entries scanned,
  * [3] walk steps (neighbour lists read), [4] edge and [5] face entries whose
- * box held q (their forms read and tested). */
+ * box held q (their forms read and tested), [6] queries whose list was
+ * scanned a second time because the gated ranking's winner was not
+ * provably the closest (see p2m_query) and [7] the exact primitive
+ * distances evaluated in those second scans. */
 p2m_status p2m_query_host(const p2m_mesh* m, const float* q, int64_t n, int32_t* prim, float* closest,
-                          float* dist, uint8_t* status, int num_threads, int64_t counters[6]);
+                          float* dist, uint8_t* status, int num_threads, int64_t counters[8]);
 
 const char* p2m_last_error(void);
 
@@ -205,7 +208,11 @@ p2m_status p2m_upload(p2m_mesh* m, int device, void* stream, int64_t* bytes);
 /* P2M query of n points q_dev float [n*3] (Algorithm A.2: nearest vertex,
  * then the gated tests of its interception list, Sec. 4.6 entry boxes
  * first; the winner re-evaluated with the exact closed segment / triangle
- * distance).  Outputs (device): prim int32 [n], closest float [n*3], dist
+ * distance; when that exact distance exceeds the winner's gated value (a
+ * face whose foot lies just off it, within the gate margin), a second scan
+ * evaluates exactly every candidate that could still be closer, so the
+ * answer is the exact minimum over the candidates up to float32 rounding,
+ * whatever the gate margin).  Outputs (device): prim int32 [n], closest float [n*3], dist
  * float [n]; status uint8 [n] (may be NULL).  For the backward pass, bary
  * float [n*3] and pvid int32 [n*3] (both NULL or both set) receive the
  * closest point's barycentric weights over the primitive's vertices (unused
@@ -244,7 +251,10 @@ p2m_status p2m_order_queries(p2m_mesh* m, const float* q_dev, int64_t n, uint32_
  *   grad_q[i]   = g[i] (q_i - c_i) / d_i            (0 when d_i = 0)
  *   grad_V[k]  += -g[i] w_ik (q_i - c_i) / d_i      (float atomics)
  * grad_dist_dev float [n]; grad_q_dev float [n*3] is overwritten (may be
- * NULL); grad_V_dev float [nv*3] is accumulated into (may be NULL). */
+ * NULL); grad_V_dev float [nv*3] is accumulated into (may be NULL; one row
+ * per mesh vertex, 16-byte aligned, else P2M_ERR_ARG: large meshes update
+ * it four floats at a time).  closest/dist/bary/pvid are the forward's
+ * outputs for the same q. */
 p2m_status p2m_query_backward(p2m_mesh* m, const float* q_dev, int64_t n, const float* closest_dev,
                               const float* dist_dev, const float* bary_dev, const int32_t* pvid_dev,
                               const float* grad_dist_dev, float* grad_q_dev, float* grad_V_dev, void* stream);

@@ -198,12 +198,13 @@ class Mesh:
         closest = np.zeros((n, 3), np.float32)
         dist = np.zeros(n, np.float32)
         status = np.zeros(n, np.uint8)
-        cnt = np.zeros(6, np.int64)
+        cnt = np.zeros(8, np.int64)
         check(lib().p2m_query_host(self._h, _ptr(q), n, _ptr(prim), _ptr(closest), _ptr(dist), _ptr(status),
                                    int(threads), _ptr(cnt)))
         return {"prim": prim, "closest": closest, "dist": dist, "status": status,
                 "nodes": int(cnt[0]), "edges": int(cnt[1]), "faces": int(cnt[2]), "steps": int(cnt[3]),
-                "edge_forms": int(cnt[4]), "face_forms": int(cnt[5])}
+                "edge_forms": int(cnt[4]), "face_forms": int(cnt[5]), "rescans": int(cnt[6]),
+                "rescan_exact": int(cnt[7])}
 
     # ----------------------------------------------------------- device
     def upload(self, device: int = 0, stream=None) -> int:
@@ -233,9 +234,10 @@ class Mesh:
         o.block_size = int(block_size)
         o.profile = 1 if profile else 0
         o.traversal = int(traversal)
-        check(lib().p2m_query(self._h, _ptr(q), n, _ptr(out["prim"]), _ptr(out["closest"]), _ptr(out["dist"]),
-                              _ptr(out.get("status")), _ptr(out.get("bary")), _ptr(out.get("pvid")),
-                              ctypes.byref(o), _stream(stream)))
+        fn = lib().p2m_query
+        check(fn(self._h, _ptr(q), n, _ptr(out["prim"]), _ptr(out["closest"]), _ptr(out["dist"]),
+                 _ptr(out.get("status")), _ptr(out.get("bary")), _ptr(out.get("pvid")), ctypes.byref(o),
+                 _stream(stream)))
         return out
 
     def query_profile(self) -> tuple[float, float, float]:
@@ -265,9 +267,26 @@ class Mesh:
     def query_backward(self, q, fwd: dict, grad_dist, grad_q=True, grad_V=None, stream=None):
         """grad_q [n,3] (new tensor or None) and grad_V accumulated into the given [nv,3] tensor."""
         torch = _torch()
+        q = _dev_tensor(q, torch.float32, (3,), "q")
         n = q.shape[0]
+        for k, tail, dt in (("closest", (3,), torch.float32), ("bary", (3,), torch.float32),
+                            ("pvid", (3,), torch.int32)):
+            if fwd.get(k) is not None:
+                _dev_tensor(fwd[k], dt, tail, k)
+                if fwd[k].shape[0] != n:
+                    raise ValueError(f"{k} must have {n} rows")
+        if fwd["dist"].shape != (n,) or fwd["dist"].dtype != torch.float32 or not fwd["dist"].is_contiguous():
+            raise ValueError(f"dist must be a contiguous float32 tensor of shape [{n}]")
+        if grad_V is not None:
+            _dev_tensor(grad_V, torch.float32, (3,), "grad_V")
+            if grad_V.shape[0] != self.nv:
+                raise ValueError(f"grad_V must have shape [{self.nv}, 3] (one row per mesh vertex)")
+            if grad_V.data_ptr() % 16:
+                raise ValueError("grad_V must be 16-byte aligned")
         gq = torch.empty((n, 3), dtype=torch.float32, device=q.device) if grad_q else None
         grad_dist = grad_dist.contiguous().to(torch.float32)
+        if grad_dist.shape != (n,) or grad_dist.device != q.device:
+            raise ValueError(f"grad_dist must have shape [{n}] on the queries' device")
         check(lib().p2m_query_backward(self._h, _ptr(q), n, _ptr(fwd["closest"]), _ptr(fwd["dist"]),
                                        _ptr(fwd.get("bary")), _ptr(fwd.get("pvid")), _ptr(grad_dist),
                                        _ptr(gq), _ptr(grad_V), _stream(stream)))
@@ -370,12 +389,19 @@ def _make_function():
         """dist = P2MDistance.apply(q, V, mesh): unsigned point-to-mesh distance.
 
         Forward runs the P2M query kernel; backward runs the hand-written
-        backward kernel, giving d dist / d q and d dist / d V (V is the
-        mesh's vertex-position tensor, [nv,3] float32 on the same device).
+        backward kernel, giving d dist / d q and d dist / d V.  V is the
+        mesh's vertex-position tensor, [nv,3] float32 on the queries' device;
+        the forward answers from the positions the mesh was precomputed and
+        uploaded with, so V must hold those positions (after V changes, build
+        and upload the mesh again).
         """
 
         @staticmethod
         def forward(ctx, q, V, mesh):
+            if not isinstance(V, torch.Tensor) or V.dtype != torch.float32 or tuple(V.shape) != (mesh.nv, 3):
+                raise ValueError(f"V must be a float32 tensor of shape [{mesh.nv}, 3] (the mesh's vertices)")
+            if V.device != q.device:
+                raise ValueError("V must be on the queries' device")
             fwd = mesh.query(q.detach().contiguous(), for_backward=True, status=False)
             ctx.mesh = mesh
             ctx.save_for_backward(q, fwd["closest"], fwd["dist"], fwd["bary"], fwd["pvid"])

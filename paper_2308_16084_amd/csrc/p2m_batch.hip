@@ -44,6 +44,7 @@ struct BatchMesh {
     float mlo[3], msc[3];  // Morton quantisation of the domain
     float gscale[3];       // seed grid cells per unit length (grid origin = dlo)
     float ctr[3], mu;      // origin and gate margin of the list-scan forms
+    float eta;             // absolute slack of the winner check
     float qlo[3], qs[3];   // 16-bit frame of D for the entry boxes
 };
 
@@ -70,6 +71,7 @@ __host__ __device__ inline MeshView arena_view(const BatchMesh& d, const KdNode*
     v.frec = frec + d.frec;
     v.erec = erec + d.erec;
     v.mu = d.mu;
+    v.eta = d.eta;
     v.grid = d.grid;
     for (int k = 0; k < 3; ++k) {
         v.dlo[k] = d.dlo[k];
@@ -509,6 +511,7 @@ p2m_status p2m_batch_create(p2m_mesh* const* meshes, int32_t count, int device, 
             d.qs[c] = hv.qs[c];
         }
         d.mu = hv.mu;
+        d.eta = hv.eta;
         node.insert(node.end(), s.pk_node.begin(), s.pk_node.end());
         vhead.insert(vhead.end(), s.pk_vhead.begin(), s.pk_vhead.end());
         lent.insert(lent.end(), s.pk_lent.begin(), s.pk_lent.end());

@@ -258,6 +258,18 @@ void pack_mesh(MeshState& s) {
     s.packed = true;
 }
 
+// Absolute slack of the winner check (query_core.hpp, step 4): 2^-21 of the
+// mesh's diagonal plus its largest coordinate magnitude, a few times the
+// float32 rounding of a distance computed near the mesh.
+float winner_slack(const MeshState& s) {
+    double diag2 = 0.0, amax = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        diag2 += (s.m.hi[k] - s.m.lo[k]) * (s.m.hi[k] - s.m.lo[k]);
+        amax = std::max(amax, std::max(std::fabs(s.m.lo[k]), std::fabs(s.m.hi[k])));
+    }
+    return (float)std::ldexp(std::sqrt(diag2) + amax, -21);
+}
+
 MeshView host_view(const MeshState& s) {
     MeshView v;
     v.node = (const KdNode*)s.pk_node.data();
@@ -271,6 +283,7 @@ MeshView host_view(const MeshState& s) {
     v.erec = (const float4*)s.pk_erec.data();
     for (int k = 0; k < 3; ++k) v.ctr[k] = s.ctr[k];
     v.mu = s.mu;
+    v.eta = winner_slack(s);
     for (int k = 0; k < 3; ++k) {
         v.qlo[k] = (float)s.dlo[k];
         v.qs[k] = (float)(65535.0 / (s.dhi[k] - s.dlo[k]));
@@ -850,28 +863,37 @@ static p2m_status ensure_scratch(MeshState& s, int64_t bytes) {
 
 // Morton keys + stable sort by key bits [lo_bit, 30) into scratch; returns
 // the permutation pointer, and the sorted keys when keys_out is not NULL.  `extra` bytes of scratch after the sort's own
-// (256-byte aligned) are returned in *extra_out.
-static p2m_status order_into_scratch(MeshState& s, const float* q, int64_t n, int lo_bit, hipStream_t st,
-                                     uint32_t** keys_out, int32_t** perm_out, int64_t extra = 0,
-                                     void** extra_out = nullptr) {
+// (256-byte aligned) are returned in *extra_out (order_into_scratch below).
+static int64_t order_scratch_bytes(int64_t n) { return (radix_plan(n).bytes + 255) / 256 * 256; }
+
+// The same into a given device buffer of at least order_scratch_bytes(n) +
+// extra bytes (256-byte aligned).
+static p2m_status order_into(MeshState& s, void* base, const float* q, int64_t n, int lo_bit, hipStream_t st,
+                             uint32_t** keys_out, int32_t** perm_out, void** extra_out) {
     RadixPlan plan = radix_plan(n);
-    const int64_t sort_bytes = (plan.bytes + 255) / 256 * 256;
-    p2m_status r = ensure_scratch(s, sort_bytes + extra);
-    if (r != P2M_OK) return r;
-    RadixBuffers b = radix_buffers(plan, s.dev.scratch);
+    const int64_t sort_bytes = order_scratch_bytes(n);
+    RadixBuffers b = radix_buffers(plan, base);
     float lo[3], sc[3];
     morton_params(s.dlo, s.dhi, lo, sc);
     const int64_t blocks = (n + 255) / 256;
     k_morton<<<(unsigned)blocks, 256, 0, st>>>(q, n, lo[0], lo[1], lo[2], sc[0], sc[1], sc[2], b.keys[0]);
-    r = check_launch("morton keys");
+    p2m_status r = check_launch("morton keys");
     if (r != P2M_OK) return r;
     int cur = radix_sort_pairs(plan, b, lo_bit, 30, keys_out != nullptr, st);
     r = check_launch("radix sort");
     if (r != P2M_OK) return r;
     if (keys_out) *keys_out = b.keys[cur];
     *perm_out = b.vals[cur];
-    if (extra_out) *extra_out = (char*)s.dev.scratch + sort_bytes;
+    if (extra_out) *extra_out = (char*)base + sort_bytes;
     return P2M_OK;
+}
+
+static p2m_status order_into_scratch(MeshState& s, const float* q, int64_t n, int lo_bit, hipStream_t st,
+                                     uint32_t** keys_out, int32_t** perm_out, int64_t extra = 0,
+                                     void** extra_out = nullptr) {
+    p2m_status r = ensure_scratch(s, order_scratch_bytes(n) + extra);
+    if (r != P2M_OK) return r;
+    return order_into(s, s.dev.scratch, q, n, lo_bit, st, keys_out, perm_out, extra_out);
 }
 
 }  // namespace p2m
@@ -981,8 +1003,13 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
     return P2M_OK;
 }
 
-p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, float* closest, float* dist,
-                     uint8_t* status, float* bary, int32_t* pvid, const p2m_query_opts* opts, void* stream) {
+}  // extern "C"
+
+namespace p2m {
+
+// The query of p2m_query.
+static p2m_status run_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, float* closest, float* dist,
+                            uint8_t* status, float* bary, int32_t* pvid, const p2m_query_opts* opts, void* stream) {
     if (!mh) return fail(P2M_ERR_ARG, "mesh is NULL");
     MeshState& s = mh->s;
     if (n < 0) return fail(P2M_ERR_ARG, "negative query count");
@@ -1050,6 +1077,15 @@ p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, flo
         s.dev.ev_sorted = sort != 0;
     }
     return r;
+}
+
+}  // namespace p2m
+
+extern "C" {
+
+p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, float* closest, float* dist,
+                     uint8_t* status, float* bary, int32_t* pvid, const p2m_query_opts* opts, void* stream) {
+    return run_query(mh, q, n, prim, closest, dist, status, bary, pvid, opts, stream);
 }
 
 p2m_status p2m_query_profile(p2m_mesh* mh, float* order_ms, float* query_ms, float* finish_ms) {
@@ -1121,6 +1157,7 @@ p2m_status p2m_query_backward(p2m_mesh* mh, const float* q, int64_t n, const flo
     if (n == 0) return P2M_OK;
     if (!q || !closest || !dist || !gd) return fail(P2M_ERR_ARG, "NULL pointer");
     if (gV && (!bary || !pvid)) return fail(P2M_ERR_ARG, "grad_V needs bary and pvid from the forward");
+    if (gV && ((uintptr_t)gV & 15u)) return fail(P2M_ERR_ARG, "grad_V must be 16-byte aligned");
     DeviceGuard g(s.dev.device);
     hipStream_t st = (hipStream_t)stream;
     const int64_t nv = s.m.nv;
@@ -1154,7 +1191,7 @@ p2m_status p2m_query_backward(p2m_mesh* mh, const float* q, int64_t n, const flo
 }
 
 p2m_status p2m_query_host(const p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, float* closest, float* dist,
-                          uint8_t* status, int num_threads, int64_t counters[6]) {
+                          uint8_t* status, int num_threads, int64_t counters[8]) {
     if (!mh) return fail(P2M_ERR_ARG, "mesh is NULL");
     MeshState& s = const_cast<MeshState&>(mh->s);
     if (!s.precomputed) return fail(P2M_ERR_STATE, "p2m_query_host before p2m_precompute");
@@ -1190,7 +1227,7 @@ p2m_status p2m_query_host(const p2m_mesh* mh, const float* q, int64_t n, int32_t
     work(0);
     for (auto& x : th) x.join();
     if (counters) {
-        for (int k = 0; k < 6; ++k) counters[k] = 0;
+        for (int k = 0; k < 8; ++k) counters[k] = 0;
         for (auto& c : cnt) {
             counters[0] += c.nodes;
             counters[1] += c.edges;
@@ -1198,6 +1235,8 @@ p2m_status p2m_query_host(const p2m_mesh* mh, const float* q, int64_t n, int32_t
             counters[3] += c.steps;
             counters[4] += c.edge_forms;
             counters[5] += c.face_forms;
+            counters[6] += c.rescans;
+            counters[7] += c.rescan_exact;
         }
     }
     return P2M_OK;

@@ -19,6 +19,18 @@
 //  4. the winner alone is re-evaluated with the exact closed segment /
 //     triangle distance, whose clamp region (inside, on a side, at a corner)
 //     names the primitive returned, its closest point and weights.
+//     A gated value is the distance to the primitive's plane (a face), or
+//     to its line plus the foot's overshoot beyond the nearer end (an edge),
+//     never more than the exact distance to the closed primitive and equal
+//     to it when q's foot lies on the primitive (always, for an edge).  So
+//     when the winner's exact distance does not exceed its own gated value,
+//     no other candidate can be closer; otherwise (a face that passed its
+//     gate within the margin, its foot just off it) the list is scanned
+//     again and every candidate whose gated value is below the best exact
+//     distance so far is evaluated exactly.  The answer is then the exact
+//     minimum over the candidates, whatever the margin, up to float32
+//     rounding and a slack of 2^-20 relative plus eta absolute (eta: 2^-21
+//     of the mesh's size).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -61,6 +73,7 @@ struct MeshView {
     const float4* erec;     // [2ne]
     float ctr[3];           // centre of the domain box, rounded to float
     float mu;               // gate margin
+    float eta;              // absolute slack of the winner check (step 4)
     float qlo[3], qs[3];    // 16-bit frame of D for the entry boxes
     float dlo[3], dhi[3];   // query domain rounded outward to float
     // Voronoi-neighbour walk (optional; null when absent)
@@ -337,6 +350,39 @@ P2M_HD float tri_d2(float qx, float qy, float qz, const float4& a, const float4&
     return d;
 }
 
+// Whether the foot of q on the plane of (a,b,c) lies in the closed triangle:
+// each side's edge-normal test signed against the face normal (the foot
+// itself is not formed: q - foot is along the normal).
+// tri_dist2: squared distance from q to the closed triangle alone, with few
+// registers (for the rare margin cases): the plane distance when the foot
+// lies in the triangle, else the nearest side's segment distance.  Near a
+// side both give nearly the same value, so a rounding slip of the inside
+// test costs only rounding.
+P2M_HD bool foot_in_triangle(float qx, float qy, float qz, const float4& a, const float4& b, const float4& c) {
+    const float abx = b.x - a.x, aby = b.y - a.y, abz = b.z - a.z;
+    const float acx = c.x - a.x, acy = c.y - a.y, acz = c.z - a.z;
+    const float nx = aby * acz - abz * acy, ny = abz * acx - abx * acz, nz = abx * acy - aby * acx;
+    auto side = [&](const float4& u, const float4& w) {
+        const float ex = w.x - u.x, ey = w.y - u.y, ez = w.z - u.z;
+        const float px = qx - u.x, py = qy - u.y, pz = qz - u.z;
+        return (ey * pz - ez * py) * nx + (ez * px - ex * pz) * ny + (ex * py - ey * px) * nz >= 0.f;
+    };
+    return side(a, b) && side(b, c) && side(c, a);
+}
+
+P2M_HD float tri_dist2(float qx, float qy, float qz, const float4& a, const float4& b, const float4& c) {
+    if (foot_in_triangle(qx, qy, qz, a, b, c)) {
+        const float abx = b.x - a.x, aby = b.y - a.y, abz = b.z - a.z;
+        const float acx = c.x - a.x, acy = c.y - a.y, acz = c.z - a.z;
+        const float nx = aby * acz - abz * acy, ny = abz * acx - abx * acz, nz = abx * acy - aby * acx;
+        const float h = (qx - a.x) * nx + (qy - a.y) * ny + (qz - a.z) * nz;
+        return h * (h / (nx * nx + ny * ny + nz * nz));
+    }
+    float t;
+    int r;
+    return fminf(fminf(seg_d2(qx, qy, qz, a, b, t, r), seg_d2(qx, qy, qz, b, c, t, r)), seg_d2(qx, qy, qz, c, a, t, r));
+}
+
 struct Answer {
     int32_t prim;            // type << 30 | id
     float cx, cy, cz, dist;
@@ -349,6 +395,7 @@ P2M_HD int32_t make_prim(int kind, int32_t id) { return (int32_t)(((uint32_t)kin
 struct ScanCounters {
     uint64_t nodes = 0, edges = 0, faces = 0, steps = 0;  // nodes: nearest-vertex candidates
     uint64_t edge_forms = 0, face_forms = 0;              // entries whose box held q
+    uint64_t rescans = 0, rescan_exact = 0;               // second scans; exact evaluations in them
 };
 
 P2M_HD Answer nonfinite_answer() {
@@ -365,14 +412,17 @@ P2M_HD uint8_t domain_status(const MeshView& m, float qx, float qy, float qz) {
 }
 
 // Steps 2-3 given the nearest vertex: list scan and the resolved answer.
-// Gated squared distance to the line of edge e (infinite when q's foot is
-// more than mu beyond an end); r* = q - ctr.
+// Gated squared distance to edge e (infinite when q's foot is more than mu
+// beyond an end): the squared distance to its line plus the square of the
+// foot's overshoot beyond the nearer end, i.e. the squared distance to the
+// closed segment for a foot within the margin; r* = q - ctr.
 P2M_HD float edge_gate_d2(const MeshView& m, int32_t e, float rx, float ry, float rz) {
     const float4 A = m.erec[2 * e], U = m.erec[2 * e + 1];
     const float wx = rx - A.x, wy = ry - A.y, wz = rz - A.z;
     const float t = wx * U.x + wy * U.y + wz * U.z;
     const float cx = wx - t * U.x, cy = wy - t * U.y, cz = wz - t * U.z;
-    const float d = cx * cx + cy * cy + cz * cz;
+    const float o = fmaxf(fmaxf(-t, t - A.w), 0.f);
+    const float d = cx * cx + cy * cy + cz * cz + o * o;
     const bool in = (t >= -m.mu) & (t <= A.w + m.mu);  // no short-circuit: branch-free
     return in ? d : INFINITY;
 }
@@ -422,9 +472,136 @@ P2M_HD float frame5(float u, uint32_t lo, uint32_t hi) {
     return fminf(fmaxf((u - (float)lo) * (31.f / span), 0.f), 31.f);
 }
 
+// Exact evaluation of candidate (kind, id) of the scan: fills a (reported
+// primitive from the clamp region, closest point, weights and vertex ids)
+// and returns the exact squared distance to the closed segment / triangle
+// (a vertex candidate is the nearest vertex nv).
+P2M_HD float resolve(const MeshView& m, float qx, float qy, float qz, const Nearest& nv, int kind, int32_t id,
+                     Answer& a) {
+    float exact = nv.d2;
+    a.w[0] = 1.f;
+    a.w[1] = a.w[2] = 0.f;
+    a.pv[1] = a.pv[2] = -1;
+    if (kind == KIND_VERTEX) {
+        a.prim = make_prim(KIND_VERTEX, nv.vid);
+        a.cx = nv.px;
+        a.cy = nv.py;
+        a.cz = nv.pz;
+        a.pv[0] = nv.vid;
+    } else if (kind == KIND_EDGE) {
+        const float4 A = m.seg[2 * id], B = m.seg[2 * id + 1];
+        float t;
+        int r;
+        exact = seg_d2(qx, qy, qz, A, B, t, r);
+        a.cx = A.x + t * (B.x - A.x);
+        a.cy = A.y + t * (B.y - A.y);
+        a.cz = A.z + t * (B.z - A.z);
+        if (r == 0) {
+            a.prim = make_prim(KIND_EDGE, id);
+            a.w[0] = 1.f - t;
+            a.w[1] = t;
+            a.pv[0] = as_int(A.w);
+            a.pv[1] = as_int(B.w);
+        } else {
+            const int32_t pid = as_int(r == 1 ? A.w : B.w);
+            a.prim = make_prim(KIND_VERTEX, pid);
+            a.cx = r == 1 ? A.x : B.x;
+            a.cy = r == 1 ? A.y : B.y;
+            a.cz = r == 1 ? A.z : B.z;
+            a.pv[0] = pid;
+        }
+    } else {
+        const float4 A = m.tri[3 * id], B = m.tri[3 * id + 1], C = m.tri[3 * id + 2];
+        float w0, w1, w2;
+        int r;
+        exact = tri_d2(qx, qy, qz, A, B, C, w0, w1, w2, r, a.cx, a.cy, a.cz);
+        const int32_t ia = as_int(A.w), ib = as_int(B.w), ic = as_int(C.w);
+        if (r == 0) {
+            a.prim = make_prim(KIND_FACE, id);
+            a.w[0] = w0;
+            a.w[1] = w1;
+            a.w[2] = w2;
+            a.pv[0] = ia;
+            a.pv[1] = ib;
+            a.pv[2] = ic;
+        } else if (r <= 3) {
+            const int side = r - 1;  // from corner side to corner side+1
+            a.prim = make_prim(KIND_EDGE, m.fedge[4 * id + side]);
+            a.w[0] = side == 0 ? w0 : (side == 1 ? w1 : w2);
+            a.w[1] = side == 0 ? w1 : (side == 1 ? w2 : w0);
+            a.pv[0] = side == 0 ? ia : (side == 1 ? ib : ic);
+            a.pv[1] = side == 0 ? ib : (side == 1 ? ic : ia);
+        } else {
+            const int corner = r - 4;
+            const int32_t pid = corner == 0 ? ia : (corner == 1 ? ib : ic);
+            a.prim = make_prim(KIND_VERTEX, pid);
+            a.cx = corner == 0 ? A.x : (corner == 1 ? B.x : C.x);
+            a.cy = corner == 0 ? A.y : (corner == 1 ? B.y : C.y);
+            a.cz = corner == 0 ? A.z : (corner == 1 ? B.z : C.z);
+            a.pv[0] = pid;
+        }
+    }
+    return exact;
+}
+
+// q in the 5-bit frame of v's list box (h1 = vhead[2v+1]): q in the 16-bit
+// frame of D, clamped to it (a query outside D is answered as an upper
+// bound), then rescaled to the list box.
+P2M_HD Cell5 list_cell(const MeshView& m, float qx, float qy, float qz, const uint4& h1) {
+    const float ux = fminf(fmaxf((qx - m.qlo[0]) * m.qs[0], 0.f), 65535.f);
+    const float uy = fminf(fmaxf((qy - m.qlo[1]) * m.qs[1], 0.f), 65535.f);
+    const float uz = fminf(fmaxf((qz - m.qlo[2]) * m.qs[2], 0.f), 65535.f);
+    return cell5(frame5(ux, h1.x & 0xffffu, h1.y >> 16), frame5(uy, h1.x >> 16, h1.z & 0xffffu),
+                 frame5(uz, h1.y & 0xffffu, h1.z >> 16));
+}
+
+// Second scan of list(v), taken only when the winner of the gated ranking
+// is not provably the closest (step 4): every candidate (box holds q, gate
+// passes) whose gated value is below the best exact squared distance so far
+// is evaluated exactly; (cur, kind, id) hold that best on entry and on exit.
+// The list head and q's frame are read again here rather than kept live
+// through the scan (fewer registers for the common path).
+P2M_HD void rescan(const MeshView& m, float qx, float qy, float qz, int32_t v, float& cur, int& kind, int32_t& id,
+                   ScanCounters& cnt) {
+    const uint4 h0 = m.vhead[2 * v], h1 = m.vhead[2 * v + 1];
+    const Cell5 qc = list_cell(m, qx, qy, qz, h1);
+    const float rx = qx - m.ctr[0], ry = qy - m.ctr[1], rz = qz - m.ctr[2];
+#pragma unroll 1
+    for (uint32_t k = h0.x; k < h0.y; ++k) {
+        const uint4 A = m.lent[k >> 1];
+        const uint32_t pid = (k & 1u) ? A.z : A.x, box = (k & 1u) ? A.w : A.y;
+        if (!in_box5(box, qc) || !(edge_gate_d2(m, (int32_t)pid, rx, ry, rz) < cur)) continue;
+        ++cnt.rescan_exact;
+        float t;
+        int r;
+        const float ex = seg_d2(qx, qy, qz, m.seg[2 * pid], m.seg[2 * pid + 1], t, r);
+        if (ex < cur) {
+            cur = ex;
+            kind = KIND_EDGE;
+            id = (int32_t)pid;
+        }
+    }
+#pragma unroll 1
+    for (uint32_t k = h0.y; k < h0.z; ++k) {
+        const uint4 A = m.lent[k >> 1];
+        const uint32_t pid = (k & 1u) ? A.z : A.x, box = (k & 1u) ? A.w : A.y;
+        if (!in_box5(box, qc) || !(face_gate_d2(m, (int32_t)pid, rx, ry, rz) < cur)) continue;
+        ++cnt.rescan_exact;
+        const float ex = tri_dist2(qx, qy, qz, m.tri[3 * pid], m.tri[3 * pid + 1], m.tri[3 * pid + 2]);
+        if (ex < cur) {
+            cur = ex;
+            kind = KIND_FACE;
+            id = (int32_t)pid;
+        }
+    }
+}
+
+constexpr float kAcceptRel = 1.00000095367431640625f;  // 1 + 2^-20
+
 P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const Nearest& nv, ScanCounters& cnt) {
     Answer a;
-    // running minimum over v and v's list; kind/id of the best
+    // running minimum of the gated values over v and v's list (kind/id of
+    // the best)
     float best = nv.d2;
     int best_kind = KIND_VERTEX;
     int32_t best_id = nv.vid;
@@ -432,16 +609,8 @@ P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const 
     const uint4 h0 = m.vhead[2 * nv.vid], h1 = m.vhead[2 * nv.vid + 1];
     const uint32_t e0 = h0.x, f0 = h0.y, f1 = h0.z;
     // Entry boxes first (Sec. 4.6): an entry whose box does not hold q is
-    // skipped without reading its forms.  q in the 16-bit frame of D,
-    // clamped to it (a query outside D is answered as an upper bound), then
-    // in the 5-bit frame of the list box.
-    const float ux = fminf(fmaxf((qx - m.qlo[0]) * m.qs[0], 0.f), 65535.f);
-    const float uy = fminf(fmaxf((qy - m.qlo[1]) * m.qs[1], 0.f), 65535.f);
-    const float uz = fminf(fmaxf((qz - m.qlo[2]) * m.qs[2], 0.f), 65535.f);
-    const float sx = frame5(ux, h1.x & 0xffffu, h1.y >> 16);
-    const float sy = frame5(uy, h1.x >> 16, h1.z & 0xffffu);
-    const float sz = frame5(uz, h1.y & 0xffffu, h1.z >> 16);
-    const Cell5 qc = cell5(sx, sy, sz);
+    // skipped without reading its forms.
+    const Cell5 qc = list_cell(m, qx, qy, qz, h1);
     // Four entries (two 16-byte loads) per step: all their boxes, then the
     // forms of those whose box holds q, are loaded before any is evaluated,
     // so a lane keeps several independent loads in flight.  Runs have even
@@ -458,12 +627,13 @@ P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const 
             d[u] = hit ? edge_gate_d2(m, (int32_t)id[u], rx, ry, rz) : INFINITY;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u) {
             if (d[u] < best) {
                 best = d[u];
                 best_kind = KIND_EDGE;
                 best_id = (int32_t)id[u];
             }
+        }
     }
     for (uint32_t k = f0; k < f1; k += 4) {
         const uint4 A = m.lent[k >> 1], B = m.lent[(k + 2 < f1 ? k + 2 : k) >> 1];
@@ -476,82 +646,44 @@ P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const 
             d[u] = hit ? face_gate_d2(m, (int32_t)id[u], rx, ry, rz) : INFINITY;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u) {
             if (d[u] < best) {
                 best = d[u];
                 best_kind = KIND_FACE;
                 best_id = (int32_t)id[u];
             }
+        }
     }
     cnt.edges += f0 - e0;
     cnt.faces += f1 - f0;
-    // resolve the winner exactly: distance, closest point, weights and the
-    // reported primitive from the closed segment / triangle
-    float exact = nv.d2;
-    a.w[0] = 1.f;
-    a.w[1] = a.w[2] = 0.f;
-    a.pv[1] = a.pv[2] = -1;
-    if (best_kind == KIND_VERTEX) {
-        a.prim = make_prim(KIND_VERTEX, nv.vid);
-        a.cx = nv.px;
-        a.cy = nv.py;
-        a.cz = nv.pz;
-        a.pv[0] = nv.vid;
-    } else if (best_kind == KIND_EDGE) {
-        const float4 A = m.seg[2 * best_id], B = m.seg[2 * best_id + 1];
-        float t;
-        int r;
-        exact = seg_d2(qx, qy, qz, A, B, t, r);
-        a.cx = A.x + t * (B.x - A.x);
-        a.cy = A.y + t * (B.y - A.y);
-        a.cz = A.z + t * (B.z - A.z);
-        if (r == 0) {
-            a.prim = make_prim(KIND_EDGE, best_id);
-            a.w[0] = 1.f - t;
-            a.w[1] = t;
-            a.pv[0] = as_int(A.w);
-            a.pv[1] = as_int(B.w);
-        } else {
-            const int32_t pid = as_int(r == 1 ? A.w : B.w);
-            a.prim = make_prim(KIND_VERTEX, pid);
-            a.cx = r == 1 ? A.x : B.x;
-            a.cy = r == 1 ? A.y : B.y;
-            a.cz = r == 1 ? A.z : B.z;
-            a.pv[0] = pid;
-        }
-    } else {
+    // The winner of the gated ranking is the closest when its exact distance
+    // is within the slack of its own gated value: that value is at most
+    // every other candidate's gated value, itself at most that candidate's
+    // exact distance.  An edge's gated value is its exact distance (the
+    // overshoot term), and so is a face's when q's foot lies in the face.
+    // Only a face that passed its gate with its foot just off it (within the
+    // margin) can fail the test; then a second scan decides.  Then the
+    // winner is resolved exactly: distance, closest point, weights and the
+    // reported primitive from the closed segment / triangle.
+    if (best_kind == KIND_FACE) {
         const float4 A = m.tri[3 * best_id], B = m.tri[3 * best_id + 1], C = m.tri[3 * best_id + 2];
-        float w0, w1, w2;
-        int r;
-        exact = tri_d2(qx, qy, qz, A, B, C, w0, w1, w2, r, a.cx, a.cy, a.cz);
-        const int32_t ia = as_int(A.w), ib = as_int(B.w), ic = as_int(C.w);
-        if (r == 0) {
-            a.prim = make_prim(KIND_FACE, best_id);
-            a.w[0] = w0;
-            a.w[1] = w1;
-            a.w[2] = w2;
-            a.pv[0] = ia;
-            a.pv[1] = ib;
-            a.pv[2] = ic;
-        } else if (r <= 3) {
-            const int side = r - 1;  // from corner side to corner side+1
-            a.prim = make_prim(KIND_EDGE, m.fedge[4 * best_id + side]);
-            a.w[0] = side == 0 ? w0 : (side == 1 ? w1 : w2);
-            a.w[1] = side == 0 ? w1 : (side == 1 ? w2 : w0);
-            a.pv[0] = side == 0 ? ia : (side == 1 ? ib : ic);
-            a.pv[1] = side == 0 ? ib : (side == 1 ? ic : ia);
-        } else {
-            const int corner = r - 4;
-            const int32_t pid = corner == 0 ? ia : (corner == 1 ? ib : ic);
-            a.prim = make_prim(KIND_VERTEX, pid);
-            a.cx = corner == 0 ? A.x : (corner == 1 ? B.x : C.x);
-            a.cy = corner == 0 ? A.y : (corner == 1 ? B.y : C.y);
-            a.cz = corner == 0 ? A.z : (corner == 1 ? B.z : C.z);
-            a.pv[0] = pid;
+        if (!foot_in_triangle(qx, qy, qz, A, B, C)) {
+            const float ex = tri_dist2(qx, qy, qz, A, B, C);
+            const float lim = sqrtf(best) * kAcceptRel + m.eta;
+            if (!(ex <= lim * lim)) {
+                ++cnt.rescans;
+                float cur = ex;
+                if (nv.d2 < cur) {
+                    cur = nv.d2;
+                    best_kind = KIND_VERTEX;
+                    best_id = nv.vid;
+                }
+                rescan(m, qx, qy, qz, nv.vid, cur, best_kind, best_id, cnt);
+            }
         }
     }
-    // a primitive that passed its gate within the margin but is farther than
-    // v in the exact test gives way to v
+    float exact = resolve(m, qx, qy, qz, nv, best_kind, best_id, a);
+    // a primitive whose exact distance exceeds d(q, v) gives way to v
     if (best_kind != KIND_VERTEX && !(exact <= nv.d2)) {
         exact = nv.d2;
         a.prim = make_prim(KIND_VERTEX, nv.vid);

@@ -84,7 +84,8 @@ def c2(n_queries: int = 10_000_000, level: int = 8) -> Workload:
     lo, hi = Q.aabb(V)
     dlo, dhi = Q.scaled_box(lo, hi, 1.5)
     rng = np.random.default_rng(QUERY_SEED + 2)
-    return _finish(f"c2_icosphere{level}_fbm", V, F, Q.mixed(V, F, n_queries, 1.5, 0.01, rng), dlo, dhi)
+    Qp, near = Q.mixed(V, F, n_queries, 1.5, 0.01, rng, return_near=True)
+    return _finish(f"c2_icosphere{level}_fbm", V, F, Qp, dlo, dhi, near=near)
 
 
 def heightfield_domain(V: np.ndarray, pad_z: float = 0.1):

@@ -71,12 +71,16 @@ def near_segments(V: np.ndarray, S: np.ndarray, n: int, sigma: float, rng: np.ra
 
 
 def mixed(V: np.ndarray, F: np.ndarray, n: int, box_scale: float, sigma_rel: float,
-          rng: np.random.Generator) -> np.ndarray:
-    """Half uniform in the scaled AABB, half near-surface, shuffled."""
+          rng: np.random.Generator, return_near: bool = False):
+    """Half uniform in the scaled AABB, half near-surface, shuffled; with
+    return_near, also the boolean mask of the near-surface rows."""
     lo, hi = aabb(V)
     blo, bhi = scaled_box(lo, hi, box_scale)
     diag = float(np.linalg.norm(hi - lo))
     nu = n // 2
     Q = np.concatenate([uniform_in_box(nu, blo, bhi, rng),
                         near_surface(V, F, n - nu, sigma_rel * diag, rng)], axis=0)
-    return Q[rng.permutation(n)]
+    p = rng.permutation(n)
+    if return_near:
+        return Q[p], p >= nu
+    return Q[p]

@@ -52,3 +52,61 @@ def random_tiny_mesh(rng: np.random.Generator, kind: str = "sphere"):
     else:
         V, F = M.heightfield(6, int(rng.integers(1 << 30)), jitter=0.3)
     return V.astype(np.float32), F.astype(np.int32)
+
+
+def gate_boundary_points(V, F, E, lo, hi, rng, n=400):
+    """Points where the list scan's gates decide: on edges (midpoints and near
+    the ends), at vertices, on faces, pushed off the surface by tiny and by
+    large amounts, and the corners of the box [lo, hi]; clipped to the box."""
+    Vd = np.asarray(V, dtype=np.float64)
+    tri = Vd[F]
+    nrm = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    pts = []
+    ke = rng.integers(0, len(E), n)
+    for t in (0.5, 1e-4, 1 - 1e-4, 0.0):
+        pts.append(Vd[E[ke, 0]] * (1 - t) + Vd[E[ke, 1]] * t)
+    kf = rng.integers(0, len(F), n)
+    b = rng.dirichlet([1, 1, 1], n)
+    on_face = (tri[kf] * b[:, :, None]).sum(1)
+    pts.append(on_face)
+    diag = float(np.linalg.norm(np.asarray(hi) - np.asarray(lo)))
+    for h in (1e-7, 1e-4, 0.05, 0.3):
+        pts.append(on_face + h * diag * nrm[kf])
+        pts.append(pts[0] + h * diag * rng.normal(size=(n, 3)))
+    corners = np.array([[x, y, z] for x in (lo[0], hi[0]) for y in (lo[1], hi[1]) for z in (lo[2], hi[2])])
+    pts.append(corners)
+    return np.clip(np.concatenate(pts), lo, hi).astype(np.float32)
+
+
+def margin_points(V, F, E, diag, mu, rng, n=1000):
+    """Points within the list scan's gate margin mu of primitive boundaries,
+    where a primitive passes its gate with its foot just off it: within
+    1e-5 diag of random edges; in a face's plane (or up to 1e-4 diag off it)
+    at -3.5 mu .. 3.5 mu from one of its sides; within 5e-5 diag of
+    vertices."""
+    Vd = np.asarray(V, dtype=np.float64)
+    pts = []
+    ke = rng.integers(0, len(E), n)
+    t = rng.uniform(0, 1, n)
+    base = Vd[E[ke, 0]] * (1 - t[:, None]) + Vd[E[ke, 1]] * t[:, None]
+    dirs = rng.normal(size=(n, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    pts.append(base + dirs * rng.uniform(0, 1e-5 * diag, (n, 1)))
+    tri = Vd[F]
+    nrm = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    kf = rng.integers(0, len(F), n)
+    side = rng.integers(0, 3, n)
+    a, b, c = tri[kf, side], tri[kf, (side + 1) % 3], tri[kf, (side + 2) % 3]
+    tt = rng.uniform(0.05, 0.95, n)
+    p = a * (1 - tt[:, None]) + b * tt[:, None]
+    inward = np.cross(nrm[kf], b - a)
+    inward /= np.linalg.norm(inward, axis=1, keepdims=True)
+    inward *= np.sign(np.einsum("ij,ij->i", inward, c - p))[:, None]
+    s = rng.uniform(-3.5, 3.5, n) * mu
+    h = rng.choice([0.0, 1e-7, 1e-6, 1e-5, 1e-4], n) * diag * rng.choice([-1, 1], n)
+    pts.append(p + inward * s[:, None] + nrm[kf] * h[:, None])
+    kv = rng.integers(0, len(Vd), n)
+    pts.append(Vd[kv] + dirs * rng.uniform(0, 5e-5 * diag, (n, 1)))
+    return np.concatenate(pts).astype(np.float32)

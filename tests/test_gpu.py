@@ -107,8 +107,17 @@ def test_golden_points_on_device():
         for i, (q, prims, d, c) in enumerate(rows):
             t = int((np.int64(out["prim"][i]) & 0xFFFFFFFF) >> 30)
             pid = int(out["prim"][i] & 0x3FFFFFFF)
-            assert (t, primitive_vertices(om.F, om.E, t, pid)) in prims or abs(out["dist"][i] - d) <= 1e-6
+            # the golden primitive (type and vertex set), or one of its listed
+            # exact ties; where the golden closest point lies on a side or
+            # corner of a face (its foot on the face's boundary), float32
+            # rounding may report that face: it must contain the golden
+            # primitive, and the closest point must be the golden one
+            got = (t, primitive_vertices(om.F, om.E, t, pid))
+            if got not in prims:
+                assert t == 2 and c is not None and any(got[1] >= pv for _, pv in prims), (name, q, got, prims)
             assert abs(out["dist"][i] - d) <= 1e-6
+            if c is not None:
+                assert np.allclose(out["closest"][i], c, atol=1e-6), (name, q, out["closest"][i], c)
 
 
 @pytest.mark.parametrize("n", [1, 2, 255, 4096, 4097, 70001, 1 << 20])
@@ -184,12 +193,19 @@ def test_edge_cases(c1):
 
 
 def _sampled_parity(w, m, n_sample, seed):
+    """n_sample seeded rows, stratified: half from the uniform rows, half from
+    the near-surface rows of the workload."""
     om = oracle.OracleMesh(w.V, w.F)
     out = _run(m, w.Q)
     rng = np.random.default_rng(seed)
-    idx = np.sort(rng.choice(len(w.Q), size=n_sample, replace=False))
+    near = w.meta["near"]
+    idx = np.sort(np.concatenate([rng.choice(np.nonzero(~near)[0], size=n_sample // 2, replace=False),
+                                  rng.choice(np.nonzero(near)[0], size=n_sample - n_sample // 2, replace=False)]))
+    print(f"case: oracle on {len(idx)} sampled rows", flush=True)
     ans = om.query(w.Q[idx])
     fails = check_answers(om, w.Q[idx], ans, out["prim"][idx], out["closest"][idx], out["dist"][idx], idx=idx)
+    err = np.abs(out["dist"][idx].astype(np.float64) - ans["dist"]) / (1e-5 * om.diag)
+    print(f"worst |d - d*| = {err.max():.3f} tol", flush=True)
     return fails, out
 
 
@@ -206,11 +222,12 @@ def c2_full():
 
 def test_c2_full_size_sampled(c2_full):
     """Workload C2 at full size (10^7 queries, one sorted launch as timed by
-    the benchmark); 1,500 sampled rows checked against the oracle; all
-    distances finite and non-negative; no row flagged out of domain."""
+    the benchmark); 10^4 seeded rows (5,000 uniform, 5,000 near-surface)
+    checked against the oracle; all distances finite and non-negative; no
+    row flagged out of domain."""
     w, m = c2_full
     print("case: c2 sampled parity", flush=True)
-    fails, out = _sampled_parity(w, m, 1500, 77)
+    fails, out = _sampled_parity(w, m, 10_000, 77)
     assert fails == []
     out1 = _run(m, w.Q[:200_000], traversal=1)
     # the traversals agree on the nearest vertex up to float64 ties

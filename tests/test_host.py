@@ -15,7 +15,8 @@ import paper_2308_16084_amd as P
 from synth import configs as C
 from synth import queries as SQ
 from tests._accept import check_answers
-from tests._helpers import CUBE_F, CUBE_V, TETRA_F, TETRA_V, random_tiny_mesh
+from tests._helpers import (CUBE_F, CUBE_V, TETRA_F, TETRA_V, gate_boundary_points, margin_points,
+                            random_tiny_mesh)
 
 
 def _mesh(V, F, domain=None, mode=P.TABLE_FLOODING, scale=1.5):
@@ -295,29 +296,38 @@ def test_host_query_gate_boundaries(name):
         V, F = V.astype(np.float32), F.astype(np.int32)
     m, st, (lo, hi) = _mesh(V, F, scale=1.5)
     om = oracle.OracleMesh(V, F)
-    Vd = V.astype(np.float64)
-    E = om.E
-    tri = Vd[F]
-    n = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
-    n /= np.linalg.norm(n, axis=1, keepdims=True)
-    pts = []
-    ke = rng.integers(0, len(E), 400)
-    for t in (0.5, 1e-4, 1 - 1e-4, 0.0):
-        pts.append(Vd[E[ke, 0]] * (1 - t) + Vd[E[ke, 1]] * t)
-    kf = rng.integers(0, len(F), 400)
-    b = rng.dirichlet([1, 1, 1], 400)
-    on_face = (tri[kf] * b[:, :, None]).sum(1)
-    pts.append(on_face)
-    diag = float(np.linalg.norm(hi - lo))
-    for h in (1e-7, 1e-4, 0.05, 0.3):
-        pts.append(on_face + h * diag * n[kf])
-        pts.append(pts[0] + h * diag * rng.normal(size=(400, 3)))
-    corners = np.array([[x, y, z] for x in (lo[0], hi[0]) for y in (lo[1], hi[1]) for z in (lo[2], hi[2])])
-    pts.append(corners)
-    Q = np.clip(np.concatenate(pts), lo, hi).astype(np.float32)
+    Q = gate_boundary_points(V, F, om.E, lo, hi, rng)
     h = m.query_host(Q)
     assert np.all(h["status"] == 0)
     assert check_answers(om, Q, om.query(Q), h["prim"], h["closest"], h["dist"]) == []
+
+
+@pytest.mark.parametrize("name,scale", [("c1", 1.5), ("c1", 10.0), ("c1", 12.0), ("fbm5", 10.0),
+                                        ("needles", 10.0)])
+def test_host_query_within_gate_margin(name, scale):
+    """Points within the gate margin mu (2^-20 of the domain diagonal) of
+    primitive boundaries, where a primitive passes its gate with its foot
+    just off it and its line / plane distance undercuts the true distance:
+    the answer stays the exact minimum (|d - d*| <= tol / 4) at any domain
+    size, the default 10x AABB included."""
+    from synth import mesh as M
+    rng = np.random.default_rng(12)
+    if name == "c1":
+        V, F = C.c1().V, C.c1().F
+    elif name == "fbm5":
+        V, F = C.sphere_mesh(5, "fbm", 17)
+    else:
+        V, F = M.heightfield(24, 77)
+        V, F = V.astype(np.float32), F.astype(np.int32)
+    m, st, (lo, hi) = _mesh(V, F, scale=scale)
+    om = oracle.OracleMesh(V, F)
+    mu = 2.0 ** -20 * float(np.linalg.norm(np.asarray(hi) - np.asarray(lo)))
+    Q = margin_points(V, F, om.E, om.diag, mu, rng)
+    h = m.query_host(Q)
+    ans = om.query(Q)
+    assert check_answers(om, Q, ans, h["prim"], h["closest"], h["dist"]) == []
+    err = np.abs(h["dist"].astype(np.float64) - ans["dist"])
+    assert err.max() <= 0.25e-5 * om.diag, err.max() / om.diag
 
 
 def test_table_completeness_dense_sampling():
