@@ -226,6 +226,22 @@ p2m_status p2m_query(p2m_mesh* m, const float* q_dev, int64_t n, int32_t* prim_d
                      float* dist_dev, uint8_t* status_dev, float* bary_dev, int32_t* pvid_dev,
                      const p2m_query_opts* opts, void* stream);
 
+/* p2m_query for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same query, arguments, kernels and answers, but the ordering buffers and
+ * the staged answers live in a fixed device array of the library (64.3
+ * MiB, held by each device the library runs on until the process ends)
+ * instead of the mesh's scratch, and the call allocates nothing, on the
+ * device or the host.  At most 2^20 queries per call (P2M_ERR_ARG beyond);
+ * opts->profile must be 0 (P2M_ERR_ARG: its events would allocate).  The
+ * first call on a device looks up that device's copy of the array.  Every
+ * call on one device shares that array and it keeps the last call's
+ * contents (nothing in it needs to start at zero): calls that overlap on one
+ * device, on any streams or meshes, race. */
+p2m_status p2m_query_noalloc(p2m_mesh* m, const float* q_dev, int64_t n, int32_t* prim_dev, float* closest_dev,
+                             float* dist_dev, uint8_t* status_dev, float* bary_dev, int32_t* pvid_dev,
+                             const p2m_query_opts* opts, void* stream);
+
 /* Stage times of the last p2m_query on this mesh that set opts->profile, in
  * milliseconds, from HIP events recorded on the call's stream: ordering
  * (Morton keys + sort), the query kernel, and the pass that writes staged

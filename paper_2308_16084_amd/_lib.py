@@ -60,6 +60,7 @@ _SIGS = {
     "p2m_last_error": (ctypes.c_char_p, []),
     "p2m_upload": (INT, [P, INT, P, P]),
     "p2m_query": (INT, [P, P, I64, P, P, P, P, P, P, P, P]),
+    "p2m_query_noalloc": (INT, [P, P, I64, P, P, P, P, P, P, P, P]),
     "p2m_query_profile": (INT, [P, P, P, P]),
     "p2m_nearest_vertex": (INT, [P, P, I64, P, P, INT, P]),
     "p2m_order_queries": (INT, [P, P, I64, P, P, P]),

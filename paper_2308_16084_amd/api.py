@@ -214,8 +214,11 @@ class Mesh:
         return nbytes.value
 
     def query(self, q, sort: bool = True, block_size: int = 0, out: dict | None = None, status: bool = True,
-              for_backward: bool = False, profile: bool = False, traversal: int = 0, stream=None) -> dict:
-        """P2M query of a CUDA float32 [n,3] tensor; returns device tensors."""
+              for_backward: bool = False, profile: bool = False, traversal: int = 0, stream=None,
+              noalloc: bool = False) -> dict:
+        """P2M query of a CUDA float32 [n,3] tensor; returns device tensors.
+        noalloc: call p2m_query_noalloc (the library allocates nothing; pass
+        `out` to allocate nothing here either)."""
         torch = _torch()
         q = _dev_tensor(q, torch.float32, (3,), "q")
         n = q.shape[0]
@@ -234,7 +237,7 @@ class Mesh:
         o.block_size = int(block_size)
         o.profile = 1 if profile else 0
         o.traversal = int(traversal)
-        fn = lib().p2m_query
+        fn = lib().p2m_query_noalloc if noalloc else lib().p2m_query
         check(fn(self._h, _ptr(q), n, _ptr(out["prim"]), _ptr(out["closest"]), _ptr(out["dist"]),
                  _ptr(out.get("status")), _ptr(out.get("bary")), _ptr(out.get("pvid")), ctypes.byref(o),
                  _stream(stream)))

@@ -8,6 +8,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1007,9 +1008,12 @@ p2m_status p2m_upload(p2m_mesh* mh, int device, void* stream, int64_t* bytes) {
 
 namespace p2m {
 
-// The query of p2m_query.
+// The query of p2m_query.  fixed != nullptr: the ordering and the staged
+// answers go to that device buffer (p2m_query_noalloc) instead of the
+// mesh's scratch, which may be grown; nothing is allocated then.
 static p2m_status run_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, float* closest, float* dist,
-                            uint8_t* status, float* bary, int32_t* pvid, const p2m_query_opts* opts, void* stream) {
+                            uint8_t* status, float* bary, int32_t* pvid, const p2m_query_opts* opts, void* stream,
+                            void* (*fixed)(int device)) {
     if (!mh) return fail(P2M_ERR_ARG, "mesh is NULL");
     MeshState& s = mh->s;
     if (n < 0) return fail(P2M_ERR_ARG, "negative query count");
@@ -1030,9 +1034,15 @@ static p2m_status run_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* pr
             block = opts->block_size;
         }
     }
+    if (fixed && profile) return fail(P2M_ERR_ARG, "profile is not available without allocation (p2m_query_noalloc)");
     DeviceGuard g(s.dev.device);
     if (!g.ok) return fail(P2M_ERR_HIP, "hipSetDevice failed");
     hipStream_t st = (hipStream_t)stream;
+    void* fixed_buf = nullptr;
+    if (fixed && sort) {
+        fixed_buf = fixed(s.dev.device);
+        if (!fixed_buf) return P2M_ERR_HIP;  // message set by the provider
+    }
     if (profile) {
         for (void*& e : s.dev.ev)
             if (!e && hipEventCreate((hipEvent_t*)&e) != hipSuccess) return fail(P2M_ERR_HIP, "hipEventCreate");
@@ -1042,7 +1052,9 @@ static p2m_status run_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* pr
     float4* stage = nullptr;
     if (sort) {
         void* x = nullptr;
-        p2m_status r = order_into_scratch(s, q, n, kQuerySortLoBit, st, nullptr, &perm, (bary ? 48 : 32) * n, &x);
+        p2m_status r = fixed_buf ? order_into(s, fixed_buf, q, n, kQuerySortLoBit, st, nullptr, &perm, &x)
+                                 : order_into_scratch(s, q, n, kQuerySortLoBit, st, nullptr, &perm,
+                                                      (bary ? 48 : 32) * n, &x);
         if (r != P2M_OK) return r;
         stage = (float4*)x;
     }
@@ -1079,13 +1091,68 @@ static p2m_status run_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* pr
     return r;
 }
 
+// ------------------------------------------------ allocation-free query
+
+// Fixed device scratch of p2m_query_noalloc: the ordering buffers and the
+// staged answers (48 bytes per query with bary/pvid) of at most
+// kNoAllocMaxQueries queries.  Each device the library runs on holds its
+// own copy until the process ends.
+constexpr int64_t kNoAllocMaxQueries = int64_t(1) << 20;
+constexpr int64_t noalloc_up256(int64_t x) { return (x + 255) / 256 * 256; }
+constexpr int64_t noalloc_sort_bytes(int64_t n) {
+    // radix_plan(n).bytes rounded up: keys and values, double-buffered; the
+    // count matrix (256 per tile of kRadixTile keys); the digit totals or
+    // scan sums
+    return noalloc_up256(4 * noalloc_up256(4 * n) + noalloc_up256(4 * 256 * ((n + kRadixTile - 1) / kRadixTile)) +
+                         noalloc_up256(4 * std::max<int64_t>(256, (256 * ((n + kRadixTile - 1) / kRadixTile) +
+                                                                   kRadixTile - 1) / kRadixTile)));
+}
+constexpr int64_t kNoAllocScratchBytes = noalloc_sort_bytes(kNoAllocMaxQueries) + 48 * kNoAllocMaxQueries;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+// Device address of `scratch` on each device, looked up once per device
+// (with that device current) on its first p2m_query_noalloc call; host code
+// uses only these addresses, never the symbol itself.
+constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static void* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+static void* noalloc_scratch(int device) {
+    if (device < 0 || device >= kNoAllocMaxDevices) {
+        fail(P2M_ERR_HIP, "device index beyond the allocation-free scratch table");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            fail(P2M_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return nullptr;
+        }
+        g_noalloc_ptr[device] = ptr;
+    }
+    return g_noalloc_ptr[device];
+}
+
 }  // namespace p2m
 
 extern "C" {
 
 p2m_status p2m_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, float* closest, float* dist,
                      uint8_t* status, float* bary, int32_t* pvid, const p2m_query_opts* opts, void* stream) {
-    return run_query(mh, q, n, prim, closest, dist, status, bary, pvid, opts, stream);
+    return run_query(mh, q, n, prim, closest, dist, status, bary, pvid, opts, stream, nullptr);
+}
+
+p2m_status p2m_query_noalloc(p2m_mesh* mh, const float* q, int64_t n, int32_t* prim, float* closest, float* dist,
+                             uint8_t* status, float* bary, int32_t* pvid, const p2m_query_opts* opts, void* stream) {
+    if (n > kNoAllocMaxQueries)
+        return fail(P2M_ERR_ARG, "p2m_query_noalloc: more than " + std::to_string(kNoAllocMaxQueries) +
+                                     " queries (the fixed scratch's limit)");
+    if (n > 0 && order_scratch_bytes(n) + 48 * n > kNoAllocScratchBytes)
+        return fail(P2M_ERR_INTERNAL, "p2m_query_noalloc: fixed scratch smaller than the ordering needs");
+    return run_query(mh, q, n, prim, closest, dist, status, bary, pvid, opts, stream, noalloc_scratch);
 }
 
 p2m_status p2m_query_profile(p2m_mesh* mh, float* order_ms, float* query_ms, float* finish_ms) {
