@@ -9,10 +9,25 @@ kernel (KD-tree nearest vertex, interception-list scan with exact
 point-segment / point-triangle tests, resolved primitive, closest point,
 distance).  The host precompute is timed separately and never counted.
 
-Also reported on the same GPU: forward+backward on 10^6 near-surface queries
-of the same mesh (loss = sum of squared distances), the FP64 brute-force
-oracle on a bounded sample of the workload's queries (host cores), and the
-multi-threaded CPU P2M query over the same tree and table.
+The roofline of the query kernel counts the method's algorithmic bytes per
+query (the query and its answer, the nearest-vertex candidates, the list
+range, 4 bytes per scanned entry, the vertices of every tested edge and
+face), measured per query by the host model over the same structures, over
+the kernel's duration from HIP events on its stream; the HBM traffic, L2 hit
+rate and VALU figures come from committed rocprofv3 summaries of the same
+kernel source (null when the kernel has changed since).
+
+Also reported on the same GPU: the ordering's bytes and bandwidth; the batch
+in input order (no ordering); the small icosphere and the needle heightfield
+workloads; Table 1's list statistics (Avg^1, Avg^2, max) per workload;
+forward+backward on 10^6 near-surface queries of the same mesh (loss = sum of
+squared distances) and the backward kernels alone; the mixed primitive set;
+the interception table built on the device; the near/far sweep (Sec. 5.3:
+the mesh precomputed for the default 10x domain, uniform queries in boxes of
+1x..10x AABB); the 256-mesh batch in one graph launch against 256 plain
+launches; the FP64 brute-force oracle on a bounded sample of the workload's
+queries (host cores) and the CPU P2M query over the same tree and table, on
+all host threads and on one.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -32,6 +47,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_query_c2.txt")
+SQ_FILE = os.path.join(ROOT, "profiles", "k_query_c2_counters.txt")
 
 
 def log(*a):
@@ -46,31 +62,75 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n_queries: int):
-    """HBM bytes per query-kernel launch from committed rocprofv3 counter
-    summaries, if they were taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def _summary(path: str, n_queries: int):
+    """key: value lines of a committed rocprofv3 counter summary, if it was
+    taken on the current kernel source at this batch size."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_hash") != kernel_source_hash():
+    if vals.get("kernel_source_hash") != kernel_source_hash() or int(vals.get("queries", -1)) != n_queries:
         return None
-    if int(vals.get("queries", -1)) != n_queries:
-        return None
-    return float(vals["hbm_bytes_per_launch"])
+    return vals
 
 
-def b_alg(visits: float, steps: float, entries: float, edge_forms: float, face_forms: float) -> float:
-    """Algorithmic bytes per query: query in (12) + results out (20) + the
-    nearest-vertex walk (seed record 16, per step the neighbour-list
+def b_alg(visits: float, entries: float, edge_forms: float, face_forms: float) -> float:
+    """Algorithmic bytes per query of the method (what it must touch, no
+    caching credit): the query in (12) and the answer out (primitive,
+    closest point, distance: 20); 16 per nearest-vertex candidate (a
+    vertex's position and id); the list range of the nearest vertex (8);
+    4 per list entry scanned (its id); per edge tested (an entry whose box
+    holds q) 4 + 8 + 24 (id, its two vertex ids and positions), per face
+    tested 4 + 12 + 36."""
+    return 12 + 20 + 16 * visits + 8 + 4 * entries + 36 * edge_forms + 52 * face_forms
+
+
+def touched_bytes(visits: float, steps: float, entries: float, edge_forms: float, face_forms: float) -> float:
+    """Bytes this implementation's layout reads and writes per query, every
+    L2 / Infinity-Cache hit counted as if it came from HBM: query in (12) +
+    results out (20) + the walk (seed record 16, per step the neighbour-list
     offsets 8, per neighbour its record 16) + the list head (32) + 8 per list
     entry (id + box; runs padded to even length) + per entry whose box holds
     q its forms (edge 32, face 48) + the winner's exact re-evaluation (48)."""
     return 12 + 20 + 16 + 8 * steps + 16 * visits + 32 + 8 * entries + 32 * edge_forms + 48 * face_forms + 48
+
+
+def list_stats(st: dict):
+    """Table 1's list statistics (edges, faces) from the build statistics."""
+    if "avg_edges" not in st:
+        return None
+    return {"avg1": [round(st["avg_edges"], 2), round(st["avg_faces"], 2)],
+            "avg2": [round(st["avg_edges_volw"], 2), round(st["avg_faces_volw"], 2)],
+            "max": [int(st["max_edges"]), int(st["max_faces"])], "avg_list": round(st["avg_list"], 2),
+            "avg_list_volw": round(st["avg_list_volw"], 2), "max_list": int(st["max_list"])}
+
+
+def host_counts(mesh, Q, k=200_000, seed=123):
+    """Per-query counts of the host model over the same structures (a sample)."""
+    rng = np.random.default_rng(seed)
+    sub = Q[rng.choice(len(Q), size=min(len(Q), k), replace=False)]
+    hs = mesh.query_host(sub)
+    per = {key: hs[key] / len(sub) for key in ("nodes", "steps", "edges", "faces", "edge_forms", "face_forms",
+                                               "rescans")}
+    return per
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
 
 
 def main():
@@ -83,11 +143,13 @@ def main():
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-primitive (triangles + segments) leg")
+    ap.add_argument("--no-configs", action="store_true", help="skip the C1 and C3 legs")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the near/far sweep leg")
     ap.add_argument("--no-precompute", action="store_true",
                     help="skip the device-inspection leg (the C2 table built with the filter and flooding on the GPU)")
-    ap.add_argument("--sweep", action="store_true",
-                    help="also run the near/far sweep: the C2 mesh precomputed for D = 10x AABB, 1e6 uniform "
-                         "queries in boxes of 1x..10x AABB (not part of the default run)")
+    ap.add_argument("--sweep-queries", type=int, default=1_000_000,
+                    help="queries per box of the near/far sweep (the C2 mesh precomputed for the default domain, "
+                         "D = 10x AABB; uniform queries in boxes of 1x..10x AABB)")
     ap.add_argument("--batched-meshes", type=int, default=256,
                     help="batched leg on the first N meshes of the seeded 256-mesh plan (default: all 256)")
     ap.add_argument("--breakdown", action="store_true",
@@ -121,7 +183,10 @@ def main():
         off, _ = mesh.table()
         stats["avg_list"] = float(off[-1]) / mesh.nv
     log(f"[bench] host precompute {t_pre:.1f}s {json.dumps({k: stats[k] for k in stats if k.startswith('t_') or k in ('avg_list', 'max_list', 'flood_tests')})}")
+    t0 = time.time()
     dev_bytes = mesh.upload(0)
+    torch.cuda.synchronize()
+    t_upload = time.time() - t0
     q = torch.from_numpy(w.Q).to(dev)
     n = q.shape[0]
     out = {"prim": torch.empty(n, dtype=torch.int32, device=dev),
@@ -195,20 +260,35 @@ def main():
 
     # algorithmic bytes per query from the same structures (host model counts)
     rng = np.random.default_rng(123)
-    sub = w.Q[rng.choice(n, size=min(n, 200_000), replace=False)]
-    hs = mesh.query_host(sub)
-    per = {k: hs[k] / len(sub) for k in ("nodes", "steps", "edges", "faces", "edge_forms", "face_forms")}
-    balg = b_alg(per["nodes"], per["steps"], per["edges"] + per["faces"], per["edge_forms"], per["face_forms"])
+    per = host_counts(mesh, w.Q)
+    entries = per["edges"] + per["faces"]
+    balg = b_alg(per["nodes"], entries, per["edge_forms"], per["face_forms"])
+    btouch = touched_bytes(per["nodes"], per["steps"], entries, per["edge_forms"], per["face_forms"])
     achieved = balg * n / (query_avg / 1e3) / 1e9
-    traffic = measured_traffic(n)
+    tr = _summary(TRAFFIC_FILE, n)
+    sq = _summary(SQ_FILE, n)
+    traffic = float(tr["hbm_bytes_per_launch"]) if tr else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_query", "kernel_ms": round(query_avg, 4),
                 "b_alg_bytes_per_query": round(balg, 1),
+                # from the committed rocprofv3 counter summaries of this kernel source (null when stale)
+                "counter_hbm_GBps": round(traffic / (query_avg / 1e3) / 1e9, 1) if traffic else None,
+                "counter_hbm_frac": round(traffic / (query_avg / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+                "l2_hit_rate": float(tr["l2_hit_rate"]) if tr else None,
+                "valu_issue_frac": float(sq["valu_issue_frac"]) if sq else None,
+                "lanes_active_frac": float(sq["lanes_active_frac"]) if sq else None,
+                "valu_insts_per_wave": float(sq["valu_insts_per_wave"]) if sq else None,
+                # bytes of this layout touched per query, cache hits counted as HBM reads
+                "touched_bytes_per_query": round(btouch, 1),
+                "touched_GBps": round(btouch * n / (query_avg / 1e3) / 1e9, 1),
                 "per_query": {"walk_vertices": round(per["nodes"], 2), "walk_steps": round(per["steps"], 2),
                               "edge_entries": round(per["edges"], 2), "face_entries": round(per["faces"], 2),
                               "edge_forms_read": round(per["edge_forms"], 2),
-                              "face_forms_read": round(per["face_forms"], 2)}}
+                              "face_forms_read": round(per["face_forms"], 2),
+                              "second_scans": per["rescans"]}}
+    log(f"[bench] roofline: B_alg {balg:.0f} B/query -> {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.3f} of HBM); "
+        f"touched {btouch:.0f} B/query; counters {'current' if tr else 'stale or missing'}")
 
     result = {"metric": "P2M queries/sec at 1.3M tris (fwd, fwd+bwd, batched); % of HBM peak",
               "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -220,12 +300,49 @@ def main():
                          "queries": n, "ordering": "morton30+radix", "host_precompute_s": round(t_pre, 1),
                          "precompute_cached": "loaded_from" in stats,
                          "avg_list": round(float(stats.get("avg_list", 0.0)), 2),
-                         "device_bytes": dev_bytes},
+                         "device_bytes": dev_bytes, "upload_s": round(t_upload, 3)},
               "roofline": roofline,
               "stages_ms": {"ordering": round(order_avg, 4), "query": round(query_avg, 4),
                             "write_out": round(finish_avg, 4)}}
+    # the ordering: Morton keys (12 B in, 4 out per query) and three 8-bit
+    # passes (count: 4 B; scatter: key + value in and out, 16 B, except
+    # that the first pass reads no values and the last writes no keys)
+    ord_bytes = 16 + (4 + 12) + (4 + 16) + (4 + 12)
+    result["ordering"] = {"bytes_per_query": ord_bytes, "ms": round(order_avg, 4),
+                          "GBps": round(ord_bytes * n / (order_avg / 1e3) / 1e9, 1),
+                          "frac": round(ord_bytes * n / (order_avg / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    result["list_stats"] = {"c2": list_stats(stats)}
     if breakdown:
         result["breakdown"] = breakdown
+
+    # the same batch without the ordering step
+    ms_uns = time_steps(lambda: mesh.query(q, out=out, sort=False), args.steps, args.warmup)
+    result["unsorted"] = {"value": round(n / (ms_uns / 1e3), 1), "unit": "queries/s", "ms_per_step": round(ms_uns, 4),
+                          "workload": "the headline batch in input order (no Morton ordering)"}
+    log(f"[bench] unsorted: {ms_uns:.3f} ms/step, {n / (ms_uns / 1e3) / 1e9:.3f} Gq/s")
+
+    if not args.no_configs:
+        # the small icosphere (C1) and the needle heightfield (C3): q/s, list statistics
+        for name, make, mode in (("c1", C.c1, P.TABLE_FLOODING), ("c3", C.c3, P.TABLE_FLOODING_DEVICE)):
+            log(f"[bench] {name}: generating and precomputing")
+            t0 = time.time()
+            wk = make()
+            mk, sk = P.Mesh.cached(wk.V, wk.F, (wk.domain_lo, wk.domain_hi), args.cache or None, table_mode=mode)
+            t_pk = time.time() - t0
+            mk.upload(0)
+            qk = torch.from_numpy(wk.Q).to(dev)
+            ok = mk.query(qk)
+            ms_k = time_steps(lambda: mk.query(qk, out=ok), args.steps, args.warmup)
+            nk = qk.shape[0]
+            pk = host_counts(mk, wk.Q, k=100_000)
+            bk = b_alg(pk["nodes"], pk["edges"] + pk["faces"], pk["edge_forms"], pk["face_forms"])
+            result[name] = {"value": round(nk / (ms_k / 1e3), 1), "unit": "queries/s", "ms_per_step": round(ms_k, 4),
+                            "queries": nk, "b_alg_bytes_per_query": round(bk, 1),
+                            "achieved_GBps_whole_step": round(bk * nk / (ms_k / 1e3) / 1e9, 1),
+                            "workload": wk.name, "setup_s": round(t_pk, 1)}
+            result["list_stats"][name] = list_stats(sk)
+            log(f"[bench] {name}: {ms_k:.3f} ms/step, {nk / (ms_k / 1e3) / 1e9:.3f} Gq/s")
+            del mk, qk, ok
 
     if not args.no_bwd:
         w5 = C.c5()
@@ -240,18 +357,24 @@ def main():
             (d * d).sum().backward()
             return qq.grad, VV.grad
 
-        for _ in range(args.warmup):
-            fb()
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.steps):
-            fb()
-        e1.record()
-        torch.cuda.synchronize()
-        ms_fb = e0.elapsed_time(e1) / args.steps
+        ms_fb = time_steps(fb, args.steps, args.warmup)
+        # the backward kernels alone: per query q, c, d, upstream gradient,
+        # weights and vertex ids in (56 B), grad_q out (12 B), and a
+        # read-modify-write of one grad_V row (24 B) per nonzero weight
+        f5 = mesh.query(q5, for_backward=True, status=False)
+        g5 = 2.0 * f5["dist"]
+        gV5 = torch.zeros((mesh.nv, 3), dtype=torch.float32, device=dev)
+        ms_bwd = time_steps(lambda: mesh.query_backward(q5, f5, g5, grad_q=True, grad_V=gV5), args.steps, args.warmup)
+        nz = float((f5["bary"] != 0).sum().item()) / n5
+        bb = 56 + 12 + 24 * nz
         result["fwd_bwd"] = {"value": round(n5 / (ms_fb / 1e3), 1), "unit": "queries/s", "ms_per_step": round(ms_fb, 4),
-                             "workload": "same mesh, 1e6 near-surface queries, loss = sum d^2, grads wrt q [1e6,3] and V [655362,3]"}
-        log(f"[bench] fwd+bwd: {ms_fb:.3f} ms/step, {n5 / (ms_fb / 1e3) / 1e9:.3f} Gq/s")
+                             "workload": "same mesh, 1e6 near-surface queries, loss = sum d^2, grads wrt q [1e6,3] and V [655362,3]",
+                             "backward_kernels": {"ms": round(ms_bwd, 4), "b_alg_bytes_per_query": round(bb, 1),
+                                                  "achieved_GBps": round(bb * n5 / (ms_bwd / 1e3) / 1e9, 1),
+                                                  "frac": round(bb * n5 / (ms_bwd / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                                                  "weights_per_query": round(nz, 3)}}
+        log(f"[bench] fwd+bwd: {ms_fb:.3f} ms/step, {n5 / (ms_fb / 1e3) / 1e9:.3f} Gq/s; backward kernels {ms_bwd:.3f} ms")
+        del f5, g5, gV5
 
     if not args.no_mixed:
         t0 = time.time()
@@ -308,44 +431,39 @@ def main():
         assert same, "device-built interception table differs from the host-built one"
         del md
 
-    if args.sweep:
+    if not args.no_sweep:
+        # Sec. 5.3's near/far study: the C2 mesh precomputed for the library's
+        # default domain (10x AABB), uniform queries in boxes of 1x..10x AABB
+        log("[bench] sweep: precomputing the mesh for the default 10x domain")
         t0 = time.time()
         lo2, hi2 = SQ.aabb(w.V)
-        d10 = SQ.scaled_box(lo2, hi2, 10.0)
-        m10, st10 = P.Mesh.cached(w.V, w.F, d10, args.cache or None)
+        m10, st10 = P.Mesh.cached(w.V, w.F, None, args.cache or None, table_mode=P.TABLE_FLOODING_DEVICE)
         t_pre10 = time.time() - t0
         m10.upload(0)
         rows = []
+        ns_ = args.sweep_queries
         for scale in (1.0, 1.5, 2.0, 3.0, 5.0, 10.0):
             blo, bhi = SQ.scaled_box(lo2, hi2, scale)
-            Qs = SQ.uniform_in_box(1_000_000, blo, bhi, np.random.default_rng(2100 + int(10 * scale)))
+            Qs = SQ.uniform_in_box(ns_, blo, bhi, np.random.default_rng(2100 + int(10 * scale)))
             qs_t = torch.from_numpy(Qs).to(dev)
             o = m10.query(qs_t)
-            for _ in range(args.warmup):
-                m10.query(qs_t, out=o)
-            torch.cuda.synchronize()
-            e0.record()
-            for _ in range(args.steps):
-                m10.query(qs_t, out=o)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / args.steps
-            hc = m10.query_host(Qs[:100_000])
-            k = 100_000
-            rows.append({"box_scale": scale, "queries_per_s": round(1e6 / (ms / 1e3), 1), "ms_per_1e6": round(ms, 4),
-                         "walk_vertices": round(hc["nodes"] / k, 2), "walk_steps": round(hc["steps"] / k, 2),
-                         "list_entries": round((hc["edges"] + hc["faces"]) / k, 2),
-                         "forms_read": round((hc["edge_forms"] + hc["face_forms"]) / k, 2)})
-            log(f"[bench] sweep box {scale}x: {ms:.3f} ms per 1e6, entries {rows[-1]['list_entries']}, "
+            ms = time_steps(lambda: m10.query(qs_t, out=o), args.steps, args.warmup)
+            hc = host_counts(m10, Qs, k=100_000)
+            rows.append({"box_scale": scale, "queries_per_s": round(ns_ / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
+                         "walk_vertices": round(hc["nodes"], 2), "walk_steps": round(hc["steps"], 2),
+                         "list_entries": round(hc["edges"] + hc["faces"], 2),
+                         "forms_read": round(hc["edge_forms"] + hc["face_forms"], 2),
+                         "second_scans": hc["rescans"]})
+            log(f"[bench] sweep box {scale}x: {ms:.3f} ms per {ns_}, entries {rows[-1]['list_entries']}, "
                 f"forms {rows[-1]['forms_read']}")
-        off10, _ = m10.table()
-        result["near_far_sweep"] = {"domain": "10x AABB", "host_precompute_s": round(t_pre10, 1),
-                                    "avg_list": round(float(off10[-1]) / m10.nv, 2), "rows": rows}
+        result["near_far_sweep"] = {"domain": "10x AABB (default)", "queries_per_box": ns_,
+                                    "setup_s": round(t_pre10, 1), "list_stats": list_stats(st10), "rows": rows}
         del m10
 
     if not args.no_batched:
         from concurrent.futures import ThreadPoolExecutor
         count = max(1, min(256, args.batched_meshes))
+        log(f"[bench] batched: generating and precomputing {count} meshes")
         t0 = time.time()
         plan = C.c4_plan()[:count]
         with ThreadPoolExecutor(max_workers=max(1, len(os.sched_getaffinity(0)))) as ex:
@@ -395,6 +513,20 @@ def main():
         torch.cuda.synchronize()
         ms_p = e0.elapsed_time(e1) / args.steps
         ntri = int(sum(len(x.F) for x in works))
+        # algorithmic bytes over the batch: host-model counts on every 16th query of each mesh
+        tot = 0.0
+        for k, m_ in enumerate(meshes):
+            Qk = works[k].Q[::16]
+            if len(Qk) == 0:
+                continue
+            hk = m_.query_host(Qk)
+            bk = b_alg(hk["nodes"] / len(Qk), (hk["edges"] + hk["faces"]) / len(Qk), hk["edge_forms"] / len(Qk),
+                       hk["face_forms"] / len(Qk))
+            tot += bk * len(works[k].Q)
+        result["batched_roofline"] = {"b_alg_bytes_per_query": round(tot / nb, 1),
+                                      "achieved_GBps_whole_launch": round(tot / (ms_b / 1e3) / 1e9, 1),
+                                      "frac": round(tot / (ms_b / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                                      "note": "over the whole graph launch (keys, sort, query, write-out)"}
         result["batched"] = {"value": round(nb / (ms_b / 1e3), 1), "unit": "queries/s", "ms_per_step": round(ms_b, 4),
                              "plain_launches": {"value": round(nb / (ms_p / 1e3), 1), "ms_per_step": round(ms_p, 4),
                                                 "launches": count},
@@ -431,10 +563,16 @@ def main():
         t0 = time.perf_counter()
         mesh.query_host(sub2, threads=nth)
         dt = time.perf_counter() - t0
+        sub1 = w.Q[:100_000]
+        t0 = time.perf_counter()
+        mesh.query_host(sub1, threads=1)
+        dt1 = time.perf_counter() - t0
         result["cpu_p2m"] = {"value": round(len(sub2) / dt, 1), "unit": "queries/s", "threads": nth,
                              "kind": "multi-threaded CPU P2M query, same structures and float32 code as the default device path",
-                             "sample": "first 1e6 queries of the workload"}
-        log(f"[bench] CPU P2M: {len(sub2) / dt:.0f} q/s")
+                             "sample": "first 1e6 queries of the workload",
+                             "one_thread": {"value": round(len(sub1) / dt1, 1), "us_per_query": round(dt1 / len(sub1) * 1e6, 3),
+                                            "sample": "first 1e5 queries of the workload"}}
+        log(f"[bench] CPU P2M: {len(sub2) / dt:.0f} q/s on {nth} threads, {len(sub1) / dt1:.0f} q/s on one")
 
     print(json.dumps(result))
 

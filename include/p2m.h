@@ -105,6 +105,18 @@ typedef struct {
      * primitives and cells the host finished */
     double t_dev_upload, t_dev_kernel, t_dev_download;
     int64_t device_redo, device_cells_back;
+    /* The list statistics of Table 1 (Sec. 5.1), edges and faces apart: the
+     * mean list over vertices (Avg^1: avg_edges, avg_faces; their sum is
+     * avg_list), the mean weighted by the volume of each vertex's Voronoi
+     * cell in D (Avg^2: the list a query uniform in D scans; estimated from
+     * one jittered sample in each cell of a 128^3 grid on D and its nearest
+     * vertex, deterministic), and the maxima over vertices. */
+    double avg_edges, avg_faces, avg_list_volw, avg_edges_volw, avg_faces_volw;
+    int64_t max_edges, max_faces;
+    /* Vertices taken from the flood queues (Algorithm 1): each primitive's
+     * own vertices plus the flood_tests; 0 in the ALL_PAIRS and EVERYTHING
+     * modes, which do not flood. */
+    int64_t flood_visits;
 } p2m_build_stats;
 
 typedef struct {
@@ -288,18 +300,19 @@ void p2m_batch_destroy(p2m_batch* b);
  * queries of mesh k at rows q_offsets_host[k] .. q_offsets_host[k+1] (host
  * int64 [count+1], q_offsets_host[0] = 0, non-decreasing, N =
  * q_offsets_host[count]).  Outputs (device) as p2m_query, in the same row
- * order; primitive ids are local to each mesh.  The launch sequence
+ * order; primitive ids are local to each mesh; status_dev uint8 [N] (may be
+ * NULL) receives the status bits of each query in its mesh's domain.  The launch sequence
  * (ordering keys and sort, work-counter reset, persistent kernel, write-out
  * of the staged 32-byte answers) is captured into a HIP graph on first use
  * and replayed while the offsets,
  * pointers and launch shape stay the same.  A new offset layout uploads a
  * tile list and waits for that copy.  Calls on one batch must not overlap. */
 p2m_status p2m_batch_query(p2m_batch* b, const float* q_dev, const int64_t* q_offsets_host, int32_t* prim_dev,
-                           float* closest_dev, float* dist_dev, void* stream);
+                           float* closest_dev, float* dist_dev, uint8_t* status_dev, void* stream);
 
 /* The same work enqueued directly on `stream` (no graph). */
 p2m_status p2m_batch_query_eager(p2m_batch* b, const float* q_dev, const int64_t* q_offsets_host, int32_t* prim_dev,
-                                 float* closest_dev, float* dist_dev, void* stream);
+                                 float* closest_dev, float* dist_dev, uint8_t* status_dev, void* stream);
 
 /* Launch shape of the batched kernel: workgroup size (64, 128, 192 or
  * 256), queries per lane in a tile (1..16), nearest-vertex traversal (1, 2

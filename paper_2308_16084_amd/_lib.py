@@ -32,7 +32,10 @@ class BuildStats(ctypes.Structure):
                                    "nnz_edges", "nnz_faces", "max_list")] + \
                [("avg_list", ctypes.c_double)] + \
                [(n, ctypes.c_double) for n in ("t_dev_upload", "t_dev_kernel", "t_dev_download")] + \
-               [("device_redo", I64), ("device_cells_back", I64)]
+               [("device_redo", I64), ("device_cells_back", I64)] + \
+               [(n, ctypes.c_double) for n in ("avg_edges", "avg_faces", "avg_list_volw", "avg_edges_volw",
+                                               "avg_faces_volw")] + \
+               [("max_edges", I64), ("max_faces", I64), ("flood_visits", I64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -67,8 +70,8 @@ _SIGS = {
     "p2m_query_backward": (INT, [P, P, I64, P, P, P, P, P, P, P, P]),
     "p2m_batch_create": (INT, [P, I32, INT, P, P]),
     "p2m_batch_destroy": (None, [P]),
-    "p2m_batch_query": (INT, [P, P, P, P, P, P, P]),
-    "p2m_batch_query_eager": (INT, [P, P, P, P, P, P, P]),
+    "p2m_batch_query": (INT, [P, P, P, P, P, P, P, P]),
+    "p2m_batch_query_eager": (INT, [P, P, P, P, P, P, P, P]),
     "p2m_batch_set_shape": (INT, [P, INT, INT, INT]),
     "p2m_batch_get_shape": (INT, [P, P, P, P]),
     "p2m_batch_set_schedule": (INT, [P, INT]),

@@ -319,25 +319,28 @@ class Batch:
         off = np.ascontiguousarray(np.asarray(q_offsets, dtype=np.int64))
         return off
 
-    def _outs(self, q, out):
+    def _outs(self, q, out, status=True):
         torch = _torch()
         n = q.shape[0]
         if out is None:
             out = {"prim": torch.empty(n, dtype=torch.int32, device=q.device),
                    "closest": torch.empty((n, 3), dtype=torch.float32, device=q.device),
                    "dist": torch.empty(n, dtype=torch.float32, device=q.device)}
+            if status:
+                out["status"] = torch.empty(n, dtype=torch.uint8, device=q.device)
         return out
 
-    def query(self, q, q_offsets, out: dict | None = None, graph: bool = True, stream=None) -> dict:
+    def query(self, q, q_offsets, out: dict | None = None, graph: bool = True, stream=None,
+              status: bool = True) -> dict:
         torch = _torch()
         q = _dev_tensor(q, torch.float32, (3,), "q")
         off = self._offsets(q_offsets)
         if off.shape[0] != len(self.meshes) + 1 or off[-1] != q.shape[0]:
             raise ValueError("q_offsets must have len(meshes)+1 entries ending at len(q)")
-        out = self._outs(q, out)
+        out = self._outs(q, out, status)
         fn = lib().p2m_batch_query if graph else lib().p2m_batch_query_eager
         check(fn(self._h, _ptr(q), _ptr(off), _ptr(out["prim"]), _ptr(out["closest"]), _ptr(out["dist"]),
-                 _stream(stream)))
+                 _ptr(out.get("status")), _stream(stream)))
         return out
 
     def set_shape(self, block: int, queries_per_lane: int, traversal: int) -> None:
@@ -360,7 +363,7 @@ class Batch:
         torch = _torch()
         q = _dev_tensor(q, torch.float32, (3,), "q")
         off = self._offsets(q_offsets)
-        out = self._outs(q, out)
+        out = self._outs(q, out, status=False)
         a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         check(lib().p2m_batch_autotune(self._h, _ptr(q), _ptr(off), _ptr(out["prim"]), _ptr(out["closest"]),
                                        _ptr(out["dist"]), _stream(stream), ctypes.byref(a), ctypes.byref(b),

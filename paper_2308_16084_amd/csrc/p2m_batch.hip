@@ -129,7 +129,7 @@ struct p2m_batch {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    const void* g_ptrs[4] = {nullptr, nullptr, nullptr, nullptr};
+    const void* g_ptrs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     int g_shape[3] = {0, 0, 0};
 };
 
@@ -293,10 +293,12 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
                 nv.pz = col[6 * S + u];
                 nv.vid = icol[S + u];
                 ScanCounters c;
-                const Answer a = finite3(qx, qy, qz) ? p2m_answer(v, qx, qy, qz, nv, c) : nonfinite_answer();
+                const bool fin = finite3(qx, qy, qz);
+                const Answer a = fin ? p2m_answer(v, qx, qy, qz, nv, c) : nonfinite_answer();
+                const int stb = fin ? (int)domain_status(v, qx, qy, qz) : 2;
                 // one 32-byte record per query; split into the outputs afterwards
                 stage[2 * i] = make_float4(__int_as_float(a.prim), a.cx, a.cy, a.cz);
-                stage[2 * i + 1] = make_float4(a.dist, 0.f, 0.f, 0.f);
+                stage[2 * i + 1] = make_float4(a.dist, __int_as_float(stb), 0.f, 0.f);
             }
             __syncthreads();  // the slots are refilled by the next rounds or tile
         }
@@ -389,7 +391,8 @@ p2m_status prepare(p2m_batch* b, const int64_t* qoff_host, hipStream_t st) {
 
 // Enqueue the whole batched query (keys, sort, counter reset, persistent
 // kernel, write-out of the staged answers).
-p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, float* dist, hipStream_t st) {
+p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, float* dist, uint8_t* status,
+                   hipStream_t st) {
     const int64_t n = b->n;
     if (n == 0) return P2M_OK;
     RadixPlan plan = radix_plan_segmented(n, b->sort_seg.ntiles, b->sort_seg.nseg);
@@ -417,7 +420,7 @@ p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, 
 #undef P2M_LAUNCH_BATCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batched query launch");
-    e = launch_split(b->stage, n, prim, closest, dist, nullptr, nullptr, nullptr, st);
+    e = launch_split(b->stage, n, prim, closest, dist, status, nullptr, nullptr, st);
     if (e != hipSuccess) return hip_fail(e, "batched answer write-out");
     return P2M_OK;
 }
@@ -632,7 +635,7 @@ p2m_status p2m_batch_get_schedule(const p2m_batch* b, int* persistent) {
 }
 
 p2m_status p2m_batch_query(p2m_batch* b, const float* q, const int64_t* qoff, int32_t* prim, float* closest,
-                           float* dist, void* stream) {
+                           float* dist, uint8_t* status, void* stream) {
     if (!b) return fail(P2M_ERR_ARG, "batch is NULL");
     if (!qoff) return fail(P2M_ERR_ARG, "q_offsets is NULL");
     Guard g(b->device);
@@ -641,13 +644,13 @@ p2m_status p2m_batch_query(p2m_batch* b, const float* q, const int64_t* qoff, in
     if (r != P2M_OK) return r;
     if (b->n == 0) return P2M_OK;
     if (!q || !prim || !closest || !dist) return fail(P2M_ERR_ARG, "NULL query or output pointer");
-    const void* ptrs[4] = {q, prim, closest, dist};
+    const void* ptrs[5] = {q, prim, closest, dist, status};
     const int shape[3] = {b->block, b->qpl, b->traversal};
     if (!b->exec || std::memcmp(ptrs, b->g_ptrs, sizeof(ptrs)) != 0 || std::memcmp(shape, b->g_shape, sizeof(shape)) != 0) {
         drop_graph(b);
         hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "graph capture begin");
-        r = enqueue(b, q, prim, closest, dist, b->cap_stream);
+        r = enqueue(b, q, prim, closest, dist, status, b->cap_stream);
         hipGraph_t gr = nullptr;
         e = hipStreamEndCapture(b->cap_stream, &gr);
         if (r != P2M_OK) {
@@ -670,7 +673,7 @@ p2m_status p2m_batch_query(p2m_batch* b, const float* q, const int64_t* qoff, in
 }
 
 p2m_status p2m_batch_query_eager(p2m_batch* b, const float* q, const int64_t* qoff, int32_t* prim, float* closest,
-                                 float* dist, void* stream) {
+                                 float* dist, uint8_t* status, void* stream) {
     if (!b) return fail(P2M_ERR_ARG, "batch is NULL");
     if (!qoff) return fail(P2M_ERR_ARG, "q_offsets is NULL");
     Guard g(b->device);
@@ -679,7 +682,7 @@ p2m_status p2m_batch_query_eager(p2m_batch* b, const float* q, const int64_t* qo
     if (r != P2M_OK) return r;
     if (b->n == 0) return P2M_OK;
     if (!q || !prim || !closest || !dist) return fail(P2M_ERR_ARG, "NULL query or output pointer");
-    return enqueue(b, q, prim, closest, dist, st);
+    return enqueue(b, q, prim, closest, dist, status, st);
 }
 
 p2m_status p2m_batch_autotune(p2m_batch* b, const float* q, const int64_t* qoff, int32_t* prim, float* closest,
@@ -703,7 +706,7 @@ p2m_status p2m_batch_autotune(p2m_batch* b, const float* q, const int64_t* qoff,
                 float tot = 0.f;
                 for (int rep = 0; rep < 3 && r == P2M_OK; ++rep) {
                     (void)hipEventRecord(e0, st);
-                    r = p2m_batch_query_eager(b, q, qoff, prim, closest, dist, stream);
+                    r = p2m_batch_query_eager(b, q, qoff, prim, closest, dist, nullptr, stream);
                     (void)hipEventRecord(e1, st);
                     float ms = 0.f;
                     if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)

@@ -18,6 +18,7 @@
 #include "nearest.hpp"
 #include "query_core.hpp"
 #include "regroup.hpp"
+#include "wave_scan.hpp"
 
 namespace p2m {
 
@@ -395,8 +396,10 @@ __global__ void k_morton(const float* __restrict__ q, int64_t n, float lox, floa
 }
 
 // Dynamic LDS of k_query: the regroup bins, then per slot 7 floats (q, the
-// nearest vertex's d2 and position) and 2 ints (query index, vertex).
+// nearest vertex's d2 and position) and 2 ints (query index, vertex); after
+// the regroup, the slots of each wavefront hold its scan rings.
 constexpr size_t regroup_lds_bytes(int block) { return sizeof(uint32_t) * (kRegroupBins + 9 * (size_t)block); }
+static_assert(sizeof(WaveScanLds) <= 9 * 64 * sizeof(uint32_t), "scan rings exceed a wavefront's regroup slots");
 
 // stage (ordered batches): query i's answer goes to stage[S*i .. S*i+S-1]
 // (S = 2, or 3 with the backward extras) as (prim, closest), (dist, status,
@@ -451,7 +454,6 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const floa
     icol[B + pos] = nv.vid;
     __syncthreads();
     i = icol[t];
-    if (i < 0) return;
     qx = col[t];
     qy = col[B + t];
     qz = col[2 * B + t];
@@ -461,8 +463,16 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const floa
     nv.pz = col[6 * B + t];
     nv.vid = icol[B + t];
     fin = finite3(qx, qy, qz);
+    // the regroup slots are free again: each wavefront's scan rings go there
+    __syncthreads();
+    WaveScanLds& ring = reinterpret_cast<WaveScanLds*>(lds + kRegroupBins)[t >> 6];
+    float best;
+    int best_kind;
+    int32_t best_id;
+    wave_scan(m, ring, i >= 0 && fin, qx, qy, qz, nv, best, best_kind, best_id, c);
+    if (i < 0) return;
     uint8_t st = fin ? domain_status(m, qx, qy, qz) : (uint8_t)2;
-    const Answer a = fin ? p2m_answer(m, qx, qy, qz, nv, c) : nonfinite_answer();
+    const Answer a = fin ? finish_answer(m, qx, qy, qz, nv, best, best_kind, best_id, c) : nonfinite_answer();
     if (stage) {
         constexpr int S = kWriteExtras ? 3 : 2;
         stage[S * i] = make_float4(__int_as_float(a.prim), a.cx, a.cy, a.cz);

@@ -1,10 +1,12 @@
 // Host side of the C interface: mesh creation, precompute, inspection,
 // save/load and error reporting.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "p2m_internal.hpp"
@@ -23,6 +25,101 @@ p2m_status fail(p2m_status s, const std::string& msg) {
     set_error(msg);
     return s;
 }
+
+namespace {
+
+// Nearest vertex of q by a greedy walk over the Voronoi (Delaunay) neighbour
+// graph from vertex v: exact for q in D (a vertex whose cell does not hold
+// q has a closer Voronoi neighbour), float64, ties to the smaller id.
+int32_t walk_nearest(const MeshData& m, const Table& t, const double q[3], int32_t v) {
+    auto d2 = [&](int32_t w) {
+        const double* p = &m.Vd[3 * (size_t)w];
+        return (q[0] - p[0]) * (q[0] - p[0]) + (q[1] - p[1]) * (q[1] - p[1]) + (q[2] - p[2]) * (q[2] - p[2]);
+    };
+    double best = d2(v);
+    for (int it = 0; it < (1 << 20); ++it) {
+        int32_t nb = v;
+        for (int64_t k = t.nb_off[(size_t)v]; k < t.nb_off[(size_t)v + 1]; ++k) {
+            const int32_t w = t.nb[(size_t)k];
+            const double d = d2(w);
+            if (d < best || (d == best && w < nb)) {
+                best = d;
+                nb = w;
+            }
+        }
+        if (nb == v) break;
+        v = nb;
+    }
+    return v;
+}
+
+uint64_t mix64(uint64_t x) {  // splitmix64 finaliser
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// The list statistics of Table 1: per vertex the edges and faces of its
+// interception list; Avg^1 the mean over vertices, Avg^2 the mean weighted
+// by the volume of the vertex's Voronoi cell (in D here: the expected list
+// of a query uniform in D), estimated from one sample in each cell of a
+// 128^3 grid on D (jittered by a hash of the cell, so the estimate is
+// deterministic) and the sample's nearest vertex (a walk from the previous
+// sample's); the maxima over vertices.
+void list_stats(const MeshState& s, int threads, p2m_build_stats& st) {
+    const int64_t nv = s.m.nv;
+    const std::vector<uint32_t>& off = s.t.off;
+    double se = 0, sf = 0;
+    int64_t me = 0, mf = 0;
+    for (int64_t v = 0; v < nv; ++v) {
+        const int64_t e = off[(size_t)(2 * v + 1)] - off[(size_t)(2 * v)];
+        const int64_t f = off[(size_t)(2 * v + 2)] - off[(size_t)(2 * v + 1)];
+        se += (double)e;
+        sf += (double)f;
+        me = std::max(me, e);
+        mf = std::max(mf, f);
+    }
+    st.avg_edges = se / (double)nv;
+    st.avg_faces = sf / (double)nv;
+    st.max_edges = me;
+    st.max_faces = mf;
+    constexpr int G = 128;
+    int nt = threads > 0 ? threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    nt = std::min(nt, G);
+    std::vector<double> ae((size_t)nt, 0.0), af((size_t)nt, 0.0);
+    auto work = [&](int w) {
+        int32_t v = 0;
+        for (int i = w; i < G; i += nt)
+            for (int j = 0; j < G; ++j)
+                for (int k = 0; k < G; ++k) {
+                    const uint64_t h = mix64(((uint64_t)i * G + (uint64_t)j) * G + (uint64_t)k);
+                    const double u[3] = {(double)(h & 0x1FFFFF) / 2097152.0, (double)((h >> 21) & 0x1FFFFF) / 2097152.0,
+                                         (double)((h >> 42) & 0x1FFFFF) / 2097152.0};
+                    const int c[3] = {i, j, k};
+                    double q[3];
+                    for (int a = 0; a < 3; ++a) q[a] = s.dlo[a] + (c[a] + u[a]) / G * (s.dhi[a] - s.dlo[a]);
+                    v = walk_nearest(s.m, s.t, q, v);
+                    ae[(size_t)w] += (double)(off[(size_t)(2 * v + 1)] - off[(size_t)(2 * v)]);
+                    af[(size_t)w] += (double)(off[(size_t)(2 * v + 2)] - off[(size_t)(2 * v + 1)]);
+                }
+    };
+    std::vector<std::thread> th;
+    for (int w = 1; w < nt; ++w) th.emplace_back(work, w);
+    work(0);
+    for (auto& x : th) x.join();
+    double te = 0, tf = 0;
+    for (int w = 0; w < nt; ++w) {
+        te += ae[(size_t)w];
+        tf += af[(size_t)w];
+    }
+    const double ns = (double)G * G * G;
+    st.avg_edges_volw = te / ns;
+    st.avg_faces_volw = tf / ns;
+    st.avg_list_volw = (te + tf) / ns;
+}
+
+}  // namespace
 
 }  // namespace p2m
 
@@ -174,6 +271,11 @@ p2m_status p2m_precompute(p2m_mesh* m, const p2m_build_opts* opts, p2m_build_sta
         st.t_dev_download = s.ts.t_dev_download;
         st.device_redo = s.ts.device_redo;
         st.device_cells_back = s.ts.device_cells_back;
+        // the flood (Algorithm 1) takes each primitive's own vertices, then
+        // every vertex it filter-tests, from its queue
+        const bool flooded = o.table_mode == P2M_TABLE_FLOODING || o.table_mode == P2M_TABLE_FLOODING_DEVICE;
+        st.flood_visits = flooded ? s.ts.flood_tests + 2 * s.m.ne + 3 * s.m.nf : 0;
+        list_stats(s, o.num_threads, st);
     }
     return P2M_OK;
 }

@@ -598,13 +598,16 @@ P2M_HD void rescan(const MeshView& m, float qx, float qy, float qz, int32_t v, f
 
 constexpr float kAcceptRel = 1.00000095367431640625f;  // 1 + 2^-20
 
-P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const Nearest& nv, ScanCounters& cnt) {
-    Answer a;
-    // running minimum of the gated values over v and v's list (kind/id of
-    // the best)
-    float best = nv.d2;
-    int best_kind = KIND_VERTEX;
-    int32_t best_id = nv.vid;
+// Step 3, one query at a time: the running minimum of the gated values
+// over v and v's list, in list order (edges, then faces, ids ascending
+// within each run), a later candidate replacing the best only when
+// strictly smaller -- so the winner is the least (value, kind, id), vertex
+// before edge before face, as the wavefront scan of the kernels finds it.
+P2M_HD void scan_list(const MeshView& m, float qx, float qy, float qz, const Nearest& nv, float& best,
+                      int& best_kind, int32_t& best_id, ScanCounters& cnt) {
+    best = nv.d2;
+    best_kind = KIND_VERTEX;
+    best_id = nv.vid;
     const float rx = qx - m.ctr[0], ry = qy - m.ctr[1], rz = qz - m.ctr[2];
     const uint4 h0 = m.vhead[2 * nv.vid], h1 = m.vhead[2 * nv.vid + 1];
     const uint32_t e0 = h0.x, f0 = h0.y, f1 = h0.z;
@@ -656,6 +659,13 @@ P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const 
     }
     cnt.edges += f0 - e0;
     cnt.faces += f1 - f0;
+}
+
+// Step 4 given the scan's winner (value best, kind, id): the winner checked
+// against its own gated value (second scan if needed) and resolved.
+P2M_HD Answer finish_answer(const MeshView& m, float qx, float qy, float qz, const Nearest& nv, float best,
+                            int best_kind, int32_t best_id, ScanCounters& cnt) {
+    Answer a;
     // The winner of the gated ranking is the closest when its exact distance
     // is within the slack of its own gated value: that value is at most
     // every other candidate's gated value, itself at most that candidate's
@@ -697,6 +707,15 @@ P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const 
     }
     a.dist = sqrtf(exact);
     return a;
+}
+
+
+P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const Nearest& nv, ScanCounters& cnt) {
+    float best;
+    int best_kind;
+    int32_t best_id;
+    scan_list(m, qx, qy, qz, nv, best, best_kind, best_id, cnt);
+    return finish_answer(m, qx, qy, qz, nv, best, best_kind, best_id, cnt);
 }
 
 // The whole query for one point (per-lane KD-tree search).

@@ -134,3 +134,29 @@ def test_autotune_and_layout_change(batch_setup):
         n2 = len(works[k].Q) // 2
         assert np.array_equal(out2["dist"][half[k]:half[k] + n2], got["dist"][off[k]:off[k] + n2]) or \
             np.max(np.abs(out2["dist"][half[k]:half[k] + n2] - got["dist"][off[k]:off[k] + n2])) <= 1e-6
+
+
+def test_batch_status_flags(batch_setup):
+    """Per-query status bits from the batched launch: out of the mesh's
+    domain and non-finite queries are flagged as by the plain launch."""
+    import torch
+
+    import paper_2308_16084_amd as P
+    works, meshes, b, Q, off, q = batch_setup
+    Q2 = Q.copy()
+    k = 1
+    r0 = int(off[k])
+    Q2[r0] = works[k].domain_hi + 1.0          # outside mesh k's domain
+    Q2[r0 + 1] = np.nan                         # non-finite
+    q2 = torch.from_numpy(Q2).cuda()
+    for graph in (True, False):
+        out = _np(b.query(q2, off, graph=graph))
+        assert out["status"][r0] == P.OUT_OF_DOMAIN and out["status"][r0 + 1] == P.NONFINITE
+        rest = np.ones(len(Q2), bool)
+        rest[[r0, r0 + 1]] = False
+        assert np.all(out["status"][rest] == 0)
+        assert np.isnan(out["dist"][r0 + 1]) and P.prim_type(out["prim"][r0 + 1]) == P.NONE
+        m = meshes[k]
+        m.upload(0)
+        o = _np(m.query(q2[r0:r0 + 2].contiguous()))
+        assert o["status"].tolist() == out["status"][r0:r0 + 2].tolist()

@@ -470,3 +470,26 @@ def test_precompute_option_validation(kw, msg):
     m = P.Mesh(TETRA_V, TETRA_F)
     with pytest.raises(P.P2MError, match=msg):
         m.precompute(**kw)
+
+
+def test_list_statistics():
+    """Table 1's list statistics: Avg^1 and the maxima from the table itself;
+    Avg^2 (weighted by Voronoi-cell volume in D) against an independent
+    estimate: uniform random points of D, their nearest vertex by brute
+    force, the mean of its list lengths (within 4 standard errors)."""
+    rng = np.random.default_rng(14)
+    V, F = random_tiny_mesh(rng, "sphere")
+    m, st, (lo, hi) = _mesh(V, F, scale=2.0)
+    off, _ = m.table()
+    ne = (off[1::2][:len(V)] - off[0::2][:len(V)]).astype(np.float64)
+    nf = (off[2::2] - off[1::2][:len(V)]).astype(np.float64)
+    assert abs(st["avg_edges"] - ne.mean()) < 1e-12 and abs(st["avg_faces"] - nf.mean()) < 1e-12
+    assert st["max_edges"] == ne.max() and st["max_faces"] == nf.max()
+    assert st["max_list"] == (ne + nf).max()
+    Q = rng.uniform(lo, hi, size=(200_000, 3))
+    nn = np.argmin(((Q[:, None, :] - V.astype(np.float64)[None]) ** 2).sum(-1), axis=1)
+    for key, per in (("avg_edges_volw", ne), ("avg_faces_volw", nf), ("avg_list_volw", ne + nf)):
+        x = per[nn]
+        se = x.std() / np.sqrt(len(x))
+        assert abs(st[key] - x.mean()) <= 4 * se + 0.01, (key, st[key], x.mean(), se)
+    assert st["flood_visits"] == st["flood_tests"] + 2 * st["ne"] + 3 * st["nf"]
