@@ -491,6 +491,10 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms_b = e0.elapsed_time(e1) / args.steps
+        # the persistent schedule (workgroups claiming tiles from a counter) at the same shape
+        batch.set_schedule(True)
+        ms_pers = time_steps(lambda: batch.query(qb, offb, out=outb), args.steps, args.warmup)
+        batch.set_schedule(False)
         # the same work as one plain launch sequence per mesh
         for m_ in meshes:
             m_.upload(0)
@@ -531,6 +535,7 @@ def main():
                              "plain_launches": {"value": round(nb / (ms_p / 1e3), 1), "ms_per_step": round(ms_p, 4),
                                                 "launches": count},
                              "speedup_vs_plain": round(ms_p / ms_b, 3),
+                             "persistent_schedule_ms": round(ms_pers, 4),
                              "shape": {"block": shape[0], "queries_per_lane": shape[1],
                                        "traversal": {1: "kd per-lane", 2: "kd wavefront", 3: "voronoi walk"}[shape[2]]},
                              "workload": (f"{'all' if count == 256 else 'first'} {count} meshes of the seeded 256-mesh plan "
@@ -539,7 +544,7 @@ def main():
                              "precompute_s": round(t_pre4, 1), "precompute": "host Delaunay + cells, inspection on the GPU",
                              "generate_s": round(t_gen, 1)}
         log(f"[bench] batched ({count} meshes, {ntri} tris, {nb} queries): {ms_b:.3f} ms graph vs {ms_p:.3f} ms "
-            f"for {count} plain launches; shape {shape}; precompute {t_pre4:.1f}s")
+            f"for {count} plain launches; persistent schedule {ms_pers:.3f} ms; shape {shape}; precompute {t_pre4:.1f}s")
         del batch, meshes, qb, outb, outs, qsl
 
     if not args.no_cpu:

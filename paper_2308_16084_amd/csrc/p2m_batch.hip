@@ -28,6 +28,7 @@
 #include "nearest.hpp"
 #include "query_core.hpp"
 #include "regroup.hpp"
+#include "wave_scan.hpp"
 
 namespace p2m {
 
@@ -197,8 +198,12 @@ constexpr int kRegroupSlots = 256;
 int regroup_rounds(int block, int qpl) { return std::max(1, std::min(qpl, kRegroupSlots / block)); }
 // Dynamic LDS: the bins, then per slot 7 floats (q, the nearest vertex's d2
 // and position) and 4 ints (query index, vertex, bin and rank, source slot).
-size_t batch_lds_bytes(int block, int qpl) {
+size_t batch_slots_bytes(int block, int qpl) {
     return sizeof(uint32_t) * (kRegroupBins + 11 * (size_t)block * (size_t)regroup_rounds(block, qpl));
+}
+// the regroup slots, then each wavefront's scan rings
+size_t batch_lds_bytes(int block, int qpl) {
+    return (batch_slots_bytes(block, qpl) + 15) / 16 * 16 + sizeof(WaveScanLds) * (size_t)(block / 64);
 }
 
 // One-workgroup-per-tile order: the tiles are dealt to the 8 XCDs
@@ -206,15 +211,18 @@ size_t batch_lds_bytes(int block, int qpl) {
 // so a run of one mesh's spatially adjacent tiles shares an L2; the grid is
 // a multiple of 8 * kTileRun and workgroups past the list exit at once.
 constexpr int64_t kTileRun = 16;
+// Persistent schedule: tiles a workgroup claims with one counter increment.
+constexpr int64_t kTileChunk = 16;
 __device__ __forceinline__ int64_t run_tile(int64_t b) {
     const int64_t sg = b / (kXcds * kTileRun), r = b % (kXcds * kTileRun);
     return sg * kXcds * kTileRun + (r % kXcds) * kTileRun + r / kXcds;
 }
 
 template <int kWalk, bool kPersistent>
-__global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
-    Arena A, const Tile* __restrict__ tiles, int64_t ntiles, uint32_t* counter, int qpl, int group,
-    const float* __restrict__ q, const int32_t* __restrict__ perm, int64_t n, float4* __restrict__ stage) {
+__device__ __forceinline__ void batch_query(Arena A, const Tile* __restrict__ tiles, int64_t ntiles,
+                                            uint32_t* counter, int qpl, int group, const float* __restrict__ q,
+                                            const int32_t* __restrict__ perm, int64_t n,
+                                            float4* __restrict__ stage) {
     extern __shared__ uint32_t lds[];
     __shared__ int64_t s_tile;
     const int t = threadIdx.x, B = blockDim.x;
@@ -222,14 +230,25 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
     uint32_t* hist = lds;
     float* col = (float*)(lds + kRegroupBins);  // qx qy qz d2 px py pz, S each
     int32_t* icol = (int32_t*)(col + 7 * S);    // query index, vertex, bin << 24 | rank, source slot
+    WaveScanLds& ring = reinterpret_cast<WaveScanLds*>(
+        (char*)lds + ((kRegroupBins + 11 * (size_t)S) * sizeof(uint32_t) + 15) / 16 * 16)[t >> 6];
+    int64_t next = 0, chunk_end = 0;  // persistent: the claimed tiles not yet taken
     for (bool more = true; more;) {
         int64_t tt = run_tile(blockIdx.x);  // one tile per workgroup
         more = false;
         if (kPersistent) {
-            if (t == 0) s_tile = (int64_t)atomicAdd(counter, 1u);
-            __syncthreads();
-            tt = s_tile;
-            __syncthreads();
+            // tiles are claimed kTileChunk at a time: one counter increment
+            // per chunk rather than per tile
+            if (next >= chunk_end) {
+                if (t == 0) s_tile = (int64_t)atomicAdd(counter, (uint32_t)kTileChunk);
+                __syncthreads();
+                // the same for every lane: kept in scalar registers, with the
+                // mesh view derived from it
+                next = (int64_t)__builtin_amdgcn_readfirstlane((int)s_tile);
+                chunk_end = next + kTileChunk;
+                __syncthreads();
+            }
+            tt = next++;
             more = true;
         }
         if (tt >= ntiles) break;  // uniform across the workgroup
@@ -284,7 +303,6 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
             for (int r = 0; r < rounds; ++r) {
                 const int u = icol[3 * S + r * B + t];
                 const int64_t i = icol[u];
-                if (i < 0) continue;
                 const float qx = col[u], qy = col[S + u], qz = col[2 * S + u];
                 Nearest nv;
                 nv.d2 = col[3 * S + u];
@@ -294,7 +312,13 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
                 nv.vid = icol[S + u];
                 ScanCounters c;
                 const bool fin = finite3(qx, qy, qz);
-                const Answer a = fin ? p2m_answer(v, qx, qy, qz, nv, c) : nonfinite_answer();
+                // every lane of the wavefront takes part in the scan
+                float best;
+                int best_kind;
+                int32_t best_id;
+                wave_scan(v, ring, i >= 0 && fin, qx, qy, qz, nv, best, best_kind, best_id, c);
+                if (i < 0) continue;
+                const Answer a = fin ? finish_answer(v, qx, qy, qz, nv, best, best_kind, best_id, c) : nonfinite_answer();
                 const int stb = fin ? (int)domain_status(v, qx, qy, qz) : 2;
                 // one 32-byte record per query; split into the outputs afterwards
                 stage[2 * i] = make_float4(__int_as_float(a.prim), a.cx, a.cy, a.cz);
@@ -303,6 +327,25 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(
             __syncthreads();  // the slots are refilled by the next rounds or tile
         }
     }
+}
+
+// The tree-walk forms (traversals 1 and 2).
+template <int kWalk, bool kPersistent>
+__global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(Arena A, const Tile* __restrict__ tiles,
+                                                                int64_t ntiles, uint32_t* counter, int qpl,
+                                                                int group, const float* __restrict__ q,
+                                                                const int32_t* __restrict__ perm, int64_t n,
+                                                                float4* __restrict__ stage) {
+    batch_query<kWalk, kPersistent>(A, tiles, ntiles, counter, qpl, group, q, perm, n, stage);
+}
+
+// The Voronoi-walk forms (the default traversal), held to 80 registers so
+// that six wavefronts fit on each SIMD.
+template <bool kPersistent>
+__global__ __launch_bounds__(kQueryMaxBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_batch_query_walk(
+    Arena A, const Tile* __restrict__ tiles, int64_t ntiles, uint32_t* counter, int qpl, int group,
+    const float* __restrict__ q, const int32_t* __restrict__ perm, int64_t n, float4* __restrict__ stage) {
+    batch_query<WALK_VORONOI, kPersistent>(A, tiles, ntiles, counter, qpl, group, q, perm, n, stage);
 }
 
 void drop_graph(p2m_batch* b) {
@@ -405,17 +448,17 @@ p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, 
     const int grid = b->persistent ? b->grid : (int)((b->ntiles + run8 - 1) / run8 * run8);
     const Arena A{b->node,  b->vhead, b->lent, b->seg,  b->tri,  b->fedge,
                   b->nboff, b->nbrec, b->seed, b->frec, b->erec, b->desc};
-#define P2M_LAUNCH_BATCH(W, P)                                                                               \
-    k_batch_query<W, P><<<grid, b->block, batch_lds_bytes(b->block, b->qpl), st>>>(                        \
+#define P2M_LAUNCH_BATCH(K)                                                                                   \
+    K<<<grid, b->block, batch_lds_bytes(b->block, b->qpl), st>>>(                                              \
         A, b->tiles, b->ntiles, b->counter, b->qpl, regroup_rounds(b->block, b->qpl), q, rb.vals[cur], n, b->stage)
     if (b->persistent) {
-        if (b->traversal == 1) P2M_LAUNCH_BATCH(WALK_LANE, true);
-        else if (b->traversal == 2) P2M_LAUNCH_BATCH(WALK_WAVE, true);
-        else P2M_LAUNCH_BATCH(WALK_VORONOI, true);
+        if (b->traversal == 1) P2M_LAUNCH_BATCH((k_batch_query<WALK_LANE, true>));
+        else if (b->traversal == 2) P2M_LAUNCH_BATCH((k_batch_query<WALK_WAVE, true>));
+        else P2M_LAUNCH_BATCH((k_batch_query<WALK_VORONOI, true>));
     } else {
-        if (b->traversal == 1) P2M_LAUNCH_BATCH(WALK_LANE, false);
-        else if (b->traversal == 2) P2M_LAUNCH_BATCH(WALK_WAVE, false);
-        else P2M_LAUNCH_BATCH(WALK_VORONOI, false);
+        if (b->traversal == 1) P2M_LAUNCH_BATCH((k_batch_query<WALK_LANE, false>));
+        else if (b->traversal == 2) P2M_LAUNCH_BATCH((k_batch_query<WALK_WAVE, false>));
+        else P2M_LAUNCH_BATCH(k_batch_query_walk<false>);
     }
 #undef P2M_LAUNCH_BATCH
     hipError_t e = hipGetLastError();

@@ -248,9 +248,11 @@ void pack_mesh(MeshState& s) {
     // entry: a walk step reads one contiguous run, no id -> position gather)
     s.pk_nboff.resize(s.t.nb_off.size());
     for (size_t k = 0; k < s.t.nb_off.size(); ++k) s.pk_nboff[k] = (uint32_t)s.t.nb_off[k];
-    s.pk_nbrec.resize(4 * s.t.nb.size());
-    for (size_t k = 0; k < s.t.nb.size(); ++k) {
-        const int32_t w = s.t.nb[k];
+    // kWalkGroup - 1 records of padding at the end (copies of the last): a
+    // walk group loads kWalkGroup consecutive records from any list start
+    s.pk_nbrec.resize(4 * (s.t.nb.size() + kWalkGroup - 1));
+    for (size_t k = 0; k < s.t.nb.size() + kWalkGroup - 1; ++k) {
+        const int32_t w = s.t.nb[std::min(k, s.t.nb.size() - 1)];
         float* d = &s.pk_nbrec[4 * k];
         for (int c = 0; c < 3; ++c) d[c] = m.V[3 * (size_t)w + c];
         d[3] = bits_as_float(w);

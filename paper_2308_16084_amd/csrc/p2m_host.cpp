@@ -179,7 +179,7 @@ p2m_status p2m_mesh_counts(const p2m_mesh* m, int64_t* nv, int64_t* ne, int64_t*
 p2m_status p2m_mesh_edges(const p2m_mesh* m, int64_t* ne, int32_t* pairs) {
     if (!m || !ne) return fail(P2M_ERR_ARG, "NULL argument");
     *ne = m->s.m.ne;
-    if (pairs) std::memcpy(pairs, m->s.m.E.data(), sizeof(int32_t) * (size_t)(2 * m->s.m.ne));
+    if (pairs && m->s.m.ne > 0) std::memcpy(pairs, m->s.m.E.data(), sizeof(int32_t) * (size_t)(2 * m->s.m.ne));
     return P2M_OK;
 }
 
@@ -285,14 +285,14 @@ p2m_status p2m_mesh_table(const p2m_mesh* m, int64_t* nnz, uint32_t* off, int32_
     if (!m->s.precomputed) return fail(P2M_ERR_STATE, "mesh not precomputed");
     *nnz = (int64_t)m->s.t.ent.size();
     if (off) std::memcpy(off, m->s.t.off.data(), sizeof(uint32_t) * m->s.t.off.size());
-    if (ent) std::memcpy(ent, m->s.t.ent.data(), sizeof(int32_t) * m->s.t.ent.size());
+    if (ent && !m->s.t.ent.empty()) std::memcpy(ent, m->s.t.ent.data(), sizeof(int32_t) * m->s.t.ent.size());
     return P2M_OK;
 }
 
 p2m_status p2m_mesh_table_boxes(const p2m_mesh* m, uint16_t* boxes) {
     if (!m || !boxes) return fail(P2M_ERR_ARG, "NULL argument");
     if (!m->s.precomputed) return fail(P2M_ERR_STATE, "mesh not precomputed");
-    std::memcpy(boxes, m->s.t.box.data(), sizeof(uint16_t) * m->s.t.box.size());
+    if (!m->s.t.box.empty()) std::memcpy(boxes, m->s.t.box.data(), sizeof(uint16_t) * m->s.t.box.size());
     return P2M_OK;
 }
 
@@ -301,7 +301,7 @@ p2m_status p2m_mesh_neighbors(const p2m_mesh* m, int64_t* nnz, int64_t* nb_off, 
     if (!m->s.precomputed) return fail(P2M_ERR_STATE, "mesh not precomputed");
     *nnz = (int64_t)m->s.t.nb.size();
     if (nb_off) std::memcpy(nb_off, m->s.t.nb_off.data(), sizeof(int64_t) * m->s.t.nb_off.size());
-    if (nb) std::memcpy(nb, m->s.t.nb.data(), sizeof(int32_t) * m->s.t.nb.size());
+    if (nb && !m->s.t.nb.empty()) std::memcpy(nb, m->s.t.nb.data(), sizeof(int32_t) * m->s.t.nb.size());
     return P2M_OK;
 }
 
@@ -361,6 +361,7 @@ struct Reader {
             ok = false;
             return;
         }
+        if (n == 0) return;  // (p may be the data() of an empty vector)
         std::memcpy(p, b.data() + pos, n);
         pos += n;
     }

@@ -139,6 +139,29 @@ P2M_HD void consider(Nearest& b, float qx, float qy, float qz, float d2, const f
     }
 }
 
+// consider() when b already holds a candidate (b.vid >= 0); an infinite d2
+// is never taken.
+P2M_HD void consider_known(Nearest& b, float qx, float qy, float qz, float d2, const float4& p) {
+    bool take;
+    if (d2 < b.d2 * kTieLo) {
+        take = true;
+    } else if (d2 <= b.d2 * kTieHi) {
+        const int32_t vid = as_int(p.w);
+        double D = d2_f64(qx, qy, qz, p.x, p.y, p.z);
+        double Db = d2_f64(qx, qy, qz, b.px, b.py, b.pz);
+        take = D < Db || (D == Db && vid < b.vid);
+    } else {
+        take = false;
+    }
+    if (take) {
+        b.d2 = d2;
+        b.px = p.x;
+        b.py = p.y;
+        b.pz = p.z;
+        b.vid = as_int(p.w);
+    }
+}
+
 // Nearest vertex by the implicit KD tree.  `visits` counts node loads.
 //
 // Node i (children 2i+1, 2i+2) is four float4: its point and vertex id, then
@@ -235,16 +258,19 @@ P2M_HD Nearest voronoi_walk(const MeshView& m, float qx, float qy, float qz, uin
         const int32_t v = b.vid;
         ++steps;
         const uint32_t k0 = m.nboff[v], k1 = m.nboff[v + 1];
-        // kWalkGroup neighbour records loaded before any is compared; slots
-        // past the end re-read the first record of the group (no effect)
+        // kWalkGroup consecutive neighbour records loaded before any is
+        // compared (the record array is padded at its end, so the loads stay
+        // in bounds); slots past the list's end do not count
         for (uint32_t k = k0; k < k1; k += kWalkGroup) {
             float4 r[kWalkGroup];
+            const float4* g = m.nbrec + k;
 #pragma unroll
-            for (int u = 0; u < kWalkGroup; ++u) r[u] = m.nbrec[k + u < k1 ? k + u : k];
+            for (int u = 0; u < kWalkGroup; ++u) r[u] = g[u];
 #pragma unroll
             for (int u = 0; u < kWalkGroup; ++u) {
                 const float dx = qx - r[u].x, dy = qy - r[u].y, dz = qz - r[u].z;
-                consider(b, qx, qy, qz, dx * dx + dy * dy + dz * dz, r[u]);
+                const float d2 = k + u < k1 ? dx * dx + dy * dy + dz * dz : INFINITY;
+                consider_known(b, qx, qy, qz, d2, r[u]);
             }
             visits += k1 - k < (uint32_t)kWalkGroup ? k1 - k : (uint32_t)kWalkGroup;
         }
@@ -440,25 +466,33 @@ P2M_HD float face_gate_d2(const MeshView& m, int32_t f, float rx, float ry, floa
 
 // Integer bounds of q in the list box's 5-bit frame: for integer box
 // bounds, lo <= s exactly when lo <= floor(s), and s <= hi exactly when
-// ceil(s) <= hi, so the integer test equals the real one.
+// ceil(s) <= hi, so the integer test equals the real one.  Kept packed as
+// an entry box is: f = the floors at bits 0, 5, 10; c = the ceilings at
+// bits 15, 20, 25.
 struct Cell5 {
-    uint32_t fx, fy, fz, cx, cy, cz;
+    uint32_t f, c;
 };
 
 P2M_HD Cell5 cell5(float sx, float sy, float sz) {
     Cell5 c;
-    c.fx = (uint32_t)floorf(sx);
-    c.fy = (uint32_t)floorf(sy);
-    c.fz = (uint32_t)floorf(sz);
-    c.cx = (uint32_t)ceilf(sx);
-    c.cy = (uint32_t)ceilf(sy);
-    c.cz = (uint32_t)ceilf(sz);
+    c.f = (uint32_t)floorf(sx) | (uint32_t)floorf(sy) << 5 | (uint32_t)floorf(sz) << 10;
+    c.c = ((uint32_t)ceilf(sx) | (uint32_t)ceilf(sy) << 5 | (uint32_t)ceilf(sz) << 10) << 15;
     return c;
 }
 
-P2M_HD bool in_box5(uint32_t b, const Cell5& c) {
-    return ((b & 31u) <= c.fx) & (((b >> 5) & 31u) <= c.fy) & (((b >> 10) & 31u) <= c.fz) &
-           (((b >> 15) & 31u) >= c.cx) & (((b >> 20) & 31u) >= c.cy) & ((b >> 25) >= c.cz);
+// lo <= floor and hi >= ceil on all three axes, the six 5-bit fields
+// compared at once: X = (floors, box highs) and Y = (box lows, ceilings)
+// field by field; a field's low four bits are compared by a subtraction
+// that cannot borrow across fields (X's top bit set, Y's cleared), and the
+// top bits decide where they differ.
+P2M_HD bool in_box5(uint32_t b, const Cell5& q) {
+    constexpr uint32_t kHigh = 0x3FFF8000u;  // bits 15..29: the box's upper corner
+    constexpr uint32_t kTop = 0x21084210u;   // the top bit of each 5-bit field
+    const uint32_t X = (b & kHigh) | q.f, Y = (b & ~kHigh) | q.c;
+    const uint32_t d = (X | kTop) - (Y & ~kTop);
+    const uint32_t diff = X ^ Y;
+    const uint32_t ge = (diff & X) | (~diff & d);
+    return (ge & kTop) == kTop;
 }
 
 // Coordinate of q in the 5-bit frame of a list box side [lo, hi] (16-bit

@@ -108,7 +108,7 @@ __device__ __forceinline__ void wave_scan(const MeshView& m, WaveScanLds& L, boo
     const int lane = (int)(threadIdx.x & 63u);
     const float rx = qx - m.ctr[0], ry = qy - m.ctr[1], rz = qz - m.ctr[2];
     uint32_t e0 = 0, f0 = 0, f1 = 0;
-    Cell5 qc = {0u, 0u, 0u, 0u, 0u, 0u};
+    Cell5 qc = {0u, 0u};
     if (active) {
         const uint4 h0 = m.vhead[2 * nv.vid], h1 = m.vhead[2 * nv.vid + 1];
         e0 = h0.x;
