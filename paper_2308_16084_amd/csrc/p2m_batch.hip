@@ -201,9 +201,10 @@ int regroup_rounds(int block, int qpl) { return std::max(1, std::min(qpl, kRegro
 size_t batch_slots_bytes(int block, int qpl) {
     return sizeof(uint32_t) * (kRegroupBins + 11 * (size_t)block * (size_t)regroup_rounds(block, qpl));
 }
-// the regroup slots, then each wavefront's scan rings
+// the regroup slots, then each wavefront's scan rings (keys and owners, ids)
 size_t batch_lds_bytes(int block, int qpl) {
-    return (batch_slots_bytes(block, qpl) + 15) / 16 * 16 + sizeof(WaveScanLds) * (size_t)(block / 64);
+    return (batch_slots_bytes(block, qpl) + 15) / 16 * 16 +
+           (sizeof(WaveScanKeys) + sizeof(WaveScanIds)) * (size_t)(block / 64);
 }
 
 // One-workgroup-per-tile order: the tiles are dealt to the 8 XCDs
@@ -230,8 +231,10 @@ __device__ __forceinline__ void batch_query(Arena A, const Tile* __restrict__ ti
     uint32_t* hist = lds;
     float* col = (float*)(lds + kRegroupBins);  // qx qy qz d2 px py pz, S each
     int32_t* icol = (int32_t*)(col + 7 * S);    // query index, vertex, bin << 24 | rank, source slot
-    WaveScanLds& ring = reinterpret_cast<WaveScanLds*>(
-        (char*)lds + ((kRegroupBins + 11 * (size_t)S) * sizeof(uint32_t) + 15) / 16 * 16)[t >> 6];
+    char* const scan_lds = (char*)lds + ((kRegroupBins + 11 * (size_t)S) * sizeof(uint32_t) + 15) / 16 * 16;
+    WaveScanLds ring;
+    ring.k = reinterpret_cast<WaveScanKeys*>(scan_lds) + (t >> 6);
+    ring.i = reinterpret_cast<WaveScanIds*>(scan_lds + sizeof(WaveScanKeys) * (size_t)(B / 64)) + (t >> 6);
     int64_t next = 0, chunk_end = 0;  // persistent: the claimed tiles not yet taken
     for (bool more = true; more;) {
         int64_t tt = run_tile(blockIdx.x);  // one tile per workgroup

@@ -399,9 +399,13 @@ __global__ void k_morton(const float* __restrict__ q, int64_t n, float lox, floa
 
 // Dynamic LDS of k_query: the regroup bins, then per slot 7 floats (q, the
 // nearest vertex's d2 and position) and 2 ints (query index, vertex); after
-// the regroup, the slots of each wavefront hold its scan rings.
-constexpr size_t regroup_lds_bytes(int block) { return sizeof(uint32_t) * (kRegroupBins + 9 * (size_t)block); }
-static_assert(sizeof(WaveScanLds) <= 9 * 64 * sizeof(uint32_t), "scan rings exceed a wavefront's regroup slots");
+// the regroup, the slots of each wavefront hold its scan keys and owners;
+// then the scan rings' candidate ids, per wavefront.
+constexpr size_t regroup_slot_bytes(int block) { return sizeof(uint32_t) * (kRegroupBins + 9 * (size_t)block); }
+constexpr size_t regroup_lds_bytes(int block) {
+    return regroup_slot_bytes(block) + sizeof(WaveScanIds) * (size_t)(block / 64);
+}
+static_assert(sizeof(WaveScanKeys) <= 9 * 64 * sizeof(uint32_t), "scan keys exceed a wavefront's regroup slots");
 
 // stage (ordered batches): query i's answer goes to stage[S*i .. S*i+S-1]
 // (S = 2, or 3 with the backward extras) as (prim, closest), (dist, status,
@@ -467,7 +471,9 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const floa
     fin = finite3(qx, qy, qz);
     // the regroup slots are free again: each wavefront's scan rings go there
     __syncthreads();
-    WaveScanLds& ring = reinterpret_cast<WaveScanLds*>(lds + kRegroupBins)[t >> 6];
+    WaveScanLds ring;
+    ring.k = reinterpret_cast<WaveScanKeys*>(lds + kRegroupBins) + (t >> 6);
+    ring.i = reinterpret_cast<WaveScanIds*>((char*)lds + regroup_slot_bytes(B)) + (t >> 6);
     float best;
     int best_kind;
     int32_t best_id;
