@@ -321,6 +321,17 @@ def main():
                           "workload": "the headline batch in input order (no Morton ordering)"}
     log(f"[bench] unsorted: {ms_uns:.3f} ms/step, {n / (ms_uns / 1e3) / 1e9:.3f} Gq/s")
 
+    # the other nearest-vertex traversals on the same batch: the per-lane tree
+    # search (with and without its top levels staged in LDS) and the
+    # wavefront tree walk
+    trav = {}
+    for name, tv, lv in (("kd_per_lane", 1, 0), ("kd_per_lane_lds8", 1, 8), ("kd_wavefront", 2, 0)):
+        ms_t = time_steps(lambda: mesh.query(q, out=out, traversal=tv, lds_levels=lv), args.steps, args.warmup)
+        trav[name] = round(ms_t, 4)
+    trav["voronoi_walk"] = round(ms_step, 4)
+    result["traversals_ms"] = trav
+    log("[bench] traversals (ms/step): " + ", ".join(f"{k} {v:.3f}" for k, v in trav.items()))
+
     if not args.no_configs:
         # the small icosphere (C1) and the needle heightfield (C3): q/s, list statistics
         for name, make, mode in (("c1", C.c1, P.TABLE_FLOODING), ("c3", C.c3, P.TABLE_FLOODING_DEVICE)):
@@ -537,7 +548,8 @@ def main():
                              "speedup_vs_plain": round(ms_p / ms_b, 3),
                              "persistent_schedule_ms": round(ms_pers, 4),
                              "shape": {"block": shape[0], "queries_per_lane": shape[1],
-                                       "traversal": {1: "kd per-lane", 2: "kd wavefront", 3: "voronoi walk"}[shape[2]]},
+                                       "traversal": {1: "kd per-lane", 2: "kd wavefront", 3: "voronoi walk"}[shape[2]],
+                                       "lds_levels": batch.lds_levels()},
                              "workload": (f"{'all' if count == 256 else 'first'} {count} meshes of the seeded 256-mesh plan "
                                           f"(displaced geodesic spheres / heightfields, log-uniform sizes): {ntri} triangles, "
                                           f"{nb} queries (log-uniform per mesh, mixed uniform/near-surface); one graph launch"),

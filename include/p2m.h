@@ -135,7 +135,13 @@ typedef struct {
                            choice returns each query's exact nearest vertex
                            (equal distances: the smallest id, up to float64
                            rounding of the squared distance) */
-    int reserved[4];    /* must be 0 */
+    int lds_levels;     /* per-lane KD-tree search (traversal 1): the top
+                           lds_levels levels of the tree (2^lds_levels - 1
+                           nodes, 64 bytes each) are copied into each
+                           workgroup's LDS and read from there; 0 (default):
+                           none; at most 9; ignored by the other traversals;
+                           the answers do not change */
+    int reserved[3];    /* must be 0 */
 } p2m_query_opts;
 
 /* ------------------------------------------------------------ host side */
@@ -320,6 +326,14 @@ p2m_status p2m_batch_query_eager(p2m_batch* b, const float* q_dev, const int64_t
 p2m_status p2m_batch_set_shape(p2m_batch* b, int block, int queries_per_lane, int traversal);
 p2m_status p2m_batch_get_shape(const p2m_batch* b, int* block, int* queries_per_lane, int* traversal);
 
+/* Tree levels the per-lane KD-tree search (traversal 1) reads from LDS:
+ * each workgroup copies the top `levels` levels of its tile's mesh's tree
+ * (2^levels - 1 nodes, 64 bytes each) into LDS before the search; 0 (when
+ * the batch is created) stages none.  0..9 (P2M_ERR_ARG beyond); the answers
+ * do not change; the other traversals ignore it. */
+p2m_status p2m_batch_set_lds_levels(p2m_batch* b, int levels);
+p2m_status p2m_batch_get_lds_levels(const p2m_batch* b, int* levels);
+
 /* Work distribution of the batched kernel: 0 (when the batch is created)
  * launches one workgroup per tile of the largest-first tile list; 1
  * launches as many workgroups as fit on the device, each taking tiles from
@@ -328,9 +342,11 @@ p2m_status p2m_batch_get_shape(const p2m_batch* b, int* block, int* queries_per_
 p2m_status p2m_batch_set_schedule(p2m_batch* b, int persistent);
 p2m_status p2m_batch_get_schedule(const p2m_batch* b, int* persistent);
 
-/* Time every launch shape in {64,128,256} x {1,2,4} x {1,2,3} on these queries
+/* Time every launch shape in {64,128,256} x {1,2,4} x {1,2,3} on these queries,
+ * traversal 1 with 0 and with 8 staged tree levels (p2m_batch_set_lds_levels),
  * (eager launches, two timed runs after a warm-up each) and keep the fastest;
- * the best_* outputs (may be NULL) report it.  Synchronises the stream. */
+ * the best_* outputs (may be NULL) report it and p2m_batch_get_lds_levels
+ * its staged levels.  Synchronises the stream. */
 p2m_status p2m_batch_autotune(p2m_batch* b, const float* q_dev, const int64_t* q_offsets_host, int32_t* prim_dev,
                               float* closest_dev, float* dist_dev, void* stream, int* best_block,
                               int* best_queries_per_lane, int* best_traversal);

@@ -43,7 +43,7 @@ class BuildStats(ctypes.Structure):
 
 class QueryOpts(ctypes.Structure):
     _fields_ = [("sort_queries", INT), ("block_size", INT), ("profile", INT), ("traversal", INT),
-                ("reserved", INT * 4)]
+                ("lds_levels", INT), ("reserved", INT * 3)]
 
 
 _SIGS = {
@@ -74,6 +74,8 @@ _SIGS = {
     "p2m_batch_query_eager": (INT, [P, P, P, P, P, P, P, P]),
     "p2m_batch_set_shape": (INT, [P, INT, INT, INT]),
     "p2m_batch_get_shape": (INT, [P, P, P, P]),
+    "p2m_batch_set_lds_levels": (INT, [P, INT]),
+    "p2m_batch_get_lds_levels": (INT, [P, P]),
     "p2m_batch_set_schedule": (INT, [P, INT]),
     "p2m_batch_get_schedule": (INT, [P, P]),
     "p2m_batch_autotune": (INT, [P, P, P, P, P, P, P, P, P, P]),

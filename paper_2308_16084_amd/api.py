@@ -215,7 +215,7 @@ class Mesh:
 
     def query(self, q, sort: bool = True, block_size: int = 0, out: dict | None = None, status: bool = True,
               for_backward: bool = False, profile: bool = False, traversal: int = 0, stream=None,
-              noalloc: bool = False) -> dict:
+              noalloc: bool = False, lds_levels: int = 0) -> dict:
         """P2M query of a CUDA float32 [n,3] tensor; returns device tensors.
         noalloc: call p2m_query_noalloc (the library allocates nothing; pass
         `out` to allocate nothing here either)."""
@@ -237,6 +237,7 @@ class Mesh:
         o.block_size = int(block_size)
         o.profile = 1 if profile else 0
         o.traversal = int(traversal)
+        o.lds_levels = int(lds_levels)
         fn = lib().p2m_query_noalloc if noalloc else lib().p2m_query
         check(fn(self._h, _ptr(q), n, _ptr(out["prim"]), _ptr(out["closest"]), _ptr(out["dist"]),
                  _ptr(out.get("status")), _ptr(out.get("bary")), _ptr(out.get("pvid")), ctypes.byref(o),
@@ -350,6 +351,15 @@ class Batch:
         a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         check(lib().p2m_batch_get_shape(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
+
+    def set_lds_levels(self, levels: int) -> None:
+        """Tree levels the per-lane tree search (traversal 1) stages in LDS."""
+        check(lib().p2m_batch_set_lds_levels(self._h, int(levels)))
+
+    def lds_levels(self) -> int:
+        x = ctypes.c_int()
+        check(lib().p2m_batch_get_lds_levels(self._h, ctypes.byref(x)))
+        return x.value
 
     def set_schedule(self, persistent: bool) -> None:
         check(lib().p2m_batch_set_schedule(self._h, 1 if persistent else 0))

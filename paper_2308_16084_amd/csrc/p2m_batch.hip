@@ -125,13 +125,14 @@ struct p2m_batch {
     // launch shape
     int block = 256, qpl = 1, traversal = 3;
     int persistent = 0;  // 0: one workgroup per tile; 1: persistent workgroups and a tile counter
+    int lds_levels = 0;  // traversal 1: tree levels staged in LDS per tile
     int grid = 0;
     // captured graph
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     const void* g_ptrs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    int g_shape[3] = {0, 0, 0};
+    int g_shape[4] = {0, 0, 0, 0};
 };
 
 namespace p2m {
@@ -201,10 +202,11 @@ int regroup_rounds(int block, int qpl) { return std::max(1, std::min(qpl, kRegro
 size_t batch_slots_bytes(int block, int qpl) {
     return sizeof(uint32_t) * (kRegroupBins + 11 * (size_t)block * (size_t)regroup_rounds(block, qpl));
 }
-// the regroup slots, then each wavefront's scan rings (keys and owners, ids)
-size_t batch_lds_bytes(int block, int qpl) {
+// the regroup slots, then each wavefront's scan rings (keys and owners, ids),
+// then (traversal 1) the tile's mesh's top tree levels
+size_t batch_lds_bytes(int block, int qpl, int32_t ntop_max) {
     return (batch_slots_bytes(block, qpl) + 15) / 16 * 16 +
-           (sizeof(WaveScanKeys) + sizeof(WaveScanIds)) * (size_t)(block / 64);
+           (sizeof(WaveScanKeys) + sizeof(WaveScanIds)) * (size_t)(block / 64) + sizeof(KdNode) * (size_t)ntop_max;
 }
 
 // One-workgroup-per-tile order: the tiles are dealt to the 8 XCDs
@@ -214,6 +216,8 @@ size_t batch_lds_bytes(int block, int qpl) {
 constexpr int64_t kTileRun = 16;
 // Persistent schedule: tiles a workgroup claims with one counter increment.
 constexpr int64_t kTileChunk = 16;
+// Tree levels the per-lane search may stage in LDS (511 nodes, 32 KB).
+constexpr int kBatchMaxLdsLevels = 9;
 __device__ __forceinline__ int64_t run_tile(int64_t b) {
     const int64_t sg = b / (kXcds * kTileRun), r = b % (kXcds * kTileRun);
     return sg * kXcds * kTileRun + (r % kXcds) * kTileRun + r / kXcds;
@@ -223,7 +227,7 @@ template <int kWalk, bool kPersistent>
 __device__ __forceinline__ void batch_query(Arena A, const Tile* __restrict__ tiles, int64_t ntiles,
                                             uint32_t* counter, int qpl, int group, const float* __restrict__ q,
                                             const int32_t* __restrict__ perm, int64_t n,
-                                            float4* __restrict__ stage) {
+                                            float4* __restrict__ stage, int32_t ntop_max) {
     extern __shared__ uint32_t lds[];
     __shared__ int64_t s_tile;
     const int t = threadIdx.x, B = blockDim.x;
@@ -235,6 +239,8 @@ __device__ __forceinline__ void batch_query(Arena A, const Tile* __restrict__ ti
     WaveScanLds ring;
     ring.k = reinterpret_cast<WaveScanKeys*>(scan_lds) + (t >> 6);
     ring.i = reinterpret_cast<WaveScanIds*>(scan_lds + sizeof(WaveScanKeys) * (size_t)(B / 64)) + (t >> 6);
+    KdNode* const staged =
+        reinterpret_cast<KdNode*>(scan_lds + (sizeof(WaveScanKeys) + sizeof(WaveScanIds)) * (size_t)(B / 64));
     int64_t next = 0, chunk_end = 0;  // persistent: the claimed tiles not yet taken
     for (bool more = true; more;) {
         int64_t tt = run_tile(blockIdx.x);  // one tile per workgroup
@@ -258,6 +264,17 @@ __device__ __forceinline__ void batch_query(Arena A, const Tile* __restrict__ ti
         const Tile T = tiles[tt];
         const MeshView v = arena_view(A.desc[T.mesh], A.node, A.vhead, A.lent, A.seg, A.tri, A.fedge, A.nboff, A.nbrec,
                                       A.seed, A.frec, A.erec);
+        // the per-lane tree search reads the top of this mesh's tree from
+        // LDS (the previous tile's readers have passed the barrier that ends
+        // its last round)
+        const KdNode* top = nullptr;
+        int32_t ntop = 0;
+        if (kWalk == WALK_LANE && ntop_max > 0) {
+            ntop = min(ntop_max, v.nv);
+            stage_top(v.node, ntop, staged);
+            __syncthreads();
+            top = staged;
+        }
         for (int r0 = 0; r0 < qpl; r0 += group) {
             const int rounds = min(group, qpl - r0);
             if (t < kRegroupBins) hist[t] = 0;
@@ -277,7 +294,7 @@ __device__ __forceinline__ void batch_query(Arena A, const Tile* __restrict__ ti
                 const bool fin = finite3(qx, qy, qz);
                 ScanCounters c;
                 // every lane of the wavefront calls this (see nearest_vertex)
-                const Nearest nv = nearest_vertex<kWalk>(v, qx, qy, qz, i >= 0 && fin, c.nodes, c.steps);
+                const Nearest nv = nearest_vertex<kWalk>(v, qx, qy, qz, i >= 0 && fin, c.nodes, c.steps, top, ntop);
                 const int bin = (i >= 0 && fin) ? regroup_bin(v, nv.vid) : 0;
                 const uint32_t rank = atomicAdd(&hist[bin], 1u);
                 const int u = r * B + t;
@@ -338,8 +355,8 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(Arena A, const T
                                                                 int64_t ntiles, uint32_t* counter, int qpl,
                                                                 int group, const float* __restrict__ q,
                                                                 const int32_t* __restrict__ perm, int64_t n,
-                                                                float4* __restrict__ stage) {
-    batch_query<kWalk, kPersistent>(A, tiles, ntiles, counter, qpl, group, q, perm, n, stage);
+                                                                float4* __restrict__ stage, int32_t ntop_max) {
+    batch_query<kWalk, kPersistent>(A, tiles, ntiles, counter, qpl, group, q, perm, n, stage, ntop_max);
 }
 
 // The Voronoi-walk forms (the default traversal), held to 80 registers so
@@ -347,8 +364,14 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(Arena A, const T
 template <bool kPersistent>
 __global__ __launch_bounds__(kQueryMaxBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_batch_query_walk(
     Arena A, const Tile* __restrict__ tiles, int64_t ntiles, uint32_t* counter, int qpl, int group,
-    const float* __restrict__ q, const int32_t* __restrict__ perm, int64_t n, float4* __restrict__ stage) {
-    batch_query<WALK_VORONOI, kPersistent>(A, tiles, ntiles, counter, qpl, group, q, perm, n, stage);
+    const float* __restrict__ q, const int32_t* __restrict__ perm, int64_t n, float4* __restrict__ stage,
+    int32_t ntop_max) {
+    batch_query<WALK_VORONOI, kPersistent>(A, tiles, ntiles, counter, qpl, group, q, perm, n, stage, ntop_max);
+}
+
+// Tree nodes the batched kernel stages per tile: traversal 1 only.
+int32_t batch_top_nodes(const p2m_batch* b) {
+    return b->traversal == 1 ? top_nodes(b->lds_levels, INT32_MAX) : 0;
 }
 
 void drop_graph(p2m_batch* b) {
@@ -451,9 +474,11 @@ p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, 
     const int grid = b->persistent ? b->grid : (int)((b->ntiles + run8 - 1) / run8 * run8);
     const Arena A{b->node,  b->vhead, b->lent, b->seg,  b->tri,  b->fedge,
                   b->nboff, b->nbrec, b->seed, b->frec, b->erec, b->desc};
+    const int32_t ntop_max = batch_top_nodes(b);
 #define P2M_LAUNCH_BATCH(K)                                                                                   \
-    K<<<grid, b->block, batch_lds_bytes(b->block, b->qpl), st>>>(                                              \
-        A, b->tiles, b->ntiles, b->counter, b->qpl, regroup_rounds(b->block, b->qpl), q, rb.vals[cur], n, b->stage)
+    K<<<grid, b->block, batch_lds_bytes(b->block, b->qpl, ntop_max), st>>>(A, b->tiles, b->ntiles, b->counter,   \
+                                                                         b->qpl, regroup_rounds(b->block, b->qpl), \
+                                                                         q, rb.vals[cur], n, b->stage, ntop_max)
     if (b->persistent) {
         if (b->traversal == 1) P2M_LAUNCH_BATCH((k_batch_query<WALK_LANE, true>));
         else if (b->traversal == 2) P2M_LAUNCH_BATCH((k_batch_query<WALK_WAVE, true>));
@@ -478,7 +503,8 @@ p2m_status set_grid(p2m_batch* b) {
     const void* k = b->traversal == 1   ? (const void*)k_batch_query<WALK_LANE, true>
                     : b->traversal == 2 ? (const void*)k_batch_query<WALK_WAVE, true>
                                         : (const void*)k_batch_query<WALK_VORONOI, true>;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, b->block, batch_lds_bytes(b->block, b->qpl));
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, b->block,
+                                                     batch_lds_bytes(b->block, b->qpl, batch_top_nodes(b)));
     if (e != hipSuccess) return hip_fail(e, "occupancy query");
     b->grid = std::max(1, cus * std::max(1, per));
     return P2M_OK;
@@ -666,6 +692,21 @@ p2m_status p2m_batch_get_shape(const p2m_batch* b, int* block, int* qpl, int* tr
     return P2M_OK;
 }
 
+p2m_status p2m_batch_set_lds_levels(p2m_batch* b, int levels) {
+    if (!b) return fail(P2M_ERR_ARG, "batch is NULL");
+    if (levels < 0 || levels > kBatchMaxLdsLevels) return fail(P2M_ERR_ARG, "lds levels must be in [0, 9]");
+    Guard g(b->device);
+    if (b->lds_levels != levels) drop_graph(b);
+    b->lds_levels = levels;
+    return set_grid(b);
+}
+
+p2m_status p2m_batch_get_lds_levels(const p2m_batch* b, int* levels) {
+    if (!b) return fail(P2M_ERR_ARG, "batch is NULL");
+    if (levels) *levels = b->lds_levels;
+    return P2M_OK;
+}
+
 p2m_status p2m_batch_set_schedule(p2m_batch* b, int persistent) {
     if (!b) return fail(P2M_ERR_ARG, "batch is NULL");
     if (persistent != 0 && persistent != 1) return fail(P2M_ERR_ARG, "persistent must be 0 or 1");
@@ -691,7 +732,7 @@ p2m_status p2m_batch_query(p2m_batch* b, const float* q, const int64_t* qoff, in
     if (b->n == 0) return P2M_OK;
     if (!q || !prim || !closest || !dist) return fail(P2M_ERR_ARG, "NULL query or output pointer");
     const void* ptrs[5] = {q, prim, closest, dist, status};
-    const int shape[3] = {b->block, b->qpl, b->traversal};
+    const int shape[4] = {b->block, b->qpl, b->traversal, batch_top_nodes(b)};
     if (!b->exec || std::memcmp(ptrs, b->g_ptrs, sizeof(ptrs)) != 0 || std::memcmp(shape, b->g_shape, sizeof(shape)) != 0) {
         drop_graph(b);
         hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
@@ -742,35 +783,39 @@ p2m_status p2m_batch_autotune(p2m_batch* b, const float* q, const int64_t* qoff,
     const int blocks[3] = {64, 128, 256};
     const int qpls[3] = {1, 2, 4};
     const int travs[3] = {1, 2, 3};
+    const int levels[2] = {0, 8};  // staged tree levels, traversal 1 only
     float best = INFINITY;
-    int bb = b->block, bq = b->qpl, bt = b->traversal;
+    int bb = b->block, bq = b->qpl, bt = b->traversal, bv = b->lds_levels;
     p2m_status r = P2M_OK;
-    for (int tv : travs)
-        for (int bl : blocks)
-            for (int qp : qpls) {
-                if ((r = p2m_batch_set_shape(b, bl, qp, tv)) != P2M_OK) break;
-                float tot = 0.f;
-                for (int rep = 0; rep < 3 && r == P2M_OK; ++rep) {
-                    (void)hipEventRecord(e0, st);
-                    r = p2m_batch_query_eager(b, q, qoff, prim, closest, dist, nullptr, stream);
-                    (void)hipEventRecord(e1, st);
-                    float ms = 0.f;
-                    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-                        r = fail(P2M_ERR_HIP, "autotune timing");
-                    if (rep > 0) tot += ms;  // first run warms caches
-                }
-                if (r != P2M_OK) break;
-                if (tot < best) {
-                    best = tot;
-                    bb = bl;
-                    bq = qp;
-                    bt = tv;
-                }
-            }
+    // every (traversal, levels, block, queries per lane); the first error ends the sweep
+    for (int k = 0; k < 3 * 2 * 3 * 3 && r == P2M_OK; ++k) {
+        const int tv = travs[k / 18], lv = levels[(k / 9) % 2], bl = blocks[(k / 3) % 3], qp = qpls[k % 3];
+        if (tv != 1 && lv != 0) continue;
+        if ((r = p2m_batch_set_lds_levels(b, lv)) != P2M_OK) break;
+        if ((r = p2m_batch_set_shape(b, bl, qp, tv)) != P2M_OK) break;
+        float tot = 0.f;
+        for (int rep = 0; rep < 3 && r == P2M_OK; ++rep) {
+            (void)hipEventRecord(e0, st);
+            r = p2m_batch_query_eager(b, q, qoff, prim, closest, dist, nullptr, stream);
+            (void)hipEventRecord(e1, st);
+            float ms = 0.f;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                r = fail(P2M_ERR_HIP, "autotune timing");
+            if (rep > 0) tot += ms;  // first run warms caches
+        }
+        if (r == P2M_OK && tot < best) {
+            best = tot;
+            bb = bl;
+            bq = qp;
+            bt = tv;
+            bv = lv;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (r != P2M_OK) return r;
-    r = p2m_batch_set_shape(b, bb, bq, bt);
+    r = p2m_batch_set_lds_levels(b, bv);
+    if (r == P2M_OK) r = p2m_batch_set_shape(b, bb, bq, bt);
     if (best_block) *best_block = bb;
     if (best_qpl) *best_qpl = bq;
     if (best_traversal) *best_traversal = bt;

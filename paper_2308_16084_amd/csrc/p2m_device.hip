@@ -406,6 +406,8 @@ constexpr size_t regroup_lds_bytes(int block) {
     return regroup_slot_bytes(block) + sizeof(WaveScanIds) * (size_t)(block / 64);
 }
 static_assert(sizeof(WaveScanKeys) <= 9 * 64 * sizeof(uint32_t), "scan keys exceed a wavefront's regroup slots");
+// then, for the per-lane tree search, the staged top of the tree (16-byte aligned)
+constexpr size_t top_lds_offset(int block) { return (regroup_lds_bytes(block) + 15) / 16 * 16; }
 
 // stage (ordered batches): query i's answer goes to stage[S*i .. S*i+S-1]
 // (S = 2, or 3 with the backward extras) as (prim, closest), (dist, status,
@@ -419,7 +421,7 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const floa
                                                 int32_t* __restrict__ prim, float* __restrict__ closest,
                                                 float* __restrict__ dist, uint8_t* __restrict__ status,
                                                 float* __restrict__ bary, int32_t* __restrict__ pvid,
-                                                float4* __restrict__ stage) {
+                                                float4* __restrict__ stage, int32_t ntop) {
     extern __shared__ uint32_t lds[];
     const int64_t tile = xcd_tile(blockIdx.x, run);
     const int t = threadIdx.x, B = blockDim.x;
@@ -434,8 +436,17 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const floa
     }
     bool fin = finite3(qx, qy, qz);
     ScanCounters c;
+    // the per-lane tree search may read the tree's top levels from a copy in
+    // LDS, after the regroup slots and the scan ids
+    const KdNode* top = nullptr;
+    if (kWalk == WALK_LANE && ntop > 0) {
+        KdNode* staged = reinterpret_cast<KdNode*>((char*)lds + top_lds_offset(B));
+        stage_top(m.node, ntop, staged);
+        __syncthreads();
+        top = staged;
+    }
     // with WALK_WAVE every lane of the wavefront takes part in the shared walk
-    Nearest nv = nearest_vertex<kWalk>(m, qx, qy, qz, i >= 0 && fin, c.nodes, c.steps);
+    Nearest nv = nearest_vertex<kWalk>(m, qx, qy, qz, i >= 0 && fin, c.nodes, c.steps, top, ntop);
 
     // regroup the block's queries by list length (regroup.hpp)
     uint32_t* hist = lds;
@@ -832,6 +843,8 @@ __global__ __launch_bounds__(256) void k_backward(const float* __restrict__ q, i
 // grid over D): three sort passes instead of four; within a grid cell the
 // input order is kept.
 constexpr int kQuerySortLoBit = 6;
+// Tree levels the per-lane search may read from LDS (511 nodes, 32 KB).
+constexpr int kMaxLdsLevels = 9;
 
 // traversal option (0 default, 1 per-lane tree, 2 wavefront tree, 3 Voronoi
 // walk) -> Walk.  The Voronoi walk reads a few dozen vertices per query
@@ -1040,11 +1053,13 @@ static p2m_status run_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* pr
     if (!q || !prim || !closest || !dist) return fail(P2M_ERR_ARG, "NULL query or output pointer");
     if ((bary == nullptr) != (pvid == nullptr)) return fail(P2M_ERR_ARG, "bary and pvid must both be set or both NULL");
     if (n > (int64_t)INT32_MAX) return fail(P2M_ERR_ARG, "more than 2^31-1 queries in one call");
-    int sort = 1, block = 256, profile = 0, traversal = 0;
+    int sort = 1, block = 256, profile = 0, traversal = 0, lds_levels = 0;
     if (opts) {
         profile = opts->profile;
         traversal = opts->traversal;
+        lds_levels = opts->lds_levels;
         if (traversal < 0 || traversal > 3) return fail(P2M_ERR_ARG, "traversal must be 0, 1, 2 or 3");
+        if (lds_levels < 0 || lds_levels > kMaxLdsLevels) return fail(P2M_ERR_ARG, "lds_levels must be in [0, 9]");
         if (opts->sort_queries >= 0) sort = opts->sort_queries ? 1 : 0;
         if (opts->block_size != 0) {
             if (opts->block_size < 64 || opts->block_size > kQueryMaxBlock || opts->block_size % 64)
@@ -1082,9 +1097,11 @@ static p2m_status run_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* pr
     const int64_t run = std::min<int64_t>(kXcdRun, (tiles + kXcds - 1) / kXcds);
     const unsigned grid = (unsigned)((tiles + kXcds * run - 1) / (kXcds * run) * (kXcds * run));
     const int walk = pick_walk(traversal);
+    // the top levels of the tree in LDS: the per-lane tree search only
+    const int32_t ntop = walk == WALK_LANE ? top_nodes(lds_levels, v.nv) : 0;
+    const size_t lds_bytes = top_lds_offset(block) + sizeof(KdNode) * (size_t)ntop;
 #define P2M_LAUNCH_QUERY(X, W) \
-    k_query<X, W><<<grid, block, regroup_lds_bytes(block), st>>>(v, q, perm, n, run, prim, closest, dist, status, \
-                                                                 bary, pvid, stage)
+    k_query<X, W><<<grid, block, lds_bytes, st>>>(v, q, perm, n, run, prim, closest, dist, status, bary, pvid, stage, ntop)
     if (bary) {
         if (walk == WALK_WAVE) P2M_LAUNCH_QUERY(true, WALK_WAVE);
         else if (walk == WALK_VORONOI) P2M_LAUNCH_QUERY(true, WALK_VORONOI);

@@ -183,8 +183,9 @@ P2M_HD float box_d2(float qx, float qy, float qz, float lx, float ly, float lz, 
     return dx * dx + dy * dy + dz * dz;
 }
 
-P2M_HD Nearest kdt_nearest(const KdNode* __restrict__ node, int32_t n, float qx, float qy, float qz,
-                           uint64_t& visits) {
+// fetch(i) returns node i (from memory, or from a copy of the top levels).
+template <class Fetch>
+P2M_HD Nearest kdt_nearest_f(Fetch fetch, int32_t n, float qx, float qy, float qz, uint64_t& visits) {
     Nearest b;
     b.d2 = INFINITY;
     b.px = b.py = b.pz = 0.f;
@@ -195,7 +196,7 @@ P2M_HD Nearest kdt_nearest(const KdNode* __restrict__ node, int32_t n, float qx,
     int32_t cur = 0;
     while (cur >= 0) {
         while (cur >= 0) {
-            const KdNode nd = node[cur];
+            const KdNode nd = fetch(cur);
             ++visits;
             const float dx = qx - nd.p.x, dy = qy - nd.p.y, dz = qz - nd.p.z;
             consider(b, qx, qy, qz, dx * dx + dy * dy + dz * dz, nd.p);
@@ -221,6 +222,11 @@ P2M_HD Nearest kdt_nearest(const KdNode* __restrict__ node, int32_t n, float qx,
         }
     }
     return b;
+}
+
+P2M_HD Nearest kdt_nearest(const KdNode* __restrict__ node, int32_t n, float qx, float qy, float qz,
+                           uint64_t& visits) {
+    return kdt_nearest_f([node](int32_t i) { return node[i]; }, n, qx, qy, qz, visits);
 }
 
 // Nearest vertex by a greedy walk over the Voronoi (Delaunay) neighbour

@@ -59,8 +59,10 @@ def test_c1_unsorted_and_block_sizes_identical(c1):
     w, m, om, ans = c1
     ref = _run(m, w.Q)
     for kw in ({"sort": False}, {"block_size": 64}, {"block_size": 128, "sort": False}, {"traversal": 1},
+               {"traversal": 1, "lds_levels": 4}, {"traversal": 1, "lds_levels": 9, "block_size": 64},
+               {"traversal": 1, "lds_levels": 8, "sort": False},
                {"traversal": 2}, {"traversal": 2, "sort": False}, {"traversal": 3},
-               {"traversal": 3, "sort": False, "block_size": 64}):
+               {"traversal": 3, "sort": False, "block_size": 64}, {"lds_levels": 9}):
         print("case: c1", kw, flush=True)
         out = _run(m, w.Q, **kw)
         for k in ("prim", "closest", "dist"):
@@ -90,7 +92,8 @@ def test_tiny_meshes(mode):
         Q = rng.uniform(dom[0], dom[1], size=(5000, 3)).astype(np.float32)
         om = oracle.OracleMesh(V, F)
         ans = om.query(Q)
-        for kw in ({}, {"traversal": 3}):
+        # the staged tree top may hold the whole tree (4 to a few hundred vertices)
+        for kw in ({}, {"traversal": 3}, {"traversal": 1, "lds_levels": 9}, {"traversal": 1, "lds_levels": 1}):
             out = _run(m, Q, **kw)
             assert check_answers(om, Q, ans, out["prim"], out["closest"], out["dist"]) == [], kw
 
@@ -188,6 +191,9 @@ def test_edge_cases(c1):
         m.query(torch.zeros((4, 3), dtype=torch.float64, device="cuda"))
     with pytest.raises(P.P2MError):
         m.query(torch.zeros((4, 3), dtype=torch.float32, device="cuda"), block_size=1024)
+    for bad in (-1, 10):
+        with pytest.raises(P.P2MError):
+            m.query(torch.zeros((4, 3), dtype=torch.float32, device="cuda"), traversal=1, lds_levels=bad)
     with pytest.raises(P.P2MError):
         P.Mesh(TETRA_V, TETRA_F).upload(0)  # before precompute
 
@@ -230,6 +236,10 @@ def test_c2_full_size_sampled(c2_full):
     fails, out = _sampled_parity(w, m, 10_000, 77)
     assert fails == []
     out1 = _run(m, w.Q[:200_000], traversal=1)
+    # the tree's top eight levels read from LDS: the same answers, bit for bit
+    out1s = _run(m, w.Q[:200_000], traversal=1, lds_levels=8)
+    for k in ("prim", "closest", "dist", "status"):
+        assert np.array_equal(out1s[k], out1[k]), k
     # the traversals agree on the nearest vertex up to float64 ties
     for t in (2, 3):
         out2 = _run(m, w.Q[:200_000], traversal=t)

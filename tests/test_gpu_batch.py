@@ -118,12 +118,39 @@ def test_persistent_schedule_same_answers(batch_setup):
         b.set_schedule(False)
 
 
+def test_lds_levels_same_answers(batch_setup):
+    """The per-lane tree search with the top of each tile's mesh's tree
+    staged in LDS gives the answers of the unstaged search, bit for bit,
+    graph and eager (meshes smaller than the staged levels included)."""
+    import paper_2308_16084_amd as P
+    works, meshes, b, Q, off, q = batch_setup
+    shape = b.shape()
+    assert b.lds_levels() == 0
+    try:
+        b.set_shape(128, 2, 1)
+        ref = _np(b.query(q, off))
+        for lv in (3, 9):
+            b.set_lds_levels(lv)
+            assert b.lds_levels() == lv
+            for graph in (True, False):
+                got = _np(b.query(q, off, graph=graph))
+                for k in ref:
+                    assert np.array_equal(got[k], ref[k]), (lv, k, graph)
+        for bad in (-1, 10):
+            with pytest.raises(P.P2MError):
+                b.set_lds_levels(bad)
+    finally:
+        b.set_lds_levels(0)
+        b.set_shape(*shape)
+
+
 def test_autotune_and_layout_change(batch_setup):
     import torch
     works, meshes, b, Q, off, q = batch_setup
     ref = _np(b.query(q, off))
     shape = b.autotune(q, off)
     assert shape[0] in (64, 128, 256) and shape[1] in (1, 2, 4) and shape[2] in (1, 2, 3)
+    assert b.lds_levels() in ((0, 8) if shape[2] == 1 else (0,))
     got = _np(b.query(q, off))
     assert np.mean(got["prim"] == ref["prim"]) > 0.999
     # a different split of the same rows between meshes: only mesh 0 and 1 swap sizes
