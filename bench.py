@@ -119,6 +119,24 @@ def host_counts(mesh, Q, k=200_000, seed=123):
     return per
 
 
+def alt_legs(args, mesh, q, out, n, ms_step, result):
+    """The headline batch without the ordering step, and with the other
+    nearest-vertex traversals: the per-lane tree search (with and without
+    its top levels staged in LDS) and the wavefront tree walk."""
+    ms_uns = time_steps(lambda: mesh.query(q, out=out, sort=False), args.steps, args.warmup)
+    result["unsorted"] = {"value": round(n / (ms_uns / 1e3), 1), "unit": "queries/s", "ms_per_step": round(ms_uns, 4),
+                          "workload": "the headline batch in input order (no Morton ordering)"}
+    log(f"[bench] unsorted: {ms_uns:.3f} ms/step, {n / (ms_uns / 1e3) / 1e9:.3f} Gq/s")
+
+    trav = {}
+    for name, tv, lv in (("kd_per_lane", 1, 0), ("kd_per_lane_lds8", 1, 8), ("kd_wavefront", 2, 0)):
+        ms_t = time_steps(lambda: mesh.query(q, out=out, traversal=tv, lds_levels=lv), args.steps, args.warmup)
+        trav[name] = round(ms_t, 4)
+    trav["voronoi_walk"] = round(ms_step, 4)
+    result["traversals_ms"] = trav
+    log("[bench] traversals (ms/step): " + ", ".join(f"{k} {v:.3f}" for k, v in trav.items()))
+
+
 def time_steps(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -145,6 +163,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-primitive (triangles + segments) leg")
     ap.add_argument("--no-configs", action="store_true", help="skip the C1 and C3 legs")
     ap.add_argument("--no-sweep", action="store_true", help="skip the near/far sweep leg")
+    ap.add_argument("--no-alt", action="store_true",
+                    help="skip the unsorted and alternative-traversal legs on the headline batch")
     ap.add_argument("--no-precompute", action="store_true",
                     help="skip the device-inspection leg (the C2 table built with the filter and flooding on the GPU)")
     ap.add_argument("--sweep-queries", type=int, default=1_000_000,
@@ -315,22 +335,9 @@ def main():
     if breakdown:
         result["breakdown"] = breakdown
 
-    # the same batch without the ordering step
-    ms_uns = time_steps(lambda: mesh.query(q, out=out, sort=False), args.steps, args.warmup)
-    result["unsorted"] = {"value": round(n / (ms_uns / 1e3), 1), "unit": "queries/s", "ms_per_step": round(ms_uns, 4),
-                          "workload": "the headline batch in input order (no Morton ordering)"}
-    log(f"[bench] unsorted: {ms_uns:.3f} ms/step, {n / (ms_uns / 1e3) / 1e9:.3f} Gq/s")
-
-    # the other nearest-vertex traversals on the same batch: the per-lane tree
-    # search (with and without its top levels staged in LDS) and the
-    # wavefront tree walk
-    trav = {}
-    for name, tv, lv in (("kd_per_lane", 1, 0), ("kd_per_lane_lds8", 1, 8), ("kd_wavefront", 2, 0)):
-        ms_t = time_steps(lambda: mesh.query(q, out=out, traversal=tv, lds_levels=lv), args.steps, args.warmup)
-        trav[name] = round(ms_t, 4)
-    trav["voronoi_walk"] = round(ms_step, 4)
-    result["traversals_ms"] = trav
-    log("[bench] traversals (ms/step): " + ", ".join(f"{k} {v:.3f}" for k, v in trav.items()))
+    # the unsorted and alternative-traversal legs
+    if not args.no_alt:
+        alt_legs(args, mesh, q, out, n, ms_step, result)
 
     if not args.no_configs:
         # the small icosphere (C1) and the needle heightfield (C3): q/s, list statistics

@@ -11,6 +11,14 @@ namespace p2m {
 constexpr int kXcds = 8;  // MI355X: 8 XCDs, blocks dispatched round-robin
 constexpr int kQueryMaxBlock = 256;  // launch bound of the query kernels
 
+// Block b of a grid of G blocks -> the tile it takes, such that the blocks
+// of each XCD (b = x mod 8) take one contiguous stretch of the tiles, in
+// order: tiles processed side by side then share an L2.
+__host__ __device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t G) {
+    const int64_t x = b % kXcds, k = b / kXcds, q = G / kXcds, r = G % kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
+
 // 30-bit Morton key: 10 bits per axis, cell = clamp(floor((q-lo)*s), 0, 1023)
 // in float32 (one subtract, one multiply); x takes the top bit of each triple.
 __host__ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
@@ -71,6 +79,7 @@ struct RadixBuffers {
 constexpr int kRadixThreads = 256;
 constexpr int kRadixItems = 16;
 constexpr int64_t kRadixTile = kRadixThreads * kRadixItems;
+constexpr int kRadixHistThreads = 1024;  // threads of a histogram block (4 keys each)
 
 // Segmented sort: the keys form consecutive segments (the queries of one
 // mesh of a batch) and each is sorted on its own, in place, so the segment

@@ -145,32 +145,34 @@ int64_t up256(int64_t x) { return (x + 255) / 256 * 256; }
 // segmented sort's tiles) -- the top 24 bits of the query's Morton code in
 // its mesh's domain box -- and the counts of their low digit, the first
 // pass's column of the count matrix.
-__global__ __launch_bounds__(kRadixThreads) void k_batch_keys(const float* __restrict__ q,
-                                                              const BatchMesh* __restrict__ desc, RadixSegments sg,
-                                                              uint32_t* __restrict__ keys,
-                                                              uint32_t* __restrict__ counts) {
+__global__ __launch_bounds__(kRadixHistThreads) void k_batch_keys(const float* __restrict__ q,
+                                                                  const BatchMesh* __restrict__ desc, RadixSegments sg,
+                                                                  uint32_t* __restrict__ keys,
+                                                                  uint32_t* __restrict__ counts) {
+    constexpr int kHI = (int)(kRadixTile / kRadixHistThreads);
     __shared__ uint32_t h[256];
     const int t = threadIdx.x;
-    h[t] = 0;
-    __syncthreads();
     const RadixSegTile st = sg.tiles[blockIdx.x];
     const RadixSegInfo si = sg.segs[st.seg];
     const BatchMesh& d = desc[st.seg];
-#pragma unroll 4
-    for (int it = 0; it < kRadixItems; ++it) {
-        const int j = it * kRadixThreads + t;
-        const bool valid = j < st.count;
-        uint32_t key = 0;
-        if (valid) {
+    uint32_t key[kHI];
+#pragma unroll
+    for (int it = 0; it < kHI; ++it) {
+        const int j = it * kRadixHistThreads + t;
+        key[it] = 0u;
+        if (j < st.count) {
             const int64_t i = st.start + j;
-            key = morton30(q[3 * i], q[3 * i + 1], q[3 * i + 2], d.mlo[0], d.mlo[1], d.mlo[2], d.msc[0], d.msc[1],
-                           d.msc[2]) >> 6;
-            keys[i] = key;
+            key[it] = morton30(q[3 * i], q[3 * i + 1], q[3 * i + 2], d.mlo[0], d.mlo[1], d.mlo[2], d.msc[0],
+                               d.msc[1], d.msc[2]) >> 6;
+            keys[i] = key[it];
         }
-        radix_hist_add(h, key & 255u, valid);
     }
+    if (t < 256) h[t] = 0;
     __syncthreads();
-    counts[si.base + (int64_t)t * si.cols + st.j] = h[t];
+#pragma unroll
+    for (int it = 0; it < kHI; ++it) radix_hist_add(h, key[it] & 255u, it * kRadixHistThreads + t < st.count);
+    __syncthreads();
+    if (t < 256) counts[si.base + (int64_t)t * si.cols + st.j] = h[t];
 }
 
 __global__ void k_reset(uint32_t* counter) {
@@ -466,7 +468,7 @@ p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, 
     if (n == 0) return P2M_OK;
     RadixPlan plan = radix_plan_segmented(n, b->sort_seg.ntiles, b->sort_seg.nseg);
     RadixBuffers rb = radix_buffers(plan, b->scratch);
-    k_batch_keys<<<(unsigned)b->sort_seg.ntiles, kRadixThreads, 0, st>>>(q, b->desc, b->sort_seg, rb.keys[0],
+    k_batch_keys<<<(unsigned)b->sort_seg.ntiles, kRadixHistThreads, 0, st>>>(q, b->desc, b->sort_seg, rb.keys[0],
                                                                           rb.counts);
     const int cur = radix_sort_pairs(plan, rb, 0, 24, false, st, &b->sort_seg, true);
     k_reset<<<1, 64, 0, st>>>(b->counter);

@@ -397,6 +397,49 @@ __global__ void k_morton(const float* __restrict__ q, int64_t n, float lox, floa
     keys[i] = morton30(q[3 * i], q[3 * i + 1], q[3 * i + 2], lox, loy, loz, sx, sy, sz);
 }
 
+// Morton keys of one sort tile (kRadixTile queries) and the tile's counts of
+// the sort's first digit, key bits [shift, shift + 8), written to the tile's
+// column of the digit-major count matrix: the sort's first pass then needs
+// no histogram kernel of its own.  kRadixHistThreads threads a tile, four
+// consecutive queries each; with kVec (q 16-byte aligned) a thread reads its
+// four queries as three float4 and writes their keys as one uint4.
+template <bool kVec>
+__global__ __launch_bounds__(kRadixHistThreads) void k_morton_hist(const float* __restrict__ q, int64_t n, float lox,
+                                                                   float loy, float loz, float sx, float sy, float sz,
+                                                                   int shift, uint32_t* __restrict__ keys,
+                                                                   uint32_t* __restrict__ counts, int64_t tiles) {
+    constexpr int kHI = (int)(kRadixTile / kRadixHistThreads);
+    static_assert(kHI == 4, "four queries a thread");
+    __shared__ uint32_t h[256];
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + 4 * t;
+    uint32_t key[kHI] = {0u, 0u, 0u, 0u};
+    if (kVec && i0 + 3 < n) {
+        const float4* q4 = reinterpret_cast<const float4*>(q + 3 * i0);
+        const float4 a = q4[0], b = q4[1], c = q4[2];
+        key[0] = morton30(a.x, a.y, a.z, lox, loy, loz, sx, sy, sz);
+        key[1] = morton30(a.w, b.x, b.y, lox, loy, loz, sx, sy, sz);
+        key[2] = morton30(b.z, b.w, c.x, lox, loy, loz, sx, sy, sz);
+        key[3] = morton30(c.y, c.z, c.w, lox, loy, loz, sx, sy, sz);
+        *reinterpret_cast<uint4*>(keys + i0) = make_uint4(key[0], key[1], key[2], key[3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kHI; ++k) {
+            const int64_t i = i0 + k;
+            if (i < n) {
+                key[k] = morton30(q[3 * i], q[3 * i + 1], q[3 * i + 2], lox, loy, loz, sx, sy, sz);
+                keys[i] = key[k];
+            }
+        }
+    }
+    if (t < 256) h[t] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kHI; ++k) radix_hist_add(h, (key[k] >> shift) & 255u, i0 + k < n);
+    __syncthreads();
+    if (t < 256) counts[(int64_t)t * tiles + blockIdx.x] = h[t];
+}
+
 // Dynamic LDS of k_query: the regroup bins, then per slot 7 floats (q, the
 // nearest vertex's d2 and position) and 2 ints (query index, vertex); after
 // the regroup, the slots of each wavefront hold its scan keys and owners;
@@ -907,11 +950,23 @@ static p2m_status order_into(MeshState& s, void* base, const float* q, int64_t n
     RadixBuffers b = radix_buffers(plan, base);
     float lo[3], sc[3];
     morton_params(s.dlo, s.dhi, lo, sc);
-    const int64_t blocks = (n + 255) / 256;
-    k_morton<<<(unsigned)blocks, 256, 0, st>>>(q, n, lo[0], lo[1], lo[2], sc[0], sc[1], sc[2], b.keys[0]);
+    // with a sort to run, the key kernel also counts the first pass's digits
+    const bool passes = n > 1 && lo_bit < 30;
+    if (passes) {
+        // the keys start the 256-byte aligned scratch, so a uint4 of keys is aligned
+        if (((uintptr_t)q & 15u) == 0u)
+            k_morton_hist<true><<<(unsigned)plan.tiles, kRadixHistThreads, 0, st>>>(
+                q, n, lo[0], lo[1], lo[2], sc[0], sc[1], sc[2], lo_bit, b.keys[0], b.counts, plan.tiles);
+        else
+            k_morton_hist<false><<<(unsigned)plan.tiles, kRadixHistThreads, 0, st>>>(
+                q, n, lo[0], lo[1], lo[2], sc[0], sc[1], sc[2], lo_bit, b.keys[0], b.counts, plan.tiles);
+    } else {
+        const int64_t blocks = (n + 255) / 256;
+        k_morton<<<(unsigned)blocks, 256, 0, st>>>(q, n, lo[0], lo[1], lo[2], sc[0], sc[1], sc[2], b.keys[0]);
+    }
     p2m_status r = check_launch("morton keys");
     if (r != P2M_OK) return r;
-    int cur = radix_sort_pairs(plan, b, lo_bit, 30, keys_out != nullptr, st);
+    int cur = radix_sort_pairs(plan, b, lo_bit, 30, keys_out != nullptr, st, nullptr, passes);
     r = check_launch("radix sort");
     if (r != P2M_OK) return r;
     if (keys_out) *keys_out = b.keys[cur];

@@ -25,6 +25,7 @@ namespace {
 constexpr int kT = kRadixThreads;
 constexpr int kI = kRadixItems;
 constexpr int kWaves = kT / 64;
+constexpr int kColRegs = 16;  // column values a colscan thread keeps in registers
 
 // Where block b's tile lies: keys [start, start+count), column j of the
 // `cols` columns of its count block at `base`, and its segment.
@@ -33,11 +34,15 @@ struct TileGeo {
     int32_t count, j, cols, seg;
 };
 
+// The blocks of each XCD take a contiguous stretch of tiles (xcd_chunk): in
+// a scatter, the runs that neighbouring tiles write for one digit are
+// adjacent, so they meet in one L2 and leave it as whole lines.
 template <bool kSeg>
 __device__ __forceinline__ TileGeo tile_geo(int64_t n, int64_t tiles, const RadixSegments& sg) {
     TileGeo g;
+    const int64_t b = xcd_chunk(blockIdx.x, gridDim.x);
     if (kSeg) {
-        const RadixSegTile st = sg.tiles[blockIdx.x];
+        const RadixSegTile st = sg.tiles[b];
         const RadixSegInfo si = sg.segs[st.seg];
         g.start = st.start;
         g.count = st.count;
@@ -46,9 +51,9 @@ __device__ __forceinline__ TileGeo tile_geo(int64_t n, int64_t tiles, const Radi
         g.base = si.base;
         g.cols = si.cols;
     } else {
-        g.start = (int64_t)blockIdx.x * kRadixTile;
+        g.start = b * kRadixTile;
         g.count = (int32_t)std::min<int64_t>(kRadixTile, n - g.start);
-        g.j = (int32_t)blockIdx.x;
+        g.j = (int32_t)b;
         g.seg = 0;
         g.base = 0;
         g.cols = (int32_t)tiles;
@@ -57,25 +62,29 @@ __device__ __forceinline__ TileGeo tile_geo(int64_t n, int64_t tiles, const Radi
 }
 
 // Digit counts of one tile in LDS (radix_hist_add), written to the tile's
-// column of the count matrix.
+// column of the count matrix.  kRadixHistThreads threads a tile, four keys
+// each, all loaded before any is counted: the grid has as many blocks as the
+// sort has tiles, and short blocks keep the chip busy to the end.
 template <bool kSeg>
-__global__ __launch_bounds__(kT) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
-                                                   uint32_t* __restrict__ counts, int64_t tiles, RadixSegments sg) {
+__global__ __launch_bounds__(kRadixHistThreads) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
+                                                                  int shift, uint32_t* __restrict__ counts,
+                                                                  int64_t tiles, RadixSegments sg) {
+    constexpr int kHT = kRadixHistThreads, kHI = (int)(kRadixTile / kRadixHistThreads);
     __shared__ uint32_t h[256];
     const int t = threadIdx.x;
     const TileGeo g = tile_geo<kSeg>(n, tiles, sg);
-    h[t] = 0;
-    __syncthreads();
-    uint32_t key[kI];
+    uint32_t key[kHI];
 #pragma unroll
-    for (int it = 0; it < kI; ++it) {
-        const int i = it * kT + t;
+    for (int it = 0; it < kHI; ++it) {
+        const int i = it * kHT + t;
         key[it] = i < g.count ? keys[g.start + i] : 0u;
     }
-#pragma unroll
-    for (int it = 0; it < kI; ++it) radix_hist_add(h, (key[it] >> shift) & 255u, it * kT + t < g.count);
+    if (t < 256) h[t] = 0;
     __syncthreads();
-    counts[g.base + (int64_t)t * g.cols + g.j] = h[t];
+#pragma unroll
+    for (int it = 0; it < kHI; ++it) radix_hist_add(h, (key[it] >> shift) & 255u, it * kHT + t < g.count);
+    __syncthreads();
+    if (t < 256) counts[g.base + (int64_t)t * g.cols + g.j] = h[t];
 }
 
 // Exclusive scan of 4096-element blocks in place; block totals to sums.
@@ -167,7 +176,9 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t x, uint32_t* wsum, 
 
 // Column d of the digit-major count matrix (the tiles' counts of digit d;
 // in a segmented sort block 256*s+d takes segment s's column d): exclusive
-// scan in place, in chunks of kT with a carry; totals[256*s+d] = its sum.
+// scan in place -- each thread sums a contiguous stretch of the column, one
+// block scan of the stretch sums, then each thread writes its stretch's
+// running offsets; totals[256*s+d] = the column's sum.
 template <bool kSeg>
 __global__ __launch_bounds__(kT) void k_radix_colscan(uint32_t* __restrict__ counts, int64_t tiles,
                                                       uint32_t* __restrict__ totals, RadixSegments sg) {
@@ -180,16 +191,35 @@ __global__ __launch_bounds__(kT) void k_radix_colscan(uint32_t* __restrict__ cou
         tiles = si.cols;
     }
     uint32_t* col = counts + base + (int64_t)d * tiles;
-    uint32_t carry = 0;
-    for (int64_t c = 0; c < tiles; c += kT) {
-        const int64_t i = c + threadIdx.x;
-        const uint32_t x = i < tiles ? col[i] : 0u;
-        uint32_t sum;
-        const uint32_t e = block_scan_excl(x, wsum, &sum);
-        if (i < tiles) col[i] = carry + e;
-        carry += sum;
+    const int64_t per = (tiles + kT - 1) / kT;
+    const int64_t a = std::min<int64_t>(tiles, (int64_t)threadIdx.x * per), e = std::min<int64_t>(tiles, a + per);
+    uint32_t sum;
+    if (per <= kColRegs) {
+        // up to kColRegs values a thread: loaded together, kept in registers
+        uint32_t x[kColRegs];
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kColRegs; ++k) {
+            x[k] = a + k < e ? col[a + k] : 0u;
+            s += x[k];
+        }
+        uint32_t run = block_scan_excl(s, wsum, &sum);
+#pragma unroll
+        for (int k = 0; k < kColRegs; ++k) {
+            if (a + k < e) col[a + k] = run;
+            run += x[k];
+        }
+    } else {
+        uint32_t s = 0;
+        for (int64_t i = a; i < e; ++i) s += col[i];
+        uint32_t run = block_scan_excl(s, wsum, &sum);
+        for (int64_t i = a; i < e; ++i) {
+            const uint32_t x = col[i];
+            col[i] = run;
+            run += x;
+        }
     }
-    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+    if (threadIdx.x == 0) totals[blockIdx.x] = sum;
 }
 
 // Scatter of one tile (kPositions: the values are the keys' positions, as in
@@ -220,6 +250,18 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
     const TileGeo g = tile_geo<kSeg>(n, tiles, sg);
     const int64_t tile0 = g.start;
     const int cnt = g.count;
+    // the tile's pairs: loaded first, so that their latency overlaps the
+    // digit offsets' loads and scan
+    const int wbase = w * (kI * 64);
+    uint32_t key[kI];
+    int32_t val[kI];
+#pragma unroll
+    for (int it = 0; it < kI; ++it) {
+        const int i = wbase + it * 64 + lane;
+        const bool valid = i < cnt;
+        key[it] = valid ? kin[tile0 + i] : 0u;
+        val[it] = valid ? (kPositions ? (int32_t)(tile0 + i) : vin[tile0 + i]) : 0;
+    }
     __shared__ uint32_t wsum[kWaves];
     {
         // digit t's run starts after the runs of smaller digits (of the
@@ -232,33 +274,31 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
 #pragma unroll
     for (int k = 0; k < kWaves; ++k) wc[k][t] = 0;
     __syncthreads();
-    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int wbase = w * (kI * 64);
-    uint32_t key[kI], rank[kI];
-    int32_t val[kI];
+    // lanes below this one, as two 32-bit halves
+    const uint32_t ltlo = lane >= 32 ? ~0u : (1u << lane) - 1u;
+    const uint32_t lthi = lane <= 32 ? 0u : (1u << (lane - 32)) - 1u;
+    uint32_t rank[kI];
 #pragma unroll
-    for (int it = 0; it < kI; ++it) {
-        const int i = wbase + it * 64 + lane;
-        const bool valid = i < cnt;
-        key[it] = valid ? kin[tile0 + i] : 0u;
-        val[it] = valid ? (kPositions ? (int32_t)(tile0 + i) : vin[tile0 + i]) : 0;
-    }
     for (int it = 0; it < kI; ++it) {
         const bool valid = wbase + it * 64 + lane < cnt;
         const uint32_t d = (key[it] >> shift) & 255u;
-        unsigned long long mask = __ballot(valid);
+        // the lanes holding the same digit: per bit, the ballot of the lanes
+        // with the bit set, or its complement when this lane's bit is clear
+        const unsigned long long vm = __ballot(valid);
+        uint32_t mlo = (uint32_t)vm, mhi = (uint32_t)(vm >> 32);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const unsigned long long bm = __ballot(bit);
-            mask &= bit ? bm : ~bm;
+            const uint32_t nb = ((d >> b) & 1u) - 1u;  // 0 when set, all ones when clear
+            const unsigned long long bm = __ballot(nb == 0u);
+            mlo &= (uint32_t)bm ^ nb;
+            mhi &= (uint32_t)(bm >> 32) ^ nb;
         }
-        const uint32_t r = (uint32_t)__popcll(mask & lt);
+        const uint32_t r = (uint32_t)(__popc(mlo & ltlo) + __popc(mhi & lthi));
         const uint32_t prior = valid ? wc[w][d] : 0u;
         rank[it] = prior + r;
         // the lowest lane of each digit advances the wave's count; this
         // wave's LDS accesses stay in program order
-        if (valid && r == 0) wc[w][d] = prior + (uint32_t)__popcll(mask);
+        if (valid && r == 0) wc[w][d] = prior + (uint32_t)(__popc(mlo) + __popc(mhi));
     }
     __syncthreads();
     // digit totals, their exclusive scan (the tile's LDS order), and each
@@ -299,6 +339,8 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
             wc[k][t] = base;
             base += c[k];
         }
+        // LDS place p of digit t goes to gbase[t] + p - lstart[t]
+        gbase[t] -= lstart[t];
     }
     __syncthreads();
 #pragma unroll
@@ -311,11 +353,11 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
         }
     }
     __syncthreads();
-    // coalesced write-out: LDS place p of digit d goes to gbase[d] + p - lstart[d]
+    // coalesced write-out: LDS place p of digit d goes to gbase[d] + p
     for (int p = t; p < cnt; p += kT) {
         const uint32_t k = lk[p];
         const uint32_t d = (k >> shift) & 255u;
-        const uint32_t pos = gbase[d] + (uint32_t)p - lstart[d];
+        const uint32_t pos = gbase[d] + (uint32_t)p;
         if (pos < (uint64_t)n) {
             if (kKeysOut) kout[pos] = k;
             vout[pos] = lv[p];
@@ -411,7 +453,8 @@ int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit
 #define P2M_PASS(S)                                                                                             \
     do {                                                                                                        \
         if (!(first && first_counts))                                                                           \
-            k_radix_hist<S><<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], p.n, shift, b.counts, p.tiles, sg);  \
+            k_radix_hist<S><<<(unsigned)p.tiles, kRadixHistThreads, 0, st>>>(b.keys[cur], p.n, shift, b.counts,  \
+                                                                          p.tiles, sg);                       \
         k_radix_colscan<S><<<cols_blocks, kT, 0, st>>>(b.counts, p.tiles, b.sums, sg);                          \
         if (first) {                                                                                            \
             if (keys_out) P2M_SCATTER(true, true, S);                                                           \

@@ -148,6 +148,16 @@ def test_order_bit_exact(c1, n):
         assert np.array_equal(rp2, np.arange(n))
         assert np.array_equal(keys.cpu().numpy().view(np.uint32), rk2)
         assert np.array_equal(perm.cpu().numpy(), rp2)
+    # queries at an address that is not 16-byte aligned (the key kernel's
+    # scalar form): the same keys and permutation
+    buf = torch.zeros(3 * n + 1, dtype=torch.float32, device="cuda")
+    buf[1:] = torch.from_numpy(Q.reshape(-1)).cuda()
+    qu = buf[1:].view(n, 3)
+    assert qu.data_ptr() % 16 != 0
+    keys, perm = m.order_queries(qu)
+    torch.cuda.synchronize()
+    assert np.array_equal(keys.cpu().numpy().view(np.uint32), rk)
+    assert np.array_equal(perm.cpu().numpy(), rp)
 
 
 @pytest.mark.parametrize("traversal", [1, 2, 3])
