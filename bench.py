@@ -56,7 +56,8 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("query_core.hpp", "nearest.hpp", "wave_kdtree.hpp", "device_common.hpp", "regroup.hpp", "p2m_device.hip"):
+    for f in ("query_core.hpp", "nearest.hpp", "wave_kdtree.hpp", "wave_scan.hpp", "device_common.hpp", "regroup.hpp",
+              "p2m_device.hip"):
         with open(os.path.join(ROOT, "paper_2308_16084_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
