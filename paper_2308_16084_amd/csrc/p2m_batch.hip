@@ -363,12 +363,19 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_batch_query(Arena A, const T
 
 // The Voronoi-walk forms (the default traversal), held to 80 registers so
 // that six wavefronts fit on each SIMD.
-template <bool kPersistent>
 __global__ __launch_bounds__(kQueryMaxBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_batch_query_walk(
     Arena A, const Tile* __restrict__ tiles, int64_t ntiles, uint32_t* counter, int qpl, int group,
     const float* __restrict__ q, const int32_t* __restrict__ perm, int64_t n, float4* __restrict__ stage,
     int32_t ntop_max) {
-    batch_query<WALK_VORONOI, kPersistent>(A, tiles, ntiles, counter, qpl, group, q, perm, n, stage, ntop_max);
+    batch_query<WALK_VORONOI, false>(A, tiles, ntiles, counter, qpl, group, q, perm, n, stage, ntop_max);
+}
+// The persistent form: its tile loop needs more registers; held to 96
+// (five wavefronts a SIMD), where it does not spill.
+__global__ __launch_bounds__(kQueryMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_query_walk_persistent(
+    Arena A, const Tile* __restrict__ tiles, int64_t ntiles, uint32_t* counter, int qpl, int group,
+    const float* __restrict__ q, const int32_t* __restrict__ perm, int64_t n, float4* __restrict__ stage,
+    int32_t ntop_max) {
+    batch_query<WALK_VORONOI, true>(A, tiles, ntiles, counter, qpl, group, q, perm, n, stage, ntop_max);
 }
 
 // Tree nodes the batched kernel stages per tile: traversal 1 only.
@@ -484,11 +491,11 @@ p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, 
     if (b->persistent) {
         if (b->traversal == 1) P2M_LAUNCH_BATCH((k_batch_query<WALK_LANE, true>));
         else if (b->traversal == 2) P2M_LAUNCH_BATCH((k_batch_query<WALK_WAVE, true>));
-        else P2M_LAUNCH_BATCH((k_batch_query<WALK_VORONOI, true>));
+        else P2M_LAUNCH_BATCH(k_batch_query_walk_persistent);
     } else {
         if (b->traversal == 1) P2M_LAUNCH_BATCH((k_batch_query<WALK_LANE, false>));
         else if (b->traversal == 2) P2M_LAUNCH_BATCH((k_batch_query<WALK_WAVE, false>));
-        else P2M_LAUNCH_BATCH(k_batch_query_walk<false>);
+        else P2M_LAUNCH_BATCH(k_batch_query_walk);
     }
 #undef P2M_LAUNCH_BATCH
     hipError_t e = hipGetLastError();
@@ -504,7 +511,7 @@ p2m_status set_grid(p2m_batch* b) {
     if (e != hipSuccess) return hip_fail(e, "device attribute");
     const void* k = b->traversal == 1   ? (const void*)k_batch_query<WALK_LANE, true>
                     : b->traversal == 2 ? (const void*)k_batch_query<WALK_WAVE, true>
-                                        : (const void*)k_batch_query<WALK_VORONOI, true>;
+                                        : (const void*)k_batch_query_walk_persistent;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, b->block,
                                                      batch_lds_bytes(b->block, b->qpl, batch_top_nodes(b)));
     if (e != hipSuccess) return hip_fail(e, "occupancy query");
