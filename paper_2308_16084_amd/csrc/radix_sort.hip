@@ -174,23 +174,16 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t x, uint32_t* wsum, 
     return before + incl - x;
 }
 
-// Column d of the digit-major count matrix (the tiles' counts of digit d;
-// in a segmented sort block 256*s+d takes segment s's column d): exclusive
-// scan in place -- each thread sums a contiguous stretch of the column, one
-// block scan of the stretch sums, then each thread writes its stretch's
-// running offsets; totals[256*s+d] = the column's sum.
-template <bool kSeg>
+// Column d of the digit-major count matrix of a plain sort (the tiles'
+// counts of digit d; block d): exclusive scan in place -- each thread sums a
+// contiguous stretch of the column, one block scan of the stretch sums, then
+// each thread writes its stretch's running offsets; totals[d] = the
+// column's sum.
 __global__ __launch_bounds__(kT) void k_radix_colscan(uint32_t* __restrict__ counts, int64_t tiles,
-                                                      uint32_t* __restrict__ totals, RadixSegments sg) {
+                                                      uint32_t* __restrict__ totals) {
     __shared__ uint32_t wsum[kWaves];
-    const int d = (int)(blockIdx.x & 255u);
-    int64_t base = 0;
-    if (kSeg) {
-        const RadixSegInfo si = sg.segs[blockIdx.x >> 8];
-        base = si.base;
-        tiles = si.cols;
-    }
-    uint32_t* col = counts + base + (int64_t)d * tiles;
+    const int d = (int)blockIdx.x;
+    uint32_t* col = counts + (int64_t)d * tiles;
     const int64_t per = (tiles + kT - 1) / kT;
     const int64_t a = std::min<int64_t>(tiles, (int64_t)threadIdx.x * per), e = std::min<int64_t>(tiles, a + per);
     uint32_t sum;
@@ -220,6 +213,30 @@ __global__ __launch_bounds__(kT) void k_radix_colscan(uint32_t* __restrict__ cou
         }
     }
     if (threadIdx.x == 0) totals[blockIdx.x] = sum;
+}
+
+// The columns of a segmented sort: one block per segment, thread d scans
+// segment s's column d (its tiles' counts of digit d, a few to a few
+// hundred), kColRegs values at a time loaded together; totals[256*s+d] =
+// the column's sum.  (One block per column and segment, as in the plain
+// sort, would launch 256 blocks per mesh, most with a handful of values.)
+__global__ __launch_bounds__(kT) void k_radix_colscan_seg(uint32_t* __restrict__ counts,
+                                                          uint32_t* __restrict__ totals, RadixSegments sg) {
+    const RadixSegInfo si = sg.segs[blockIdx.x];
+    const int d = threadIdx.x;
+    uint32_t* col = counts + si.base + (int64_t)d * si.cols;
+    uint32_t run = 0;
+    for (int32_t j0 = 0; j0 < si.cols; j0 += kColRegs) {
+        uint32_t x[kColRegs];
+#pragma unroll
+        for (int k = 0; k < kColRegs; ++k) x[k] = j0 + k < si.cols ? col[j0 + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < kColRegs; ++k) {
+            if (j0 + k < si.cols) col[j0 + k] = run;
+            run += x[k];
+        }
+    }
+    totals[256 * (int64_t)blockIdx.x + d] = run;
 }
 
 // Scatter of one tile (kPositions: the values are the keys' positions, as in
@@ -443,7 +460,6 @@ int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit
         return cur;
     }
     const RadixSegments sg = seg ? *seg : RadixSegments{};
-    const unsigned cols_blocks = seg ? 256u * (unsigned)seg->nseg : 256u;
     for (int shift = lo_bit; shift < hi_bit; shift += 8) {
         const bool first = shift == lo_bit, last = shift + 8 >= hi_bit;
         const bool keys_out = !last || keep_keys;
@@ -455,7 +471,8 @@ int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit
         if (!(first && first_counts))                                                                           \
             k_radix_hist<S><<<(unsigned)p.tiles, kRadixHistThreads, 0, st>>>(b.keys[cur], p.n, shift, b.counts,  \
                                                                           p.tiles, sg);                       \
-        k_radix_colscan<S><<<cols_blocks, kT, 0, st>>>(b.counts, p.tiles, b.sums, sg);                          \
+        if (S) k_radix_colscan_seg<<<(unsigned)seg->nseg, kT, 0, st>>>(b.counts, b.sums, sg);                    \
+        else k_radix_colscan<<<256u, kT, 0, st>>>(b.counts, p.tiles, b.sums);                                    \
         if (first) {                                                                                            \
             if (keys_out) P2M_SCATTER(true, true, S);                                                           \
             else P2M_SCATTER(true, false, S);                                                                   \
