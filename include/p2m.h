@@ -231,12 +231,13 @@ p2m_status p2m_upload(p2m_mesh* m, int device, void* stream, int64_t* bytes);
  * evaluates exactly every candidate that could still be closer, so the
  * answer is the exact minimum over the candidates up to float32 rounding,
  * whatever the gate margin).  Outputs (device): prim int32 [n], closest float [n*3], dist
- * float [n]; status uint8 [n] (may be NULL).  For the backward pass, bary
+ * float [n] (|q - closest| in float32, every operation rounded on its own);
+ * status uint8 [n] (may be NULL).  For the backward pass, bary
  * float [n*3] and pvid int32 [n*3] (both NULL or both set) receive the
  * closest point's barycentric weights over the primitive's vertices (unused
  * slots: weight 0, id -1).  Non-finite queries give P2M_NONE, NaN distance
  * and P2M_Q_NONFINITE.  n = 0 is a no-op.  Scratch device memory (ordering,
- * and 32 bytes per query of staged answers for an ordered batch, 48 with
+ * and 16 bytes per query of staged answers for an ordered batch, 48 with
  * bary/pvid) is owned
  * by the mesh, grown on demand and reused; concurrent calls on the same
  * mesh from different streams race. */

@@ -452,12 +452,16 @@ static_assert(sizeof(WaveScanKeys) <= 9 * 64 * sizeof(uint32_t), "scan keys exce
 // then, for the per-lane tree search, the staged top of the tree (16-byte aligned)
 constexpr size_t top_lds_offset(int block) { return (regroup_lds_bytes(block) + 15) / 16 * 16; }
 
-// stage (ordered batches): query i's answer goes to stage[S*i .. S*i+S-1]
-// (S = 2, or 3 with the backward extras) as (prim, closest), (dist, status,
-// w0, w1), (w2, pv0, pv1, pv2) -- one aligned record per query instead of
-// several partial cache lines in the output arrays; k_split then writes
-// those arrays with coalesced stores.  Without stage the answer goes to the
-// output arrays directly.
+// stage (ordered batches): query i's answer goes to one aligned record at
+// its input position instead of several partial cache lines in the output
+// arrays, and a write-out kernel then fills those arrays with coalesced
+// stores.  Without the backward extras the record is 16 bytes, (prim,
+// closest): the write-out forms the distance (point_dist) and the status
+// from q itself.  Each record is a write to a random place of the batch,
+// and these writes cost about a sixth of the kernel on 10^7 queries; 16
+// bytes cost less than the 32 of (prim, closest), (dist, status).  With
+// the extras: 48 bytes, (prim, closest), (dist, status, w0, w1), (w2, pv0,
+// pv1, pv2).  Without stage the answer goes to the output arrays directly.
 template <bool kWriteExtras, int kWalk>
 __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const float* __restrict__ q,
                                                 const int32_t* __restrict__ perm, int64_t n, int64_t run,
@@ -536,12 +540,14 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const floa
     uint8_t st = fin ? domain_status(m, qx, qy, qz) : (uint8_t)2;
     const Answer a = fin ? finish_answer(m, qx, qy, qz, nv, best, best_kind, best_id, c) : nonfinite_answer();
     if (stage) {
-        constexpr int S = kWriteExtras ? 3 : 2;
-        stage[S * i] = make_float4(__int_as_float(a.prim), a.cx, a.cy, a.cz);
-        stage[S * i + 1] = make_float4(a.dist, __int_as_float((int)st), a.w[0], a.w[1]);
-        if (kWriteExtras)
-            stage[S * i + 2] = make_float4(a.w[2], __int_as_float(a.pv[0]), __int_as_float(a.pv[1]),
+        if (kWriteExtras) {
+            stage[3 * i] = make_float4(__int_as_float(a.prim), a.cx, a.cy, a.cz);
+            stage[3 * i + 1] = make_float4(a.dist, __int_as_float((int)st), a.w[0], a.w[1]);
+            stage[3 * i + 2] = make_float4(a.w[2], __int_as_float(a.pv[0]), __int_as_float(a.pv[1]),
                                            __int_as_float(a.pv[2]));
+        } else {
+            stage[i] = make_float4(__int_as_float(a.prim), a.cx, a.cy, a.cz);
+        }
         return;
     }
     prim[i] = a.prim;
@@ -581,6 +587,30 @@ __global__ __launch_bounds__(256) void k_split(const float4* __restrict__ stage,
         pvid[3 * i] = __float_as_int(c.y);
         pvid[3 * i + 1] = __float_as_int(c.z);
         pvid[3 * i + 2] = __float_as_int(c.w);
+    }
+}
+
+// Write-out of 16-byte records (prim, closest) of one mesh's ordered query:
+// the distance |q - c| (point_dist, as the query kernel forms it) and the
+// status (outside the domain box, non-finite) are rebuilt from q, read here
+// in input order.
+__global__ __launch_bounds__(256) void k_split_compact(const float4* __restrict__ stage, const float* __restrict__ q,
+                                                       int64_t n, float lox, float loy, float loz, float hix,
+                                                       float hiy, float hiz, int32_t* __restrict__ prim,
+                                                       float* __restrict__ closest, float* __restrict__ dist,
+                                                       uint8_t* __restrict__ status) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 a = stage[i];
+    const float qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
+    prim[i] = __float_as_int(a.x);
+    closest[3 * i] = a.y;
+    closest[3 * i + 1] = a.z;
+    closest[3 * i + 2] = a.w;
+    dist[i] = point_dist(qx, qy, qz, a.y, a.z, a.w);
+    if (status) {
+        const bool out = qx < lox || qy < loy || qz < loz || qx > hix || qy > hiy || qz > hiz;
+        status[i] = finite3(qx, qy, qz) ? (out ? 1 : 0) : 2;
     }
 }
 
@@ -1142,7 +1172,7 @@ static p2m_status run_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* pr
         void* x = nullptr;
         p2m_status r = fixed_buf ? order_into(s, fixed_buf, q, n, kQuerySortLoBit, st, nullptr, &perm, &x)
                                  : order_into_scratch(s, q, n, kQuerySortLoBit, st, nullptr, &perm,
-                                                      (bary ? 48 : 32) * n, &x);
+                                                      (bary ? 48 : 16) * n, &x);
         if (r != P2M_OK) return r;
         stage = (float4*)x;
     }
@@ -1170,7 +1200,15 @@ static p2m_status run_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* pr
     p2m_status r = check_launch("query kernel");
     if (profile) (void)hipEventRecord((hipEvent_t)s.dev.ev[2], st);
     if (r == P2M_OK && stage) {
-        const hipError_t e = launch_split(stage, n, prim, closest, dist, status, bary, pvid, st);
+        hipError_t e = hipSuccess;
+        if (bary) {
+            e = launch_split(stage, n, prim, closest, dist, status, bary, pvid, st);
+        } else {
+            k_split_compact<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(stage, q, n, v.dlo[0], v.dlo[1], v.dlo[2],
+                                                                          v.dhi[0], v.dhi[1], v.dhi[2], prim, closest,
+                                                                          dist, status);
+            e = hipGetLastError();
+        }
         if (e != hipSuccess) r = fail(P2M_ERR_HIP, std::string("answer write-out: ") + hipGetErrorString(e));
     }
     if (r == P2M_OK && profile) {

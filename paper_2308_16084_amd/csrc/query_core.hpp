@@ -430,6 +430,19 @@ struct ScanCounters {
     uint64_t rescans = 0, rescan_exact = 0;               // second scans; exact evaluations in them
 };
 
+// The reported distance: |q - c| for the reported closest point c, each
+// operation rounded on its own (no fused multiply-add), so that every kernel
+// that forms it -- the query kernels and the write-out that rebuilds it
+// from a staged closest point -- gives the same bits.
+P2M_HD float point_dist(float qx, float qy, float qz, float cx, float cy, float cz) {
+#if defined(__clang__)
+#pragma clang fp contract(off)
+#endif
+    const float dx = qx - cx, dy = qy - cy, dz = qz - cz;
+    const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    return sqrtf((xx + yy) + zz);
+}
+
 P2M_HD Answer nonfinite_answer() {
     Answer a;
     a.prim = make_prim(KIND_NONE, 0);
@@ -732,10 +745,9 @@ P2M_HD Answer finish_answer(const MeshView& m, float qx, float qy, float qz, con
             }
         }
     }
-    float exact = resolve(m, qx, qy, qz, nv, best_kind, best_id, a);
+    const float exact = resolve(m, qx, qy, qz, nv, best_kind, best_id, a);
     // a primitive whose exact distance exceeds d(q, v) gives way to v
     if (best_kind != KIND_VERTEX && !(exact <= nv.d2)) {
-        exact = nv.d2;
         a.prim = make_prim(KIND_VERTEX, nv.vid);
         a.cx = nv.px;
         a.cy = nv.py;
@@ -745,7 +757,9 @@ P2M_HD Answer finish_answer(const MeshView& m, float qx, float qy, float qz, con
         a.pv[0] = nv.vid;
         a.pv[1] = a.pv[2] = -1;
     }
-    a.dist = sqrtf(exact);
+    // the exact squared distance decided the answer; the reported distance
+    // is that of the reported closest point (point_dist)
+    a.dist = point_dist(qx, qy, qz, a.cx, a.cy, a.cz);
     return a;
 }
 
