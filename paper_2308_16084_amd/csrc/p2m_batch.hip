@@ -175,6 +175,39 @@ __global__ __launch_bounds__(kRadixHistThreads) void k_batch_keys(const float* _
     if (t < 256) counts[si.base + (int64_t)t * si.cols + st.j] = h[t];
 }
 
+// Write-out of the batch's 16-byte records (prim, closest point) in input
+// order: row i belongs to the last mesh whose query range starts at or
+// before it (empty ranges are skipped that way); the distance |q - c|
+// (point_dist, as the query kernel forms it) and the status (outside that
+// mesh's domain box, non-finite) are rebuilt from q.
+__global__ __launch_bounds__(256) void k_batch_split(const float4* __restrict__ stage, const float* __restrict__ q,
+                                                     int64_t n, const RadixSegInfo* __restrict__ segs, int32_t nseg,
+                                                     const BatchMesh* __restrict__ desc, int32_t* __restrict__ prim,
+                                                     float* __restrict__ closest, float* __restrict__ dist,
+                                                     uint8_t* __restrict__ status) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 a = stage[i];
+    const float qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
+    prim[i] = __float_as_int(a.x);
+    closest[3 * i] = a.y;
+    closest[3 * i + 1] = a.z;
+    closest[3 * i + 2] = a.w;
+    dist[i] = point_dist(qx, qy, qz, a.y, a.z, a.w);
+    if (status) {
+        int32_t lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (segs[mid].start <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchMesh& d = desc[lo];
+        const bool out = qx < d.dlo[0] || qy < d.dlo[1] || qz < d.dlo[2] || qx > d.dhi[0] || qy > d.dhi[1] ||
+                         qz > d.dhi[2];
+        status[i] = finite3(qx, qy, qz) ? (out ? 1 : 0) : 2;
+    }
+}
+
 __global__ void k_reset(uint32_t* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0u;
 }
@@ -341,10 +374,9 @@ __device__ __forceinline__ void batch_query(Arena A, const Tile* __restrict__ ti
                 wave_scan(v, ring, i >= 0 && fin, qx, qy, qz, nv, best, best_kind, best_id, c);
                 if (i < 0) continue;
                 const Answer a = fin ? finish_answer(v, qx, qy, qz, nv, best, best_kind, best_id, c) : nonfinite_answer();
-                const int stb = fin ? (int)domain_status(v, qx, qy, qz) : 2;
-                // one 32-byte record per query; split into the outputs afterwards
-                stage[2 * i] = make_float4(__int_as_float(a.prim), a.cx, a.cy, a.cz);
-                stage[2 * i + 1] = make_float4(a.dist, __int_as_float(stb), 0.f, 0.f);
+                // one 16-byte record per query, (prim, closest point); the
+                // write-out (k_batch_split) rebuilds the distance and status
+                stage[i] = make_float4(__int_as_float(a.prim), a.cx, a.cy, a.cz);
             }
             __syncthreads();  // the slots are refilled by the next rounds or tile
         }
@@ -425,7 +457,7 @@ p2m_status prepare(p2m_batch* b, const int64_t* qoff_host, hipStream_t st) {
         for (int64_t s = layout[(size_t)k]; s < layout[(size_t)k + 1]; s += tsize)
             tiles.push_back(Tile{(int32_t)k, (int32_t)s, (int32_t)std::min(tsize, layout[(size_t)k + 1] - s), 0});
     const int64_t need = up256((int64_t)sizeof(Tile) * std::max<size_t>(1, tiles.size())) + 256 + b_stiles + b_ssegs +
-                         up256(plan.bytes) + 32 * std::max<int64_t>(n, 1);
+                         up256(plan.bytes) + 16 * std::max<int64_t>(n, 1);
     if (need > b->work_bytes) {
         if (b->work) (void)hipFree(b->work);
         b->work = nullptr;
@@ -500,7 +532,9 @@ p2m_status enqueue(p2m_batch* b, const float* q, int32_t* prim, float* closest, 
 #undef P2M_LAUNCH_BATCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batched query launch");
-    e = launch_split(b->stage, n, prim, closest, dist, status, nullptr, nullptr, st);
+    k_batch_split<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(b->stage, q, n, b->sort_seg.segs, b->sort_seg.nseg,
+                                                              b->desc, prim, closest, dist, status);
+    e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batched answer write-out");
     return P2M_OK;
 }
