@@ -310,7 +310,7 @@ void p2m_batch_destroy(p2m_batch* b);
  * order; primitive ids are local to each mesh; status_dev uint8 [N] (may be
  * NULL) receives the status bits of each query in its mesh's domain.  The launch sequence
  * (ordering keys and sort, work-counter reset, persistent kernel, write-out
- * of the staged 32-byte answers) is captured into a HIP graph on first use
+ * of the staged 16-byte answers) is captured into a HIP graph on first use
  * and replayed while the offsets,
  * pointers and launch shape stay the same.  A new offset layout uploads a
  * tile list and waits for that copy.  Calls on one batch must not overlap. */

@@ -120,7 +120,7 @@ struct p2m_batch {
     uint32_t* counter = nullptr;
     p2m::RadixSegments sort_seg;  // the segmented sort's tiles and segments (device)
     void* scratch = nullptr;
-    float4* stage = nullptr;  // 32-byte answer record per query
+    float4* stage = nullptr;  // 16-byte answer record per query (prim, closest point)
     int tile_block = 0, tile_qpl = 0;
     // launch shape
     int block = 256, qpl = 1, traversal = 3;
