@@ -182,7 +182,8 @@ def main():
                     help="directory to save/load the precomputed mesh (default $P2M_CACHE_DIR; empty: none)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU: --gpus must be 1 (the queries of a batch are "
+                                   "independent, so more GPUs would each take a share of the sorted batch)"}))
         sys.exit(2)
 
     import torch
