@@ -89,7 +89,8 @@ def test_c3_backward_large_mesh(c3_mesh):
 def test_c4_batched_sampled():
     """All 256 meshes of the seeded C4 plan (tables built with the inspection
     on the device) in one graph launch at the autotuned launch shape; 64
-    sampled queries per mesh against the oracle."""
+    sampled queries per mesh against the oracle; the persistent schedule at
+    that shape gives the same answers."""
     from concurrent.futures import ThreadPoolExecutor
 
     import torch
@@ -118,6 +119,16 @@ def test_c4_batched_sampled():
         fails = check_answers(om, x.Q[idx], om.query(x.Q[idx]), out["prim"][rows], out["closest"][rows],
                               out["dist"][rows], idx=rows)
         assert fails == [], (k, x.name, fails)
+    # the persistent schedule at the same shape: the same answers, bit for bit
+    print("case: c4 persistent schedule", flush=True)
+    try:
+        b.set_schedule(True)
+        got = _np(b.query(qd, off))
+        torch.cuda.synchronize()
+        for key in out:
+            assert np.array_equal(got[key], out[key]), key
+    finally:
+        b.set_schedule(False)
 
 
 def _star_fd(om64, q, k, axis, h, faces_of):
