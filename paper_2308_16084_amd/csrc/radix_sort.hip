@@ -26,6 +26,12 @@ constexpr int kT = kRadixThreads;
 constexpr int kI = kRadixItems;
 constexpr int kWaves = kT / 64;
 constexpr int kColRegs = 16;  // column values a colscan thread keeps in registers
+// Scatter blocks: 512 threads, 8 keys a thread, 8 wavefronts (at about 55
+// registers, three blocks -- 24 wavefronts -- fit on a CU by LDS, where 256
+// threads of 16 keys needed 100 registers and fitted 16).
+constexpr int kST = 512;
+constexpr int kSI = (int)(kRadixTile / kST);
+constexpr int kSWaves = kST / 64;
 
 // Where block b's tile lies: keys [start, start+count), column j of the
 // `cols` columns of its count block at `base`, and its segment.
@@ -153,6 +159,7 @@ __global__ __launch_bounds__(kT) void k_scan_add(uint32_t* __restrict__ a, int64
 
 // Exclusive scan of one value per thread over the kT threads of a block;
 // *total receives the block's sum.  Every thread calls it (barriers inside).
+template <int kW = kWaves>
 __device__ __forceinline__ uint32_t block_scan_excl(uint32_t x, uint32_t* wsum, uint32_t* total) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     uint32_t incl = x;
@@ -165,7 +172,7 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t x, uint32_t* wsum, 
     __syncthreads();
     uint32_t before = 0, all = 0;
 #pragma unroll
-    for (int k = 0; k < kWaves; ++k) {
+    for (int k = 0; k < kW; ++k) {
         before += k < w ? wsum[k] : 0u;
         all += wsum[k];
     }
@@ -246,19 +253,19 @@ __global__ __launch_bounds__(kT) void k_radix_colscan_seg(uint32_t* __restrict__
 // digit order (stable: by digit, then by position in the tile), then written
 // out so that consecutive threads write consecutive places of each digit's
 // run -- coalesced runs of ~16 keys instead of one cache line per key.
-// Each wavefront ranks its own contiguous quarter of the tile, 64 keys per
+// Each wavefront ranks its own contiguous eighth of the tile, 64 keys per
 // round, against a running per-digit count of its earlier rounds (ballots
 // on the 8 digit bits find the lanes of equal digit), so the block meets at
 // a barrier only a few times per tile.
 template <bool kPositions, bool kKeysOut, bool kSeg>
-__global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
+__global__ __launch_bounds__(kST) void k_radix_scatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
                                                       int64_t n, int shift, const uint32_t* __restrict__ offs,
                                                       const uint32_t* __restrict__ totals, int64_t tiles,
                                                       uint32_t* __restrict__ kout, int32_t* __restrict__ vout,
                                                       RadixSegments sg) {
     __shared__ uint32_t gbase[256];        // global start of each digit's run of this tile
     __shared__ uint32_t lstart[256];       // start of each digit in the tile's LDS order
-    __shared__ uint32_t wc[kWaves][256];   // per wave: running count, then its base per digit
+    __shared__ uint32_t wc[kSWaves][256];   // per wave: running count, then its base per digit
     __shared__ uint32_t lk[kRadixTile];
     __shared__ int32_t lv[kRadixTile];
     const int t = threadIdx.x;
@@ -269,34 +276,33 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
     const int cnt = g.count;
     // the tile's pairs: loaded first, so that their latency overlaps the
     // digit offsets' loads and scan
-    const int wbase = w * (kI * 64);
-    uint32_t key[kI];
-    int32_t val[kI];
+    const int wbase = w * (kSI * 64);
+    uint32_t key[kSI];
+    int32_t val[kSI];
 #pragma unroll
-    for (int it = 0; it < kI; ++it) {
+    for (int it = 0; it < kSI; ++it) {
         const int i = wbase + it * 64 + lane;
         const bool valid = i < cnt;
         key[it] = valid ? kin[tile0 + i] : 0u;
         val[it] = valid ? (kPositions ? (int32_t)(tile0 + i) : vin[tile0 + i]) : 0;
     }
-    __shared__ uint32_t wsum[kWaves];
+    __shared__ uint32_t wsum[kSWaves];
     {
         // digit t's run starts after the runs of smaller digits (of the
         // tile's segment, which starts at its first key)
         uint32_t all;
-        const uint32_t dpre = block_scan_excl(totals[256 * g.seg + t], wsum, &all);
+        const uint32_t dpre = block_scan_excl<kSWaves>(t < 256 ? totals[256 * g.seg + t] : 0u, wsum, &all);
         const uint32_t seg0 = kSeg ? (uint32_t)sg.segs[g.seg].start : 0u;
-        gbase[t] = seg0 + dpre + offs[g.base + (int64_t)t * g.cols + g.j];
+        if (t < 256) gbase[t] = seg0 + dpre + offs[g.base + (int64_t)t * g.cols + g.j];
     }
-#pragma unroll
-    for (int k = 0; k < kWaves; ++k) wc[k][t] = 0;
+    for (int i = t; i < kSWaves * 256; i += kST) (&wc[0][0])[i] = 0u;
     __syncthreads();
     // lanes below this one, as two 32-bit halves
     const uint32_t ltlo = lane >= 32 ? ~0u : (1u << lane) - 1u;
     const uint32_t lthi = lane <= 32 ? 0u : (1u << (lane - 32)) - 1u;
-    uint32_t rank[kI];
+    uint32_t rank[kSI];
 #pragma unroll
-    for (int it = 0; it < kI; ++it) {
+    for (int it = 0; it < kSI; ++it) {
         const bool valid = wbase + it * 64 + lane < cnt;
         const uint32_t d = (key[it] >> shift) & 255u;
         // the lanes holding the same digit: per bit, the ballot of the lanes
@@ -320,13 +326,13 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
     __syncthreads();
     // digit totals, their exclusive scan (the tile's LDS order), and each
     // wave's base within each digit
-    uint32_t c[kWaves], tot = 0;
+    uint32_t c[kSWaves], tot = 0;
 #pragma unroll
-    for (int k = 0; k < kWaves; ++k) {
-        c[k] = wc[k][t];
+    for (int k = 0; k < kSWaves; ++k) {
+        c[k] = t < 256 ? wc[k][t] : 0u;
         tot += c[k];
     }
-    lstart[t] = tot;
+    if (t < 256) lstart[t] = tot;
     __syncthreads();
     if (w == 0) {
         uint32_t v[4], sum = 0;
@@ -349,10 +355,10 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
         }
     }
     __syncthreads();
-    {
+    if (t < 256) {
         uint32_t base = lstart[t];
 #pragma unroll
-        for (int k = 0; k < kWaves; ++k) {
+        for (int k = 0; k < kSWaves; ++k) {
             wc[k][t] = base;
             base += c[k];
         }
@@ -361,7 +367,7 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
     }
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < kI; ++it) {
+    for (int it = 0; it < kSI; ++it) {
         if (wbase + it * 64 + lane < cnt) {
             const uint32_t d = (key[it] >> shift) & 255u;
             const uint32_t pos = wc[w][d] + rank[it];
@@ -371,7 +377,7 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
     }
     __syncthreads();
     // coalesced write-out: LDS place p of digit d goes to gbase[d] + p
-    for (int p = t; p < cnt; p += kT) {
+    for (int p = t; p < cnt; p += kST) {
         const uint32_t k = lk[p];
         const uint32_t d = (k >> shift) & 255u;
         const uint32_t pos = gbase[d] + (uint32_t)p;
@@ -464,7 +470,7 @@ int radix_sort_pairs(const RadixPlan& p, RadixBuffers& b, int lo_bit, int hi_bit
         const bool first = shift == lo_bit, last = shift + 8 >= hi_bit;
         const bool keys_out = !last || keep_keys;
 #define P2M_SCATTER(P, K, S)                                                                                       \
-    k_radix_scatter<P, K, S><<<(unsigned)p.tiles, kT, 0, st>>>(b.keys[cur], b.vals[cur], p.n, shift, b.counts,      \
+    k_radix_scatter<P, K, S><<<(unsigned)p.tiles, kST, 0, st>>>(b.keys[cur], b.vals[cur], p.n, shift, b.counts,      \
                                                                b.sums, p.tiles, b.keys[cur ^ 1], b.vals[cur ^ 1], sg)
 #define P2M_PASS(S)                                                                                             \
     do {                                                                                                        \
