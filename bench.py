@@ -5,9 +5,11 @@ Workload (the headline configuration): icosphere level 8 (655,362 vertices,
 queries, half uniform in the 1.5x AABB and half near the surface.  One step
 is one pass of the whole query path over the batch with the inputs resident
 in HBM: Morton keys + stable radix sort of the queries, then the query
-kernel (KD-tree nearest vertex, interception-list scan with exact
-point-segment / point-triangle tests, resolved primitive, closest point,
-distance).  The host precompute is timed separately and never counted.
+kernel (nearest vertex by a walk over the Voronoi neighbour graph, the
+interception-list scan with its entry boxes and gated point-line /
+point-plane tests, the winner resolved exactly: primitive, closest point,
+distance), then the write-out of the answers in input order.  The host
+precompute is timed separately and never counted.
 
 The roofline of the query kernel counts the method's algorithmic bytes per
 query (the query and its answer, the nearest-vertex candidates, the list
