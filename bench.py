@@ -491,10 +491,16 @@ def main():
         with ThreadPoolExecutor(max_workers=max(1, len(os.sched_getaffinity(0)))) as ex:
             works = list(ex.map(C.c4_mesh, plan))
         t_gen = time.time() - t0
+        log(f"[bench] batched: {count} meshes generated in {t_gen:.1f}s")
         t0 = time.time()
-        # inspection on the device (the table is the host build's)
-        meshes = P.precompute_many([(x.V, x.F, (x.domain_lo, x.domain_hi)) for x in works], args.cache or None,
-                                   table_mode=P.TABLE_FLOODING_DEVICE)
+        # inspection on the device (the table is the host build's), 32 meshes
+        # at a time with a progress line after each group
+        meshes = []
+        for k0 in range(0, count, 32):
+            part = works[k0:k0 + 32]
+            meshes += P.precompute_many([(x.V, x.F, (x.domain_lo, x.domain_hi)) for x in part], args.cache or None,
+                                        table_mode=P.TABLE_FLOODING_DEVICE)
+            log(f"[bench] batched: {len(meshes)} of {count} meshes precomputed ({time.time() - t0:.1f}s)")
         t_pre4 = time.time() - t0
         Qb = np.concatenate([x.Q for x in works])
         offb = np.concatenate([[0], np.cumsum([len(x.Q) for x in works])]).astype(np.int64)
