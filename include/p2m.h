@@ -120,9 +120,12 @@ typedef struct {
 } p2m_build_stats;
 
 typedef struct {
-    int sort_queries;   /* <0 default (on), 0 off, 1 Morton-order the batch:
-                           a stable sort by the top 24 bits of the key of
-                           p2m_order_queries (8 per axis: a 256^3 grid on D) */
+    int sort_queries;   /* <0 default (on for n >= 2^19 queries, off
+                           below, where the ordering costs more than the
+                           coherence it brings saves), 0 off, 1 Morton-order
+                           the batch: a stable sort by the top 24 bits of
+                           the key of p2m_order_queries (8 per axis: a
+                           256^3 grid on D).  Answers do not depend on it. */
     int block_size;     /* 0 default (256); else 64, 128, 192 or 256 */
     int profile;        /* nonzero: record HIP events around the ordering and
                            query kernels (read with p2m_query_profile) */

@@ -213,12 +213,13 @@ class Mesh:
         self.device = int(device)
         return nbytes.value
 
-    def query(self, q, sort: bool = True, block_size: int = 0, out: dict | None = None, status: bool = True,
+    def query(self, q, sort: bool | None = None, block_size: int = 0, out: dict | None = None, status: bool = True,
               for_backward: bool = False, profile: bool = False, traversal: int = 0, stream=None,
               noalloc: bool = False, lds_levels: int = 0) -> dict:
         """P2M query of a CUDA float32 [n,3] tensor; returns device tensors.
-        noalloc: call p2m_query_noalloc (the library allocates nothing; pass
-        `out` to allocate nothing here either)."""
+        sort: Morton-order the batch first (None: the library's default, on
+        from 2^19 queries).  noalloc: call p2m_query_noalloc (the library
+        allocates nothing; pass `out` to allocate nothing here either)."""
         torch = _torch()
         q = _dev_tensor(q, torch.float32, (3,), "q")
         n = q.shape[0]
@@ -233,7 +234,7 @@ class Mesh:
                 out["bary"] = torch.empty((n, 3), dtype=torch.float32, device=dev)
                 out["pvid"] = torch.empty((n, 3), dtype=torch.int32, device=dev)
         o = QueryOpts()
-        o.sort_queries = 1 if sort else 0
+        o.sort_queries = -1 if sort is None else (1 if sort else 0)
         o.block_size = int(block_size)
         o.profile = 1 if profile else 0
         o.traversal = int(traversal)

@@ -916,6 +916,13 @@ __global__ __launch_bounds__(256) void k_backward(const float* __restrict__ q, i
 // grid over D): three sort passes instead of four; within a grid cell the
 // input order is kept.
 constexpr int kQuerySortLoBit = 6;
+// The default orders a batch of at least this many queries.  Smaller
+// batches put too few queries in each Voronoi cell for the ordering to make
+// neighbouring lanes share cells and lists, and its launches cost more than
+// the coherence saves (on the sphere, heightfield and near-surface
+// workloads the unordered query is faster up to 2^18 queries and slower
+// from 2^19).
+constexpr int64_t kOrderMinQueries = int64_t(1) << 19;
 // Tree levels the per-lane search may read from LDS (511 nodes, 32 KB).
 constexpr int kMaxLdsLevels = 9;
 
@@ -1138,7 +1145,7 @@ static p2m_status run_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* pr
     if (!q || !prim || !closest || !dist) return fail(P2M_ERR_ARG, "NULL query or output pointer");
     if ((bary == nullptr) != (pvid == nullptr)) return fail(P2M_ERR_ARG, "bary and pvid must both be set or both NULL");
     if (n > (int64_t)INT32_MAX) return fail(P2M_ERR_ARG, "more than 2^31-1 queries in one call");
-    int sort = 1, block = 256, profile = 0, traversal = 0, lds_levels = 0;
+    int sort = n >= kOrderMinQueries ? 1 : 0, block = 256, profile = 0, traversal = 0, lds_levels = 0;
     if (opts) {
         profile = opts->profile;
         traversal = opts->traversal;

@@ -49,7 +49,7 @@ def test_c1_all_queries(c1):
     """Workload C1: icosphere level 4, all 10^4 queries, sorted launch."""
     w, m, om, ans = c1
     print("case: c1 sorted", flush=True)
-    out = _run(m, w.Q)
+    out = _run(m, w.Q, sort=True)
     assert check_answers(om, w.Q, ans, out["prim"], out["closest"], out["dist"]) == []
     assert np.all(out["status"] == 0)
 
@@ -58,7 +58,8 @@ def test_c1_unsorted_and_block_sizes_identical(c1):
     """Ordering and launch shape change which lane runs a query, never its answer."""
     w, m, om, ans = c1
     ref = _run(m, w.Q)
-    for kw in ({"sort": False}, {"block_size": 64}, {"block_size": 128, "sort": False}, {"traversal": 1},
+    for kw in ({"sort": True}, {"sort": False}, {"block_size": 64}, {"block_size": 64, "sort": True},
+               {"block_size": 128, "sort": False}, {"traversal": 1},
                {"traversal": 1, "lds_levels": 4}, {"traversal": 1, "lds_levels": 9, "block_size": 64},
                {"traversal": 1, "lds_levels": 8, "sort": False},
                {"traversal": 2}, {"traversal": 2, "sort": False}, {"traversal": 3},
@@ -67,6 +68,26 @@ def test_c1_unsorted_and_block_sizes_identical(c1):
         out = _run(m, w.Q, **kw)
         for k in ("prim", "closest", "dist"):
             assert np.array_equal(out[k], ref[k]), (kw, k)
+
+
+def test_default_ordering_by_batch_size(c1):
+    """The default orders a batch from 2^19 queries on and leaves smaller
+    ones in input order; the profile's ordering time is zero exactly when no
+    ordering ran, and the answers are those of an explicit choice."""
+    torch = _torch()
+    w, m, om, ans = c1
+    rng = np.random.default_rng(5)
+    for n in (1000, (1 << 19) - 1, 1 << 19):
+        print("case: default ordering n =", n, flush=True)
+        Q = w.Q[rng.integers(0, len(w.Q), n)]
+        q = torch.from_numpy(np.ascontiguousarray(Q, dtype=np.float32)).cuda()
+        out = m.query(q, profile=True)
+        order_ms, query_ms, finish_ms = m.query_profile()
+        ordered = n >= (1 << 19)
+        assert (order_ms > 0) == ordered and (finish_ms > 0) == ordered and query_ms > 0, (n, order_ms, finish_ms)
+        ref = m.query(q, sort=ordered)
+        for k in ("prim", "closest", "dist", "status"):
+            assert torch.equal(out[k], ref[k]), (n, k)
 
 
 def test_c1_matches_host_model(c1):
