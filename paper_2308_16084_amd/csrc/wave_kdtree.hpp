@@ -85,9 +85,10 @@ __device__ __forceinline__ Nearest kdt_nearest_wave(const KdNode* __restrict__ n
             const int32_t cf = 2 * cur + (right_near ? 1 : 2);
             next = parent;
             if (prev == cn) {  // back from the near child: is the far one still owed?
+                // (the far child is the left one exactly when the near one is the right)
                 const KdNode nd = node[cur];
                 const bool wf = active && cf < n &&
-                                child_box_d2(qx, qy, qz, nd, !right_near) <= b.d2 * kTieHi;
+                                child_box_d2(qx, qy, qz, nd, right_near) <= b.d2 * kTieHi;
                 if (__ballot(wf)) next = cf;
             }
             depth += next == parent ? -1 : 1;

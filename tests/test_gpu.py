@@ -278,3 +278,34 @@ def test_c2_full_size_sampled(c2_full):
         assert np.max(np.abs(out1["dist"] - out2["dist"])) <= 1e-5 * 3.8, t
     assert np.all(np.isfinite(out["dist"])) and np.all(out["dist"] >= 0)
     assert np.all(out["status"] == 0)
+
+
+def test_c2_traversals_same_vertex(c2_full):
+    """All 10^7 C2 queries in the query kernel's order (stable by the top 24
+    Morton bits): the per-lane tree search, the wavefront tree walk and the
+    Voronoi walk return the same nearest vertex for every query.  The batch
+    holds the wavefront whose lanes 23 and 41 (input rows 1,314,140 and
+    6,265,676) the wavefront tree walk once answered with their
+    second-nearest vertex: returning from a node's near child it tested the
+    near child's box where the far child's was meant, and a lane whose near
+    box sat at its bound by one rounding let the far child go for all."""
+    torch = _torch()
+    w, m = c2_full
+    k = OM.morton_keys(w.Q, w.domain_lo, w.domain_hi) >> 6
+    perm = np.argsort(k, kind="stable")
+    q = torch.from_numpy(np.ascontiguousarray(w.Q[perm])).cuda()
+    vids = {}
+    for t in (1, 2, 3):
+        print("case: c2 nearest vertex, traversal", t, flush=True)
+        vid, _ = m.nearest_vertex(q, traversal=t)
+        torch.cuda.synchronize()
+        vids[t] = vid.cpu().numpy()
+    for t in (2, 3):
+        diff = np.nonzero(vids[1] != vids[t])[0]
+        assert len(diff) == 0, (t, len(diff), perm[diff[:5]].tolist())
+    pos = np.empty(len(perm), np.int64)
+    pos[perm] = np.arange(len(perm))
+    V = w.V.astype(np.float64)
+    for r in (1_314_140, 6_265_676):
+        D = ((V - w.Q[r].astype(np.float64)) ** 2).sum(1)
+        assert vids[2][pos[r]] == int(np.argmin(D)), r
