@@ -187,3 +187,43 @@ def test_batch_status_flags(batch_setup):
         m.upload(0)
         o = _np(m.query(q2[r0:r0 + 2].contiguous()))
         assert o["status"].tolist() == out["status"][r0:r0 + 2].tolist()
+
+
+def test_batch_outside_domain_nearest_vertex(batch_setup):
+    """Queries in a box twice each mesh's domain (seven in eight outside D,
+    where the walk hands over to the wavefront tree walk): the batched launch
+    flags and answers them as a plain launch does (primitives equal up to
+    0.1 %, as inside D), the plain launch's three traversals agree bit for
+    bit, and the wavefront tree walk's vertex is the brute-force nearest one
+    (outside D the answer itself is only an upper bound)."""
+    import torch
+    works, meshes, b, Q, off, q = batch_setup
+    rng = np.random.default_rng(21)
+    parts = []
+    for w in works:
+        ext = w.domain_hi - w.domain_lo
+        parts.append(rng.uniform(w.domain_lo - 0.5 * ext, w.domain_hi + 0.5 * ext,
+                                 size=(len(w.Q), 3)).astype(np.float32))
+    Q2 = np.concatenate(parts)
+    q2 = torch.from_numpy(Q2).cuda()
+    out = _np(b.query(q2, off))
+    for k, (w, m) in enumerate(zip(works, meshes)):
+        if len(w.Q) == 0:
+            continue
+        print(f"case: batch mesh {k} outside-domain queries", flush=True)
+        sl = slice(off[k], off[k + 1])
+        m.upload(0)
+        qk = q2[sl].contiguous()
+        ref = _np(m.query(qk))
+        for t in (1, 2):
+            o = _np(m.query(qk, traversal=t))
+            for key in ref:
+                assert np.array_equal(o[key], ref[key]), (k, t, key)
+        assert np.array_equal(out["status"][sl], ref["status"])
+        assert np.mean(out["prim"][sl] == ref["prim"]) > 0.999
+        vid, _ = m.nearest_vertex(qk, traversal=2)
+        idx = rng.choice(len(w.Q), size=min(500, len(w.Q)), replace=False)
+        vid = vid.cpu().numpy()[idx]
+        D = ((Q2[sl][idx].astype(np.float64)[:, None, :] - w.V.astype(np.float64)[None]) ** 2).sum(-1)
+        assert np.all(D[np.arange(len(vid)), vid] <= D.min(1) * (1 + 1e-12)), k
+    assert np.any(out["status"] == 0) and np.any(out["status"] != 0)

@@ -53,6 +53,25 @@ def test_c3_full_size_sampled(c3_mesh):
     print(f"c3: worst |d - d*| = {err.max():.3f} tol", flush=True)
 
 
+def test_c3_traversals_and_ordering_identical(c3_mesh):
+    """Which traversal finds the nearest vertex, and whether the batch is
+    ordered, never changes an answer: 10^6 of the C3 queries and 10^6 seeded
+    points in a box twice D's size (seven in eight of them outside D, where every
+    traversal ends in the wavefront tree walk), bit for bit."""
+    import torch
+    w, m = c3_mesh
+    ext = w.domain_hi - w.domain_lo
+    Qo = np.random.default_rng(9).uniform(w.domain_lo - 0.5 * ext, w.domain_hi + 0.5 * ext, size=(1_000_000, 3))
+    for name, Q in (("c3 queries", w.Q[:1_000_000]), ("c3 wide box", Qo)):
+        q = torch.from_numpy(np.ascontiguousarray(Q, dtype=np.float32)).cuda()
+        ref = _np(m.query(q))
+        for kw in ({"traversal": 1}, {"traversal": 2}, {"sort": False}, {"sort": True}):
+            print("case:", name, kw, flush=True)
+            out = _np(m.query(q, **kw))
+            for k in ref:
+                assert np.array_equal(out[k], ref[k]), (name, kw, k)
+
+
 def test_c3_backward_large_mesh(c3_mesh):
     """Backward on the 1,048,576-vertex heightfield (10^6 of its queries,
     loss = sum d^2): at this size every 1,024-vertex bucket of the vertex
