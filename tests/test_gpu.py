@@ -144,9 +144,11 @@ def test_golden_points_on_device():
                 assert np.allclose(out["closest"][i], c, atol=1e-6), (name, q, out["closest"][i], c)
 
 
-@pytest.mark.parametrize("n", [1, 2, 255, 4096, 4097, 70001, 1 << 20])
+@pytest.mark.parametrize("n", [1, 2, 255, 4096, 4097, 70001, 1 << 20, (1 << 24) + 4097])
 def test_order_bit_exact(c1, n):
-    """Morton keys and their stable sort equal the definition exactly."""
+    """Morton keys and their stable sort equal the definition exactly (the
+    largest size has more than 16 count tiles per column-scan thread, the
+    column scan's looped form)."""
     torch = _torch()
     w, m, _, _ = c1
     rng = np.random.default_rng(n)
