@@ -214,6 +214,11 @@ def test_edge_cases(c1):
     assert out["dist"].shape == (0,)
     Q = np.array([[0.1, 0.2, 0.3], [np.nan, 0, 0], [0, np.inf, 0], [30.0, 0, 0]], np.float32)
     out = _run(m, Q)
+    # the ordered path (keys, sort, staged answers, write-out) on a tiny batch: same answers
+    for n in (0, 1, 4):
+        o = _run(m, Q[:n], sort=True)
+        for k in out:
+            assert np.array_equal(o[k], out[k][:n], equal_nan=o[k].dtype.kind == "f"), (n, k)
     assert out["status"].tolist() == [0, P.NONFINITE, P.NONFINITE, P.OUT_OF_DOMAIN]
     assert np.isnan(out["dist"][1]) and np.isnan(out["dist"][2])
     assert P.prim_type(out["prim"][1]) == P.NONE
