@@ -320,6 +320,17 @@ void p2m_batch_destroy(p2m_batch* b);
 p2m_status p2m_batch_query(p2m_batch* b, const float* q_dev, const int64_t* q_offsets_host, int32_t* prim_dev,
                            float* closest_dev, float* dist_dev, uint8_t* status_dev, void* stream);
 
+/* The batched query's ordering on its own (the ordering step of
+ * p2m_batch_query, not in the paper): each query's key -- the top 24 bits of
+ * the 30-bit Morton code of p2m_order_queries, taken in its own mesh's
+ * domain -- and a stable sort of each mesh's rows by key, in place (mesh k's
+ * rows stay at q_offsets_host[k] .. q_offsets_host[k+1]).  keys_dev uint32
+ * [N] receives the sorted keys, perm_dev int32 [N] the input row of each
+ * sorted position.  q_dev and q_offsets_host as for p2m_batch_query; calls
+ * on one batch must not overlap. */
+p2m_status p2m_batch_order_queries(p2m_batch* b, const float* q_dev, const int64_t* q_offsets_host, uint32_t* keys_dev,
+                                   int32_t* perm_dev, void* stream);
+
 /* The same work enqueued directly on `stream` (no graph). */
 p2m_status p2m_batch_query_eager(p2m_batch* b, const float* q_dev, const int64_t* q_offsets_host, int32_t* prim_dev,
                                  float* closest_dev, float* dist_dev, uint8_t* status_dev, void* stream);

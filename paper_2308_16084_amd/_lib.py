@@ -72,6 +72,7 @@ _SIGS = {
     "p2m_batch_destroy": (None, [P]),
     "p2m_batch_query": (INT, [P, P, P, P, P, P, P, P]),
     "p2m_batch_query_eager": (INT, [P, P, P, P, P, P, P, P]),
+    "p2m_batch_order_queries": (INT, [P, P, P, P, P, P]),
     "p2m_batch_set_shape": (INT, [P, INT, INT, INT]),
     "p2m_batch_get_shape": (INT, [P, P, P, P]),
     "p2m_batch_set_lds_levels": (INT, [P, INT]),

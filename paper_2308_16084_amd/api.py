@@ -345,6 +345,20 @@ class Batch:
                  _ptr(out.get("status")), _stream(stream)))
         return out
 
+    def order_queries(self, q, q_offsets, stream=None):
+        """The batched query's ordering: (sorted keys uint32 viewed as int32,
+        perm int32) of the stable per-mesh sort by 24-bit Morton key."""
+        torch = _torch()
+        q = _dev_tensor(q, torch.float32, (3,), "q")
+        off = self._offsets(q_offsets)
+        if off.shape[0] != len(self.meshes) + 1 or off[-1] != q.shape[0]:
+            raise ValueError("q_offsets must have len(meshes)+1 entries ending at len(q)")
+        n = q.shape[0]
+        keys = torch.empty(n, dtype=torch.int32, device=q.device)
+        perm = torch.empty(n, dtype=torch.int32, device=q.device)
+        check(lib().p2m_batch_order_queries(self._h, _ptr(q), _ptr(off), _ptr(keys), _ptr(perm), _stream(stream)))
+        return keys, perm
+
     def set_shape(self, block: int, queries_per_lane: int, traversal: int) -> None:
         check(lib().p2m_batch_set_shape(self._h, int(block), int(queries_per_lane), int(traversal)))
 

@@ -802,6 +802,31 @@ p2m_status p2m_batch_query(p2m_batch* b, const float* q, const int64_t* qoff, in
     return P2M_OK;
 }
 
+p2m_status p2m_batch_order_queries(p2m_batch* b, const float* q, const int64_t* qoff, uint32_t* keys_out,
+                                   int32_t* perm_out, void* stream) {
+    if (!b) return fail(P2M_ERR_ARG, "batch is NULL");
+    if (!qoff) return fail(P2M_ERR_ARG, "q_offsets is NULL");
+    Guard g(b->device);
+    hipStream_t st = (hipStream_t)stream;
+    p2m_status r = prepare(b, qoff, st);
+    if (r != P2M_OK) return r;
+    const int64_t n = b->n;
+    if (n == 0) return P2M_OK;
+    if (!q || !keys_out || !perm_out) return fail(P2M_ERR_ARG, "NULL query or output pointer");
+    RadixPlan plan = radix_plan_segmented(n, b->sort_seg.ntiles, b->sort_seg.nseg);
+    RadixBuffers rb = radix_buffers(plan, b->scratch);
+    k_batch_keys<<<(unsigned)b->sort_seg.ntiles, kRadixHistThreads, 0, st>>>(q, b->desc, b->sort_seg, rb.keys[0],
+                                                                          rb.counts);
+    const int cur = radix_sort_pairs(plan, rb, 0, 24, true, st, &b->sort_seg, true);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(keys_out, rb.keys[cur], sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(perm_out, rb.vals[cur], sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "batch ordering");
+    return P2M_OK;
+}
+
 p2m_status p2m_batch_query_eager(p2m_batch* b, const float* q, const int64_t* qoff, int32_t* prim, float* closest,
                                  float* dist, uint8_t* status, void* stream) {
     if (!b) return fail(P2M_ERR_ARG, "batch is NULL");

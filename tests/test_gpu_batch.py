@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import morton as OM
 from synth import configs as C
 from tests._accept import check_answers
 
@@ -227,3 +228,25 @@ def test_batch_outside_domain_nearest_vertex(batch_setup):
         D = ((Q2[sl][idx].astype(np.float64)[:, None, :] - w.V.astype(np.float64)[None]) ** 2).sum(-1)
         assert np.all(D[np.arange(len(vid)), vid] <= D.min(1) * (1 + 1e-12)), k
     assert np.any(out["status"] == 0) and np.any(out["status"] != 0)
+
+
+def test_batch_order_bit_exact(batch_setup):
+    """The batched query's ordering equals its definition: per mesh, the top
+    24 bits of the Morton key in the mesh's own domain and a stable sort of
+    the mesh's rows, in place (an empty mesh included); also with runs of
+    equal keys and a non-finite query."""
+    import torch
+    works, meshes, b, Q, off, q = batch_setup
+    Q2 = Q.copy()
+    k1 = 1
+    Q2[off[k1]:off[k1] + 40] = Q2[off[k1]]      # a run of equal keys
+    Q2[off[k1] + 50] = np.nan                    # non-finite: cell 0
+    for Qx in (Q, Q2):
+        keys, perm = b.order_queries(torch.from_numpy(Qx).cuda(), off)
+        torch.cuda.synchronize()
+        keys, perm = keys.cpu().numpy().view(np.uint32), perm.cpu().numpy()
+        for k, w in enumerate(works):
+            rk = OM.morton_keys(Qx[off[k]:off[k + 1]], w.domain_lo, w.domain_hi) >> 6
+            rp = np.argsort(rk, kind="stable")
+            assert np.array_equal(keys[off[k]:off[k + 1]], rk[rp]), k
+            assert np.array_equal(perm[off[k]:off[k + 1]], rp + off[k]), k

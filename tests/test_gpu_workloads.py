@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import morton as OM
 from oracle import grad as OG
 from synth import configs as C
 from tests._accept import check_answers
@@ -138,6 +139,17 @@ def test_c4_batched_sampled():
         fails = check_answers(om, x.Q[idx], om.query(x.Q[idx]), out["prim"][rows], out["closest"][rows],
                               out["dist"][rows], idx=rows)
         assert fails == [], (k, x.name, fails)
+    # the batch's ordering (37.9 M queries, segments of up to a few hundred
+    # sort tiles) against its definition, bit for bit
+    print("case: c4 ordering", flush=True)
+    keys, perm = b.order_queries(qd, off)
+    torch.cuda.synchronize()
+    keys, perm = keys.cpu().numpy().view(np.uint32), perm.cpu().numpy()
+    for k, x in enumerate(works):
+        rk = OM.morton_keys(x.Q, x.domain_lo, x.domain_hi) >> 6
+        rp = np.argsort(rk, kind="stable")
+        assert np.array_equal(keys[off[k]:off[k + 1]], rk[rp]), k
+        assert np.array_equal(perm[off[k]:off[k + 1]], rp + off[k]), k
     # the persistent schedule at the same shape: the same answers, bit for bit
     print("case: c4 persistent schedule", flush=True)
     try:
