@@ -110,3 +110,26 @@ def margin_points(V, F, E, diag, mu, rng, n=1000):
     kv = rng.integers(0, len(Vd), n)
     pts.append(Vd[kv] + dirs * rng.uniform(0, 5e-5 * diag, (n, 1)))
     return np.concatenate(pts).astype(np.float32)
+
+
+def odd_meshes(rng: np.random.Generator):
+    """Inputs far from a clean surface mesh: a soup of 200 disconnected,
+    intersecting triangles; a fan of 64 triangles round one vertex; 150
+    slivers (third corner near the opposite side); 300 triangles drawn at
+    random over 120 shared vertices (non-manifold, long lists)."""
+    def soup(nf):
+        return rng.uniform(0, 1, size=(3 * nf, 3)).astype(np.float32), np.arange(3 * nf, dtype=np.int32).reshape(nf, 3)
+
+    out = [("soup200",) + soup(200)]
+    a = np.linspace(0, 2 * np.pi, 64, endpoint=False)
+    ring = np.stack([np.cos(a), np.sin(a), 0.05 * rng.standard_normal(64)], 1)
+    out.append(("fan64", np.vstack([[0.0, 0.0, 0.0], ring]).astype(np.float32),
+                np.array([[0, 1 + i, 1 + (i + 1) % 64] for i in range(64)], np.int32)))
+    V, F = soup(150)
+    V = V.reshape(150, 3, 3)
+    V[:, 2] = V[:, 0] + (V[:, 1] - V[:, 0]) * rng.uniform(0.2, 0.8, (150, 1)) + 1e-3 * rng.standard_normal((150, 3))
+    out.append(("slivers150", V.reshape(-1, 3).astype(np.float32), F))
+    V = rng.uniform(0, 1, size=(120, 3)).astype(np.float32)
+    F = np.array([rng.choice(120, 3, replace=False) for _ in range(300)], np.int32)
+    out.append(("shared300", V, F))
+    return out

@@ -119,6 +119,38 @@ def test_tiny_meshes(mode):
             assert check_answers(om, Q, ans, out["prim"], out["closest"], out["dist"]) == [], kw
 
 
+def test_odd_meshes_on_device():
+    """Triangle soups, a high-valence fan, slivers and a non-manifold set
+    with lists of 500 entries: every answer against the oracle, the
+    traversals and the ordering change no answer, and the inspection on the
+    device builds the host's table."""
+    from tests._helpers import odd_meshes
+    rng = np.random.default_rng(7)
+    for name, V, F in odd_meshes(rng):
+        lo, hi = SQ.aabb(V)
+        dom = SQ.scaled_box(lo, hi, 1.5)
+        print(f"case: odd mesh {name}", flush=True)
+        m = _build(V, F, dom)
+        tri = V.astype(np.float64)[F]
+        b = rng.dirichlet([1, 1, 1], 1000)
+        near = (tri[rng.integers(0, len(F), 1000)] * b[:, :, None]).sum(1) + 1e-3 * rng.standard_normal((1000, 3))
+        Q = np.concatenate([rng.uniform(dom[0], dom[1], size=(3000, 3)), near]).astype(np.float32)
+        om = oracle.OracleMesh(V, F)
+        ans = om.query(Q)
+        ref = _run(m, Q)
+        assert check_answers(om, Q, ans, ref["prim"], ref["closest"], ref["dist"]) == [], name
+        for kw in ({"traversal": 1}, {"traversal": 2}, {"sort": True}):
+            out = _run(m, Q, **kw)
+            for k in ref:
+                assert np.array_equal(out[k], ref[k]), (name, kw, k)
+        # the inspection on the device builds the host's table, entry for entry
+        import paper_2308_16084_amd as P
+        md = P.Mesh(V, F)
+        md.precompute(domain=dom, table_mode=P.TABLE_FLOODING_DEVICE)
+        assert all(np.array_equal(a, c) for a, c in zip(md.table(), m.table())), name
+        assert np.array_equal(md.table_boxes(), m.table_boxes()), name
+
+
 def test_golden_points_on_device():
     from tests._helpers import load_golden, primitive_vertices
     for V, F, name in ((TETRA_V, TETRA_F, "tetra.txt"), (CUBE_V, CUBE_F, "cube.txt")):

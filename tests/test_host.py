@@ -493,3 +493,28 @@ def test_list_statistics():
         se = x.std() / np.sqrt(len(x))
         assert abs(st[key] - x.mean()) <= 4 * se + 0.01, (key, st[key], x.mean(), se)
     assert st["flood_visits"] == st["flood_tests"] + 2 * st["ne"] + 3 * st["nf"]
+
+
+def test_host_odd_meshes():
+    """Triangle soups, a high-valence fan, slivers and a non-manifold set
+    (tests/_helpers.odd_meshes) through the host model, every answer against
+    the oracle; flooding (Algorithm 1) gives the table that testing every
+    vertex-primitive pair gives (Theorem 7), on these inputs too."""
+    from tests._helpers import odd_meshes
+    rng = np.random.default_rng(7)
+    for name, V, F in odd_meshes(rng):
+        lo, hi = SQ.aabb(V)
+        dom = SQ.scaled_box(lo, hi, 1.5)
+        m, _, _ = _mesh(V, F, domain=dom)
+        Q = rng.uniform(dom[0], dom[1], size=(2000, 3)).astype(np.float32)
+        om = oracle.OracleMesh(V, F)
+        out = m.query_host(Q)
+        assert check_answers(om, Q, om.query(Q), out["prim"], out["closest"], out["dist"]) == [], name
+        m2, _, _ = _mesh(V, F, domain=dom, mode=P.TABLE_ALL_PAIRS)
+        o1, e1 = m.table()
+        o2, e2 = m2.table()
+        for v in range(len(V)):
+            for r in (0, 1):
+                a = set(e1[o1[2 * v + r]:o1[2 * v + r + 1]].tolist())
+                b = set(e2[o2[2 * v + r]:o2[2 * v + r + 1]].tolist())
+                assert a == b, (name, v, r)
