@@ -456,8 +456,8 @@ constexpr size_t top_lds_offset(int block) { return (regroup_lds_bytes(block) + 
 // its input position instead of several partial cache lines in the output
 // arrays, and a write-out kernel then fills those arrays with coalesced
 // stores.  Without the backward extras the record is 16 bytes, (prim,
-// closest): the write-out forms the distance (point_dist) and the status
-// from q itself.  Each record is a write to a random place of the batch,
+// staged point): the write-out forms the closest point and distance
+// (staged_point) and the status from q itself.  Each record is a write to a random place of the batch,
 // and these writes cost about a sixth of the kernel on 10^7 queries; 16
 // bytes cost less than the 32 of (prim, closest), (dist, status).  With
 // the extras: 48 bytes, (prim, closest), (dist, status, w0, w1), (w2, pv0,
@@ -538,15 +538,18 @@ __global__ __launch_bounds__(kQueryMaxBlock) void k_query(MeshView m, const floa
     wave_scan(m, ring, i >= 0 && fin, qx, qy, qz, nv, best, best_kind, best_id, c);
     if (i < 0) return;
     uint8_t st = fin ? domain_status(m, qx, qy, qz) : (uint8_t)2;
-    const Answer a = fin ? finish_answer(m, qx, qy, qz, nv, best, best_kind, best_id, c) : nonfinite_answer();
+    Answer a = fin ? finish_answer(m, qx, qy, qz, nv, best, best_kind, best_id, c) : nonfinite_answer();
+    if (stage && !kWriteExtras) {
+        stage[i] = make_float4(__int_as_float(a.prim), a.sx, a.sy, a.sz);
+        return;
+    }
+    if (fin) report_answer(m, qx, qy, qz, a);
     if (stage) {
         if (kWriteExtras) {
             stage[3 * i] = make_float4(__int_as_float(a.prim), a.cx, a.cy, a.cz);
             stage[3 * i + 1] = make_float4(a.dist, __int_as_float((int)st), a.w[0], a.w[1]);
             stage[3 * i + 2] = make_float4(a.w[2], __int_as_float(a.pv[0]), __int_as_float(a.pv[1]),
                                            __int_as_float(a.pv[2]));
-        } else {
-            stage[i] = make_float4(__int_as_float(a.prim), a.cx, a.cy, a.cz);
         }
         return;
     }
@@ -590,24 +593,28 @@ __global__ __launch_bounds__(256) void k_split(const float4* __restrict__ stage,
     }
 }
 
-// Write-out of 16-byte records (prim, closest) of one mesh's ordered query:
-// the distance |q - c| (point_dist, as the query kernel forms it) and the
-// status (outside the domain box, non-finite) are rebuilt from q, read here
-// in input order.
+// Write-out of 16-byte records (prim, staged point) of one mesh's ordered
+// query: the closest point and distance (staged_point, as the query kernel
+// forms them, with the domain centre ctr) and the status (outside the domain
+// box, non-finite) are rebuilt from q, read here in input order.
 __global__ __launch_bounds__(256) void k_split_compact(const float4* __restrict__ stage, const float* __restrict__ q,
                                                        int64_t n, float lox, float loy, float loz, float hix,
-                                                       float hiy, float hiz, int32_t* __restrict__ prim,
-                                                       float* __restrict__ closest, float* __restrict__ dist,
-                                                       uint8_t* __restrict__ status) {
+                                                       float hiy, float hiz, float ctrx, float ctry, float ctrz,
+                                                       int32_t* __restrict__ prim, float* __restrict__ closest,
+                                                       float* __restrict__ dist, uint8_t* __restrict__ status) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float4 a = stage[i];
     const float qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
-    prim[i] = __float_as_int(a.x);
-    closest[3 * i] = a.y;
-    closest[3 * i + 1] = a.z;
-    closest[3 * i + 2] = a.w;
-    dist[i] = point_dist(qx, qy, qz, a.y, a.z, a.w);
+    const int32_t pr = __float_as_int(a.x);
+    const float ctr[3] = {ctrx, ctry, ctrz};
+    float cx, cy, cz, d;
+    staged_point(pr, a.y, a.z, a.w, qx, qy, qz, ctr, cx, cy, cz, d);
+    prim[i] = pr;
+    closest[3 * i] = cx;
+    closest[3 * i + 1] = cy;
+    closest[3 * i + 2] = cz;
+    dist[i] = d;
     if (status) {
         const bool out = qx < lox || qy < loy || qz < loz || qx > hix || qy > hiy || qz > hiz;
         status[i] = finite3(qx, qy, qz) ? (out ? 1 : 0) : 2;
@@ -1212,8 +1219,9 @@ static p2m_status run_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* pr
             e = launch_split(stage, n, prim, closest, dist, status, bary, pvid, st);
         } else {
             k_split_compact<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(stage, q, n, v.dlo[0], v.dlo[1], v.dlo[2],
-                                                                          v.dhi[0], v.dhi[1], v.dhi[2], prim, closest,
-                                                                          dist, status);
+                                                                          v.dhi[0], v.dhi[1], v.dhi[2], v.ctr[0],
+                                                                          v.ctr[1], v.ctr[2], prim, closest, dist,
+                                                                          status);
             e = hipGetLastError();
         }
         if (e != hipSuccess) r = fail(P2M_ERR_HIP, std::string("answer write-out: ") + hipGetErrorString(e));

@@ -418,6 +418,9 @@ P2M_HD float tri_dist2(float qx, float qy, float qz, const float4& a, const floa
 struct Answer {
     int32_t prim;            // type << 30 | id
     float cx, cy, cz, dist;
+    // the closest point as staged (staged_point): the point itself for a
+    // vertex (or no primitive), else the point less the domain centre ctr
+    float sx, sy, sz;
     float w[3];
     int32_t pv[3];
 };
@@ -430,10 +433,10 @@ struct ScanCounters {
     uint64_t rescans = 0, rescan_exact = 0;               // second scans; exact evaluations in them
 };
 
-// The reported distance: |q - c| for the reported closest point c, each
-// operation rounded on its own (no fused multiply-add), so that every kernel
-// that forms it -- the query kernels and the write-out that rebuilds it
-// from a staged closest point -- gives the same bits.
+// |q - c|, each operation rounded on its own (no fused multiply-add), so
+// that every kernel that forms a reported distance -- the query kernels and
+// the write-outs that rebuild it from a staged answer (staged_point) --
+// gives the same bits.
 P2M_HD float point_dist(float qx, float qy, float qz, float cx, float cy, float cz) {
 #if defined(__clang__)
 #pragma clang fp contract(off)
@@ -443,10 +446,39 @@ P2M_HD float point_dist(float qx, float qy, float qz, float cx, float cy, float 
     return sqrtf((xx + yy) + zz);
 }
 
+// The reported closest point c and distance d of an answer from its staged
+// form s.  A vertex is reported exactly (c = s) and d = |q - c|.  An edge's
+// or face's point is formed relative to the domain centre ctr, where the
+// coordinates are small even for a mesh far from the origin: c = s + ctr
+// (rounded once, as float32 output must be) and d = |(q - ctr) - s|, which
+// keeps the distance to the accuracy of the arithmetic instead of the
+// rounding of c's absolute coordinates.  The query kernels and the
+// write-outs that rebuild c and d from a staged (prim, s) call this one
+// function, so all give the same bits.
+P2M_HD void staged_point(int32_t prim, float sx, float sy, float sz, float qx, float qy, float qz, const float ctr[3],
+                         float& cx, float& cy, float& cz, float& dist) {
+#if defined(__clang__)
+#pragma clang fp contract(off)
+#endif
+    const uint32_t kind = (uint32_t)prim >> 30;
+    if (kind == (uint32_t)KIND_EDGE || kind == (uint32_t)KIND_FACE) {
+        cx = sx + ctr[0];
+        cy = sy + ctr[1];
+        cz = sz + ctr[2];
+        dist = point_dist(qx - ctr[0], qy - ctr[1], qz - ctr[2], sx, sy, sz);
+    } else {
+        cx = sx;
+        cy = sy;
+        cz = sz;
+        dist = point_dist(qx, qy, qz, sx, sy, sz);
+    }
+}
+
 P2M_HD Answer nonfinite_answer() {
     Answer a;
     a.prim = make_prim(KIND_NONE, 0);
     a.cx = a.cy = a.cz = a.dist = NAN;
+    a.sx = a.sy = a.sz = NAN;
     a.w[0] = a.w[1] = a.w[2] = 0.f;
     a.pv[0] = a.pv[1] = a.pv[2] = -1;
     return a;
@@ -535,40 +567,46 @@ P2M_HD float resolve(const MeshView& m, float qx, float qy, float qz, const Near
     a.w[0] = 1.f;
     a.w[1] = a.w[2] = 0.f;
     a.pv[1] = a.pv[2] = -1;
+    // edges and faces are evaluated relative to the domain centre (see
+    // staged_point); a vertex is staged as itself
+    const float ox = m.ctr[0], oy = m.ctr[1], oz = m.ctr[2];
+    auto rel = [&](const float4& p) { return make_float4(p.x - ox, p.y - oy, p.z - oz, p.w); };
+    const float rx = qx - ox, ry = qy - oy, rz = qz - oz;
     if (kind == KIND_VERTEX) {
         a.prim = make_prim(KIND_VERTEX, nv.vid);
-        a.cx = nv.px;
-        a.cy = nv.py;
-        a.cz = nv.pz;
+        a.sx = nv.px;
+        a.sy = nv.py;
+        a.sz = nv.pz;
         a.pv[0] = nv.vid;
     } else if (kind == KIND_EDGE) {
-        const float4 A = m.seg[2 * id], B = m.seg[2 * id + 1];
+        const float4 Ar = rel(m.seg[2 * id]), Br = rel(m.seg[2 * id + 1]);
         float t;
         int r;
-        exact = seg_d2(qx, qy, qz, A, B, t, r);
-        a.cx = A.x + t * (B.x - A.x);
-        a.cy = A.y + t * (B.y - A.y);
-        a.cz = A.z + t * (B.z - A.z);
+        exact = seg_d2(rx, ry, rz, Ar, Br, t, r);
         if (r == 0) {
             a.prim = make_prim(KIND_EDGE, id);
+            a.sx = Ar.x + t * (Br.x - Ar.x);
+            a.sy = Ar.y + t * (Br.y - Ar.y);
+            a.sz = Ar.z + t * (Br.z - Ar.z);
             a.w[0] = 1.f - t;
             a.w[1] = t;
-            a.pv[0] = as_int(A.w);
-            a.pv[1] = as_int(B.w);
+            a.pv[0] = as_int(Ar.w);
+            a.pv[1] = as_int(Br.w);
         } else {
-            const int32_t pid = as_int(r == 1 ? A.w : B.w);
-            a.prim = make_prim(KIND_VERTEX, pid);
-            a.cx = r == 1 ? A.x : B.x;
-            a.cy = r == 1 ? A.y : B.y;
-            a.cz = r == 1 ? A.z : B.z;
-            a.pv[0] = pid;
+            // an end point: reported exactly, read again
+            const float4 P = m.seg[2 * id + (r == 1 ? 0 : 1)];
+            a.prim = make_prim(KIND_VERTEX, as_int(P.w));
+            a.sx = P.x;
+            a.sy = P.y;
+            a.sz = P.z;
+            a.pv[0] = as_int(P.w);
         }
     } else {
-        const float4 A = m.tri[3 * id], B = m.tri[3 * id + 1], C = m.tri[3 * id + 2];
+        const float4 Ar = rel(m.tri[3 * id]), Br = rel(m.tri[3 * id + 1]), Cr = rel(m.tri[3 * id + 2]);
         float w0, w1, w2;
         int r;
-        exact = tri_d2(qx, qy, qz, A, B, C, w0, w1, w2, r, a.cx, a.cy, a.cz);
-        const int32_t ia = as_int(A.w), ib = as_int(B.w), ic = as_int(C.w);
+        exact = tri_d2(rx, ry, rz, Ar, Br, Cr, w0, w1, w2, r, a.sx, a.sy, a.sz);
+        const int32_t ia = as_int(Ar.w), ib = as_int(Br.w), ic = as_int(Cr.w);
         if (r == 0) {
             a.prim = make_prim(KIND_FACE, id);
             a.w[0] = w0;
@@ -585,13 +623,13 @@ P2M_HD float resolve(const MeshView& m, float qx, float qy, float qz, const Near
             a.pv[0] = side == 0 ? ia : (side == 1 ? ib : ic);
             a.pv[1] = side == 0 ? ib : (side == 1 ? ic : ia);
         } else {
-            const int corner = r - 4;
-            const int32_t pid = corner == 0 ? ia : (corner == 1 ? ib : ic);
-            a.prim = make_prim(KIND_VERTEX, pid);
-            a.cx = corner == 0 ? A.x : (corner == 1 ? B.x : C.x);
-            a.cy = corner == 0 ? A.y : (corner == 1 ? B.y : C.y);
-            a.cz = corner == 0 ? A.z : (corner == 1 ? B.z : C.z);
-            a.pv[0] = pid;
+            // a corner: reported exactly, read again
+            const float4 P = m.tri[3 * id + (r - 4)];
+            a.prim = make_prim(KIND_VERTEX, as_int(P.w));
+            a.sx = P.x;
+            a.sy = P.y;
+            a.sz = P.z;
+            a.pv[0] = as_int(P.w);
         }
     }
     return exact;
@@ -749,27 +787,34 @@ P2M_HD Answer finish_answer(const MeshView& m, float qx, float qy, float qz, con
     // a primitive whose exact distance exceeds d(q, v) gives way to v
     if (best_kind != KIND_VERTEX && !(exact <= nv.d2)) {
         a.prim = make_prim(KIND_VERTEX, nv.vid);
-        a.cx = nv.px;
-        a.cy = nv.py;
-        a.cz = nv.pz;
+        a.sx = nv.px;
+        a.sy = nv.py;
+        a.sz = nv.pz;
         a.w[0] = 1.f;
         a.w[1] = a.w[2] = 0.f;
         a.pv[0] = nv.vid;
         a.pv[1] = a.pv[2] = -1;
     }
-    // the exact squared distance decided the answer; the reported distance
-    // is that of the reported closest point (point_dist)
-    a.dist = point_dist(qx, qy, qz, a.cx, a.cy, a.cz);
+    // the exact squared distance decided the answer; the reported point and
+    // distance come from its staged form (report_answer)
     return a;
 }
 
+
+// The reported closest point and distance of an answer from finish_answer
+// (staged_point on its staged form).
+P2M_HD void report_answer(const MeshView& m, float qx, float qy, float qz, Answer& a) {
+    staged_point(a.prim, a.sx, a.sy, a.sz, qx, qy, qz, m.ctr, a.cx, a.cy, a.cz, a.dist);
+}
 
 P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const Nearest& nv, ScanCounters& cnt) {
     float best;
     int best_kind;
     int32_t best_id;
     scan_list(m, qx, qy, qz, nv, best, best_kind, best_id, cnt);
-    return finish_answer(m, qx, qy, qz, nv, best, best_kind, best_id, cnt);
+    Answer a = finish_answer(m, qx, qy, qz, nv, best, best_kind, best_id, cnt);
+    report_answer(m, qx, qy, qz, a);
+    return a;
 }
 
 // The whole query for one point (per-lane KD-tree search).

@@ -250,3 +250,41 @@ def test_batch_order_bit_exact(batch_setup):
             rp = np.argsort(rk, kind="stable")
             assert np.array_equal(keys[off[k]:off[k + 1]], rk[rp]), k
             assert np.array_equal(perm[off[k]:off[k + 1]], rp + off[k]), k
+
+
+def test_far_from_origin_single_and_batched():
+    """C1 moved 10^4 units from the origin: the plain launch, ordered and in
+    input order, and a batch of it with the mesh at its own place, all against
+    the oracle (the write-outs rebuild the distance from the point staged
+    relative to each mesh's domain centre)."""
+    import torch
+
+    import paper_2308_16084_amd as P
+    from synth import queries as SQ
+    w = C.c1(n_queries=4000)
+    works = []
+    for off in (0.0, 1e4):
+        V = (w.V.astype(np.float64) + off).astype(np.float32)
+        Q = (w.Q.astype(np.float64) + off).astype(np.float32)
+        works.append((V, Q))
+    meshes = []
+    for V, Q in works:
+        lo, hi = SQ.aabb(V)
+        m = P.Mesh(V, w.F)
+        m.precompute(domain=SQ.scaled_box(lo, hi, 1.5))
+        meshes.append(m)
+    V, Q = works[1]
+    om = oracle.OracleMesh(V, w.F)
+    ans = om.query(Q)
+    meshes[1].upload(0)
+    q = torch.from_numpy(Q).cuda()
+    for sort in (True, False):
+        print("case: far mesh, sort", sort, flush=True)
+        out = _np(meshes[1].query(q, sort=sort))
+        assert check_answers(om, Q, ans, out["prim"], out["closest"], out["dist"]) == [], sort
+    b = P.Batch(meshes, 0)
+    Qb = np.concatenate([x[1] for x in works])
+    off = np.array([0, len(works[0][1]), len(Qb)], np.int64)
+    out = _np(b.query(torch.from_numpy(Qb).cuda(), off))
+    sl = slice(int(off[1]), int(off[2]))
+    assert check_answers(om, Q, ans, out["prim"][sl], out["closest"][sl], out["dist"][sl]) == []

@@ -518,3 +518,18 @@ def test_host_odd_meshes():
                 a = set(e1[o1[2 * v + r]:o1[2 * v + r + 1]].tolist())
                 b = set(e2[o2[2 * v + r]:o2[2 * v + r + 1]].tolist())
                 assert a == b, (name, v, r)
+
+
+@pytest.mark.parametrize("scale,offset", [(1.0, 1e3), (1.0, 1e4), (1.0, -3e4), (1e-3, 5.0), (1e3, 0.0)])
+def test_host_far_from_origin(scale, offset):
+    """A mesh far from the origin (or tiny, or large): the distance keeps the
+    tolerance because an edge's or face's closest point is formed relative to
+    the domain centre; the reported float32 point carries its own rounding
+    (tests/_accept.py)."""
+    w = C.c1(n_queries=2000)
+    V = (w.V.astype(np.float64) * scale + offset).astype(np.float32)
+    Q = (w.Q.astype(np.float64) * scale + offset).astype(np.float32)
+    m, _, _ = _mesh(V, w.F)
+    om = oracle.OracleMesh(V, w.F)
+    out = m.query_host(Q)
+    assert check_answers(om, Q, om.query(Q), out["prim"], out["closest"], out["dist"]) == []
