@@ -234,10 +234,11 @@ p2m_status p2m_upload(p2m_mesh* m, int device, void* stream, int64_t* bytes);
  * evaluates exactly every candidate that could still be closer, so the
  * answer is the exact minimum over the candidates up to float32 rounding,
  * whatever the gate margin).  Outputs (device): prim int32 [n], closest float [n*3], dist
- * float [n] (|q - closest| in float32, every operation rounded on its own;
- * for an edge or face the point is formed relative to the domain centre
- * and the distance taken there, before the point is rounded to absolute
- * float32 coordinates, so a mesh far from the origin keeps its accuracy);
+ * float [n] (in float32, every operation rounded on its own: |q - closest|
+ * for a vertex; for an edge or face the point is formed relative to the
+ * domain centre and the distance is the length of the vector from q to it,
+ * taken before the point is rounded to absolute float32 coordinates, so a
+ * mesh far from the origin keeps its accuracy);
  * status uint8 [n] (may be NULL).  For the backward pass, bary
  * float [n*3] and pvid int32 [n*3] (both NULL or both set) receive the
  * closest point's barycentric weights over the primitive's vertices (unused

@@ -176,11 +176,10 @@ __global__ __launch_bounds__(kRadixHistThreads) void k_batch_keys(const float* _
 }
 
 // Write-out of the batch's 16-byte records (prim, staged point) in input
-// order: row i belongs to the last mesh whose query range starts at or
-// before it (empty ranges are skipped that way); the closest point and
-// distance (staged_point with that mesh's domain centre, as the query kernel
-// forms them) and the status (outside that mesh's domain box, non-finite)
-// are rebuilt from q.
+// order: the closest point and distance (staged_point, as the query kernel
+// forms them) are rebuilt from q; for the status (outside the domain box,
+// non-finite), row i belongs to the last mesh whose query range starts at
+// or before it (empty ranges are skipped that way).
 __global__ __launch_bounds__(256) void k_batch_split(const float4* __restrict__ stage, const float* __restrict__ q,
                                                      int64_t n, const RadixSegInfo* __restrict__ segs, int32_t nseg,
                                                      const BatchMesh* __restrict__ desc, int32_t* __restrict__ prim,
@@ -190,22 +189,22 @@ __global__ __launch_bounds__(256) void k_batch_split(const float4* __restrict__ 
     if (i >= n) return;
     const float4 a = stage[i];
     const float qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
-    int32_t lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if (segs[mid].start <= i) lo = mid;
-        else hi = mid - 1;
-    }
-    const BatchMesh& d = desc[lo];
     const int32_t pr = __float_as_int(a.x);
     float cx, cy, cz, dd;
-    staged_point(pr, a.y, a.z, a.w, qx, qy, qz, d.ctr, cx, cy, cz, dd);
+    staged_point(pr, a.y, a.z, a.w, qx, qy, qz, cx, cy, cz, dd);
     prim[i] = pr;
     closest[3 * i] = cx;
     closest[3 * i + 1] = cy;
     closest[3 * i + 2] = cz;
     dist[i] = dd;
     if (status) {
+        int32_t lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (segs[mid].start <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchMesh& d = desc[lo];
         const bool out = qx < d.dlo[0] || qy < d.dlo[1] || qz < d.dlo[2] || qx > d.dhi[0] || qy > d.dhi[1] ||
                          qz > d.dhi[2];
         status[i] = finite3(qx, qy, qz) ? (out ? 1 : 0) : 2;

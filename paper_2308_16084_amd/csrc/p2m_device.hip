@@ -595,21 +595,20 @@ __global__ __launch_bounds__(256) void k_split(const float4* __restrict__ stage,
 
 // Write-out of 16-byte records (prim, staged point) of one mesh's ordered
 // query: the closest point and distance (staged_point, as the query kernel
-// forms them, with the domain centre ctr) and the status (outside the domain
-// box, non-finite) are rebuilt from q, read here in input order.
+// forms them) and the status (outside the domain box, non-finite) are
+// rebuilt from q, read here in input order.
 __global__ __launch_bounds__(256) void k_split_compact(const float4* __restrict__ stage, const float* __restrict__ q,
                                                        int64_t n, float lox, float loy, float loz, float hix,
-                                                       float hiy, float hiz, float ctrx, float ctry, float ctrz,
-                                                       int32_t* __restrict__ prim, float* __restrict__ closest,
-                                                       float* __restrict__ dist, uint8_t* __restrict__ status) {
+                                                       float hiy, float hiz, int32_t* __restrict__ prim,
+                                                       float* __restrict__ closest, float* __restrict__ dist,
+                                                       uint8_t* __restrict__ status) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float4 a = stage[i];
     const float qx = q[3 * i], qy = q[3 * i + 1], qz = q[3 * i + 2];
     const int32_t pr = __float_as_int(a.x);
-    const float ctr[3] = {ctrx, ctry, ctrz};
     float cx, cy, cz, d;
-    staged_point(pr, a.y, a.z, a.w, qx, qy, qz, ctr, cx, cy, cz, d);
+    staged_point(pr, a.y, a.z, a.w, qx, qy, qz, cx, cy, cz, d);
     prim[i] = pr;
     closest[3 * i] = cx;
     closest[3 * i + 1] = cy;
@@ -1219,9 +1218,8 @@ static p2m_status run_query(p2m_mesh* mh, const float* q, int64_t n, int32_t* pr
             e = launch_split(stage, n, prim, closest, dist, status, bary, pvid, st);
         } else {
             k_split_compact<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(stage, q, n, v.dlo[0], v.dlo[1], v.dlo[2],
-                                                                          v.dhi[0], v.dhi[1], v.dhi[2], v.ctr[0],
-                                                                          v.ctr[1], v.ctr[2], prim, closest, dist,
-                                                                          status);
+                                                                          v.dhi[0], v.dhi[1], v.dhi[2], prim, closest,
+                                                                          dist, status);
             e = hipGetLastError();
         }
         if (e != hipSuccess) r = fail(P2M_ERR_HIP, std::string("answer write-out: ") + hipGetErrorString(e));

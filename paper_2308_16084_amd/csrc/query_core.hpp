@@ -419,7 +419,7 @@ struct Answer {
     int32_t prim;            // type << 30 | id
     float cx, cy, cz, dist;
     // the closest point as staged (staged_point): the point itself for a
-    // vertex (or no primitive), else the point less the domain centre ctr
+    // vertex (or no primitive), else the vector from q to the point
     float sx, sy, sz;
     float w[3];
     int32_t pv[3];
@@ -448,24 +448,24 @@ P2M_HD float point_dist(float qx, float qy, float qz, float cx, float cy, float 
 
 // The reported closest point c and distance d of an answer from its staged
 // form s.  A vertex is reported exactly (c = s) and d = |q - c|.  An edge's
-// or face's point is formed relative to the domain centre ctr, where the
-// coordinates are small even for a mesh far from the origin: c = s + ctr
-// (rounded once, as float32 output must be) and d = |(q - ctr) - s|, which
-// keeps the distance to the accuracy of the arithmetic instead of the
-// rounding of c's absolute coordinates.  The query kernels and the
-// write-outs that rebuild c and d from a staged (prim, s) call this one
-// function, so all give the same bits.
-P2M_HD void staged_point(int32_t prim, float sx, float sy, float sz, float qx, float qy, float qz, const float ctr[3],
-                         float& cx, float& cy, float& cz, float& dist) {
+// or face's point is formed relative to the domain centre, where the
+// coordinates are small even for a mesh far from the origin, and staged as
+// the vector s from q to it: c = q + s (rounded once, as float32 output must
+// be) and d = |s|, which keeps the distance to the accuracy of the
+// arithmetic instead of the rounding of c's absolute coordinates.  The query
+// kernels and the write-outs that rebuild c and d from a staged (prim, s)
+// call this one function, so all give the same bits.
+P2M_HD void staged_point(int32_t prim, float sx, float sy, float sz, float qx, float qy, float qz, float& cx,
+                         float& cy, float& cz, float& dist) {
 #if defined(__clang__)
 #pragma clang fp contract(off)
 #endif
     const uint32_t kind = (uint32_t)prim >> 30;
     if (kind == (uint32_t)KIND_EDGE || kind == (uint32_t)KIND_FACE) {
-        cx = sx + ctr[0];
-        cy = sy + ctr[1];
-        cz = sz + ctr[2];
-        dist = point_dist(qx - ctr[0], qy - ctr[1], qz - ctr[2], sx, sy, sz);
+        cx = qx + sx;
+        cy = qy + sy;
+        cz = qz + sz;
+        dist = point_dist(sx, sy, sz, 0.f, 0.f, 0.f);
     } else {
         cx = sx;
         cy = sy;
@@ -585,9 +585,9 @@ P2M_HD float resolve(const MeshView& m, float qx, float qy, float qz, const Near
         exact = seg_d2(rx, ry, rz, Ar, Br, t, r);
         if (r == 0) {
             a.prim = make_prim(KIND_EDGE, id);
-            a.sx = Ar.x + t * (Br.x - Ar.x);
-            a.sy = Ar.y + t * (Br.y - Ar.y);
-            a.sz = Ar.z + t * (Br.z - Ar.z);
+            a.sx = (Ar.x + t * (Br.x - Ar.x)) - rx;
+            a.sy = (Ar.y + t * (Br.y - Ar.y)) - ry;
+            a.sz = (Ar.z + t * (Br.z - Ar.z)) - rz;
             a.w[0] = 1.f - t;
             a.w[1] = t;
             a.pv[0] = as_int(Ar.w);
@@ -606,6 +606,9 @@ P2M_HD float resolve(const MeshView& m, float qx, float qy, float qz, const Near
         float w0, w1, w2;
         int r;
         exact = tri_d2(rx, ry, rz, Ar, Br, Cr, w0, w1, w2, r, a.sx, a.sy, a.sz);
+        a.sx -= rx;
+        a.sy -= ry;
+        a.sz -= rz;
         const int32_t ia = as_int(Ar.w), ib = as_int(Br.w), ic = as_int(Cr.w);
         if (r == 0) {
             a.prim = make_prim(KIND_FACE, id);
@@ -804,7 +807,7 @@ P2M_HD Answer finish_answer(const MeshView& m, float qx, float qy, float qz, con
 // The reported closest point and distance of an answer from finish_answer
 // (staged_point on its staged form).
 P2M_HD void report_answer(const MeshView& m, float qx, float qy, float qz, Answer& a) {
-    staged_point(a.prim, a.sx, a.sy, a.sz, qx, qy, qz, m.ctr, a.cx, a.cy, a.cz, a.dist);
+    staged_point(a.prim, a.sx, a.sy, a.sz, qx, qy, qz, a.cx, a.cy, a.cz, a.dist);
 }
 
 P2M_HD Answer p2m_answer(const MeshView& m, float qx, float qy, float qz, const Nearest& nv, ScanCounters& cnt) {
