@@ -151,6 +151,25 @@ def test_odd_meshes_on_device():
         assert np.array_equal(md.table_boxes(), m.table_boxes()), name
 
 
+def test_domains_not_holding_the_mesh_on_device():
+    """The host suite's odd domains (part of the mesh, a thin slab, a box
+    away from it, the mesh's own box) through the device path, ordered and
+    in input order, against the oracle."""
+    from tests.test_host import _odd_domains
+    w = C.c1(n_queries=10)
+    rng = np.random.default_rng(3)
+    om = oracle.OracleMesh(w.V, w.F)
+    for name, dlo, dhi in _odd_domains(w.V):
+        print("case: domain", name, flush=True)
+        m = _build(w.V, w.F, (dlo, dhi))
+        Q = rng.uniform(dlo, dhi, size=(3000, 3)).astype(np.float32)
+        ans = om.query(Q)
+        for sort in (True, False):
+            out = _run(m, Q, sort=sort)
+            assert check_answers(om, Q, ans, out["prim"], out["closest"], out["dist"]) == [], (name, sort)
+            assert np.all(out["status"] == 0), name
+
+
 def test_golden_points_on_device():
     from tests._helpers import load_golden, primitive_vertices
     for V, F, name in ((TETRA_V, TETRA_F, "tetra.txt"), (CUBE_V, CUBE_F, "cube.txt")):

@@ -533,3 +533,25 @@ def test_host_far_from_origin(scale, offset):
     om = oracle.OracleMesh(V, w.F)
     out = m.query_host(Q)
     assert check_answers(om, Q, om.query(Q), out["prim"], out["closest"], out["dist"]) == []
+
+
+def _odd_domains(V):
+    lo, hi = SQ.aabb(V)
+    c, e = 0.5 * (lo + hi), hi - lo
+    return [("inner half", c - 0.25 * e, c + 0.25 * e), ("one octant", c, hi),
+            ("thin slab", np.array([lo[0], lo[1], c[2] - 1e-3]), np.array([hi[0], hi[1], c[2] + 1e-3])),
+            ("far box", hi + 2 * e, hi + 3 * e), ("exact box", lo, hi)]
+
+
+def test_host_domains_not_holding_the_mesh():
+    """Query domains that hold only part of the mesh, a thin slab, a box
+    away from it, the mesh's own box: answers in D stay exact (the cells are
+    clipped to D, the primitives are not)."""
+    w = C.c1(n_queries=10)
+    rng = np.random.default_rng(3)
+    om = oracle.OracleMesh(w.V, w.F)
+    for name, dlo, dhi in _odd_domains(w.V):
+        m, _, _ = _mesh(w.V, w.F, domain=(dlo, dhi))
+        Q = rng.uniform(dlo, dhi, size=(2000, 3)).astype(np.float32)
+        out = m.query_host(Q)
+        assert check_answers(om, Q, om.query(Q), out["prim"], out["closest"], out["dist"]) == [], name
