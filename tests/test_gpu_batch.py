@@ -288,3 +288,52 @@ def test_far_from_origin_single_and_batched():
     out = _np(b.query(torch.from_numpy(Qb).cuda(), off))
     sl = slice(int(off[1]), int(off[2]))
     assert check_answers(om, Q, ans, out["prim"][sl], out["closest"][sl], out["dist"][sl]) == []
+
+
+def test_many_small_meshes():
+    """1,500 small meshes (tetrahedra, cubes, displaced icospheres, each at
+    its own place) with 0 to 60 queries each in one batch: answers against
+    the oracle on a sample of meshes, the batched ordering against its
+    definition, and the status bits as plain launches give them."""
+    import torch
+
+    import paper_2308_16084_amd as P
+    from synth import queries as SQ
+    from tests._helpers import CUBE_F, CUBE_V, TETRA_F, TETRA_V, random_tiny_mesh
+    rng = np.random.default_rng(12)
+    tiny = random_tiny_mesh(rng, "sphere")
+    shapes = [(TETRA_V, TETRA_F), (CUBE_V, CUBE_F), tiny]
+    meshes, works = [], []
+    for k in range(1500):
+        V0, F = shapes[k % 3]
+        V = (V0.astype(np.float64) * rng.uniform(0.5, 2.0) + rng.uniform(-50, 50, 3)).astype(np.float32)
+        lo, hi = SQ.aabb(V)
+        dom = SQ.scaled_box(lo, hi, 2.0)
+        nq = int(rng.integers(0, 61))
+        Q = rng.uniform(dom[0], dom[1], size=(nq, 3)).astype(np.float32)
+        works.append((V, F, Q, dom))
+    print("case: precomputing 1,500 meshes", flush=True)
+    meshes = P.precompute_many([(V, F, dom) for V, F, Q, dom in works], None)
+    b = P.Batch(meshes, 0)
+    Qb = np.concatenate([x[2] for x in works]).astype(np.float32)
+    off = np.concatenate([[0], np.cumsum([len(x[2]) for x in works])]).astype(np.int64)
+    qd = torch.from_numpy(Qb).cuda()
+    out = _np(b.query(qd, off))
+    keys, perm = b.order_queries(qd, off)
+    torch.cuda.synchronize()
+    keys, perm = keys.cpu().numpy().view(np.uint32), perm.cpu().numpy()
+    for k, (V, F, Q, dom) in enumerate(works):
+        sl = slice(int(off[k]), int(off[k + 1]))
+        rk = OM.morton_keys(Q, dom[0], dom[1]) >> 6
+        rp = np.argsort(rk, kind="stable")
+        assert np.array_equal(keys[sl], rk[rp]) and np.array_equal(perm[sl], rp + off[k]), k
+    for k in range(0, 1500, 50):
+        V, F, Q, dom = works[k]
+        if len(Q) == 0:
+            continue
+        sl = slice(int(off[k]), int(off[k + 1]))
+        om = oracle.OracleMesh(V, F)
+        assert check_answers(om, Q, om.query(Q), out["prim"][sl], out["closest"][sl], out["dist"][sl]) == [], k
+        meshes[k].upload(0)
+        o = _np(meshes[k].query(qd[sl].contiguous()))
+        assert np.array_equal(o["status"], out["status"][sl]), k
