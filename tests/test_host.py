@@ -555,3 +555,23 @@ def test_host_domains_not_holding_the_mesh():
         Q = rng.uniform(dlo, dhi, size=(2000, 3)).astype(np.float32)
         out = m.query_host(Q)
         assert check_answers(om, Q, om.query(Q), out["prim"], out["closest"], out["dist"]) == [], name
+
+
+def test_host_domain_1000x():
+    """A domain 1,000 times the mesh's box, queries over all of it (up to
+    hundreds of diagonals from the mesh): answers exact to the float32
+    output (the distance within two float32 spacings of the exact one,
+    tests/_accept.py), and within tol near the mesh."""
+    w = C.c1(n_queries=10)
+    lo, hi = SQ.aabb(w.V)
+    m, _, dom = _mesh(w.V, w.F, scale=1000.0)
+    om = oracle.OracleMesh(w.V, w.F)
+    rng = np.random.default_rng(5)
+    for qs in (1.2, 1000.0):
+        b = SQ.scaled_box(lo, hi, qs)
+        Q = rng.uniform(b[0], b[1], size=(2000, 3)).astype(np.float32)
+        out = m.query_host(Q)
+        ans = om.query(Q)
+        assert check_answers(om, Q, ans, out["prim"], out["closest"], out["dist"]) == [], qs
+        if qs < 2:
+            assert np.max(np.abs(out["dist"].astype(np.float64) - ans["dist"])) <= 1e-5 * om.diag
