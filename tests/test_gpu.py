@@ -170,6 +170,25 @@ def test_domains_not_holding_the_mesh_on_device():
             assert np.all(out["status"] == 0), name
 
 
+def test_domain_1000x_on_device():
+    """D 1,000 times the mesh's box (the walk's second seed grid covers the
+    mesh), queries near the mesh and over all of D, ordered and in input
+    order: exact to the float32 output (tests/_accept.py)."""
+    w = C.c1(n_queries=10)
+    lo, hi = SQ.aabb(w.V)
+    m = _build(w.V, w.F, SQ.scaled_box(lo, hi, 1000.0))
+    om = oracle.OracleMesh(w.V, w.F)
+    rng = np.random.default_rng(5)
+    for qs in (1.2, 30.0, 1000.0):
+        b = SQ.scaled_box(lo, hi, qs)
+        Q = rng.uniform(b[0], b[1], size=(3000, 3)).astype(np.float32)
+        ans = om.query(Q)
+        for sort in (True, False):
+            print("case: D 1000x, queries in", qs, "sort", sort, flush=True)
+            out = _run(m, Q, sort=sort)
+            assert check_answers(om, Q, ans, out["prim"], out["closest"], out["dist"]) == [], (qs, sort)
+
+
 def test_golden_points_on_device():
     from tests._helpers import load_golden, primitive_vertices
     for V, F, name in ((TETRA_V, TETRA_F, "tetra.txt"), (CUBE_V, CUBE_F, "cube.txt")):
