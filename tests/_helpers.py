@@ -133,3 +133,25 @@ def odd_meshes(rng: np.random.Generator):
     F = np.array([rng.choice(120, 3, replace=False) for _ in range(300)], np.int32)
     out.append(("shared300", V, F))
     return out
+
+
+def flat_meshes():
+    """Meshes whose vertices are coplanar (the Delaunay step meets a flat
+    point set): one triangle, two coplanar triangles, planar grids of 8 x 8
+    and 30 x 30 vertices, and a nearly collinear strip."""
+    def grid(n):
+        x, y = np.meshgrid(np.linspace(0, 1, n), np.linspace(0, 1, n))
+        V = np.stack([x.ravel(), y.ravel(), np.zeros(n * n)], 1).astype(np.float32)
+        F = []
+        for i in range(n - 1):
+            for j in range(n - 1):
+                a = i * n + j
+                F += [[a, a + 1, a + n], [a + 1, a + n + 1, a + n]]
+        return V, np.array(F, np.int32)
+
+    return [("one triangle", np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32), np.array([[0, 1, 2]], np.int32)),
+            ("two coplanar", np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]], np.float32),
+             np.array([[0, 1, 2], [1, 3, 2]], np.int32)),
+            ("grid 8",) + grid(8), ("grid 30",) + grid(30),
+            ("strip", np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [0.5, 1e-3, 0], [1.5, 1e-3, 0]], np.float32),
+             np.array([[0, 1, 3], [1, 2, 4]], np.int32))]

@@ -189,6 +189,23 @@ def test_domain_1000x_on_device():
             assert check_answers(om, Q, ans, out["prim"], out["closest"], out["dist"]) == [], (qs, sort)
 
 
+def test_flat_meshes_on_device():
+    """Coplanar vertex sets (tests/_helpers.flat_meshes) through the device
+    path, ordered and in input order, against the oracle."""
+    from tests._helpers import flat_meshes
+    rng = np.random.default_rng(1)
+    for name, V, F in flat_meshes():
+        lo, hi = SQ.aabb(V)
+        print("case: flat mesh", name, flush=True)
+        m = _build(V, F, (lo - 0.5, hi + 0.5))
+        Q = rng.uniform(lo - 0.5, hi + 0.5, size=(2000, 3)).astype(np.float32)
+        om = oracle.OracleMesh(V, F)
+        ans = om.query(Q)
+        for sort in (True, False):
+            out = _run(m, Q, sort=sort)
+            assert check_answers(om, Q, ans, out["prim"], out["closest"], out["dist"]) == [], (name, sort)
+
+
 def test_golden_points_on_device():
     from tests._helpers import load_golden, primitive_vertices
     for V, F, name in ((TETRA_V, TETRA_F, "tetra.txt"), (CUBE_V, CUBE_F, "cube.txt")):

@@ -575,3 +575,20 @@ def test_host_domain_1000x():
         assert check_answers(om, Q, ans, out["prim"], out["closest"], out["dist"]) == [], qs
         if qs < 2:
             assert np.max(np.abs(out["dist"].astype(np.float64) - ans["dist"])) <= 1e-5 * om.diag
+
+
+def test_host_flat_meshes():
+    """Coplanar vertex sets (tests/_helpers.flat_meshes) with a padded domain
+    and with the default one: every answer against the oracle."""
+    from tests._helpers import flat_meshes
+    rng = np.random.default_rng(1)
+    for name, V, F in flat_meshes():
+        lo, hi = SQ.aabb(V)
+        for dom in ((lo - 0.5, hi + 0.5), None):
+            m = P.Mesh(V, F)
+            m.precompute(domain=dom)
+            qlo, qhi = (lo - 0.5, hi + 0.5)
+            Q = rng.uniform(qlo, qhi, size=(1500, 3)).astype(np.float32)
+            om = oracle.OracleMesh(V, F)
+            out = m.query_host(Q)
+            assert check_answers(om, Q, om.query(Q), out["prim"], out["closest"], out["dist"]) == [], (name, dom)
