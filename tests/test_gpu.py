@@ -204,6 +204,27 @@ def test_flat_meshes_on_device():
         for sort in (True, False):
             out = _run(m, Q, sort=sort)
             assert check_answers(om, Q, ans, out["prim"], out["closest"], out["dist"]) == [], (name, sort)
+        # the inspection on the device builds the host's table here too
+        import paper_2308_16084_amd as P
+        md = P.Mesh(V, F)
+        md.precompute(domain=(lo - 0.5, hi + 0.5), table_mode=P.TABLE_FLOODING_DEVICE)
+        assert all(np.array_equal(a, c) for a, c in zip(md.table(), m.table())), name
+
+
+def test_far_mesh_device_table():
+    """C1 moved 10^4 units from the origin: the inspection on the device
+    builds the host's table, entry for entry."""
+    import paper_2308_16084_amd as P
+    w = C.c1(n_queries=10)
+    V = (w.V.astype(np.float64) + 1e4).astype(np.float32)
+    lo, hi = SQ.aabb(V)
+    dom = SQ.scaled_box(lo, hi, 1.5)
+    h = P.Mesh(V, w.F)
+    h.precompute(domain=dom)
+    d = P.Mesh(V, w.F)
+    d.precompute(domain=dom, table_mode=P.TABLE_FLOODING_DEVICE)
+    assert all(np.array_equal(a, c) for a, c in zip(d.table(), h.table()))
+    assert np.array_equal(d.table_boxes(), h.table_boxes())
 
 
 def test_golden_points_on_device():
